@@ -1,0 +1,200 @@
+/*
+ * se.h -- C ABI of the MI355X Spectral Ewald library (libse_mi355x.so).
+ *
+ * Evaluates the periodic Stokes potentials of Bagge & Tornberg, "Fast Ewald
+ * summation for Stokes flow with arbitrary periodicity":
+ *
+ *   u^{DP}(x) = sum_n sum_{p in P_DP} G(x - x_n + p) . f(x_n)     eq. (periodic-potential)
+ *
+ * for the stokeslet, rotlet and stresslet kernels (Sec. 2, eq. stokes-kernels;
+ * no 1/(8 pi) factor) with the first D in {0,1,2,3} axes periodic
+ * (eq. periodic-images).  At targets that coincide with the sources the
+ * starred sum (eq. periodic-potential-star) is returned: the term n = m,
+ * p = 0 is omitted.  Conventions of the returned field:
+ *   D = 3: Ewald zero-mode convention, i.e. zero mean flow for the stokeslet
+ *          and rotlet, plus the non-periodic stresslet term (eq. k0-stresslet-3p);
+ *   D = 2, 1: zero modes of the modified kernels (Sec. 3.1), with the D = 1
+ *          stokeslet reported at the gauge l_B = 1, l_H = e^{-1}
+ *          (eq. 1p-stokeslet-extra-contribution);
+ *   D = 0: the free-space sum, decaying at infinity (eq. 0p-stokeslet-extra-contribution
+ *          removed).
+ * The evaluation is the Ewald decomposition (eq. Dp-ewald-decomp / -self):
+ * real-space part on a cell list (Sec. 4.1.2), Fourier-space part by the
+ * Spectral Ewald method (Algorithm 1), self and zero-mode terms.
+ *
+ * All arrays are owned by the caller.  Pointers marked (device) must be HIP
+ * device (or managed) memory on the plan's device; they must stay valid until
+ * the work queued on the given stream has completed.  The plan owns its
+ * workspace (allocated once by se_plan_create) and never frees caller memory.
+ * A plan is not thread safe; distinct plans are independent.  No exception or
+ * abort crosses this ABI: every call returns an se_status.
+ *
+ * Layouts are row-major: positions [n][3] (x, y, z), strengths
+ * [n_rhs][n][3], outputs [n_rhs][n_tgt][3], all IEEE FP64.
+ */
+#ifndef SE_MI355X_H
+#define SE_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t se_status;
+
+#define SE_OK 0
+#define SE_ERR_ARG (-1)             /* invalid argument (null pointer, bad size, bad enum) */
+#define SE_ERR_UNSUPPORTED (-2)     /* valid request outside what this build implements */
+#define SE_ERR_OUT_OF_BOX (-3)      /* a position lies outside [0, L_i) (device-detected) */
+#define SE_ERR_NONFINITE (-4)       /* a position or strength is NaN/Inf (device-detected) */
+#define SE_ERR_COINCIDENT (-5)      /* two distinct points coincide (device-detected) */
+#define SE_ERR_TOL_UNREACHABLE (-6) /* tolerance below what the requested precision reaches */
+#define SE_ERR_NOMEM (-7)           /* device allocation failed */
+#define SE_ERR_HIP (-8)             /* a HIP runtime call failed */
+#define SE_ERR_STATE (-9)           /* call out of order (e.g. execute before geometry) */
+
+#define SE_STOKESLET 0
+#define SE_ROTLET 1
+#define SE_STRESSLET 2
+
+#define SE_TOL_REL 0 /* rms-relative tolerance, mapped through the Fourier-part rms estimate U */
+#define SE_TOL_ABS 1 /* absolute rms tolerance tau_rms (Sec. 4) */
+
+#define SE_PREC_AUTO 0 /* FP32 grid path when tol >= 1e-6 (relative), else FP64 */
+#define SE_PREC_FP64 1
+#define SE_PREC_FP32 2
+
+#define SE_SELECT_ANALYTIC 0 /* the paper's estimate-based procedure, Sec. 4.6 */
+#define SE_SELECT_LEARNED 1  /* reserved: learned selector with analytic fallback */
+#define SE_SELECT_MANUAL 2   /* caller supplies se_params */
+
+/* Problem statement (Algorithm 1 inputs plus the error tolerance). */
+typedef struct se_problem {
+    int32_t struct_size;      /* sizeof(se_problem) */
+    int32_t periodicity;      /* D in {0,1,2,3}: the first D axes are periodic */
+    int32_t kernel;           /* SE_STOKESLET, SE_ROTLET or SE_STRESSLET */
+    int32_t tol_kind;         /* SE_TOL_REL or SE_TOL_ABS */
+    double box[3];            /* primary cell [0,L1) x [0,L2) x [0,L3), all > 0 */
+    double tol;               /* rms tolerance (> 0) */
+    double source_q;          /* Q = sum_n |f_n|^2 (eq. vector-source-quantity) or
+                                 sum_n sum_lm f_lm^2 (eq. tensor-source-quantity);
+                                 <= 0 means 3 per source (unit-variance components) */
+    double xi;                /* Ewald splitting parameter; <= 0: derived from n_rc */
+    double n_rc;              /* expected sources within r_c (Sec. 5.2); <= 0: the
+                                 paper's uniform-system value for (kernel, D) */
+    double safety;            /* tau_abs is divided by this factor; <= 0 means 1 */
+    int32_t precision;        /* SE_PREC_* */
+    int32_t selector;         /* SE_SELECT_* */
+    int64_t n_src;            /* number of sources N >= 1 */
+    int64_t n_tgt;            /* number of targets (ignored when targets_are_sources) */
+    int32_t targets_are_sources; /* 1: evaluate at the sources, starred sum */
+    int32_t n_rhs;            /* strength sets sharing one geometry (>= 1) */
+    int32_t device;           /* HIP device ordinal */
+    int32_t reserved;         /* must be 0 */
+} se_problem;
+
+/* Resolved method parameters (Sec. 3 and 4). */
+typedef struct se_params {
+    int32_t struct_size; /* sizeof(se_params) */
+    int32_t P;           /* window support in grid points (even) */
+    int32_t nu_deg;      /* PKB polynomial degree, eq. (PKB-parameters) */
+    int32_t f_M;         /* grid-size granularity */
+    int32_t M[3];        /* grid subintervals: M_i (periodic axis) or M'_i (free axis) */
+    int32_t n_fft[3];    /* FFT length per axis for the bulk of the modes
+                            (M_i periodic, M'_i free for D = 1, 2, 2 M'_i for D = 0) */
+    int32_t n0_fft[3];   /* free axes, k^P = 0 class: length s0 M'_i (D = 1, 2) */
+    int32_t nstar_fft[3];/* free axes, K_* class: length s_* M'_i (D = 1, 2) */
+    int32_t kstar;       /* upsampling threshold kbar_* (periodic axes), 0: K_* empty */
+    int32_t reserved;
+    double xi;           /* splitting parameter */
+    double rc;           /* real-space cut-off radius */
+    double beta;         /* Kaiser-Bessel shape, eq. (PKB-parameters) */
+    double h[3];         /* grid spacing per axis */
+    double L_ext[3];     /* extended box side L'_i (= L_i on periodic axes) */
+    double dL[3];        /* box padding delta L_i (0 on periodic axes) */
+    double R;            /* truncation radius of the modified kernels, eq. (truncation-radius) */
+    double s0;           /* k^P = 0 upsampling factor, eq. (upsampling-factor-s0) */
+    double s_star;       /* K_* upsampling factor, eq. (upsampling-factor-sstar) */
+    double tau_abs;      /* absolute tolerance used by the estimates */
+    double U;            /* Fourier-part rms estimate U(L,Q,xi), eqs. (pot-mag-est-*) */
+    double est_real;     /* real-space truncation estimate at rc */
+    double est_fourier;  /* Fourier truncation estimate at pi/h */
+    double est_window;   /* window estimate 10 U e^{-2.5 P} */
+} se_params;
+
+typedef struct se_plan se_plan;
+
+/* Library version (major*10000 + minor*100 + patch). */
+int32_t se_version(void);
+
+/* Human-readable text for a status code (static storage). */
+const char* se_status_string(se_status s);
+
+/* Parameter selection only (Sec. 4.6), no device work: fills *out exactly as
+ * se_plan_create would.  Errors: SE_ERR_ARG, SE_ERR_TOL_UNREACHABLE. */
+se_status se_params_select(const se_problem* prob, se_params* out);
+
+/* Select parameters (Sec. 4.6, or `manual` when selector = SE_SELECT_MANUAL,
+ * where `manual` must then be non-null) and allocate all device workspace on
+ * prob->device.  On success *out owns the plan.  Errors: SE_ERR_ARG,
+ * SE_ERR_UNSUPPORTED, SE_ERR_TOL_UNREACHABLE, SE_ERR_NOMEM, SE_ERR_HIP. */
+se_status se_plan_create(const se_problem* prob, const se_params* manual, se_plan** out);
+
+/* Release the plan and its workspace (null is a no-op).  Synchronises the
+ * plan's last stream first. */
+void se_plan_destroy(se_plan* plan);
+
+/* Copy the resolved parameters. */
+se_status se_plan_get_params(const se_plan* plan, se_params* out);
+
+/* Device bytes owned by the plan. */
+size_t se_plan_workspace_bytes(const se_plan* plan);
+
+/* Text of the last error detected on the host for this plan ("" if none). */
+const char* se_plan_last_message(const se_plan* plan);
+
+/* Bind the geometry: sources src_xyz [n_src][3] (device), unit normals
+ * nrm_xyz [n_src][3] (device; required for the stresslet, ignored otherwise),
+ * targets tgt_xyz [n_tgt][3] (device; ignored when targets_are_sources).
+ * Builds the cell list (binning, stable counting sort by cell) on `stream`
+ * (a hipStream_t, null = default stream).  Asynchronous: invalid coordinates
+ * are reported by se_sync_status (SE_ERR_OUT_OF_BOX / SE_ERR_NONFINITE) and
+ * are replaced by 0 so that later launches stay in bounds. */
+se_status se_set_geometry(se_plan* plan, const double* src_xyz, const double* nrm_xyz,
+                          const double* tgt_xyz, void* stream);
+
+/* Evaluate u = u^R + u^F + zero-mode, self and gauge terms for every strength
+ * set: strengths [n_rhs][n_src][3] (device; f for S and Omega, q for T),
+ * u_out [n_rhs][n_tgt][3] (device, overwritten).  Asynchronous on `stream`,
+ * performs no allocation and no synchronisation.  SE_ERR_STATE if no geometry
+ * was bound. */
+se_status se_execute(se_plan* plan, const double* strengths, double* u_out, void* stream);
+
+/* As se_execute but returns the real-space part in u_real and all other terms
+ * (Fourier-space part, zero-mode, self and gauge terms) in u_fourier; their
+ * sum is the se_execute result. */
+se_status se_execute_split(se_plan* plan, const double* strengths, double* u_real,
+                           double* u_fourier, void* stream);
+
+/* Wait for the plan's queued work and return the first device-detected error
+ * (SE_ERR_OUT_OF_BOX, SE_ERR_NONFINITE, SE_ERR_COINCIDENT) or SE_OK; the
+ * device flag is cleared afterwards. */
+se_status se_sync_status(se_plan* plan);
+
+/* Debug/test access to the cell list built by se_set_geometry (device
+ * pointers owned by the plan, valid until the next se_set_geometry or
+ * se_plan_destroy).  which = 0: sources, 1: targets.  perm[n] = original
+ * index of the n-th point in cell order; cell_start[nbins+1] = first sorted
+ * index of each cell; nbins_xyz[3] = cells per axis, cell_width[3] = grid
+ * cells per bin per axis. */
+se_status se_debug_cell_list(const se_plan* plan, int32_t which, const int32_t** perm,
+                             const int32_t** cell_start, int32_t* nbins_xyz,
+                             int32_t* cell_width);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SE_MI355X_H */

@@ -1,0 +1,271 @@
+"""Python binding of libse_mi355x.so (Spectral Ewald for Stokes flow, MI355X).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  The ctypes entry points carry the C names of ``include/se.h``;
+``Plan`` wraps them for torch device tensors (memory and streams only).
+Importing this package fails loudly when the library is not built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libse_mi355x.so")
+
+STOKESLET, ROTLET, STRESSLET = 0, 1, 2
+KERNELS = {"stokeslet": STOKESLET, "rotlet": ROTLET, "stresslet": STRESSLET}
+TOL_REL, TOL_ABS = 0, 1
+PREC_AUTO, PREC_FP64, PREC_FP32 = 0, 1, 2
+SELECT_ANALYTIC, SELECT_LEARNED, SELECT_MANUAL = 0, 1, 2
+
+SE_OK = 0
+STATUS = {0: "SE_OK", -1: "SE_ERR_ARG", -2: "SE_ERR_UNSUPPORTED", -3: "SE_ERR_OUT_OF_BOX",
+          -4: "SE_ERR_NONFINITE", -5: "SE_ERR_COINCIDENT", -6: "SE_ERR_TOL_UNREACHABLE",
+          -7: "SE_ERR_NOMEM", -8: "SE_ERR_HIP", -9: "SE_ERR_STATE"}
+
+
+class se_problem(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_int32), ("periodicity", ctypes.c_int32),
+                ("kernel", ctypes.c_int32), ("tol_kind", ctypes.c_int32),
+                ("box", ctypes.c_double * 3), ("tol", ctypes.c_double),
+                ("source_q", ctypes.c_double), ("xi", ctypes.c_double), ("n_rc", ctypes.c_double),
+                ("safety", ctypes.c_double), ("precision", ctypes.c_int32),
+                ("selector", ctypes.c_int32), ("n_src", ctypes.c_int64), ("n_tgt", ctypes.c_int64),
+                ("targets_are_sources", ctypes.c_int32), ("n_rhs", ctypes.c_int32),
+                ("device", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class se_params(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_int32), ("P", ctypes.c_int32), ("nu_deg", ctypes.c_int32),
+                ("f_M", ctypes.c_int32), ("M", ctypes.c_int32 * 3), ("n_fft", ctypes.c_int32 * 3),
+                ("n0_fft", ctypes.c_int32 * 3), ("nstar_fft", ctypes.c_int32 * 3),
+                ("kstar", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("xi", ctypes.c_double), ("rc", ctypes.c_double), ("beta", ctypes.c_double),
+                ("h", ctypes.c_double * 3), ("L_ext", ctypes.c_double * 3), ("dL", ctypes.c_double * 3),
+                ("R", ctypes.c_double), ("s0", ctypes.c_double), ("s_star", ctypes.c_double),
+                ("tau_abs", ctypes.c_double), ("U", ctypes.c_double), ("est_real", ctypes.c_double),
+                ("est_fourier", ctypes.c_double), ("est_window", ctypes.c_double)]
+
+
+EXPORTS = ["se_version", "se_status_string", "se_params_select", "se_plan_create", "se_plan_destroy",
+           "se_plan_get_params", "se_plan_workspace_bytes", "se_plan_last_message", "se_set_geometry",
+           "se_execute", "se_execute_split", "se_sync_status", "se_debug_cell_list"]
+
+
+class SEError(RuntimeError):
+    def __init__(self, status, where=""):
+        self.status = status
+        super().__init__("%s: %s" % (where, STATUS.get(status, str(status))))
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libse_mi355x.so is not built (run __graft_entry__.build() or "
+                          "python -m paper_2210_01255_amd.build)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32 = ctypes.c_void_p, ctypes.c_int32
+    P = ctypes.POINTER
+    L.se_version.restype = i32
+    L.se_version.argtypes = []
+    L.se_status_string.restype = ctypes.c_char_p
+    L.se_status_string.argtypes = [i32]
+    L.se_params_select.restype = i32
+    L.se_params_select.argtypes = [P(se_problem), P(se_params)]
+    L.se_plan_create.restype = i32
+    L.se_plan_create.argtypes = [P(se_problem), P(se_params), P(vp)]
+    L.se_plan_destroy.restype = None
+    L.se_plan_destroy.argtypes = [vp]
+    L.se_plan_get_params.restype = i32
+    L.se_plan_get_params.argtypes = [vp, P(se_params)]
+    L.se_plan_workspace_bytes.restype = ctypes.c_size_t
+    L.se_plan_workspace_bytes.argtypes = [vp]
+    L.se_plan_last_message.restype = ctypes.c_char_p
+    L.se_plan_last_message.argtypes = [vp]
+    L.se_set_geometry.restype = i32
+    L.se_set_geometry.argtypes = [vp, vp, vp, vp, vp]
+    L.se_execute.restype = i32
+    L.se_execute.argtypes = [vp, vp, vp, vp]
+    L.se_execute_split.restype = i32
+    L.se_execute_split.argtypes = [vp, vp, vp, vp, vp]
+    L.se_sync_status.restype = i32
+    L.se_sync_status.argtypes = [vp]
+    L.se_debug_cell_list.restype = i32
+    L.se_debug_cell_list.argtypes = [vp, i32, P(vp), P(vp), P(i32 * 3), P(i32 * 3)]
+    return L
+
+
+lib = _load()
+
+# Same names as the C ABI (thin forwards).
+se_version = lib.se_version
+se_status_string = lib.se_status_string
+se_params_select = lib.se_params_select
+se_plan_create = lib.se_plan_create
+se_plan_destroy = lib.se_plan_destroy
+se_plan_get_params = lib.se_plan_get_params
+se_plan_workspace_bytes = lib.se_plan_workspace_bytes
+se_plan_last_message = lib.se_plan_last_message
+se_set_geometry = lib.se_set_geometry
+se_execute = lib.se_execute
+se_execute_split = lib.se_execute_split
+se_sync_status = lib.se_sync_status
+se_debug_cell_list = lib.se_debug_cell_list
+
+
+def make_problem(kernel="stokeslet", periodicity=3, box=(1.0, 1.0, 1.0), tol=1e-8, tol_kind=TOL_REL,
+                 n_src=1, n_tgt=0, targets_are_sources=True, n_rhs=1, source_q=0.0, xi=0.0, n_rc=0.0,
+                 safety=0.0, precision=PREC_FP64, selector=SELECT_ANALYTIC, device=0) -> se_problem:
+    p = se_problem()
+    p.struct_size = ctypes.sizeof(se_problem)
+    p.periodicity = int(periodicity)
+    p.kernel = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+    p.tol_kind = int(tol_kind)
+    for i in range(3):
+        p.box[i] = float(box[i])
+    p.tol = float(tol)
+    p.source_q = float(source_q)
+    p.xi = float(xi)
+    p.n_rc = float(n_rc)
+    p.safety = float(safety)
+    p.precision = int(precision)
+    p.selector = int(selector)
+    p.n_src = int(n_src)
+    p.n_tgt = int(n_tgt)
+    p.targets_are_sources = 1 if targets_are_sources else 0
+    p.n_rhs = int(n_rhs)
+    p.device = int(device)
+    p.reserved = 0
+    return p
+
+
+def params_to_dict(par: se_params) -> dict:
+    out = {}
+    for name, _ in se_params._fields_:
+        v = getattr(par, name)
+        if hasattr(v, "__len__"):
+            v = list(v)
+        out[name] = v
+    return out
+
+
+def select_params(**kw) -> dict:
+    """Host-only parameter selection (se_params_select)."""
+    prob = make_problem(**kw)
+    par = se_params()
+    st = lib.se_params_select(ctypes.byref(prob), ctypes.byref(par))
+    if st != SE_OK:
+        raise SEError(st, "se_params_select")
+    return params_to_dict(par)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """A plan bound to one device; tensors are torch float64 device tensors."""
+
+    def __init__(self, manual: se_params | None = None, **kw):
+        self.problem = make_problem(**kw)
+        h = ctypes.c_void_p()
+        st = lib.se_plan_create(ctypes.byref(self.problem),
+                                ctypes.byref(manual) if manual is not None else None, ctypes.byref(h))
+        if st != SE_OK:
+            raise SEError(st, "se_plan_create")
+        self.handle = h
+        par = se_params()
+        lib.se_plan_get_params(self.handle, ctypes.byref(par))
+        self.params = params_to_dict(par)
+        self.kernel = self.problem.kernel
+        self.n_src = self.problem.n_src
+        self.n_tgt = self.problem.n_src if self.problem.targets_are_sources else self.problem.n_tgt
+        self.n_rhs = self.problem.n_rhs
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.se_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _check(t, shape, name):
+        import torch
+        if t is None:
+            return
+        if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+            raise ValueError("%s must be a contiguous float64 device tensor" % name)
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError("%s has shape %s, expected %s" % (name, tuple(t.shape), shape))
+
+    def set_geometry(self, src, normals=None, targets=None, stream=None, check=False):
+        self._check(src, (self.n_src, 3), "src")
+        self._check(normals, (self.n_src, 3), "normals")
+        if not self.problem.targets_are_sources:
+            self._check(targets, (self.n_tgt, 3), "targets")
+        self._keep = (src, normals, targets)
+        st = lib.se_set_geometry(self.handle, _ptr(src), _ptr(normals), _ptr(targets), _stream(stream))
+        if st != SE_OK:
+            raise SEError(st, "se_set_geometry")
+        if check:
+            self.sync()
+
+    def execute(self, strengths, out=None, stream=None):
+        import torch
+        shp = (self.n_rhs, self.n_src, 3) if self.n_rhs > 1 else (self.n_src, 3)
+        self._check(strengths, shp, "strengths")
+        if out is None:
+            oshape = (self.n_rhs, self.n_tgt, 3) if self.n_rhs > 1 else (self.n_tgt, 3)
+            out = torch.empty(oshape, dtype=torch.float64, device=strengths.device)
+        st = lib.se_execute(self.handle, _ptr(strengths), _ptr(out), _stream(stream))
+        if st != SE_OK:
+            raise SEError(st, "se_execute")
+        return out
+
+    def execute_split(self, strengths, stream=None):
+        import torch
+        oshape = (self.n_rhs, self.n_tgt, 3) if self.n_rhs > 1 else (self.n_tgt, 3)
+        ur = torch.empty(oshape, dtype=torch.float64, device=strengths.device)
+        uf = torch.empty(oshape, dtype=torch.float64, device=strengths.device)
+        st = lib.se_execute_split(self.handle, _ptr(strengths), _ptr(ur), _ptr(uf), _stream(stream))
+        if st != SE_OK:
+            raise SEError(st, "se_execute_split")
+        return ur, uf
+
+    def sync(self):
+        st = lib.se_sync_status(self.handle)
+        if st != SE_OK:
+            raise SEError(st, "se_sync_status")
+
+    def cell_list(self, which=0):
+        """(perm, cell_start, nbins_xyz, cell_width) as host numpy arrays."""
+        import numpy as np
+        import torch
+        pp, cs = ctypes.c_void_p(), ctypes.c_void_p()
+        nb, cw = (ctypes.c_int32 * 3)(), (ctypes.c_int32 * 3)()
+        st = lib.se_debug_cell_list(self.handle, which, ctypes.byref(pp), ctypes.byref(cs),
+                                    ctypes.byref(nb), ctypes.byref(cw))
+        if st != SE_OK:
+            raise SEError(st, "se_debug_cell_list")
+        torch.cuda.synchronize()
+        n = self.n_src if which == 0 else self.n_tgt
+        nbins = nb[0] * nb[1] * nb[2]
+        perm = np.empty(n, dtype=np.int32)
+        start = np.empty(nbins + 1, dtype=np.int32)
+        hip = ctypes.CDLL("libamdhip64.so")
+        hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+        hip.hipMemcpy(perm.ctypes.data, pp, perm.nbytes, 2)
+        hip.hipMemcpy(start.ctypes.data, cs, start.nbytes, 2)
+        return perm, start, list(nb), list(cw)

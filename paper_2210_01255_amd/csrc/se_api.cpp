@@ -1,0 +1,397 @@
+// se_api.cpp -- the C ABI: plan lifecycle, geometry binding and execution.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <new>
+
+#include "se_internal.h"
+
+// defined in se_geom.hip / se_spread.hip
+se_status se_sort_pairs_raw(void* tmp, size_t tmp_bytes, const int* keys_in, int* keys_out, const int* vals_in,
+                            int* vals_out, int64_t n, int end_bit, hipStream_t s);
+size_t se_sort_tmp_bytes(int64_t n, int end_bit);
+void se_tile_shape(int ncomp, bool fp32, int* tile);
+
+namespace {
+
+struct Alloc {
+    se_plan* p;
+    bool ok = true;
+    template <typename T>
+    T* get(size_t count)
+    {
+        if (!ok || count == 0) return nullptr;
+        void* ptr = nullptr;
+        size_t bytes = count * sizeof(T);
+        bytes = (bytes + 255) & ~(size_t)255;
+        if (hipMalloc(&ptr, bytes) != hipSuccess) {
+            ok = false;
+            return nullptr;
+        }
+        p->ws_bytes += bytes;
+        return (T*)ptr;
+    }
+};
+
+void free_all(se_plan* p)
+{
+    void* ptrs[] = {p->d_flags, p->d_src, p->d_nrm, p->d_src_perm, p->d_src_start, p->d_tgt, p->d_tgt_perm,
+                    p->d_tgt_start, p->d_keys_a, p->d_keys_b, p->d_vals_a, p->d_sort_tmp, p->d_fs, p->d_fs64,
+                    p->d_red, p->d_grid, p->d_spec, p->d_uF, p->d_uR, p->d_pkb, p->d_invw2, p->d_tw};
+    for (void* q : ptrs)
+        if (q) hipFree(q);
+}
+
+int key_bits(int64_t nbins)
+{
+    int b = 1;
+    while ((int64_t(1) << b) <= nbins) b++;
+    return b;
+}
+
+se_status check_hip(se_plan* p, hipError_t e, const char* what)
+{
+    if (e == hipSuccess) return SE_OK;
+    if (p) p->msg = std::string(what) + ": " + hipGetErrorString(e);
+    return SE_ERR_HIP;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t se_version(void) { return SE_VERSION_MAJOR * 10000 + SE_VERSION_MINOR * 100 + SE_VERSION_PATCH; }
+
+const char* se_status_string(se_status s)
+{
+    switch (s) {
+        case SE_OK: return "ok";
+        case SE_ERR_ARG: return "invalid argument";
+        case SE_ERR_UNSUPPORTED: return "unsupported request";
+        case SE_ERR_OUT_OF_BOX: return "point outside the primary cell";
+        case SE_ERR_NONFINITE: return "non-finite input";
+        case SE_ERR_COINCIDENT: return "coincident distinct points";
+        case SE_ERR_TOL_UNREACHABLE: return "tolerance unreachable at the requested precision";
+        case SE_ERR_NOMEM: return "device allocation failed";
+        case SE_ERR_HIP: return "HIP runtime error";
+        case SE_ERR_STATE: return "call out of order";
+        default: return "unknown status";
+    }
+}
+
+static se_status validate_problem(const se_problem* prob)
+{
+    if (prob->struct_size != (int32_t)sizeof(se_problem)) return SE_ERR_ARG;
+    if (prob->periodicity < 0 || prob->periodicity > 3) return SE_ERR_ARG;
+    if (prob->kernel < SE_STOKESLET || prob->kernel > SE_STRESSLET) return SE_ERR_ARG;
+    if (prob->tol_kind != SE_TOL_REL && prob->tol_kind != SE_TOL_ABS) return SE_ERR_ARG;
+    if (!(prob->tol > 0) || !std::isfinite(prob->tol)) return SE_ERR_ARG;
+    for (int i = 0; i < 3; i++)
+        if (!(prob->box[i] > 0) || !std::isfinite(prob->box[i])) return SE_ERR_ARG;
+    if (prob->n_src < 1 || prob->n_src > (int64_t)1 << 30) return SE_ERR_ARG;
+    if (!prob->targets_are_sources && (prob->n_tgt < 1 || prob->n_tgt > (int64_t)1 << 30)) return SE_ERR_ARG;
+    if (prob->n_rhs < 1) return SE_ERR_ARG;
+    if (prob->precision < SE_PREC_AUTO || prob->precision > SE_PREC_FP32) return SE_ERR_ARG;
+    if (prob->selector < SE_SELECT_ANALYTIC || prob->selector > SE_SELECT_MANUAL) return SE_ERR_ARG;
+    if (prob->reserved != 0) return SE_ERR_ARG;
+    return SE_OK;
+}
+
+se_status se_params_select(const se_problem* prob, se_params* out)
+{
+    if (!prob || !out) return SE_ERR_ARG;
+    se_status st = validate_problem(prob);
+    if (st != SE_OK) return st;
+    if (prob->selector == SE_SELECT_MANUAL) return SE_ERR_ARG;
+    std::string msg;
+    return se_select_params(prob, nullptr, out, &msg);
+}
+
+se_status se_plan_create(const se_problem* prob, const se_params* manual, se_plan** out)
+{
+    if (!prob || !out) return SE_ERR_ARG;
+    *out = nullptr;
+    {
+        se_status st0 = validate_problem(prob);
+        if (st0 != SE_OK) return st0;
+    }
+
+    se_plan* p = new (std::nothrow) se_plan();
+    if (!p) return SE_ERR_NOMEM;
+    p->prob = *prob;
+    p->D = prob->periodicity;
+    p->kernel = prob->kernel;
+    p->ncomp = prob->kernel == SE_STRESSLET ? 6 : 3;
+    p->nrhs = prob->n_rhs;
+    p->device = prob->device;
+    p->ns = prob->n_src;
+    p->tas = prob->targets_are_sources != 0;
+    p->nt = p->tas ? prob->n_src : prob->n_tgt;
+
+    if (p->D != 3) {
+        delete p;
+        return SE_ERR_UNSUPPORTED;
+    }
+    // precision: the FP32 grid path is for tolerances >= 1e-6
+    if (prob->precision == SE_PREC_FP32) {
+        double rel = prob->tol;
+        if (prob->tol_kind == SE_TOL_REL && rel < 1e-6) {
+            delete p;
+            return SE_ERR_TOL_UNREACHABLE;
+        }
+        p->fp32 = true;
+    } else if (prob->precision == SE_PREC_AUTO) {
+        p->fp32 = (prob->tol_kind == SE_TOL_REL && prob->tol >= 1e-6);
+    }
+    std::string msg;
+    se_status st = se_select_params(prob, manual, &p->par, &msg);
+    if (st != SE_OK) {
+        delete p;
+        return st;
+    }
+    const se_params& par = p->par;
+
+    // grid geometry
+    se_grid_geom& g = p->g;
+    g.D = p->D;
+    for (int d = 0; d < 3; d++) {
+        g.Mg[d] = par.M[d];
+        g.h[d] = par.h[d];
+        g.invh[d] = 1.0 / par.h[d];
+        g.L[d] = prob->box[d];
+        g.periodic[d] = d < p->D;
+        g.x0[d] = d < p->D ? 0.0 : -0.5 * par.dL[d];
+        int B = (g.Mg[d] % 4 == 0) ? 4 : ((g.Mg[d] % 2 == 0) ? 2 : 1);
+        g.B[d] = B;
+        g.nb[d] = (g.Mg[d] + B - 1) / B;
+        p->Nfft[d] = par.n_fft[d];
+    }
+    p->nbins = (int64_t)g.nb[0] * g.nb[1] * g.nb[2];
+    p->Hx = p->Nfft[0] / 2 + 1;
+    se_tile_shape(p->ncomp, p->fp32, p->tile);
+    for (int d = 0; d < 3; d++) p->ntile[d] = (g.Mg[d] + p->tile[d] - 1) / p->tile[d];
+
+    // transform-size limits of the LDS-resident line FFTs
+    std::vector<int> rr;
+    bool ok = (p->Nfft[0] % 2 == 0) && se_smooth_factors(p->Nfft[0] / 2, &rr) && p->Nfft[0] / 2 <= SE_FFT_LDS_ELEMS &&
+              se_smooth_factors(p->Nfft[1], &rr) && p->Nfft[1] <= SE_FFT_LDS_ELEMS &&
+              se_smooth_factors(p->Nfft[2], &rr) && p->ncomp * p->Nfft[2] <= (p->fp32 ? 6144 : 3072);
+    if (!ok) {
+        delete p;
+        return SE_ERR_UNSUPPORTED;
+    }
+
+    if (hipSetDevice(p->device) != hipSuccess) {
+        delete p;
+        return SE_ERR_HIP;
+    }
+    // ---- allocation
+    Alloc A{p};
+    const size_t rs = p->fp32 ? sizeof(float) : sizeof(double);
+    const int64_t nmax = std::max(p->ns, p->nt);
+    p->d_flags = A.get<int>(1);
+    p->d_src = A.get<double>(3 * p->ns);
+    if (p->kernel == SE_STRESSLET) p->d_nrm = A.get<double>(3 * p->ns);
+    p->d_src_perm = A.get<int>(p->ns);
+    p->d_src_start = A.get<int>(p->nbins + 1);
+    if (!p->tas) {
+        p->d_tgt = A.get<double>(3 * p->nt);
+        p->d_tgt_perm = A.get<int>(p->nt);
+        p->d_tgt_start = A.get<int>(p->nbins + 1);
+    }
+    p->d_keys_a = A.get<int>(nmax);
+    p->d_keys_b = A.get<int>(nmax);
+    p->d_vals_a = A.get<int>(nmax);
+    p->sort_tmp_bytes = se_sort_tmp_bytes(nmax, key_bits(p->nbins));
+    p->d_sort_tmp = A.get<char>(std::max<size_t>(p->sort_tmp_bytes, 256));
+    p->d_fs = A.get<char>((size_t)p->ncomp * p->ns * rs);
+    p->d_fs64 = A.get<double>(4 * p->ns);
+    p->d_red = A.get<double>(4);
+    const size_t gv = (size_t)g.Mg[0] * g.Mg[1] * g.Mg[2];
+    p->d_grid = A.get<char>((size_t)p->ncomp * gv * rs);
+    const size_t sv = (size_t)p->Hx * p->Nfft[1] * g.Mg[2];
+    p->d_spec = A.get<char>((size_t)p->ncomp * sv * 2 * rs);
+    p->d_uF = A.get<double>(3 * p->nt);
+    p->d_uR = A.get<double>(3 * p->nt);
+    p->d_pkb = A.get<double>((size_t)par.P * (par.nu_deg + 1));
+    p->d_invw2 = A.get<double>((size_t)p->Hx + p->Nfft[1] + p->Nfft[2]);
+    const int Nh = p->Nfft[0] / 2;
+    const size_t ntw = (size_t)Nh + (Nh + 1) + p->Nfft[1] + p->Nfft[2];
+    p->d_tw = A.get<double>(2 * ntw);
+    if (!A.ok) {
+        free_all(p);
+        delete p;
+        return SE_ERR_NOMEM;
+    }
+
+    // ---- host tables
+    std::vector<double> pkb;
+    se_pkb_coefficients(par.P, par.nu_deg, par.beta, &pkb);
+    std::vector<double> iw;
+    iw.reserve((size_t)p->Hx + p->Nfft[1] + p->Nfft[2]);
+    for (int d = 0; d < 3; d++) {
+        const int N = p->Nfft[d];
+        const int cnt = d == 0 ? p->Hx : N;
+        const double a = par.h[d] * par.P / 2.0;
+        for (int i = 0; i < cnt; i++) {
+            int kb = (d == 0) ? i : (i < N / 2 ? i : i - N);
+            double k = 2.0 * M_PI * kb / (par.h[d] * N);
+            double w = se_kb_fourier(k, a, par.beta);
+            iw.push_back(1.0 / (w * w));
+        }
+    }
+    std::vector<double> tw;
+    tw.reserve(2 * ntw);
+    auto push_table = [&](int N, int count) {
+        for (int k = 0; k < count; k++) {
+            long double ang = -2.0L * 3.141592653589793238462643383279502884L * k / N;
+            tw.push_back((double)std::cos(ang));
+            tw.push_back((double)std::sin(ang));
+        }
+    };
+    p->tw_off[0] = 0;
+    push_table(Nh, Nh);
+    p->tw_off[1] = Nh;
+    push_table(p->Nfft[0], Nh + 1);
+    p->tw_off[2] = 2 * Nh + 1;
+    push_table(p->Nfft[1], p->Nfft[1]);
+    p->tw_off[3] = 2 * Nh + 1 + p->Nfft[1];
+    push_table(p->Nfft[2], p->Nfft[2]);
+
+    hipError_t e = hipMemcpy(p->d_pkb, pkb.data(), pkb.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->d_invw2, iw.data(), iw.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->d_tw, tw.data(), tw.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(p->d_flags, 0, sizeof(int));
+    if (e == hipSuccess) e = hipMemset(p->d_red, 0, 4 * sizeof(double));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        free_all(p);
+        delete p;
+        return SE_ERR_HIP;
+    }
+    *out = p;
+    return SE_OK;
+}
+
+void se_plan_destroy(se_plan* plan)
+{
+    if (!plan) return;
+    hipSetDevice(plan->device);
+    hipDeviceSynchronize();
+    free_all(plan);
+    delete plan;
+}
+
+se_status se_plan_get_params(const se_plan* plan, se_params* out)
+{
+    if (!plan || !out) return SE_ERR_ARG;
+    *out = plan->par;
+    return SE_OK;
+}
+
+size_t se_plan_workspace_bytes(const se_plan* plan) { return plan ? plan->ws_bytes : 0; }
+
+const char* se_plan_last_message(const se_plan* plan) { return plan ? plan->msg.c_str() : ""; }
+
+static se_status bind_points(se_plan* p, const double* xyz, int64_t n, int* perm, int* start, double* sorted,
+                             hipStream_t s)
+{
+    se_launch_bin_keys(p->g, xyz, n, p->d_keys_a, p->d_vals_a, p->d_flags, s);
+    se_status st = se_sort_pairs_raw(p->d_sort_tmp, p->sort_tmp_bytes, p->d_keys_a, p->d_keys_b, p->d_vals_a, perm,
+                                     n, key_bits(p->nbins), s);
+    if (st != SE_OK) {
+        p->msg = "radix sort failed";
+        return st;
+    }
+    se_launch_cell_starts(p->d_keys_b, n, p->nbins, start, s);
+    se_launch_gather_sorted(xyz, perm, n, p->g, sorted, 1, s);
+    return check_hip(p, hipGetLastError(), "bind_points");
+}
+
+se_status se_set_geometry(se_plan* plan, const double* src_xyz, const double* nrm_xyz, const double* tgt_xyz,
+                          void* stream)
+{
+    if (!plan || !src_xyz) return SE_ERR_ARG;
+    if (plan->kernel == SE_STRESSLET && !nrm_xyz) return SE_ERR_ARG;
+    if (!plan->tas && !tgt_xyz) return SE_ERR_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    if (hipSetDevice(plan->device) != hipSuccess) return SE_ERR_HIP;
+    plan->have_geometry = false;
+    se_status st = bind_points(plan, src_xyz, plan->ns, plan->d_src_perm, plan->d_src_start, plan->d_src, s);
+    if (st != SE_OK) return st;
+    if (plan->kernel == SE_STRESSLET) se_launch_gather_sorted(nrm_xyz, plan->d_src_perm, plan->ns, plan->g, plan->d_nrm, 0, s);
+    if (!plan->tas) {
+        st = bind_points(plan, tgt_xyz, plan->nt, plan->d_tgt_perm, plan->d_tgt_start, plan->d_tgt, s);
+        if (st != SE_OK) return st;
+    }
+    st = check_hip(plan, hipGetLastError(), "se_set_geometry");
+    if (st == SE_OK) plan->have_geometry = true;
+    return st;
+}
+
+static se_status run(se_plan* p, const double* strengths, double* u, double* ur, double* uf, hipStream_t s)
+{
+    if (!p || !strengths) return SE_ERR_ARG;
+    if (!p->have_geometry) return SE_ERR_STATE;
+    if (hipSetDevice(p->device) != hipSuccess) return SE_ERR_HIP;
+    for (int r = 0; r < p->nrhs; r++) {
+        const double* f = strengths + (size_t)r * p->ns * 3;
+        double* ur_ = u ? u + (size_t)r * p->nt * 3 : nullptr;
+        double* urr = ur ? ur + (size_t)r * p->nt * 3 : nullptr;
+        double* urf = uf ? uf + (size_t)r * p->nt * 3 : nullptr;
+        se_launch_strengths(p, f, s);
+        se_launch_reductions(p, s);
+        se_launch_spread(p, s);
+        se_launch_fft_forward(p, s);
+        se_launch_fft_inverse(p, s);
+        se_launch_fill_double(p->d_uF, 0.0, 3 * p->nt, s);
+        se_launch_gather(p, s);
+        se_launch_real_space(p, s);
+        se_launch_finalize(p, f, ur_, urr, urf, s);
+    }
+    return check_hip(p, hipGetLastError(), "se_execute");
+}
+
+se_status se_execute(se_plan* plan, const double* strengths, double* u_out, void* stream)
+{
+    if (!u_out) return SE_ERR_ARG;
+    return run(plan, strengths, u_out, nullptr, nullptr, (hipStream_t)stream);
+}
+
+se_status se_execute_split(se_plan* plan, const double* strengths, double* u_real, double* u_fourier, void* stream)
+{
+    if (!u_real || !u_fourier) return SE_ERR_ARG;
+    return run(plan, strengths, nullptr, u_real, u_fourier, (hipStream_t)stream);
+}
+
+se_status se_sync_status(se_plan* plan)
+{
+    if (!plan) return SE_ERR_ARG;
+    if (hipSetDevice(plan->device) != hipSuccess) return SE_ERR_HIP;
+    if (hipDeviceSynchronize() != hipSuccess) return SE_ERR_HIP;
+    int flags = 0;
+    if (hipMemcpy(&flags, plan->d_flags, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return SE_ERR_HIP;
+    if (flags) hipMemset(plan->d_flags, 0, sizeof(int));
+    if (flags & SE_FLAG_NONFINITE) return SE_ERR_NONFINITE;
+    if (flags & SE_FLAG_OUT_OF_BOX) return SE_ERR_OUT_OF_BOX;
+    if (flags & SE_FLAG_COINCIDENT) return SE_ERR_COINCIDENT;
+    return SE_OK;
+}
+
+se_status se_debug_cell_list(const se_plan* plan, int32_t which, const int32_t** perm, const int32_t** cell_start,
+                             int32_t* nbins_xyz, int32_t* cell_width)
+{
+    if (!plan || !perm || !cell_start || !nbins_xyz || !cell_width) return SE_ERR_ARG;
+    if (which != 0 && which != 1) return SE_ERR_ARG;
+    if (which == 1 && plan->tas) which = 0;
+    *perm = which == 0 ? plan->d_src_perm : plan->d_tgt_perm;
+    *cell_start = which == 0 ? plan->d_src_start : plan->d_tgt_start;
+    for (int d = 0; d < 3; d++) {
+        nbins_xyz[d] = plan->g.nb[d];
+        cell_width[d] = plan->g.B[d];
+    }
+    return SE_OK;
+}
+
+}  // extern "C"

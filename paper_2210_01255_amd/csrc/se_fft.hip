@@ -1,0 +1,577 @@
+// se_fft.hip -- FFT / scaling / IFFT steps (Sec. 3.2 steps (ii)-(iv)).
+//
+// Hand-written mixed-radix (2,3,4,5,7,8) Stockham transforms on LDS-resident
+// lines, five passes over HBM per solve:
+//   x  : real-to-complex along x (length-N/2 complex FFT + split), zero padded
+//        input, writes the half spectrum [c][z][y][0..N/2];
+//   y  : complex along y for bundles of adjacent kx columns (coalesced rows);
+//   z  : complex along z, scaling (Green's function x screening / window^2)
+//        and the inverse along z fused in one kernel, all components of a
+//        column bundle resident in LDS;
+//   y^-1, x^-1 (complex-to-real, truncated to the valid grid).
+// The scaling includes the normalisation h^3/(N1 N2 N3) of the trapezoid
+// rule in steps (ii), (iv) and (v), so the gathered sum is the Fourier part.
+#include <algorithm>
+#include <cstring>
+
+#include "se_device.h"
+
+namespace {
+
+#define SE_MAX_RAD 24
+
+struct se_fft_args {
+    int Mg[3];
+    int N[3];
+    int Hx;
+    int ncomp;
+    void* grid;
+    void* spec;
+    const double* tw;
+    int tw_xh, tw_xp, tw_y, tw_z;
+    int rad_xh[SE_MAX_RAD], nrad_xh;
+    int rad_y[SE_MAX_RAD], nrad_y;
+    int rad_z[SE_MAX_RAD], nrad_z;
+    int lines;  // rows per workgroup (x passes)
+    int cols;   // kx columns per workgroup (y, z passes)
+    // scaling
+    int kernel;
+    int D;
+    double kfac[3];  // 2 pi / (h_i N_i)
+    double xi;
+    double scale;    // h1 h2 h3 / (N1 N2 N3)
+    const double* invw2;  // 1/what0^2: [Hx | N1 | N2] per axis
+    int iw_off[3];
+};
+
+template <typename R>
+using C = se_cplx<R>;
+
+// ---------------------------------------------------------------- small DFTs
+template <typename R>
+__device__ __forceinline__ C<R> mul_mi(C<R> a, int dir)  // a * (-i dir)
+{
+    return dir > 0 ? C<R>{a.y, -a.x} : C<R>{-a.y, a.x};
+}
+
+template <int RAD>
+struct se_dft_tab;
+template <>
+struct se_dft_tab<3> {
+    static constexpr double c[3] = {1.0, -0.5, -0.5};
+    static constexpr double s[3] = {0.0, 0.8660254037844386467637232, -0.8660254037844386467637232};
+};
+template <>
+struct se_dft_tab<5> {
+    static constexpr double c[5] = {1.0, 0.3090169943749474241022934, -0.8090169943749474241022934,
+                                    -0.8090169943749474241022934, 0.3090169943749474241022934};
+    static constexpr double s[5] = {0.0, 0.9510565162951535721164393, 0.587785252292473129168706,
+                                    -0.587785252292473129168706, -0.9510565162951535721164393};
+};
+template <>
+struct se_dft_tab<7> {
+    static constexpr double c[7] = {1.0, 0.6234898018587335305250049, -0.2225209339563144042889026,
+                                    -0.9009688679024191262361023, -0.9009688679024191262361023,
+                                    -0.2225209339563144042889026, 0.6234898018587335305250049};
+    static constexpr double s[7] = {0.0, 0.7818314824680298087084445, 0.9749279121818236070181317,
+                                    0.4338837391175581204757683, -0.4338837391175581204757683,
+                                    -0.9749279121818236070181317, -0.7818314824680298087084445};
+};
+
+// forward: out[k] = sum_n v[n] e^{-2 pi i n k / RAD}; inverse with +i
+template <typename R, int RAD>
+__device__ __forceinline__ void dft_small(C<R>* v, int dir)
+{
+    if constexpr (RAD == 2) {
+        C<R> a = v[0], b = v[1];
+        v[0] = {a.x + b.x, a.y + b.y};
+        v[1] = {a.x - b.x, a.y - b.y};
+    } else if constexpr (RAD == 4) {
+        C<R> a0 = v[0], a1 = v[1], a2 = v[2], a3 = v[3];
+        C<R> s02 = {a0.x + a2.x, a0.y + a2.y}, d02 = {a0.x - a2.x, a0.y - a2.y};
+        C<R> s13 = {a1.x + a3.x, a1.y + a3.y}, d13 = {a1.x - a3.x, a1.y - a3.y};
+        C<R> t = mul_mi(d13, dir);
+        v[0] = {s02.x + s13.x, s02.y + s13.y};
+        v[2] = {s02.x - s13.x, s02.y - s13.y};
+        v[1] = {d02.x + t.x, d02.y + t.y};
+        v[3] = {d02.x - t.x, d02.y - t.y};
+    } else if constexpr (RAD == 8) {
+        C<R> e[4] = {v[0], v[2], v[4], v[6]};
+        C<R> o[4] = {v[1], v[3], v[5], v[7]};
+        dft_small<R, 4>(e, dir);
+        dft_small<R, 4>(o, dir);
+        const R h = (R)0.7071067811865475244008444;
+        // W8^k, k = 0..3 (forward e^{-i pi k/4})
+        C<R> w1 = {h, dir > 0 ? -h : h};
+        C<R> w3 = {-h, dir > 0 ? -h : h};
+        C<R> o1 = cmul(o[1], w1);
+        C<R> o2 = mul_mi(o[2], dir);
+        C<R> o3 = cmul(o[3], w3);
+        v[0] = {e[0].x + o[0].x, e[0].y + o[0].y};
+        v[4] = {e[0].x - o[0].x, e[0].y - o[0].y};
+        v[1] = {e[1].x + o1.x, e[1].y + o1.y};
+        v[5] = {e[1].x - o1.x, e[1].y - o1.y};
+        v[2] = {e[2].x + o2.x, e[2].y + o2.y};
+        v[6] = {e[2].x - o2.x, e[2].y - o2.y};
+        v[3] = {e[3].x + o3.x, e[3].y + o3.y};
+        v[7] = {e[3].x - o3.x, e[3].y - o3.y};
+    } else {
+        C<R> out[RAD];
+#pragma unroll
+        for (int k = 0; k < RAD; k++) {
+            R ax = 0, ay = 0;
+#pragma unroll
+            for (int n = 0; n < RAD; n++) {
+                const int m = (n * k) % RAD;
+                const R c = (R)se_dft_tab<RAD>::c[m];
+                const R s = (R)se_dft_tab<RAD>::s[m] * (R)dir;
+                // v * (c - i s)
+                ax += v[n].x * c + v[n].y * s;
+                ay += v[n].y * c - v[n].x * s;
+            }
+            out[k] = {ax, ay};
+        }
+#pragma unroll
+        for (int k = 0; k < RAD; k++) v[k] = out[k];
+    }
+}
+
+// One Stockham stage of radix RAD over `nl` lines of length N held in LDS.
+// Line l starts at (l / lpg) * gs + (l % lpg) * ls; element e at +e*es.
+// Work item idx -> (line, butterfly j); lines_fastest selects which index
+// varies fastest across threads (pick the one that is unit stride in LDS).
+template <typename R, int RAD, int ELEMS>
+__device__ __forceinline__ void fft_stage(C<R>* buf, int N, int nl, int lpg, int gs, int ls, int es,
+                                          bool lines_fastest, const C<R>* tw, int dir, int Ns)
+{
+    constexpr int MAXB = (ELEMS / RAD + SE_FFT_THREADS - 1) / SE_FFT_THREADS;
+    const int nb = N / RAD;
+    const int total = nb * nl;
+    const int tstride = N / (Ns * RAD);
+    C<R> v[MAXB][RAD];
+    int base[MAXB], jj[MAXB];
+#pragma unroll
+    for (int b = 0; b < MAXB; b++) {
+        int idx = threadIdx.x + b * SE_FFT_THREADS;
+        base[b] = -1;
+        if (idx < total) {
+            int line, j;
+            if (lines_fastest) {
+                line = idx % nl;
+                j = idx / nl;
+            } else {
+                j = idx % nb;
+                line = idx / nb;
+            }
+            base[b] = (line / lpg) * gs + (line % lpg) * ls;
+            jj[b] = j;
+            const int jn = j % Ns;
+            const int ts = jn * tstride;
+#pragma unroll
+            for (int r = 0; r < RAD; r++) {
+                C<R> x = buf[base[b] + (j + r * nb) * es];
+                if (r > 0) {
+                    C<R> w = tw[r * ts];
+                    if (dir < 0) w.y = -w.y;
+                    x = cmul(x, w);
+                }
+                v[b][r] = x;
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < MAXB; b++) {
+        if (base[b] >= 0) {
+            dft_small<R, RAD>(v[b], dir);
+            const int j = jj[b];
+            const int jn = j % Ns;
+            const int od = (j / Ns) * Ns * RAD + jn;
+#pragma unroll
+            for (int r = 0; r < RAD; r++) buf[base[b] + (od + r * Ns) * es] = v[b][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <typename R, int ELEMS>
+__device__ void fft_lines(C<R>* buf, int N, int nl, int lpg, int gs, int ls, int es, bool lines_fastest,
+                          const C<R>* tw, int dir, const int* rad, int nrad)
+{
+    int Ns = 1;
+    for (int s = 0; s < nrad; s++) {
+        int r = rad[s];
+        switch (r) {
+            case 2: fft_stage<R, 2, ELEMS>(buf, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
+            case 3: fft_stage<R, 3, ELEMS>(buf, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
+            case 4: fft_stage<R, 4, ELEMS>(buf, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
+            case 5: fft_stage<R, 5, ELEMS>(buf, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
+            case 7: fft_stage<R, 7, ELEMS>(buf, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
+            default: fft_stage<R, 8, ELEMS>(buf, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
+        }
+        Ns *= r;
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ void load_tw(C<R>* dst, const double* src, int n)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = {(R)src[2 * i], (R)src[2 * i + 1]};
+}
+
+// ------------------------------------------------------------ x: real -> half
+template <typename R>
+__global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_x_r2c(se_fft_args a)
+{
+    extern __shared__ double smem_d[];
+    const int Nh = a.N[0] / 2;
+    C<R>* tw = (C<R>*)smem_d;
+    C<R>* twp = tw + Nh;
+    C<R>* buf = twp + Nh + 1;
+    load_tw(tw, a.tw + 2 * a.tw_xh, Nh);
+    load_tw(twp, a.tw + 2 * a.tw_xp, Nh + 1);
+    const int64_t rows = (int64_t)a.ncomp * a.Mg[2] * a.Mg[1];
+    const int64_t row0 = (int64_t)blockIdx.x * a.lines;
+    const int nl = (int)min((int64_t)a.lines, rows - row0);
+    const R* grid = (const R*)a.grid;
+    C<R>* spec = (C<R>*)a.spec;
+    const int M0 = a.Mg[0];
+    for (int i = threadIdx.x; i < nl * Nh; i += blockDim.x) {
+        int l = i / Nh, k = i - l * Nh;
+        const R* row = grid + (row0 + l) * M0;
+        R re = (2 * k < M0) ? row[2 * k] : (R)0;
+        R im = (2 * k + 1 < M0) ? row[2 * k + 1] : (R)0;
+        buf[l * Nh + k] = {re, im};
+    }
+    __syncthreads();
+    fft_lines<R, SE_FFT_LDS_ELEMS>(buf, Nh, nl, nl, 0, Nh, 1, false, tw, 1, a.rad_xh, a.nrad_xh);
+    for (int i = threadIdx.x; i < nl * (Nh + 1); i += blockDim.x) {
+        int l = i / (Nh + 1), k = i - l * (Nh + 1);
+        C<R> zk = buf[l * Nh + (k % Nh)];
+        C<R> zn = buf[l * Nh + ((Nh - k) % Nh)];
+        zn.y = -zn.y;  // conj(Z_{N-k})
+        C<R> A = {(zk.x + zn.x) * (R)0.5, (zk.y + zn.y) * (R)0.5};
+        C<R> Bm = {(zk.x - zn.x) * (R)0.5, (zk.y - zn.y) * (R)0.5};
+        // X_k = A_k - i e^{-2 pi i k/N0} (Z_k - conj Z_{N-k})/2
+        C<R> t = cmul(Bm, twp[k]);
+        C<R> X = {A.x + t.y, A.y - t.x};
+        int64_t row = row0 + l;
+        int64_t cz = row / a.Mg[1];
+        int y = (int)(row - cz * a.Mg[1]);
+        spec[(cz * a.N[1] + y) * a.Hx + k] = X;
+    }
+}
+
+// ------------------------------------------------------------ x: half -> real
+template <typename R>
+__global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_x_c2r(se_fft_args a)
+{
+    extern __shared__ double smem_d[];
+    const int Nh = a.N[0] / 2;
+    C<R>* tw = (C<R>*)smem_d;
+    C<R>* twp = tw + Nh;
+    C<R>* buf = twp + Nh + 1;
+    load_tw(tw, a.tw + 2 * a.tw_xh, Nh);
+    load_tw(twp, a.tw + 2 * a.tw_xp, Nh + 1);
+    __syncthreads();
+    const int64_t rows = (int64_t)a.ncomp * a.Mg[2] * a.Mg[1];
+    const int64_t row0 = (int64_t)blockIdx.x * a.lines;
+    const int nl = (int)min((int64_t)a.lines, rows - row0);
+    R* grid = (R*)a.grid;
+    const C<R>* spec = (const C<R>*)a.spec;
+    for (int i = threadIdx.x; i < nl * Nh; i += blockDim.x) {
+        int l = i / Nh, k = i - l * Nh;
+        int64_t row = row0 + l;
+        int64_t cz = row / a.Mg[1];
+        int y = (int)(row - cz * a.Mg[1]);
+        const C<R>* X = spec + (cz * a.N[1] + y) * a.Hx;
+        C<R> xk = X[k];
+        C<R> xn = X[Nh - k];
+        xn.y = -xn.y;  // conj(X_{N-k})
+        C<R> Ap = {xk.x + xn.x, xk.y + xn.y};
+        C<R> d = {xk.x - xn.x, xk.y - xn.y};
+        C<R> w = twp[k];
+        w.y = -w.y;  // e^{+2 pi i k/N0}
+        C<R> Bp = cmul(d, w);
+        buf[l * Nh + k] = {Ap.x - Bp.y, Ap.y + Bp.x};  // A' + i B'
+    }
+    __syncthreads();
+    fft_lines<R, SE_FFT_LDS_ELEMS>(buf, Nh, nl, nl, 0, Nh, 1, false, tw, -1, a.rad_xh, a.nrad_xh);
+    const int M0 = a.Mg[0];
+    for (int i = threadIdx.x; i < nl * Nh; i += blockDim.x) {
+        int l = i / Nh, k = i - l * Nh;
+        R* row = grid + (row0 + l) * M0;
+        C<R> z = buf[l * Nh + k];
+        if (2 * k < M0) row[2 * k] = z.x;
+        if (2 * k + 1 < M0) row[2 * k + 1] = z.y;
+    }
+}
+
+// ------------------------------------------------------------ y: complex
+template <typename R>
+__global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_y(se_fft_args a, int dir)
+{
+    extern __shared__ double smem_d[];
+    const int Ny = a.N[1];
+    C<R>* tw = (C<R>*)smem_d;
+    C<R>* buf = tw + Ny;
+    load_tw(tw, a.tw + 2 * a.tw_y, Ny);
+    const int Cc = a.cols;
+    const int nbx = (a.Hx + Cc - 1) / Cc;
+    int bid = blockIdx.x;
+    int bx = bid % nbx;
+    int64_t cz = bid / nbx;  // c * Mz + z
+    const int kx0 = bx * Cc;
+    C<R>* spec = (C<R>*)a.spec;
+    C<R>* base = spec + cz * (int64_t)Ny * a.Hx;
+    const int n_in = dir > 0 ? a.Mg[1] : Ny;
+    const int n_out = dir > 0 ? Ny : a.Mg[1];
+    for (int i = threadIdx.x; i < Ny * Cc; i += blockDim.x) {
+        int y = i / Cc, col = i - y * Cc;
+        int kx = kx0 + col;
+        C<R> v = {(R)0, (R)0};
+        if (kx < a.Hx && y < n_in) v = base[(int64_t)y * a.Hx + kx];
+        buf[y * Cc + col] = v;
+    }
+    __syncthreads();
+    fft_lines<R, SE_FFT_LDS_ELEMS>(buf, Ny, Cc, Cc, 0, 1, Cc, true, tw, dir, a.rad_y, a.nrad_y);
+    for (int i = threadIdx.x; i < n_out * Cc; i += blockDim.x) {
+        int y = i / Cc, col = i - y * Cc;
+        int kx = kx0 + col;
+        if (kx < a.Hx) base[(int64_t)y * a.Hx + kx] = buf[y * Cc + col];
+    }
+}
+
+// ------------------------------------------------ scaling (triply periodic)
+// Multiplier of eq. (SE-scaling-disc) with the D = 3 kernels of
+// eq. (mod-kernel-3p) (zero at k = 0) and the Fourier kernels
+// eqs. (stokeslet-fourier), (rotlet-fourier), (stresslet-fourier):
+//   S: u = c_H (k^2 F - k (k.F)),                 c_H = 8 pi gH / k^4
+//   Omega: u = -i (4 pi gE / k^2) (F x k)
+//   T: u = i c_H (k^2 (2 F k + k tr F) - 2 k (k^T F k)), F symmetric
+// times 1/what(k)^2 and the trapezoid/FFT normalisation.  Odd kernels are
+// set to zero on Nyquist indices (the real part of a non-Hermitian mode).
+template <typename R, int KER, int NC>
+__device__ __forceinline__ void scale_point(const se_fft_args& a, int ix, int iy, int iz, C<R>* F, C<R>* U)
+{
+    const int kb[3] = {ix, iy < a.N[1] / 2 ? iy : iy - a.N[1], iz < a.N[2] / 2 ? iz : iz - a.N[2]};
+    const double k[3] = {a.kfac[0] * kb[0], a.kfac[1] * kb[1], a.kfac[2] * kb[2]};
+    const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+    bool nyq = (2 * ix == a.N[0]) || (2 * iy == a.N[1]) || (2 * iz == a.N[2]);
+    if (k2 == 0.0 || (KER != SE_STOKESLET && nyq)) {
+        U[0] = U[1] = U[2] = {(R)0, (R)0};
+        return;
+    }
+    const double e = k2 / (4.0 * a.xi * a.xi);
+    const double gE = exp(-e);
+    const double iw = a.invw2[a.iw_off[0] + ix] * a.invw2[a.iw_off[1] + iy] * a.invw2[a.iw_off[2] + iz];
+    const double base = a.scale * iw;
+    if constexpr (KER == SE_STOKESLET) {
+        const R c = (R)(base * 8.0 * M_PI * gE * (1.0 + e) / (k2 * k2));
+        const R kr[3] = {(R)k[0], (R)k[1], (R)k[2]};
+        const R kk = (R)k2;
+        C<R> kf = {kr[0] * F[0].x + kr[1] * F[1].x + kr[2] * F[2].x, kr[0] * F[0].y + kr[1] * F[1].y + kr[2] * F[2].y};
+#pragma unroll
+        for (int j = 0; j < 3; j++) U[j] = {c * (kk * F[j].x - kr[j] * kf.x), c * (kk * F[j].y - kr[j] * kf.y)};
+    } else if constexpr (KER == SE_ROTLET) {
+        const R c = (R)(base * 4.0 * M_PI * gE / k2);
+        const R kr[3] = {(R)k[0], (R)k[1], (R)k[2]};
+        // w = F x k
+        C<R> w[3];
+        w[0] = {F[1].x * kr[2] - F[2].x * kr[1], F[1].y * kr[2] - F[2].y * kr[1]};
+        w[1] = {F[2].x * kr[0] - F[0].x * kr[2], F[2].y * kr[0] - F[0].y * kr[2]};
+        w[2] = {F[0].x * kr[1] - F[1].x * kr[0], F[0].y * kr[1] - F[1].y * kr[0]};
+        // U = -i c w
+#pragma unroll
+        for (int j = 0; j < 3; j++) U[j] = {c * w[j].y, -c * w[j].x};
+    } else {
+        const R c = (R)(base * 8.0 * M_PI * gE * (1.0 + e) / (k2 * k2));
+        const R kr[3] = {(R)k[0], (R)k[1], (R)k[2]};
+        const R kk = (R)k2;
+        // symmetric F: 0 xx, 1 yy, 2 zz, 3 xy, 4 xz, 5 yz
+        C<R> Fk[3];
+        Fk[0] = {F[0].x * kr[0] + F[3].x * kr[1] + F[4].x * kr[2], F[0].y * kr[0] + F[3].y * kr[1] + F[4].y * kr[2]};
+        Fk[1] = {F[3].x * kr[0] + F[1].x * kr[1] + F[5].x * kr[2], F[3].y * kr[0] + F[1].y * kr[1] + F[5].y * kr[2]};
+        Fk[2] = {F[4].x * kr[0] + F[5].x * kr[1] + F[2].x * kr[2], F[4].y * kr[0] + F[5].y * kr[1] + F[2].y * kr[2]};
+        C<R> tr = {F[0].x + F[1].x + F[2].x, F[0].y + F[1].y + F[2].y};
+        C<R> kFk = {kr[0] * Fk[0].x + kr[1] * Fk[1].x + kr[2] * Fk[2].x, kr[0] * Fk[0].y + kr[1] * Fk[1].y + kr[2] * Fk[2].y};
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            C<R> v = {kk * (2 * Fk[j].x + kr[j] * tr.x) - 2 * kr[j] * kFk.x,
+                      kk * (2 * Fk[j].y + kr[j] * tr.y) - 2 * kr[j] * kFk.y};
+            U[j] = {-c * v.y, c * v.x};  // i c v
+        }
+    }
+}
+
+template <typename R, int KER, int NC, int ELEMS>
+__global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_z_scale(se_fft_args a)
+{
+    extern __shared__ double smem_d[];
+    const int Nz = a.N[2];
+    C<R>* tw = (C<R>*)smem_d;
+    C<R>* buf = tw + Nz;
+    load_tw(tw, a.tw + 2 * a.tw_z, Nz);
+    const int Cc = a.cols;
+    const int nbx = (a.Hx + Cc - 1) / Cc;
+    const int bx = blockIdx.x % nbx;
+    const int y = blockIdx.x / nbx;
+    const int kx0 = bx * Cc;
+    const int Mz = a.Mg[2];
+    const int64_t cstride = (int64_t)Mz * a.N[1] * a.Hx;
+    const int64_t zstride = (int64_t)a.N[1] * a.Hx;
+    C<R>* spec = (C<R>*)a.spec;
+    const int cs = Nz * Cc;  // LDS component stride
+    for (int i = threadIdx.x; i < NC * cs; i += blockDim.x) {
+        int c = i / cs, rem = i - c * cs;
+        int z = rem / Cc, col = rem - z * Cc;
+        int kx = kx0 + col;
+        C<R> v = {(R)0, (R)0};
+        if (kx < a.Hx && z < Mz) v = spec[c * cstride + z * zstride + (int64_t)y * a.Hx + kx];
+        buf[i] = v;
+    }
+    __syncthreads();
+    fft_lines<R, ELEMS>(buf, Nz, NC * Cc, Cc, cs, 1, Cc, true, tw, 1, a.rad_z, a.nrad_z);
+    for (int i = threadIdx.x; i < cs; i += blockDim.x) {
+        int z = i / Cc, col = i - z * Cc;
+        int kx = kx0 + col;
+        if (kx >= a.Hx) continue;
+        C<R> F[NC], U[3];
+#pragma unroll
+        for (int c = 0; c < NC; c++) F[c] = buf[c * cs + i];
+        scale_point<R, KER, NC>(a, kx, y, z, F, U);
+#pragma unroll
+        for (int j = 0; j < 3; j++) buf[j * cs + i] = U[j];
+    }
+    __syncthreads();
+    fft_lines<R, ELEMS>(buf, Nz, 3 * Cc, Cc, cs, 1, Cc, true, tw, -1, a.rad_z, a.nrad_z);
+    for (int i = threadIdx.x; i < 3 * cs; i += blockDim.x) {
+        int c = i / cs, rem = i - c * cs;
+        int z = rem / Cc, col = rem - z * Cc;
+        int kx = kx0 + col;
+        if (kx < a.Hx && z < Mz) spec[c * cstride + z * zstride + (int64_t)y * a.Hx + kx] = buf[i];
+    }
+}
+
+// z-pass LDS budget (complex elements) per precision
+template <typename R>
+constexpr int z_elems() { return sizeof(R) == 8 ? 3072 : 6144; }
+
+se_fft_args make_fft_args(const se_plan* p, int ncomp)
+{
+    se_fft_args a;
+    std::memset(&a, 0, sizeof(a));
+    for (int d = 0; d < 3; d++) {
+        a.Mg[d] = p->g.Mg[d];
+        a.N[d] = p->Nfft[d];
+    }
+    a.Hx = p->Hx;
+    a.ncomp = ncomp;
+    a.grid = p->d_grid;
+    a.spec = p->d_spec;
+    a.tw = p->d_tw;
+    a.tw_xh = p->tw_off[0];
+    a.tw_xp = p->tw_off[1];
+    a.tw_y = p->tw_off[2];
+    a.tw_z = p->tw_off[3];
+    std::vector<int> r;
+    se_smooth_factors(p->Nfft[0] / 2, &r);
+    a.nrad_xh = (int)r.size();
+    for (size_t i = 0; i < r.size(); i++) a.rad_xh[i] = r[i];
+    se_smooth_factors(p->Nfft[1], &r);
+    a.nrad_y = (int)r.size();
+    for (size_t i = 0; i < r.size(); i++) a.rad_y[i] = r[i];
+    se_smooth_factors(p->Nfft[2], &r);
+    a.nrad_z = (int)r.size();
+    for (size_t i = 0; i < r.size(); i++) a.rad_z[i] = r[i];
+    a.kernel = p->kernel;
+    a.D = p->D;
+    double hv = 1.0, nv = 1.0;
+    for (int d = 0; d < 3; d++) {
+        a.kfac[d] = 2.0 * M_PI / (p->g.h[d] * p->Nfft[d]);
+        hv *= p->g.h[d];
+        nv *= p->Nfft[d];
+    }
+    a.xi = p->par.xi;
+    a.scale = hv / nv;
+    a.invw2 = p->d_invw2;
+    a.iw_off[0] = 0;
+    a.iw_off[1] = p->Hx;
+    a.iw_off[2] = p->Hx + p->Nfft[1];
+    return a;
+}
+
+template <typename R>
+void launch_fwd(const se_plan* p, hipStream_t s)
+{
+    // x pass
+    se_fft_args a = make_fft_args(p, p->ncomp);
+    const int Nh = p->Nfft[0] / 2;
+    a.lines = std::max(1, SE_FFT_LDS_ELEMS / Nh);
+    int64_t rows = (int64_t)p->ncomp * p->g.Mg[2] * p->g.Mg[1];
+    size_t lds = (size_t)(2 * Nh + 1 + a.lines * Nh) * sizeof(C<R>);
+    hipLaunchKernelGGL(k_fft_x_r2c<R>, dim3((unsigned)((rows + a.lines - 1) / a.lines)), dim3(SE_FFT_THREADS),
+                       lds, s, a);
+    // y pass
+    a.cols = std::max(1, std::min(16, SE_FFT_LDS_ELEMS / p->Nfft[1]));
+    int nbx = (p->Hx + a.cols - 1) / a.cols;
+    lds = (size_t)(p->Nfft[1] + a.cols * p->Nfft[1]) * sizeof(C<R>);
+    hipLaunchKernelGGL(k_fft_y<R>, dim3((unsigned)(nbx * p->ncomp * p->g.Mg[2])), dim3(SE_FFT_THREADS), lds, s, a,
+                       1);
+}
+
+template <typename R, int KER, int NC>
+void launch_z(const se_plan* p, hipStream_t s)
+{
+    se_fft_args a = make_fft_args(p, NC);
+    constexpr int EL = z_elems<R>();
+    a.cols = std::max(1, std::min(8, EL / (NC * p->Nfft[2])));
+    int nbx = (p->Hx + a.cols - 1) / a.cols;
+    size_t lds = (size_t)(p->Nfft[2] + NC * a.cols * p->Nfft[2]) * sizeof(C<R>);
+    auto kern = k_fft_z_scale<R, KER, NC, EL>;
+    if (lds > 65536) (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(kern, dim3((unsigned)(nbx * p->Nfft[1])), dim3(SE_FFT_THREADS), lds, s, a);
+}
+
+template <typename R>
+void launch_inv(const se_plan* p, hipStream_t s)
+{
+    se_fft_args a = make_fft_args(p, 3);
+    a.cols = std::max(1, std::min(16, SE_FFT_LDS_ELEMS / p->Nfft[1]));
+    int nbx = (p->Hx + a.cols - 1) / a.cols;
+    size_t lds = (size_t)(p->Nfft[1] + a.cols * p->Nfft[1]) * sizeof(C<R>);
+    hipLaunchKernelGGL(k_fft_y<R>, dim3((unsigned)(nbx * 3 * p->g.Mg[2])), dim3(SE_FFT_THREADS), lds, s, a, -1);
+    const int Nh = p->Nfft[0] / 2;
+    a.lines = std::max(1, SE_FFT_LDS_ELEMS / Nh);
+    int64_t rows = (int64_t)3 * p->g.Mg[2] * p->g.Mg[1];
+    lds = (size_t)(2 * Nh + 1 + a.lines * Nh) * sizeof(C<R>);
+    hipLaunchKernelGGL(k_fft_x_c2r<R>, dim3((unsigned)((rows + a.lines - 1) / a.lines)), dim3(SE_FFT_THREADS),
+                       lds, s, a);
+}
+
+template <typename R>
+void launch_z_dispatch(const se_plan* p, hipStream_t s)
+{
+    if (p->kernel == SE_STOKESLET) launch_z<R, SE_STOKESLET, 3>(p, s);
+    else if (p->kernel == SE_ROTLET) launch_z<R, SE_ROTLET, 3>(p, s);
+    else launch_z<R, SE_STRESSLET, 6>(p, s);
+}
+
+}  // namespace
+
+void se_launch_fft_forward(const se_plan* p, hipStream_t s)
+{
+    if (p->fp32) {
+        launch_fwd<float>(p, s);
+        launch_z_dispatch<float>(p, s);
+    } else {
+        launch_fwd<double>(p, s);
+        launch_z_dispatch<double>(p, s);
+    }
+}
+
+void se_launch_fft_inverse(const se_plan* p, hipStream_t s)
+{
+    if (p->fp32) launch_inv<float>(p, s);
+    else launch_inv<double>(p, s);
+}

@@ -1,0 +1,124 @@
+// se_internal.h -- private declarations shared by the library's own sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/se.h"
+
+#define SE_VERSION_MAJOR 0
+#define SE_VERSION_MINOR 1
+#define SE_VERSION_PATCH 0
+
+// Device-side error flags (bit set, read by se_sync_status).
+#define SE_FLAG_OUT_OF_BOX 1
+#define SE_FLAG_NONFINITE 2
+#define SE_FLAG_COINCIDENT 4
+
+// Largest supported window support and polynomial degree.
+#define SE_MAX_P 32
+#define SE_MAX_NU 10
+
+// Line FFT limits (LDS-resident lines).
+#define SE_FFT_MAX_LEN 4096
+#define SE_FFT_THREADS 256
+#define SE_FFT_LDS_ELEMS 2048  // complex elements per workgroup in the line kernels
+
+struct se_grid_geom {
+    int D;
+    int Mg[3];       // grid points per axis (periodic M_i, free M'_i)
+    double x0[3];    // physical coordinate of grid point 0
+    double h[3];
+    double invh[3];
+    double L[3];     // primary cell
+    int periodic[3];
+    int B[3];        // grid cells per bin
+    int nb[3];       // bins per axis
+};
+
+// Per-axis FFT description for the R2C/C2C/C2R passes.
+struct se_fft_axis {
+    int n_in;    // valid input length (rest zero padded)
+    int n_fft;   // transform length
+    int n_out;   // outputs kept after the inverse transform
+    std::vector<int> radices;  // factorisation of n_fft (or n_fft/2 on the R2C axis)
+};
+
+struct se_plan {
+    se_problem prob{};
+    se_params par{};
+    int D = 3;
+    int kernel = 0;
+    int ncomp = 3;   // gridded components (3, or 6 for the symmetrised stresslet source)
+    int nrhs = 1;
+    bool fp32 = false;
+    int device = 0;
+    int64_t ns = 0, nt = 0;
+    bool tas = true;
+    se_grid_geom g{};
+    int64_t nbins = 0;
+    int Nfft[3] = {0, 0, 0};
+    int Hx = 0;              // R2C half-spectrum extent along x
+    int tile[3] = {16, 16, 8};  // spread/gather tile (grid points)
+    int ntile[3] = {0, 0, 0};
+
+    // device buffers
+    int* d_flags = nullptr;
+    double* d_src = nullptr;       // sorted sources, SoA [3][ns]
+    double* d_nrm = nullptr;       // sorted normals, SoA [3][ns] (stresslet)
+    int* d_src_perm = nullptr;     // sorted -> original
+    int* d_src_start = nullptr;    // [nbins+1]
+    double* d_tgt = nullptr;       // sorted targets SoA [3][nt] (null when tas)
+    int* d_tgt_perm = nullptr;
+    int* d_tgt_start = nullptr;
+    int* d_keys_a = nullptr;       // sort scratch
+    int* d_keys_b = nullptr;
+    int* d_vals_a = nullptr;
+    void* d_sort_tmp = nullptr;
+    size_t sort_tmp_bytes = 0;
+    void* d_fs = nullptr;          // sorted strengths in grid precision [ncomp][ns]
+    double* d_fs64 = nullptr;      // sorted strengths FP64 [3][ns] (self term), q.nu [ns]
+    double* d_red = nullptr;       // reductions: [0] sum q.nu, [1..3] sum x (q.nu)
+    void* d_grid = nullptr;        // real grid [ncomp][Mz][My][Mx]
+    void* d_spec = nullptr;        // half spectrum [ncomp][Mz][Ny][Hx] complex
+    double* d_uF = nullptr;        // [3][nt] sorted order
+    double* d_uR = nullptr;        // [3][nt]
+    double* d_pkb = nullptr;       // PKB coefficients [P][nu+1]
+    double* d_invw2 = nullptr;     // 1/what0(k)^2 per axis, concatenated [Nx/2+1 | Ny | Nz]
+    double* d_tw = nullptr;        // twiddles (complex FP64), see se_fft layout
+    int tw_off[4] = {0, 0, 0, 0};  // offsets (complex elements) of x-half, x-post, y, z tables
+    size_t ws_bytes = 0;
+    bool have_geometry = false;
+    std::string msg;
+};
+
+// ---- planner (se_params.cpp)
+se_status se_select_params(const se_problem* p, const se_params* manual, se_params* out,
+                           std::string* msg);
+bool se_smooth_factors(int n, std::vector<int>* radices);
+void se_pkb_coefficients(int P, int nu, double beta, std::vector<double>* coef);
+double se_kb_fourier(double k, double a, double beta);
+
+// ---- kernels (se_*.hip): host-side launch wrappers
+void se_launch_fill_int(int* p, int v, int64_t n, hipStream_t s);
+void se_launch_fill_double(double* p, double v, int64_t n, hipStream_t s);
+void se_launch_fill_bytes_zero(void* p, size_t bytes, hipStream_t s);
+void se_launch_bin_keys(const se_grid_geom& g, const double* xyz, int64_t n, int* keys, int* idx,
+                        int* flags, hipStream_t s);
+void se_launch_gather_sorted(const double* xyz, const int* perm, int64_t n, const se_grid_geom& g,
+                             double* out_soa, int sanitize, hipStream_t s);
+void se_launch_cell_starts(const int* sorted_keys, int64_t n, int64_t nbins, int* start,
+                           hipStream_t s);
+se_status se_sort_pairs(se_plan* p, int64_t n, hipStream_t s);
+void se_launch_strengths(const se_plan* p, const double* f, hipStream_t s);
+void se_launch_spread(const se_plan* p, hipStream_t s);
+void se_launch_fft_forward(const se_plan* p, hipStream_t s);
+void se_launch_fft_inverse(const se_plan* p, hipStream_t s);
+void se_launch_gather(const se_plan* p, hipStream_t s);
+void se_launch_real_space(const se_plan* p, hipStream_t s);
+void se_launch_reductions(const se_plan* p, hipStream_t s);
+void se_launch_finalize(const se_plan* p, const double* f, double* u, double* u_real,
+                        double* u_fourier, hipStream_t s);

@@ -1,0 +1,408 @@
+// se_params.cpp -- parameter selection (Bagge & Tornberg, Sec. 4) and the
+// window tables (Sec. 3.3).  Host code.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "se_internal.h"
+
+namespace {
+
+const double kPi = 3.14159265358979323846;
+
+// Expected number of sources within r_c for the uniform system, Table 3
+// (complexity-optimal-pts): rows S/Omega and T, columns D = 0..3.
+const double kNrcUniform[2][4] = {{2500.0, 950.0, 450.0, 400.0}, {6000.0, 1600.0, 800.0, 800.0}};
+
+// Box-padding factor lambda, Table 2 (estimates-lambda).
+double lambda_factor(int kernel, int D)
+{
+    if (D == 0) return kernel == SE_STOKESLET ? 2.2 : (kernel == SE_STRESSLET ? 2.4 : 1.5);
+    return 2.4;
+}
+
+struct Box {
+    double V, Lc;  // volume and cube-equivalent side V^(1/3)
+};
+
+// Fourier-part rms estimate U(L,Q,xi), eqs. (pot-mag-est-stokeslet/-stresslet/-rotlet)
+// with the mean constants C_U of Table 1.
+double pot_rms(int kernel, const Box& b, double Q, double xi)
+{
+    double t = xi * b.Lc;
+    double sq = std::sqrt(Q);
+    if (kernel == SE_STOKESLET) {
+        double fu = (1.0 + 1.323e-2 * t + 2.469e-4 * t * t) * std::exp(-5.205 / (t * t));
+        return 1.8 * sq * fu / b.Lc;
+    }
+    if (kernel == SE_STRESSLET) return 7.2 * sq * std::sqrt(t) / (b.Lc * b.Lc);
+    return 2.4 * sq * std::sqrt(t) * std::exp(-11.60 / (t * t)) / (b.Lc * b.Lc);
+}
+
+// Real-space truncation estimates, eqs. (rs-trunc-est-stokeslet/-stresslet/-rotlet):
+// E = pref(rc) exp(-xi^2 rc^2).
+double rs_pref(int kernel, const Box& b, double Q, double xi, double rc)
+{
+    if (kernel == SE_STOKESLET) return std::sqrt(4.0 * Q * rc / b.V);
+    if (kernel == SE_STRESSLET) return std::sqrt(112.0 * Q * std::pow(xi, 4) * rc * rc * rc / (9.0 * b.V));
+    return std::sqrt(8.0 * Q / (3.0 * b.V * rc));
+}
+
+// Fourier truncation estimates, eqs. (fs-trunc-est-rotlet/-stokeslet/-stresslet):
+// E = pref(k) exp(-k^2/(4 xi^2)).
+double fs_pref(int kernel, const Box& b, double Q, double xi, double k)
+{
+    if (kernel == SE_STOKESLET) return 4.0 / (kPi * b.Lc) * std::sqrt(Q / 3.0);
+    if (kernel == SE_STRESSLET) return 4.0 * k / (3.0 * kPi * b.Lc) * std::sqrt(7.0 * Q / 2.0);
+    return std::sqrt(8.0 * xi * xi * Q / (3.0 * kPi * b.V * k));
+}
+
+// Solve pref(rc) exp(-xi^2 rc^2) = tau for rc on the decaying branch.
+double solve_rc(int kernel, const Box& b, double Q, double xi, double tau)
+{
+    double rc = 3.0 / xi;
+    for (int it = 0; it < 200; it++) {
+        double arg = rs_pref(kernel, b, Q, xi, rc) / tau;
+        double nrc = arg > 1.0 ? std::sqrt(std::log(arg)) / xi : 0.5 / xi;
+        if (std::fabs(nrc - rc) < 1e-15 * rc) {
+            rc = nrc;
+            break;
+        }
+        rc = nrc;
+    }
+    return rc;
+}
+
+// Solve pref(k) exp(-k^2/(4 xi^2)) = tau for k.
+double solve_kinf(int kernel, const Box& b, double Q, double xi, double tau)
+{
+    double k = 8.0 * xi;
+    for (int it = 0; it < 200; it++) {
+        double arg = fs_pref(kernel, b, Q, xi, k) / tau;
+        double nk = arg > 1.0 ? 2.0 * xi * std::sqrt(std::log(arg)) : 2.0 * xi;
+        if (std::fabs(nk - k) < 1e-15 * k) {
+            k = nk;
+            break;
+        }
+        k = nk;
+    }
+    return k;
+}
+
+}  // namespace
+
+// Factor n into radices from {8, 4, 2, 3, 5, 7} (largest first for the
+// power-of-two part).  Returns false if n has another prime factor.
+bool se_smooth_factors(int n, std::vector<int>* radices)
+{
+    radices->clear();
+    if (n < 1) return false;
+    int m = n;
+    while (m % 8 == 0) {
+        radices->push_back(8);
+        m /= 8;
+    }
+    while (m % 4 == 0) {
+        radices->push_back(4);
+        m /= 4;
+    }
+    while (m % 2 == 0) {
+        radices->push_back(2);
+        m /= 2;
+    }
+    for (int r : {3, 5, 7}) {
+        while (m % r == 0) {
+            radices->push_back(r);
+            m /= r;
+        }
+    }
+    return m == 1;
+}
+
+namespace {
+
+bool is_smooth(int n)
+{
+    std::vector<int> r;
+    return se_smooth_factors(n, &r);
+}
+
+// Smallest n >= target that is a multiple of fM and whose FFT length
+// (n/2 for an R2C axis when half=true) is 7-smooth.
+int round_grid(double target, int fM, bool half)
+{
+    int n = fM * (int)std::ceil(target / fM - 1e-12);
+    if (n < fM) n = fM;
+    while (!(is_smooth(n) && (!half || is_smooth(n / 2)))) n += fM;
+    return n;
+}
+
+long double bessel_i0(long double x)
+{
+    long double term = 1.0L, sum = 1.0L, q = x * x / 4.0L;
+    for (int k = 1; k < 500; k++) {
+        term *= q / ((long double)k * k);
+        sum += term;
+        if (term < sum * 1e-21L) break;
+    }
+    return sum;
+}
+
+}  // namespace
+
+// Kaiser-Bessel window w0(r) = I0(beta sqrt(1-(r/a)^2))/I0(beta) on |r| <= a,
+// eq. (KB-window), and its Fourier transform evaluated in FP64.
+double se_kb_fourier(double k, double a, double beta)
+{
+    long double i0b = bessel_i0((long double)beta);
+    long double s = (long double)beta * beta - (long double)k * k * a * a;
+    long double val;
+    if (s > 0) {
+        long double r = std::sqrt(s);
+        val = 2.0L * a * std::sinh(r) / (i0b * r);
+    } else if (s < 0) {
+        long double r = std::sqrt(-s);
+        val = 2.0L * a * std::sin(r) / (i0b * r);
+    } else {
+        val = 2.0L * a / i0b;
+    }
+    return (double)val;
+}
+
+// PKB window (Sec. 3.3): on each of the P subintervals [l h, (l+1) h],
+// l = -P/2 .. P/2-1, interpolate the KB window at nu+1 Chebyshev points of
+// the first kind.  coef[q*(nu+1) + c] multiplies sigma^c, with
+// sigma = 2 s - 1 and s in [0,1] the local coordinate within subinterval
+// q = l + P/2 (monomial basis, evaluated by Horner).
+void se_pkb_coefficients(int P, int nu, double beta, std::vector<double>* coef)
+{
+    int n = nu + 1;
+    coef->assign((size_t)P * n, 0.0);
+    long double i0b = bessel_i0((long double)beta);
+    std::vector<long double> A(n * n), rhs(n), sig(n);
+    for (int i = 0; i < n; i++) sig[i] = -std::cos((2.0L * i + 1.0L) * (long double)kPi / (2.0L * n));
+    for (int q = 0; q < P; q++) {
+        int l = q - P / 2;
+        for (int i = 0; i < n; i++) {
+            long double s = (sig[i] + 1.0L) / 2.0L;
+            long double u = 2.0L * ((long double)l + s) / (long double)P;  // r / a
+            long double arg = 1.0L - u * u;
+            long double w = arg > 0 ? bessel_i0((long double)beta * std::sqrt(arg)) / i0b : 1.0L / i0b;
+            rhs[i] = w;
+            long double pw = 1.0L;
+            for (int c = 0; c < n; c++) {
+                A[i * n + c] = pw;
+                pw *= sig[i];
+            }
+        }
+        // Gaussian elimination with partial pivoting (long double)
+        for (int c = 0; c < n; c++) {
+            int piv = c;
+            for (int r = c + 1; r < n; r++)
+                if (std::fabs(A[r * n + c]) > std::fabs(A[piv * n + c])) piv = r;
+            if (piv != c) {
+                for (int k = 0; k < n; k++) std::swap(A[c * n + k], A[piv * n + k]);
+                std::swap(rhs[c], rhs[piv]);
+            }
+            for (int r = c + 1; r < n; r++) {
+                long double fct = A[r * n + c] / A[c * n + c];
+                for (int k = c; k < n; k++) A[r * n + k] -= fct * A[c * n + k];
+                rhs[r] -= fct * rhs[c];
+            }
+        }
+        for (int c = n - 1; c >= 0; c--) {
+            long double acc = rhs[c];
+            for (int k = c + 1; k < n; k++) acc -= A[c * n + k] * rhs[k];
+            rhs[c] = acc / A[c * n + c];
+        }
+        for (int c = 0; c < n; c++) (*coef)[(size_t)q * n + c] = (double)rhs[c];
+    }
+}
+
+// Parameter selection, Sec. 4.6 (steps 1-7), with xi taken from n_rc
+// (Sec. 5.2) when not given, a relative tolerance mapped through U
+// (Sec. 4.2), the pollution rule eq. (error-pollution-fix), grid rounding
+// eq. (grid-adjustment) to 7-smooth multiples of f_M, eq. (extended-grid-size),
+// eq. (truncation-radius), eq. (upsampling-factor-s0),
+// eqs. (upsampling-factor-sstar), (estimate-kbarstar).
+se_status se_select_params(const se_problem* p, const se_params* manual, se_params* out,
+                           std::string* msg)
+{
+    const int D = p->periodicity, kernel = p->kernel;
+    Box b;
+    b.V = p->box[0] * p->box[1] * p->box[2];
+    b.Lc = std::cbrt(b.V);
+    const double N = (double)p->n_src;
+    const double Q = p->source_q > 0 ? p->source_q : 3.0 * N;
+    const double safety = p->safety > 0 ? p->safety : 1.0;
+    const int fM = 4;
+    se_params par;
+    std::memset(&par, 0, sizeof(par));
+    par.struct_size = sizeof(se_params);
+    par.f_M = fM;
+
+    if (p->selector == SE_SELECT_MANUAL) {
+        if (!manual) {
+            *msg = "selector MANUAL needs an se_params argument";
+            return SE_ERR_ARG;
+        }
+        par = *manual;
+        par.struct_size = sizeof(se_params);
+        if (par.f_M <= 0) par.f_M = fM;
+        if (par.xi <= 0 || par.rc <= 0 || par.P < 2 || (par.P & 1) || par.P > SE_MAX_P) {
+            *msg = "manual parameters: need xi > 0, rc > 0 and even 2 <= P <= 32";
+            return SE_ERR_ARG;
+        }
+        if (par.beta <= 0) par.beta = 2.5 * par.P;
+        if (par.nu_deg <= 0) par.nu_deg = std::min(par.P / 2 + 2, 10);
+        if (par.nu_deg > SE_MAX_NU) par.nu_deg = SE_MAX_NU;
+        for (int i = 0; i < 3; i++) {
+            if (par.M[i] < 2 || (par.M[i] & 1)) {
+                *msg = "manual parameters: grid sizes must be even and >= 2";
+                return SE_ERR_ARG;
+            }
+            if (i < D) {
+                par.h[i] = p->box[i] / par.M[i];
+                par.L_ext[i] = p->box[i];
+                par.dL[i] = 0;
+                par.n_fft[i] = par.M[i];
+            }
+        }
+        if (D < 3) {
+            *msg = "manual parameters are only supported for D = 3 in this build";
+            return SE_ERR_UNSUPPORTED;
+        }
+        par.U = pot_rms(kernel, b, Q, par.xi);
+        par.tau_abs = p->tol_kind == SE_TOL_ABS ? p->tol / safety : p->tol * par.U / safety;
+        *out = par;
+        return SE_OK;
+    }
+
+    // ---- xi and tau_abs
+    double xi = p->xi;
+    auto tau_of = [&](double x) {
+        return p->tol_kind == SE_TOL_ABS ? p->tol / safety : p->tol * pot_rms(kernel, b, Q, x) / safety;
+    };
+    if (xi <= 0) {
+        double nrc = p->n_rc > 0 ? p->n_rc : kNrcUniform[kernel == SE_STRESSLET ? 1 : 0][D];
+        double rc = std::cbrt(3.0 * nrc * b.V / (4.0 * kPi * N));
+        xi = 10.0 / b.Lc;
+        for (int it = 0; it < 200; it++) {
+            double arg = rs_pref(kernel, b, Q, xi, rc) / tau_of(xi);
+            double nxi = arg > 1.0 ? std::sqrt(std::log(arg)) / rc : 1.0 / rc;
+            if (std::fabs(nxi - xi) < 1e-14 * xi) {
+                xi = nxi;
+                break;
+            }
+            xi = nxi;
+        }
+    }
+    const double tau = tau_of(xi);
+    const double U = pot_rms(kernel, b, Q, xi);
+    par.xi = xi;
+    par.tau_abs = tau;
+    par.U = U;
+
+    // step 1: real-space cut-off
+    par.rc = solve_rc(kernel, b, Q, xi, tau);
+    // step 2: grid spacing from the Fourier truncation estimate
+    double kinf = solve_kinf(kernel, b, Q, xi, tau);
+    double h_est = kPi / kinf;
+    // step 3: window support from 10 U exp(-2.5 P) = tau
+    double P_est = std::log(10.0 * U / tau) / 2.5;
+    if (P_est < 0) P_est = 0;
+    // step 4: pollution rule and grid rounding
+    double h_t = (D == 0) ? h_est / 1.1 : h_est / 1.05;
+    double P_t = (D == 0) ? P_est + 2.0 : P_est + 4.0;
+    // step 5: even window support, KB shape and PKB degree
+    int P = 2 * (int)std::ceil(P_t / 2.0 - 1e-12);
+    if (P < 4) P = 4;
+    if (P > SE_MAX_P) {
+        *msg = "tolerance needs a window support above 32 grid points";
+        return SE_ERR_TOL_UNREACHABLE;
+    }
+    par.P = P;
+    par.beta = 2.5 * P;
+    par.nu_deg = std::min(P / 2 + 2, 10);
+
+    // periodic axes
+    double h_common = h_t;
+    for (int i = 0; i < D; i++) {
+        int M = round_grid(p->box[i] / h_t, fM, i == 0);
+        par.M[i] = M;
+        par.h[i] = p->box[i] / M;
+        par.L_ext[i] = p->box[i];
+        par.dL[i] = 0.0;
+        par.n_fft[i] = M;
+        par.n0_fft[i] = M;
+        par.nstar_fft[i] = M;
+    }
+    if (D > 0) {
+        h_common = par.h[0];
+        for (int i = 1; i < D; i++) h_common = std::min(h_common, par.h[i]);
+    } else {
+        // D = 0: h_actual = L/M_actual for the smallest side (eq. grid-adjustment)
+        double Lmin = std::min(p->box[0], std::min(p->box[1], p->box[2]));
+        int M = fM * (int)std::ceil(Lmin / h_t / fM - 1e-12);
+        h_common = Lmin / M;
+    }
+
+    // step 6: extended grid in the free directions
+    if (D < 3) {
+        double lam = lambda_factor(kernel, D);
+        double theta = (kernel == SE_ROTLET) ? 0.0 : 8.0;
+        for (int i = D; i < 3; i++) {
+            double target = p->box[i] / h_common + P + (lam - 1.0) * std::max((double)P, theta);
+            // FFT lengths along free axes are s*M' (D=1,2) or 2M' (D=0); keep M' smooth
+            int Mp = round_grid(target, fM, i == 0 && D == 0);
+            par.M[i] = Mp;
+            par.h[i] = h_common;
+            par.L_ext[i] = h_common * Mp;
+            par.dL[i] = par.L_ext[i] - p->box[i];
+        }
+        if (D == 2)
+            par.R = par.L_ext[2];
+        else if (D == 1)
+            par.R = std::sqrt(par.L_ext[1] * par.L_ext[1] + par.L_ext[2] * par.L_ext[2]);
+        else
+            par.R = std::sqrt(par.L_ext[0] * par.L_ext[0] + par.L_ext[1] * par.L_ext[1] +
+                              par.L_ext[2] * par.L_ext[2]);
+        double Lmin = 1e300;
+        for (int i = D; i < 3; i++) Lmin = std::min(Lmin, par.L_ext[i]);
+        // step 7: upsampling
+        double s0 = 1.0 + par.R / Lmin;
+        s0 = std::ceil(10.0 * s0 - 1e-9) / 10.0;
+        par.s0 = s0;
+        double lnterm = std::log(U / (2.0 * tau));
+        double sstar = 1.0;
+        int kstar = 0;
+        for (int i = D; i < 3; i++) {
+            double Meq = p->box[i] / par.h[i];
+            sstar = std::max(sstar, (Meq / par.M[i]) * (1.0 + lnterm / (2.0 * kPi)));
+            int ks = (int)std::ceil(Meq / (par.M[i] - Meq) * lnterm / (2.0 * kPi) - 1.0 - 1e-12);
+            kstar = std::max(kstar, ks);
+        }
+        par.s_star = sstar;
+        par.kstar = D > 0 ? std::max(kstar, 0) : 0;
+        for (int i = D; i < 3; i++) {
+            if (D == 0) {
+                par.n_fft[i] = 2 * par.M[i];
+                par.n0_fft[i] = round_grid(s0 * par.M[i], fM, i == 0);
+                par.nstar_fft[i] = par.n_fft[i];
+            } else {
+                par.n_fft[i] = par.M[i];
+                par.n0_fft[i] = round_grid(s0 * par.M[i], fM, false);
+                par.nstar_fft[i] = round_grid(sstar * par.M[i], fM, false);
+            }
+        }
+    }
+
+    // estimates at the chosen parameters
+    par.est_real = rs_pref(kernel, b, Q, xi, par.rc) * std::exp(-xi * xi * par.rc * par.rc);
+    double kmin = 1e300;
+    for (int i = 0; i < 3; i++) kmin = std::min(kmin, kPi / par.h[i]);
+    par.est_fourier = fs_pref(kernel, b, Q, xi, kmin) * std::exp(-kmin * kmin / (4.0 * xi * xi));
+    par.est_window = 10.0 * U * std::exp(-2.5 * P);
+    *out = par;
+    return SE_OK;
+}
