@@ -1,0 +1,179 @@
+"""Benchmark: N = 1e6 triply periodic stokeslet at 1e-8 rms-relative error on one MI355X.
+
+One step = one pass of the whole hot path over the batch: se_set_geometry (cell
+list) + se_execute (gridding, FFT, scaling, IFFT, gathering, real-space sum,
+self term).  Inputs are resident in HBM before the timed region starts.
+Prints ONE JSON line (see the design doc for the roofline and baseline recipes).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads as W  # noqa: E402
+
+# MI355X published peaks
+PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6
+PEAK_FP32_TFLOPS = 157.3
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--safety", type=float, default=2.0)
+    ap.add_argument("--seed", type=int, default=5000)
+    ap.add_argument("--cpu-sample", type=int, default=24, help="targets in the oracle sample (0: skip)")
+    return ap.parse_args()
+
+
+def roofline_for(phase, ms_per_launch, par, n_src, n_tgt, ncomp, fp64):
+    """Algorithmic work of one launch of the phase divided by its duration."""
+    P = par["P"]
+    M = par["M"]
+    sec = ms_per_launch * 1e-3
+    if phase == "spread":
+        flops = 2.0 * P ** 3 * ncomp * n_src  # P^3 ncomp FMAs per source
+        return {"bound": "alu", "achieved": flops / sec / 1e12,
+                "peak": PEAK_FP64_TFLOPS if fp64 else PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "work_per_launch": flops}
+    if phase == "gather":
+        flops = 2.0 * P ** 3 * 3 * n_tgt
+        return {"bound": "alu", "achieved": flops / sec / 1e12,
+                "peak": PEAK_FP64_TFLOPS if fp64 else PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "work_per_launch": flops}
+    rs = 8 if fp64 else 4
+    hx = M[0] // 2 + 1
+    spec = hx * M[1] * M[2] * 2 * rs  # one complex half-spectrum component
+    grid = M[0] * M[1] * M[2] * rs
+    if phase == "fft_fwd_xy":
+        byt = ncomp * (grid + spec) + ncomp * 2 * spec  # x: read grid, write spec; y: read+write
+    elif phase == "fft_z_scale":
+        byt = ncomp * spec + 3 * spec
+    elif phase == "fft_inv_yx":
+        byt = 3 * 2 * spec + 3 * (spec + grid)
+    else:
+        return None
+    return {"bound": "hbm", "achieved": byt / sec / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "work_per_launch": byt}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (--gpus %d requested); "
+              "the multi-GPU design is described in DESIGN.md, nothing is launched." % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2210_01255_amd as se
+
+    dev = torch.device("cuda:0")
+    n = args.n
+    s = W.system(args.seed, n, kernel="stokeslet", zero_mean=True)
+    x = torch.tensor(s["x"], device=dev)
+    f = torch.tensor(s["f"], device=dev)
+    Q = float(np.sum(s["f"] ** 2))
+    plan = se.Plan(kernel="stokeslet", periodicity=3, box=(1.0, 1.0, 1.0), tol=args.tol, tol_kind=se.TOL_REL,
+                   n_src=n, source_q=Q, safety=args.safety, precision=se.PREC_FP64)
+    par = plan.params
+    u = torch.empty((n, 3), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        plan.set_geometry(x)
+        plan.execute(f, out=u)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.sync()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = n / (ms_per_step * 1e-3)
+
+    # live per-phase durations (HIP events on the execution stream)
+    plan.set_timing(True)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    phases = plan.phase_times()
+    plan.set_timing(False)
+    per_launch = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in phases.items()}
+    dom = max((k for k in per_launch if k not in ("geometry",)), key=lambda k: per_launch[k])
+    rl = roofline_for(dom, per_launch[dom], par, n, n, 3, True)
+    roof = None
+    if rl is not None:
+        roof = {"kernel": dom, "bound": rl["bound"], "achieved": round(rl["achieved"], 4), "peak": rl["peak"],
+                "unit": rl["unit"], "frac": round(rl["achieved"] / rl["peak"], 5), "traffic": None,
+                "ms_per_launch": round(per_launch[dom], 4)}
+
+    cpu = None
+    err_sample = None
+    if args.cpu_sample > 0:
+        import oracle
+        oracle.build(force=False)
+        idx = np.sort(W.rng(args.seed + 1).choice(n, args.cpu_sample, replace=False))
+        c0 = time.perf_counter()
+        ref = oracle.ewald(3, "stokeslet", [1.0, 1.0, 1.0], s["x"], f=s["f"], targets=s["x"][idx],
+                           self_src=idx)
+        c1 = time.perf_counter()
+        cores = os.cpu_count()
+        try:
+            cores = len(os.sched_getaffinity(0))
+        except Exception:
+            pass
+        omp = os.environ.get("OMP_NUM_THREADS")
+        if omp:
+            cores = min(cores, int(omp))
+        cpu = {"value": round(args.cpu_sample / (c1 - c0), 4), "unit": "targets/s", "cores": cores,
+               "kind": "oracle",
+               "sample": "%d of %d targets (all %d sources), FP64 classical Ewald, xi_o=%.3f, %.1f s"
+                         % (args.cpu_sample, n, n, ref["xi"], c1 - c0)}
+        ug = u.cpu().numpy()[idx]
+        err_sample = oracle.rms_rel_error(ug, ref.total)
+
+    out = {
+        "metric": "targets/sec at 1e-8 rms-rel err, N=1M TP stokeslet",
+        "value": round(value, 1),
+        "unit": "targets/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "triply periodic stokeslet, unit cube, N=1e6 uniform sources = targets, "
+                               "f~N(0,1)^3 zero mean, tol 1e-8 rms-rel (plain analytic parameters, 1 rhs, FP64)",
+                   "form": "plain", "xi": round(par["xi"], 4), "rc": round(par["rc"], 5), "M": par["M"],
+                   "P": par["P"], "safety": args.safety},
+        "phases_ms": {k: round(v, 4) for k, v in per_launch.items()},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "err_rms_rel_sample": err_sample,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

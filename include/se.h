@@ -183,6 +183,18 @@ se_status se_execute_split(se_plan* plan, const double* strengths, double* u_rea
  * device flag is cleared afterwards. */
 se_status se_sync_status(se_plan* plan);
 
+/* Phase timing with HIP events recorded on the execution stream around each
+ * phase.  Phases: 0 geometry (se_set_geometry), 1 strengths staging,
+ * 2 gridding, 3 forward x/y FFT passes, 4 z FFT + scaling + inverse z,
+ * 5 inverse y/x FFT passes, 6 gathering, 7 real-space sum, 8 epilogue.
+ * se_plan_set_timing(plan, 1) clears the accumulators and starts recording;
+ * while it is on, every se_set_geometry / se_execute waits for its own events
+ * before returning (a host synchronisation per call).  se_plan_phase_times
+ * copies up to n accumulated milliseconds and launch counts. */
+#define SE_NUM_PHASES 9
+se_status se_plan_set_timing(se_plan* plan, int32_t on);
+se_status se_plan_phase_times(const se_plan* plan, double* ms, int32_t* counts, int32_t n);
+
 /* Debug/test access to the cell list built by se_set_geometry (device
  * pointers owned by the plan, valid until the next se_set_geometry or
  * se_plan_destroy).  which = 0: sources, 1: targets.  perm[n] = original

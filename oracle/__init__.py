@@ -134,11 +134,12 @@ def choose_xi(n_src, n_tgt, box, margin=6.0):
 
     Real-space work ~ n_tgt n_src (4/3) pi (margin/xi)^3 / V pairs and k-space
     work ~ (n_src + n_tgt) (2/3) pi (2 margin xi / 2 pi)^3 V terms; equal when
-    xi^6 = c n_tgt n_src / ((n_src + n_tgt) V^2) with c = (4/3)(margin^3) /
-    ((2/3)(margin/pi)^3) = 2 pi^3.
+    xi^6 = c n_tgt n_src / ((n_src + n_tgt) V^2) with c = 2 pi^3 w, where
+    w = 16 weighs one real-space pair (erfc, exp, image search) against one
+    k-space term (measured on this code).
     """
     V = float(np.prod(box))
-    c = 2.0 * math.pi ** 3
+    c = 2.0 * math.pi ** 3 * 16.0
     return (c * n_tgt * n_src / ((n_src + n_tgt) * V * V)) ** (1.0 / 6.0)
 
 

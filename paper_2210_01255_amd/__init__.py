@@ -50,7 +50,11 @@ class se_params(ctypes.Structure):
 
 EXPORTS = ["se_version", "se_status_string", "se_params_select", "se_plan_create", "se_plan_destroy",
            "se_plan_get_params", "se_plan_workspace_bytes", "se_plan_last_message", "se_set_geometry",
-           "se_execute", "se_execute_split", "se_sync_status", "se_debug_cell_list"]
+           "se_execute", "se_execute_split", "se_sync_status", "se_plan_set_timing", "se_plan_phase_times",
+           "se_debug_cell_list"]
+
+PHASES = ["geometry", "strengths", "spread", "fft_fwd_xy", "fft_z_scale", "fft_inv_yx", "gather", "real_space",
+          "epilogue"]
 
 
 class SEError(RuntimeError):
@@ -90,6 +94,10 @@ def _load():
     L.se_execute_split.argtypes = [vp, vp, vp, vp, vp]
     L.se_sync_status.restype = i32
     L.se_sync_status.argtypes = [vp]
+    L.se_plan_set_timing.restype = i32
+    L.se_plan_set_timing.argtypes = [vp, i32]
+    L.se_plan_phase_times.restype = i32
+    L.se_plan_phase_times.argtypes = [vp, P(ctypes.c_double), P(i32), i32]
     L.se_debug_cell_list.restype = i32
     L.se_debug_cell_list.argtypes = [vp, i32, P(vp), P(vp), P(i32 * 3), P(i32 * 3)]
     return L
@@ -110,6 +118,8 @@ se_set_geometry = lib.se_set_geometry
 se_execute = lib.se_execute
 se_execute_split = lib.se_execute_split
 se_sync_status = lib.se_sync_status
+se_plan_set_timing = lib.se_plan_set_timing
+se_plan_phase_times = lib.se_plan_phase_times
 se_debug_cell_list = lib.se_debug_cell_list
 
 
@@ -248,6 +258,21 @@ class Plan:
         st = lib.se_sync_status(self.handle)
         if st != SE_OK:
             raise SEError(st, "se_sync_status")
+
+    def set_timing(self, on=True):
+        st = lib.se_plan_set_timing(self.handle, 1 if on else 0)
+        if st != SE_OK:
+            raise SEError(st, "se_plan_set_timing")
+
+    def phase_times(self):
+        """{phase: (total ms, launches)} accumulated since set_timing(True)."""
+        n = len(PHASES)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int32 * n)()
+        st = lib.se_plan_phase_times(self.handle, ms, cnt, n)
+        if st != SE_OK:
+            raise SEError(st, "se_plan_phase_times")
+        return {PHASES[i]: (ms[i], cnt[i]) for i in range(n)}
 
     def cell_list(self, which=0):
         """(perm, cell_start, nbins_xyz, cell_width) as host numpy arrays."""

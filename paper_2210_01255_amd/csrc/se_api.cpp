@@ -279,6 +279,8 @@ void se_plan_destroy(se_plan* plan)
     if (!plan) return;
     hipSetDevice(plan->device);
     hipDeviceSynchronize();
+    for (auto& e : plan->ev)
+        if (e) hipEventDestroy(e);
     free_all(plan);
     delete plan;
 }
@@ -293,6 +295,61 @@ se_status se_plan_get_params(const se_plan* plan, se_params* out)
 size_t se_plan_workspace_bytes(const se_plan* plan) { return plan ? plan->ws_bytes : 0; }
 
 const char* se_plan_last_message(const se_plan* plan) { return plan ? plan->msg.c_str() : ""; }
+
+namespace {
+struct PhaseScope {
+    se_plan* p;
+    int ph;
+    hipStream_t s;
+    PhaseScope(se_plan* p_, int ph_, hipStream_t s_) : p(p_), ph(ph_), s(s_)
+    {
+        if (p->timing) hipEventRecord(p->ev[2 * ph], s);
+    }
+    ~PhaseScope()
+    {
+        if (p->timing) hipEventRecord(p->ev[2 * ph + 1], s);
+    }
+};
+
+void collect_phases(se_plan* p, const int* phases, int n)
+{
+    if (!p->timing) return;
+    hipEventSynchronize(p->ev[2 * phases[n - 1] + 1]);
+    for (int i = 0; i < n; i++) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p->ev[2 * phases[i]], p->ev[2 * phases[i] + 1]) == hipSuccess) {
+            p->phase_ms[phases[i]] += ms;
+            p->phase_n[phases[i]] += 1;
+        }
+    }
+}
+}  // namespace
+
+se_status se_plan_set_timing(se_plan* plan, int32_t on)
+{
+    if (!plan) return SE_ERR_ARG;
+    if (hipSetDevice(plan->device) != hipSuccess) return SE_ERR_HIP;
+    if (on) {
+        for (auto& e : plan->ev)
+            if (!e && hipEventCreate(&e) != hipSuccess) return SE_ERR_HIP;
+        for (int i = 0; i < SE_NUM_PHASES; i++) {
+            plan->phase_ms[i] = 0.0;
+            plan->phase_n[i] = 0;
+        }
+    }
+    plan->timing = on != 0;
+    return SE_OK;
+}
+
+se_status se_plan_phase_times(const se_plan* plan, double* ms, int32_t* counts, int32_t n)
+{
+    if (!plan || n < 0 || (n > 0 && (!ms || !counts))) return SE_ERR_ARG;
+    for (int i = 0; i < n && i < SE_NUM_PHASES; i++) {
+        ms[i] = plan->phase_ms[i];
+        counts[i] = plan->phase_n[i];
+    }
+    return SE_OK;
+}
 
 static se_status bind_points(se_plan* p, const double* xyz, int64_t n, int* perm, int* start, double* sorted,
                              hipStream_t s)
@@ -318,12 +375,21 @@ se_status se_set_geometry(se_plan* plan, const double* src_xyz, const double* nr
     hipStream_t s = (hipStream_t)stream;
     if (hipSetDevice(plan->device) != hipSuccess) return SE_ERR_HIP;
     plan->have_geometry = false;
-    se_status st = bind_points(plan, src_xyz, plan->ns, plan->d_src_perm, plan->d_src_start, plan->d_src, s);
-    if (st != SE_OK) return st;
-    if (plan->kernel == SE_STRESSLET) se_launch_gather_sorted(nrm_xyz, plan->d_src_perm, plan->ns, plan->g, plan->d_nrm, 0, s);
-    if (!plan->tas) {
-        st = bind_points(plan, tgt_xyz, plan->nt, plan->d_tgt_perm, plan->d_tgt_start, plan->d_tgt, s);
+    se_status st;
+    {
+        PhaseScope ps(plan, 0, s);
+        st = bind_points(plan, src_xyz, plan->ns, plan->d_src_perm, plan->d_src_start, plan->d_src, s);
         if (st != SE_OK) return st;
+        if (plan->kernel == SE_STRESSLET)
+            se_launch_gather_sorted(nrm_xyz, plan->d_src_perm, plan->ns, plan->g, plan->d_nrm, 0, s);
+        if (!plan->tas) {
+            st = bind_points(plan, tgt_xyz, plan->nt, plan->d_tgt_perm, plan->d_tgt_start, plan->d_tgt, s);
+            if (st != SE_OK) return st;
+        }
+    }
+    {
+        const int ph[1] = {0};
+        collect_phases(plan, ph, 1);
     }
     st = check_hip(plan, hipGetLastError(), "se_set_geometry");
     if (st == SE_OK) plan->have_geometry = true;
@@ -340,15 +406,42 @@ static se_status run(se_plan* p, const double* strengths, double* u, double* ur,
         double* ur_ = u ? u + (size_t)r * p->nt * 3 : nullptr;
         double* urr = ur ? ur + (size_t)r * p->nt * 3 : nullptr;
         double* urf = uf ? uf + (size_t)r * p->nt * 3 : nullptr;
-        se_launch_strengths(p, f, s);
-        se_launch_reductions(p, s);
-        se_launch_spread(p, s);
-        se_launch_fft_forward(p, s);
-        se_launch_fft_inverse(p, s);
-        se_launch_fill_double(p->d_uF, 0.0, 3 * p->nt, s);
-        se_launch_gather(p, s);
-        se_launch_real_space(p, s);
-        se_launch_finalize(p, f, ur_, urr, urf, s);
+        {
+            PhaseScope ps(p, 1, s);
+            se_launch_strengths(p, f, s);
+            se_launch_reductions(p, s);
+            se_launch_fill_double(p->d_uF, 0.0, 3 * p->nt, s);
+        }
+        {
+            PhaseScope ps(p, 2, s);
+            se_launch_spread(p, s);
+        }
+        {
+            PhaseScope ps(p, 3, s);
+            se_launch_fft_xy_forward(p, s);
+        }
+        {
+            PhaseScope ps(p, 4, s);
+            se_launch_fft_z_scale(p, s);
+        }
+        {
+            PhaseScope ps(p, 5, s);
+            se_launch_fft_inverse(p, s);
+        }
+        {
+            PhaseScope ps(p, 6, s);
+            se_launch_gather(p, s);
+        }
+        {
+            PhaseScope ps(p, 7, s);
+            se_launch_real_space(p, s);
+        }
+        {
+            PhaseScope ps(p, 8, s);
+            se_launch_finalize(p, f, ur_, urr, urf, s);
+        }
+        const int ph[8] = {1, 2, 3, 4, 5, 6, 7, 8};
+        collect_phases(p, ph, 8);
     }
     return check_hip(p, hipGetLastError(), "se_execute");
 }

@@ -559,15 +559,16 @@ void launch_z_dispatch(const se_plan* p, hipStream_t s)
 
 }  // namespace
 
-void se_launch_fft_forward(const se_plan* p, hipStream_t s)
+void se_launch_fft_xy_forward(const se_plan* p, hipStream_t s)
 {
-    if (p->fp32) {
-        launch_fwd<float>(p, s);
-        launch_z_dispatch<float>(p, s);
-    } else {
-        launch_fwd<double>(p, s);
-        launch_z_dispatch<double>(p, s);
-    }
+    if (p->fp32) launch_fwd<float>(p, s);
+    else launch_fwd<double>(p, s);
+}
+
+void se_launch_fft_z_scale(const se_plan* p, hipStream_t s)
+{
+    if (p->fp32) launch_z_dispatch<float>(p, s);
+    else launch_z_dispatch<double>(p, s);
 }
 
 void se_launch_fft_inverse(const se_plan* p, hipStream_t s)

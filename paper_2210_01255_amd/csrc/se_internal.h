@@ -91,6 +91,10 @@ struct se_plan {
     double* d_tw = nullptr;        // twiddles (complex FP64), see se_fft layout
     int tw_off[4] = {0, 0, 0, 0};  // offsets (complex elements) of x-half, x-post, y, z tables
     size_t ws_bytes = 0;
+    bool timing = false;
+    hipEvent_t ev[2 * SE_NUM_PHASES] = {};
+    double phase_ms[SE_NUM_PHASES] = {};
+    int phase_n[SE_NUM_PHASES] = {};
     bool have_geometry = false;
     std::string msg;
 };
@@ -115,7 +119,8 @@ void se_launch_cell_starts(const int* sorted_keys, int64_t n, int64_t nbins, int
 se_status se_sort_pairs(se_plan* p, int64_t n, hipStream_t s);
 void se_launch_strengths(const se_plan* p, const double* f, hipStream_t s);
 void se_launch_spread(const se_plan* p, hipStream_t s);
-void se_launch_fft_forward(const se_plan* p, hipStream_t s);
+void se_launch_fft_xy_forward(const se_plan* p, hipStream_t s);
+void se_launch_fft_z_scale(const se_plan* p, hipStream_t s);
 void se_launch_fft_inverse(const se_plan* p, hipStream_t s);
 void se_launch_gather(const se_plan* p, hipStream_t s);
 void se_launch_real_space(const se_plan* p, hipStream_t s);
