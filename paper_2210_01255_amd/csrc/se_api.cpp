@@ -38,7 +38,8 @@ void free_all(se_plan* p)
 {
     void* ptrs[] = {p->d_flags, p->d_src, p->d_nrm, p->d_src_perm, p->d_src_start, p->d_tgt, p->d_tgt_perm,
                     p->d_tgt_start, p->d_keys_a, p->d_keys_b, p->d_vals_a, p->d_sort_tmp, p->d_fs, p->d_fs64,
-                    p->d_red, p->d_grid, p->d_spec, p->d_uF, p->d_uR, p->d_pkb, p->d_invw2, p->d_tw};
+                    p->d_red, p->d_grid, p->d_spec, p->d_uF, p->d_uR, p->d_pkb, p->d_invw2, p->d_tw,
+                    p->d_pos4, p->d_tpos4, p->d_str4, p->d_nrm4, p->d_rtab};
     for (void* q : ptrs)
         if (q) hipFree(q);
 }
@@ -212,6 +213,11 @@ se_status se_plan_create(const se_problem* prob, const se_params* manual, se_pla
     p->d_grid = A.get<char>((size_t)p->ncomp * gv * rs);
     const size_t sv = (size_t)p->Hx * p->Nfft[1] * g.Mg[2];
     p->d_spec = A.get<char>((size_t)p->ncomp * sv * 2 * rs);
+    p->d_pos4 = A.get<double>(4 * p->ns);
+    if (!p->tas) p->d_tpos4 = A.get<double>(4 * p->nt);
+    p->d_str4 = A.get<double>(4 * p->ns);
+    if (p->kernel == SE_STRESSLET) p->d_nrm4 = A.get<double>(4 * p->ns);
+    p->d_rtab = A.get<double>((size_t)2 * SE_RTAB_N * (SE_RTAB_DEG + 1));
     p->d_uF = A.get<double>(3 * p->nt);
     p->d_uR = A.get<double>(3 * p->nt);
     p->d_pkb = A.get<double>((size_t)par.P * (par.nu_deg + 1));
@@ -241,6 +247,8 @@ se_status se_plan_create(const se_problem* prob, const se_params* manual, se_pla
             iw.push_back(1.0 / (w * w));
         }
     }
+    std::vector<double> rtab;
+    se_radial_table(&rtab);
     std::vector<double> tw;
     tw.reserve(2 * ntw);
     auto push_table = [&](int N, int count) {
@@ -262,6 +270,7 @@ se_status se_plan_create(const se_problem* prob, const se_params* manual, se_pla
     hipError_t e = hipMemcpy(p->d_pkb, pkb.data(), pkb.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p->d_invw2, iw.data(), iw.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p->d_tw, tw.data(), tw.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->d_rtab, rtab.data(), rtab.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(p->d_flags, 0, sizeof(int));
     if (e == hipSuccess) e = hipMemset(p->d_red, 0, 4 * sizeof(double));
     if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -352,7 +361,7 @@ se_status se_plan_phase_times(const se_plan* plan, double* ms, int32_t* counts, 
 }
 
 static se_status bind_points(se_plan* p, const double* xyz, int64_t n, int* perm, int* start, double* sorted,
-                             hipStream_t s)
+                             double* sorted4, hipStream_t s)
 {
     se_launch_bin_keys(p->g, xyz, n, p->d_keys_a, p->d_vals_a, p->d_flags, s);
     se_status st = se_sort_pairs_raw(p->d_sort_tmp, p->sort_tmp_bytes, p->d_keys_a, p->d_keys_b, p->d_vals_a, perm,
@@ -362,7 +371,7 @@ static se_status bind_points(se_plan* p, const double* xyz, int64_t n, int* perm
         return st;
     }
     se_launch_cell_starts(p->d_keys_b, n, p->nbins, start, s);
-    se_launch_gather_sorted(xyz, perm, n, p->g, sorted, 1, s);
+    se_launch_gather_sorted(xyz, perm, n, p->g, sorted, sorted4, 1, s);
     return check_hip(p, hipGetLastError(), "bind_points");
 }
 
@@ -378,12 +387,13 @@ se_status se_set_geometry(se_plan* plan, const double* src_xyz, const double* nr
     se_status st;
     {
         PhaseScope ps(plan, 0, s);
-        st = bind_points(plan, src_xyz, plan->ns, plan->d_src_perm, plan->d_src_start, plan->d_src, s);
+        st = bind_points(plan, src_xyz, plan->ns, plan->d_src_perm, plan->d_src_start, plan->d_src, plan->d_pos4, s);
         if (st != SE_OK) return st;
         if (plan->kernel == SE_STRESSLET)
-            se_launch_gather_sorted(nrm_xyz, plan->d_src_perm, plan->ns, plan->g, plan->d_nrm, 0, s);
+            se_launch_gather_sorted(nrm_xyz, plan->d_src_perm, plan->ns, plan->g, plan->d_nrm, plan->d_nrm4, 0, s);
         if (!plan->tas) {
-            st = bind_points(plan, tgt_xyz, plan->nt, plan->d_tgt_perm, plan->d_tgt_start, plan->d_tgt, s);
+            st = bind_points(plan, tgt_xyz, plan->nt, plan->d_tgt_perm, plan->d_tgt_start, plan->d_tgt, plan->d_tpos4,
+                             s);
             if (st != SE_OK) return st;
         }
     }

@@ -51,6 +51,17 @@ __device__ __forceinline__ float se_readlane(float v, int lane)
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  Remap the hardware block id so that every XCD works on one contiguous
+// range of logical blocks (spatial neighbours share an L2).  Bijective on
+// [0, nblocks).
+__device__ __forceinline__ int se_xcd_block(int b, int nblocks)
+{
+    const int q = nblocks / 8, r = nblocks % 8;
+    const int xcd = b % 8, idx = b / 8;
+    return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
+}
+
 template <typename R>
 struct se_cplx {
     R x, y;

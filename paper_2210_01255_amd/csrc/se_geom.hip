@@ -46,7 +46,8 @@ __global__ void k_bin_keys(se_grid_geom g, const double* __restrict__ xyz, int64
 
 // out[d*n + s] = xyz[perm[s]][d]; invalid points are replaced by the origin.
 __global__ void k_gather_sorted(const double* __restrict__ xyz, const int* __restrict__ perm,
-                                int64_t n, se_grid_geom g, double* __restrict__ out, int sanitize)
+                                int64_t n, se_grid_geom g, double* __restrict__ out, double* __restrict__ out4,
+                                int sanitize)
 {
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
@@ -59,6 +60,14 @@ __global__ void k_gather_sorted(const double* __restrict__ xyz, const int* __res
         if (!sanitize && !isfinite(x[d])) x[d] = 0.0;
     }
     for (int d = 0; d < 3; d++) out[d * n + s] = bad ? 0.0 : x[d];
+    if (out4) {
+        double4 v;
+        v.x = bad ? 0.0 : x[0];
+        v.y = bad ? 0.0 : x[1];
+        v.z = bad ? 0.0 : x[2];
+        v.w = 0.0;
+        reinterpret_cast<double4*>(out4)[s] = v;
+    }
 }
 
 // start[b] = first sorted position whose key >= b (binary search), b in [0, nbins].
@@ -104,11 +113,11 @@ void se_launch_bin_keys(const se_grid_geom& g, const double* xyz, int64_t n, int
 }
 
 void se_launch_gather_sorted(const double* xyz, const int* perm, int64_t n, const se_grid_geom& g,
-                             double* out_soa, int sanitize, hipStream_t s)
+                             double* out_soa, double* out_aos4, int sanitize, hipStream_t s)
 {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_gather_sorted, dim3(grid1d(n, 256)), dim3(256), 0, s, xyz, perm, n, g,
-                       out_soa, sanitize);
+                       out_soa, out_aos4, sanitize);
 }
 
 void se_launch_cell_starts(const int* sorted_keys, int64_t n, int64_t nbins, int* start, hipStream_t s)

@@ -22,6 +22,11 @@
 #define SE_MAX_P 32
 #define SE_MAX_NU 10
 
+// Real-space radial-function table (see se_radial_table)
+#define SE_RTAB_N 64
+#define SE_RTAB_DEG 10
+#define SE_RTAB_X 8.0
+
 // Line FFT limits (LDS-resident lines).
 #define SE_FFT_MAX_LEN 4096
 #define SE_FFT_THREADS 256
@@ -84,6 +89,11 @@ struct se_plan {
     double* d_red = nullptr;       // reductions: [0] sum q.nu, [1..3] sum x (q.nu)
     void* d_grid = nullptr;        // real grid [ncomp][Mz][My][Mx]
     void* d_spec = nullptr;        // half spectrum [ncomp][Mz][Ny][Hx] complex
+    double* d_pos4 = nullptr;      // sorted sources AoS [ns][4] (x, y, z, 0)
+    double* d_tpos4 = nullptr;     // sorted targets AoS [nt][4] (null when tas)
+    double* d_str4 = nullptr;      // sorted strengths AoS [ns][4] (f or q, 0)
+    double* d_nrm4 = nullptr;      // sorted normals AoS [ns][4] (stresslet)
+    double* d_rtab = nullptr;      // radial-function table
     double* d_uF = nullptr;        // [3][nt] sorted order
     double* d_uR = nullptr;        // [3][nt]
     double* d_pkb = nullptr;       // PKB coefficients [P][nu+1]
@@ -104,6 +114,7 @@ se_status se_select_params(const se_problem* p, const se_params* manual, se_para
                            std::string* msg);
 bool se_smooth_factors(int n, std::vector<int>* radices);
 void se_pkb_coefficients(int P, int nu, double beta, std::vector<double>* coef);
+void se_radial_table(std::vector<double>* tab);
 double se_kb_fourier(double k, double a, double beta);
 
 // ---- kernels (se_*.hip): host-side launch wrappers
@@ -113,7 +124,7 @@ void se_launch_fill_bytes_zero(void* p, size_t bytes, hipStream_t s);
 void se_launch_bin_keys(const se_grid_geom& g, const double* xyz, int64_t n, int* keys, int* idx,
                         int* flags, hipStream_t s);
 void se_launch_gather_sorted(const double* xyz, const int* perm, int64_t n, const se_grid_geom& g,
-                             double* out_soa, int sanitize, hipStream_t s);
+                             double* out_soa, double* out_aos4, int sanitize, hipStream_t s);
 void se_launch_cell_starts(const int* sorted_keys, int64_t n, int64_t nbins, int* start,
                            hipStream_t s);
 se_status se_sort_pairs(se_plan* p, int64_t n, hipStream_t s);

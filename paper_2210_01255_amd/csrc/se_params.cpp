@@ -219,6 +219,56 @@ void se_pkb_coefficients(int P, int nu, double beta, std::vector<double>* coef)
     }
 }
 
+// Radial functions of the real-space kernels in x = xi r:
+//   G(x) = erfc(x) + (2x/sqrt(pi)) e^{-x^2},   E(x) = e^{-x^2},
+// (eqs. stokeslet-real, rotlet-real, stresslet-real are combinations of G/r
+// and E), as piecewise polynomials on SE_RTAB_N intervals of width
+// SE_RTAB_X/SE_RTAB_N, each interpolating at SE_RTAB_DEG+1 Chebyshev points
+// of the first kind; monomial basis in sigma = 2 s - 1 (s local in [0,1]).
+// Layout tab[f][interval][SE_RTAB_DEG+1], f = 0: G, 1: E.
+void se_radial_table(std::vector<double>* tab)
+{
+    const int n = SE_RTAB_DEG + 1;
+    tab->assign((size_t)2 * SE_RTAB_N * n, 0.0);
+    const long double w = (long double)SE_RTAB_X / SE_RTAB_N;
+    const long double sqpi = std::sqrt((long double)kPi);
+    std::vector<long double> A(n * n), rhs(n), sig(n);
+    for (int i = 0; i < n; i++) sig[i] = -std::cos((2.0L * i + 1.0L) * (long double)kPi / (2.0L * n));
+    for (int f = 0; f < 2; f++)
+        for (int iv = 0; iv < SE_RTAB_N; iv++) {
+            for (int i = 0; i < n; i++) {
+                long double x = w * (iv + (sig[i] + 1.0L) / 2.0L);
+                long double e = std::exp(-x * x);
+                rhs[i] = f == 0 ? std::erfc(x) + 2.0L * x * e / sqpi : e;
+                long double pw = 1.0L;
+                for (int c = 0; c < n; c++) {
+                    A[i * n + c] = pw;
+                    pw *= sig[i];
+                }
+            }
+            for (int c = 0; c < n; c++) {
+                int piv = c;
+                for (int r = c + 1; r < n; r++)
+                    if (std::fabs(A[r * n + c]) > std::fabs(A[piv * n + c])) piv = r;
+                if (piv != c) {
+                    for (int k = 0; k < n; k++) std::swap(A[c * n + k], A[piv * n + k]);
+                    std::swap(rhs[c], rhs[piv]);
+                }
+                for (int r = c + 1; r < n; r++) {
+                    long double fct = A[r * n + c] / A[c * n + c];
+                    for (int k = c; k < n; k++) A[r * n + k] -= fct * A[c * n + k];
+                    rhs[r] -= fct * rhs[c];
+                }
+            }
+            for (int c = n - 1; c >= 0; c--) {
+                long double acc = rhs[c];
+                for (int k = c + 1; k < n; k++) acc -= A[c * n + k] * rhs[k];
+                rhs[c] = acc / A[c * n + c];
+            }
+            for (int c = 0; c < n; c++) (*tab)[((size_t)f * SE_RTAB_N + iv) * n + c] = (double)rhs[c];
+        }
+}
+
 // Parameter selection, Sec. 4.6 (steps 1-7), with xi taken from n_rc
 // (Sec. 5.2) when not given, a relative tolerance mapped through U
 // (Sec. 4.2), the pollution rule eq. (error-pollution-fix), grid rounding

@@ -2,6 +2,8 @@
 // list, strength staging, FP64 reductions and the epilogue that adds the
 // self term (eq. 3p-stokeslet-self-term), the non-periodic stresslet term
 // (eq. k0-stresslet-3p) and scatters back to the caller's order.
+#include <algorithm>
+
 #include "se_device.h"
 
 namespace {
@@ -10,13 +12,15 @@ const double kSqrtPi = 1.7724538509055160272981675;
 
 struct se_real_args {
     se_grid_geom g;
-    const double* xt;  // sorted targets SoA [3][nt]
+    const double4* xt; // sorted targets [nt] (x, y, z, 0)
     int64_t nt;
-    const double* xs;  // sorted sources SoA [3][ns]
+    const double4* xs; // sorted sources [ns]
     int64_t ns;
-    const double* f;   // sorted strengths FP64 SoA [3][ns] (f, or q for T)
-    const double* nrm; // sorted normals SoA [3][ns] (T)
+    const double4* f;  // sorted strengths [ns] (f, or q for T)
+    const double4* nrm;// sorted normals [ns] (T)
+    const double* rtab;// radial-function table
     const int* start;  // source cell starts
+    const int* tstart; // target cell starts
     double xi, rc2;
     int Ra[3];         // anchor reach ceil(rc/h)+1
     int tas;
@@ -24,98 +28,249 @@ struct se_real_args {
     int* flags;
 };
 
-// u_j += G^R_{jl(m)}(r; xi) . f, eqs. (stokeslet-real), (rotlet-real), (stresslet-real)
-template <int KER>
-__device__ __forceinline__ void real_kernel(double xi, const double* r, double r2, const double* f,
-                                            const double* nu, double* u)
+constexpr int kRn = SE_RTAB_DEG + 1;
+
+__device__ __forceinline__ double horner_tab(const double* c, double sg)
 {
-    const double rn = sqrt(r2);
-    const double ec = erfc(xi * rn);
-    const double ga = exp(-xi * xi * r2) * (2.0 * xi / kSqrtPi);  // 2 xi e^{-xi^2 r^2}/sqrt(pi)
+    double acc = c[SE_RTAB_DEG];
+#pragma unroll
+    for (int k = SE_RTAB_DEG - 1; k >= 0; k--) acc = acc * sg + c[k];
+    return acc;
+}
+
+// u_j += G^R_{jl(m)}(r; xi) . f, eqs. (stokeslet-real), (rotlet-real),
+// (stresslet-real), written with x = xi r through G(x) = erfc(x) +
+// (2x/sqrt(pi)) e^{-x^2} and E(x) = e^{-x^2} (tabulated, see se_radial_table):
+//   S:     (G/r)(f + r (r.f)/r^2) - (4 xi/sqrt(pi)) E f
+//   Omega: (G/r^3) (f x r)
+//   T:     -2 r (r.q)(r.nu)/r^4 * (3G + (4x^3/sqrt(pi)) E)/r
+//          + (4 xi^3/sqrt(pi)) E (q (r.nu) + nu (r.q) + r (q.nu))
+template <int KER>
+__device__ __forceinline__ void real_pair(const double* tab, double xi, const double* r, double r2, const double* f,
+                                          const double* nu, double* u)
+{
+    const double inv = rsqrt(r2);
+    const double x = xi * r2 * inv;
+    const double xs = x * (SE_RTAB_N / SE_RTAB_X);
+    const int iv = min((int)xs, SE_RTAB_N - 1);
+    const double sg = 2.0 * (xs - iv) - 1.0;
+    const double G = horner_tab(tab + iv * kRn, sg);
+    const double E = horner_tab(tab + (SE_RTAB_N + iv) * kRn, sg);
     if constexpr (KER == SE_STOKESLET) {
-        const double c1 = ec / rn + ga;
-        const double c2 = 2.0 * ga;
-        const double rf = (r[0] * f[0] + r[1] * f[1] + r[2] * f[2]) / r2;
+        const double c1 = G * inv;
+        const double c2 = (4.0 / kSqrtPi) * xi * E;
+        const double rf = (r[0] * f[0] + r[1] * f[1] + r[2] * f[2]) * inv * inv;
 #pragma unroll
         for (int j = 0; j < 3; j++) u[j] += c1 * (f[j] + r[j] * rf) - c2 * f[j];
     } else if constexpr (KER == SE_ROTLET) {
-        const double c1 = (ec / rn + ga) / r2;
+        const double c1 = G * inv * inv * inv;
         u[0] += c1 * (f[1] * r[2] - f[2] * r[1]);
         u[1] += c1 * (f[2] * r[0] - f[0] * r[2]);
         u[2] += c1 * (f[0] * r[1] - f[1] * r[0]);
     } else {
-        const double c1 = 3.0 * ec / rn + (3.0 + 2.0 * xi * xi * r2) * ga;
-        const double c2 = 2.0 * xi * xi * ga;  // 4 xi^3 e^{-xi^2 r^2}/sqrt(pi)
+        const double c1 = (3.0 * G + (4.0 / kSqrtPi) * x * x * x * E) * inv;
+        const double c2 = (4.0 / kSqrtPi) * xi * xi * xi * E;
         const double rq = r[0] * f[0] + r[1] * f[1] + r[2] * f[2];
         const double rv = r[0] * nu[0] + r[1] * nu[1] + r[2] * nu[2];
         const double qv = f[0] * nu[0] + f[1] * nu[1] + f[2] * nu[2];
-        const double a = -2.0 * rq * rv / (r2 * r2) * c1;
+        const double i2 = inv * inv;
+        const double a = -2.0 * rq * rv * i2 * i2 * c1;
 #pragma unroll
         for (int j = 0; j < 3; j++) u[j] += a * r[j] + c2 * (f[j] * rv + nu[j] * rq + r[j] * qv);
     }
 }
 
-template <int KER>
-__global__ void __launch_bounds__(256) k_real(se_real_args a)
+// Persistent workgroups of 4 wavefronts; each wavefront walks a contiguous
+// range of target cells (XCD-aware), taking up to 64 targets of a cell at a
+// time.  The cell's neighbour bins form rows (by, bz) of consecutive x bins;
+// each row, per x run with one image shift, is a contiguous range of the
+// sorted sources.  Lanes take one row each and scan their ranges in lock
+// step: every candidate source is loaded once and tested against all targets
+// of the cell, so the neighbourhood is read once per cell, not once per
+// target.  Hits |r| < rc are compacted with a ballot into a per-wave LDS queue
+// of (target, source, image shift); every 64 queued pairs are evaluated by
+// the 64 lanes together (full SIMD width) and added to per-target LDS
+// accumulators.
+#define SE_RQ 128
+#define SE_REAL_BLOCKS 2048
+#define SE_RT 64
+
+__device__ __forceinline__ int pack_shift(int kx, int ky, int kz)
 {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= a.nt) return;
+    return (kx + 64) | ((ky + 64) << 7) | ((kz + 64) << 14);
+}
+
+struct se_real_lds {
+    int qs[SE_RQ];        // queued source index
+    int qk[SE_RQ];        // queued (target << 21) | packed image shift
+    double4 tp[SE_RT];    // target positions of the current chunk
+    double acc[3][SE_RT]; // per-target accumulators
+};
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int KER>
+__device__ __forceinline__ void eval_queue(const se_real_args& a, const double* tab, se_real_lds& L, int cnt,
+                                           int lane)
+{
+    wave_sync();
+    if (lane < cnt) {
+        const se_grid_geom& g = a.g;
+        const int s = L.qs[lane];
+        const int pk = L.qk[lane];
+        const int j = pk >> 21;
+        const int kx = (pk & 127) - 64, ky = ((pk >> 7) & 127) - 64, kz = ((pk >> 14) & 127) - 64;
+        const double4 p = a.xs[s];
+        const double4 tq = L.tp[j];
+        double r[3] = {tq.x - (p.x + kx * g.L[0]), tq.y - (p.y + ky * g.L[1]), tq.z - (p.z + kz * g.L[2])};
+        double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+        const double4 fv = a.f[s];
+        double f[3] = {fv.x, fv.y, fv.z};
+        double nu[3] = {0.0, 0.0, 0.0};
+        if (KER == SE_STRESSLET) {
+            const double4 nv = a.nrm[s];
+            nu[0] = nv.x;
+            nu[1] = nv.y;
+            nu[2] = nv.z;
+        }
+        double u[3] = {0.0, 0.0, 0.0};
+        real_pair<KER>(tab, a.xi, r, r2, f, nu, u);
+        atomicAdd(&L.acc[0][j], u[0]);
+        atomicAdd(&L.acc[1][j], u[1]);
+        atomicAdd(&L.acc[2][j], u[2]);
+    }
+}
+
+// Targets [tb, tb + nt) of one cell with anchor bins (cbx, cby, cbz).
+template <int KER>
+__device__ __forceinline__ void real_cell(const se_real_args& a, const double* tab, se_real_lds& L, int cb[3],
+                                          int64_t tb, int ntc, int lane)
+{
     const se_grid_geom& g = a.g;
-    double xt[3] = {a.xt[t], a.xt[a.nt + t], a.xt[2 * a.nt + t]};
+    // neighbour bin range of the whole cell
     int blo[3], bhi[3];
 #pragma unroll
     for (int d = 0; d < 3; d++) {
-        int an = se_anchor(g, d, xt[d]);
-        blo[d] = se_floordiv(an - a.Ra[d], g.B[d]);
-        bhi[d] = se_floordiv(an + a.Ra[d], g.B[d]);
+        const int a0 = cb[d] * g.B[d], a1 = min(a0 + g.B[d] - 1, g.Mg[d] - 1);
+        blo[d] = se_floordiv(a0 - a.Ra[d], g.B[d]);
+        bhi[d] = se_floordiv(a1 + a.Ra[d], g.B[d]);
         if (!g.periodic[d]) {
             blo[d] = max(blo[d], 0);
             bhi[d] = min(bhi[d], g.nb[d] - 1);
         }
     }
-    double acc[3] = {0.0, 0.0, 0.0};
+    // stage the targets
+    if (lane < ntc) {
+        L.tp[lane] = a.xt[tb + lane];
+        L.acc[0][lane] = 0.0;
+        L.acc[1][lane] = 0.0;
+        L.acc[2][lane] = 0.0;
+    }
+    wave_sync();
+    const int ny = max(bhi[1] - blo[1] + 1, 0), nz = max(bhi[2] - blo[2] + 1, 0);
+    const int nrows = ny * nz;
+    int qn = 0;
     int coinc = 0;
-    for (int bz = blo[2]; bz <= bhi[2]; bz++) {
-        int kz = g.periodic[2] ? se_floordiv(bz, g.nb[2]) : 0;
-        int wz = bz - kz * g.nb[2];
-        double sz = kz * g.L[2];
-        for (int by = blo[1]; by <= bhi[1]; by++) {
-            int ky = g.periodic[1] ? se_floordiv(by, g.nb[1]) : 0;
-            int wy = by - ky * g.nb[1];
-            double sy = ky * g.L[1];
-            for (int bx = blo[0]; bx <= bhi[0]; bx++) {
-                int kx = g.periodic[0] ? se_floordiv(bx, g.nb[0]) : 0;
-                int wx = bx - kx * g.nb[0];
-                double sx = kx * g.L[0];
-                int bin = (wz * g.nb[1] + wy) * g.nb[0] + wx;
-                int s0 = a.start[bin], s1 = a.start[bin + 1];
-                bool zero_shift = (kx == 0 && ky == 0 && kz == 0);
-                for (int s = s0; s < s1; s++) {
-                    double r[3] = {xt[0] - (a.xs[s] + sx), xt[1] - (a.xs[a.ns + s] + sy),
-                                   xt[2] - (a.xs[2 * a.ns + s] + sz)};
-                    double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-                    if (r2 >= a.rc2) continue;
-                    if (zero_shift && a.tas && s == t) continue;
-                    if (r2 == 0.0) {
+    int ux = blo[0];
+    while (ux <= bhi[0]) {
+        const int kx = g.periodic[0] ? se_floordiv(ux, g.nb[0]) : 0;
+        const int wx0 = ux - kx * g.nb[0];
+        const int run = min(bhi[0] - ux + 1, g.nb[0] - wx0);
+        for (int rb = 0; rb < nrows; rb += 64) {
+            const int row = rb + lane;
+            int s = 0, e = 0, ky = 0, kz = 0;
+            if (row < nrows) {
+                const int by = blo[1] + row % ny, bz = blo[2] + row / ny;
+                ky = g.periodic[1] ? se_floordiv(by, g.nb[1]) : 0;
+                kz = g.periodic[2] ? se_floordiv(bz, g.nb[2]) : 0;
+                const int wy = by - ky * g.nb[1], wz = bz - kz * g.nb[2];
+                const int rowbase = (wz * g.nb[1] + wy) * g.nb[0] + wx0;
+                s = a.start[rowbase];
+                e = a.start[rowbase + run];
+            }
+            const double sx = kx * g.L[0], sy = ky * g.L[1], sz = kz * g.L[2];
+            const bool zero_row = kx == 0 && ky == 0 && kz == 0;
+            const int pk = pack_shift(kx, ky, kz);
+            while (__ballot(s < e)) {
+                const bool active = s < e;
+                const int sc = active ? s : 0;
+                const double4 p = a.xs[sc];
+                const double px = p.x + sx, py = p.y + sy, pz = p.z + sz;
+                for (int j = 0; j < ntc; j++) {
+                    const double4 tq = L.tp[j];
+                    const double d0 = tq.x - px, d1 = tq.y - py, d2 = tq.z - pz;
+                    const double rr = d0 * d0 + d1 * d1 + d2 * d2;
+                    bool hit = active && rr < a.rc2 && !(a.tas && zero_row && (int64_t)sc == tb + j);
+                    if (hit && rr == 0.0) {
                         coinc = 1;
-                        continue;
+                        hit = false;
                     }
-                    double f[3] = {a.f[s], a.f[a.ns + s], a.f[2 * a.ns + s]};
-                    double nu[3] = {0.0, 0.0, 0.0};
-                    if (KER == SE_STRESSLET) {
-                        nu[0] = a.nrm[s];
-                        nu[1] = a.nrm[a.ns + s];
-                        nu[2] = a.nrm[2 * a.ns + s];
+                    const uint64_t m = __ballot(hit);
+                    if (m) {
+                        if (hit) {
+                            const int rank = __popcll(m & ((1ull << lane) - 1ull));
+                            L.qs[qn + rank] = sc;
+                            L.qk[qn + rank] = pk | (j << 21);
+                        }
+                        qn += __popcll(m);
+                        if (qn >= 64) {
+                            eval_queue<KER>(a, tab, L, 64, lane);
+                            const int rem = qn - 64;
+                            int ts = 0, tk = 0;
+                            if (lane < rem) {
+                                ts = L.qs[64 + lane];
+                                tk = L.qk[64 + lane];
+                            }
+                            wave_sync();
+                            if (lane < rem) {
+                                L.qs[lane] = ts;
+                                L.qk[lane] = tk;
+                            }
+                            qn = rem;
+                        }
                     }
-                    real_kernel<KER>(a.xi, r, r2, f, nu, acc);
                 }
+                s += active ? 1 : 0;
             }
         }
+        ux += run;
     }
-    if (coinc) atomicOr(a.flags, SE_FLAG_COINCIDENT);
-    a.u[t] = acc[0];
-    a.u[a.nt + t] = acc[1];
-    a.u[2 * a.nt + t] = acc[2];
+    eval_queue<KER>(a, tab, L, qn, lane);
+    wave_sync();
+    if (__ballot(coinc) && lane == 0) atomicOr(a.flags, SE_FLAG_COINCIDENT);
+    if (lane < ntc) {
+        a.u[tb + lane] = L.acc[0][lane];
+        a.u[a.nt + tb + lane] = L.acc[1][lane];
+        a.u[2 * a.nt + tb + lane] = L.acc[2][lane];
+    }
+    wave_sync();
+}
+
+template <int KER>
+__global__ void __launch_bounds__(256) k_real(se_real_args a)
+{
+    __shared__ double tab[2 * SE_RTAB_N * kRn];
+    __shared__ se_real_lds lds[4];
+    for (int i = threadIdx.x; i < 2 * SE_RTAB_N * kRn; i += 256) tab[i] = a.rtab[i];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const se_grid_geom& g = a.g;
+    const int64_t nbins = (int64_t)g.nb[0] * g.nb[1] * g.nb[2];
+    const int64_t nw = (int64_t)gridDim.x * 4;
+    const int64_t w = (int64_t)se_xcd_block(blockIdx.x, gridDim.x) * 4 + wave;
+    const int64_t chunk = (nbins + nw - 1) / nw;
+    const int64_t c0 = w * chunk, c1 = min(nbins, c0 + chunk);
+    for (int64_t c = c0; c < c1; c++) {
+        const int tb = a.tstart[c], te = a.tstart[c + 1];
+        if (tb == te) continue;
+        int cb[3] = {(int)(c % g.nb[0]), (int)((c / g.nb[0]) % g.nb[1]), (int)(c / ((int64_t)g.nb[0] * g.nb[1]))};
+        for (int t0 = tb; t0 < te; t0 += SE_RT) real_cell<KER>(a, tab, lds[wave], cb, t0, min(SE_RT, te - t0), lane);
+    }
 }
 
 // Sorted strengths: FP64 copy [3][ns] of f (or q) for the real-space sum and
@@ -124,7 +279,7 @@ __global__ void __launch_bounds__(256) k_real(se_real_args a)
 template <typename R>
 __global__ void k_strengths(const double* __restrict__ f, const int* __restrict__ perm, int64_t n,
                             const double* __restrict__ nrm, int ncomp, double* __restrict__ f64,
-                            R* __restrict__ fs, double* __restrict__ qn, int* flags)
+                            R* __restrict__ fs, double* __restrict__ qn, double4* __restrict__ f4, int* flags)
 {
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
@@ -140,6 +295,7 @@ __global__ void k_strengths(const double* __restrict__ f, const int* __restrict_
         v[0] = v[1] = v[2] = 0.0;
     }
     for (int c = 0; c < 3; c++) f64[c * n + s] = v[c];
+    f4[s] = make_double4(v[0], v[1], v[2], 0.0);
     if (ncomp == 3) {
         for (int c = 0; c < 3; c++) fs[c * n + s] = (R)v[c];
     } else {
@@ -220,10 +376,12 @@ void se_launch_strengths(const se_plan* p, const double* f, hipStream_t s)
 {
     if (p->fp32)
         hipLaunchKernelGGL(k_strengths<float>, dim3(grid1d(p->ns, 256)), dim3(256), 0, s, f, p->d_src_perm, p->ns,
-                           p->d_nrm, p->ncomp, p->d_fs64, (float*)p->d_fs, p->d_fs64 + 3 * p->ns, p->d_flags);
+                           p->d_nrm, p->ncomp, p->d_fs64, (float*)p->d_fs, p->d_fs64 + 3 * p->ns, (double4*)p->d_str4,
+                           p->d_flags);
     else
         hipLaunchKernelGGL(k_strengths<double>, dim3(grid1d(p->ns, 256)), dim3(256), 0, s, f, p->d_src_perm, p->ns,
-                           p->d_nrm, p->ncomp, p->d_fs64, (double*)p->d_fs, p->d_fs64 + 3 * p->ns, p->d_flags);
+                           p->d_nrm, p->ncomp, p->d_fs64, (double*)p->d_fs, p->d_fs64 + 3 * p->ns, (double4*)p->d_str4,
+                           p->d_flags);
 }
 
 void se_launch_reductions(const se_plan* p, hipStream_t s)
@@ -236,20 +394,22 @@ void se_launch_real_space(const se_plan* p, hipStream_t s)
 {
     se_real_args a;
     a.g = p->g;
-    a.xt = p->tas ? p->d_src : p->d_tgt;
+    a.xt = (const double4*)(p->tas ? p->d_pos4 : p->d_tpos4);
     a.nt = p->nt;
-    a.xs = p->d_src;
+    a.xs = (const double4*)p->d_pos4;
     a.ns = p->ns;
-    a.f = p->d_fs64;
-    a.nrm = p->d_nrm;
+    a.f = (const double4*)p->d_str4;
+    a.nrm = (const double4*)p->d_nrm4;
+    a.rtab = p->d_rtab;
     a.start = p->d_src_start;
+    a.tstart = p->tas ? p->d_src_start : p->d_tgt_start;
     a.xi = p->par.xi;
     a.rc2 = p->par.rc * p->par.rc;
     for (int d = 0; d < 3; d++) a.Ra[d] = (int)std::ceil(p->par.rc / p->g.h[d]) + 1;
     a.tas = p->tas ? 1 : 0;
     a.u = p->d_uR;
     a.flags = p->d_flags;
-    unsigned nb = grid1d(p->nt, 256);
+    unsigned nb = (unsigned)std::min<int64_t>((p->nt + 3) / 4, SE_REAL_BLOCKS);
     if (p->kernel == SE_STOKESLET) hipLaunchKernelGGL(k_real<SE_STOKESLET>, dim3(nb), dim3(256), 0, s, a);
     else if (p->kernel == SE_ROTLET) hipLaunchKernelGGL(k_real<SE_ROTLET>, dim3(nb), dim3(256), 0, s, a);
     else hipLaunchKernelGGL(k_real<SE_STRESSLET>, dim3(nb), dim3(256), 0, s, a);

@@ -17,6 +17,9 @@
 // free axes are clipped.
 #include "se_device.h"
 
+#define SE_TILE_THREADS 512
+#define SE_TILE_WAVES (SE_TILE_THREADS / 64)
+
 namespace {
 
 struct se_tile_args {
@@ -102,7 +105,7 @@ __device__ __forceinline__ int wrap_bin(const se_grid_geom& g, const int* ub, in
 __device__ __forceinline__ void tile_origin(const int* ntile, int TX, int TY, int TZ, const se_grid_geom& g,
                                             int* t0, int* te)
 {
-    int bid = blockIdx.x;
+    int bid = se_xcd_block(blockIdx.x, gridDim.x);
     int tx = bid % ntile[0];
     int ty = (bid / ntile[0]) % ntile[1];
     int tz = bid / (ntile[0] * ntile[1]);
@@ -114,61 +117,135 @@ __device__ __forceinline__ void tile_origin(const int* ntile, int TX, int TY, in
     te[2] = min(TZ, g.Mg[2] - t0[2]);
 }
 
+// Unrolled Horner with SE_MAX_NU + 1 coefficients (zero padded beyond nu,
+// which leaves the arithmetic of the lower-degree polynomial unchanged).
+template <typename R>
+__device__ __forceinline__ R pkb_weight(const double* coef, int q, R s)
+{
+    const double* c = coef + q * (SE_MAX_NU + 1);
+    R sig = (R)2 * s - (R)1;
+    R acc = (R)c[SE_MAX_NU];
+#pragma unroll
+    for (int k = SE_MAX_NU - 1; k >= 0; k--) acc = acc * sig + (R)c[k];
+    return acc;
+}
+
+__device__ __forceinline__ int rl_i(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+
+// Per-wave walk over the points whose anchors lie in the block's halo: rows
+// of bins (by, bz) are split into runs of consecutive x bins with one wrap
+// shift, each run is a contiguous range of sorted points.  Points are loaded
+// 64 at a time (one per lane), intersected lane-parallel, and the non-empty
+// ones are handed to `body` one by one (uniform control flow).
+template <typename Body>
+__device__ __forceinline__ void walk_points(const se_tile_args& a, const int* t0, const int* te, int wave, int lane,
+                                            Body&& body)
+{
+    const se_grid_geom& g = a.g;
+    int b0[3], nbr[3];
+    halo_bins(g, t0, te, a.P, b0, nbr);
+    const int nrows = nbr[1] * nbr[2];
+    const int64_t n = a.n;
+    for (int row = wave; row < nrows; row += SE_TILE_WAVES) {
+        int uy = b0[1] + row % nbr[1], uz = b0[2] + row / nbr[1];
+        int sy = 0, sz = 0, wy = uy, wz = uz;
+        if (g.periodic[1]) {
+            int k = se_floordiv(uy, g.nb[1]);
+            wy = uy - k * g.nb[1];
+            sy = k * g.Mg[1];
+        }
+        if (g.periodic[2]) {
+            int k = se_floordiv(uz, g.nb[2]);
+            wz = uz - k * g.nb[2];
+            sz = k * g.Mg[2];
+        }
+        const int rowbase = (wz * g.nb[1] + wy) * g.nb[0];
+        int ux = b0[0];
+        const int uxe = b0[0] + nbr[0] - 1;
+        while (ux <= uxe) {
+            int kx = g.periodic[0] ? se_floordiv(ux, g.nb[0]) : 0;
+            int wx0 = ux - kx * g.nb[0];
+            int run = min(uxe - ux + 1, g.nb[0] - wx0);
+            int shift[3] = {kx * g.Mg[0], sy, sz};
+            int s_beg = a.start[rowbase + wx0], s_end = a.start[rowbase + wx0 + run];
+            for (int base = s_beg; base < s_end; base += 64) {
+                int s = base + lane;
+                bool valid = s < s_end;
+                int sc = valid ? s : s_beg;
+                double xp[3] = {a.xs[sc], a.xs[n + sc], a.xs[2 * n + sc]};
+                se_isect q;
+                bool ok = point_isect(g, xp, shift, t0, te, a.P, q) && valid;
+                uint64_t mask = __ballot(ok);
+                body(mask, sc, q);
+            }
+            ux += run;
+        }
+    }
+}
+
 template <typename R, int NC, int TX, int TY, int TZ>
-__global__ void __launch_bounds__(256) k_spread(se_tile_args a)
+__global__ void __launch_bounds__(SE_TILE_THREADS) k_spread(se_tile_args a)
 {
     extern __shared__ double smem_d[];
     constexpr int TV = TX * TY * TZ;
     double* s_pkb = smem_d;
     R* acc = (R*)(smem_d + SE_MAX_P * (SE_MAX_NU + 1));
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const se_grid_geom& g = a.g;
     int t0[3], te[3];
     tile_origin(a.ntile, TX, TY, TZ, g, t0, te);
-    for (int i = tid; i < NC * TV; i += 256) acc[i] = (R)0;
-    for (int i = tid; i < a.P * (a.nu + 1); i += 256) s_pkb[i] = a.pkb[i];
+    for (int i = tid; i < NC * TV; i += SE_TILE_THREADS) acc[i] = (R)0;
+    for (int i = tid; i < SE_MAX_P * (SE_MAX_NU + 1); i += SE_TILE_THREADS) {
+        int q = i / (SE_MAX_NU + 1), k = i - q * (SE_MAX_NU + 1);
+        s_pkb[i] = (q < a.P && k <= a.nu) ? a.pkb[q * (a.nu + 1) + k] : 0.0;
+    }
     __syncthreads();
-
-    int b0[3], nbr[3];
-    halo_bins(g, t0, te, a.P, b0, nbr);
-    const int nrange = nbr[0] * nbr[1] * nbr[2];
     const R* fs = (const R*)a.fs;
     const int64_t n = a.n;
-    for (int r = wave; r < nrange; r += 4) {
-        int ub[3] = {b0[0] + r % nbr[0], b0[1] + (r / nbr[0]) % nbr[1], b0[2] + r / (nbr[0] * nbr[1])};
-        int shift[3];
-        int bin = wrap_bin(g, ub, shift);
-        int s0 = a.start[bin], s1 = a.start[bin + 1];
-        for (int s = s0; s < s1; s++) {
-            double xp[3] = {a.xs[s], a.xs[n + s], a.xs[2 * n + s]};
-            se_isect q;
-            if (!point_isect(g, xp, shift, t0, te, a.P, q)) continue;
-            R w = (R)0;
-            if (lane < q.ex[0])
-                w = se_pkb_eval<R>(s_pkb, a.nu, q.qoff[0] + lane, (R)(1.0 - q.t[0]));
-            else if (lane < q.ex[0] + q.ex[1])
-                w = se_pkb_eval<R>(s_pkb, a.nu, q.qoff[1] + lane - q.ex[0], (R)(1.0 - q.t[1]));
-            else if (lane < q.ex[0] + q.ex[1] + q.ex[2])
-                w = se_pkb_eval<R>(s_pkb, a.nu, q.qoff[2] + lane - q.ex[0] - q.ex[1], (R)(1.0 - q.t[2]));
+    walk_points(a, t0, te, wave, lane, [&](uint64_t mask, int sc, const se_isect& q) {
+        R fl[NC];
+#pragma unroll
+        for (int c = 0; c < NC; c++) fl[c] = fs[c * n + sc];
+        while (mask) {
+            const int j = __builtin_ctzll(mask);
+            mask &= mask - 1;
+            const int lo0 = rl_i(q.lo[0], j), lo1 = rl_i(q.lo[1], j), lo2 = rl_i(q.lo[2], j);
+            const int ex0 = rl_i(q.ex[0], j), ex1 = rl_i(q.ex[1], j), ex2 = rl_i(q.ex[2], j);
+            const int qo0 = rl_i(q.qoff[0], j), qo1 = rl_i(q.qoff[1], j), qo2 = rl_i(q.qoff[2], j);
             R f[NC];
 #pragma unroll
-            for (int c = 0; c < NC; c++) f[c] = fs[c * n + s];
-            const int nxy = q.ex[0] * q.ex[1];
-            const int zl = q.lo[2] - t0[2], yl = q.lo[1] - t0[1], xl = q.lo[0] - t0[0];
+            for (int c = 0; c < NC; c++) f[c] = se_readlane(fl[c], j);
+            int dim, qq;
+            double tt;
+            if (lane < ex0) {
+                dim = 0;
+                qq = qo0 + lane;
+            } else if (lane < ex0 + ex1) {
+                dim = 1;
+                qq = qo1 + lane - ex0;
+            } else {
+                dim = 2;
+                qq = qo2 + min(lane - ex0 - ex1, ex2 - 1);
+            }
+            const double tj0 = se_readlane(q.t[0], j), tj1 = se_readlane(q.t[1], j), tj2 = se_readlane(q.t[2], j);
+            tt = dim == 0 ? tj0 : (dim == 1 ? tj1 : tj2);
+            const R w = pkb_weight<R>(s_pkb, qq, (R)(1.0 - tt));
+            const int nxy = ex0 * ex1;
+            const int zl = lo2 - t0[2], yl = lo1 - t0[1], xl = lo0 - t0[0];
             for (int base = 0; base < nxy; base += 64) {
                 int idx = base + lane;
                 bool act = idx < nxy;
                 int idc = act ? idx : 0;
-                int iy = idc / q.ex[0];
-                int ix = idc - iy * q.ex[0];
+                int iy = idc / ex0;
+                int ix = idc - iy * ex0;
                 R wx = shfl_r(w, ix);
-                R wy = shfl_r(w, q.ex[0] + iy);
+                R wy = shfl_r(w, ex0 + iy);
                 R gv[NC];
 #pragma unroll
                 for (int c = 0; c < NC; c++) gv[c] = wx * wy * f[c];
                 int lb = (zl * TY + yl + iy) * TX + xl + ix;
-                for (int iz = 0; iz < q.ex[2]; iz++) {
-                    R wz = se_readlane(w, q.ex[0] + q.ex[1] + iz);
+                for (int iz = 0; iz < ex2; iz++) {
+                    R wz = se_readlane(w, ex0 + ex1 + iz);
                     if (act) {
 #pragma unroll
                         for (int c = 0; c < NC; c++) atomicAdd(&acc[c * TV + lb + iz * TX * TY], wz * gv[c]);
@@ -176,12 +253,12 @@ __global__ void __launch_bounds__(256) k_spread(se_tile_args a)
                 }
             }
         }
-    }
+    });
     __syncthreads();
     R* grid = (R*)a.grid;
     const int64_t plane = (int64_t)g.Mg[0] * g.Mg[1];
     const int64_t vol = plane * g.Mg[2];
-    for (int i = tid; i < TV; i += 256) {
+    for (int i = tid; i < TV; i += SE_TILE_THREADS) {
         int ix = i % TX, iy = (i / TX) % TY, iz = i / (TX * TY);
         if (ix < te[0] && iy < te[1] && iz < te[2]) {
             int64_t o = (int64_t)(t0[2] + iz) * plane + (int64_t)(t0[1] + iy) * g.Mg[0] + t0[0] + ix;
@@ -192,64 +269,70 @@ __global__ void __launch_bounds__(256) k_spread(se_tile_args a)
 }
 
 template <typename R, int TX, int TY, int TZ>
-__global__ void __launch_bounds__(256) k_gather(se_tile_args a)
+__global__ void __launch_bounds__(SE_TILE_THREADS) k_gather(se_tile_args a)
 {
     extern __shared__ double smem_d[];
     constexpr int TV = TX * TY * TZ;
     double* s_pkb = smem_d;
     R* tile = (R*)(smem_d + SE_MAX_P * (SE_MAX_NU + 1));
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const se_grid_geom& g = a.g;
     int t0[3], te[3];
     tile_origin(a.ntile, TX, TY, TZ, g, t0, te);
     const R* grid = (const R*)a.grid;
     const int64_t plane = (int64_t)g.Mg[0] * g.Mg[1];
     const int64_t vol = plane * g.Mg[2];
-    for (int i = tid; i < TV; i += 256) {
+    for (int i = tid; i < TV; i += SE_TILE_THREADS) {
         int ix = i % TX, iy = (i / TX) % TY, iz = i / (TX * TY);
         bool in = ix < te[0] && iy < te[1] && iz < te[2];
         int64_t o = (int64_t)(t0[2] + iz) * plane + (int64_t)(t0[1] + iy) * g.Mg[0] + t0[0] + ix;
 #pragma unroll
         for (int c = 0; c < 3; c++) tile[c * TV + i] = in ? grid[c * vol + o] : (R)0;
     }
-    for (int i = tid; i < a.P * (a.nu + 1); i += 256) s_pkb[i] = a.pkb[i];
+    for (int i = tid; i < SE_MAX_P * (SE_MAX_NU + 1); i += SE_TILE_THREADS) {
+        int q = i / (SE_MAX_NU + 1), k = i - q * (SE_MAX_NU + 1);
+        s_pkb[i] = (q < a.P && k <= a.nu) ? a.pkb[q * (a.nu + 1) + k] : 0.0;
+    }
     __syncthreads();
-
-    int b0[3], nbr[3];
-    halo_bins(g, t0, te, a.P, b0, nbr);
-    const int nrange = nbr[0] * nbr[1] * nbr[2];
     const int64_t n = a.n;
-    for (int r = wave; r < nrange; r += 4) {
-        int ub[3] = {b0[0] + r % nbr[0], b0[1] + (r / nbr[0]) % nbr[1], b0[2] + r / (nbr[0] * nbr[1])};
-        int shift[3];
-        int bin = wrap_bin(g, ub, shift);
-        int s0 = a.start[bin], s1 = a.start[bin + 1];
-        for (int s = s0; s < s1; s++) {
-            double xp[3] = {a.xs[s], a.xs[n + s], a.xs[2 * n + s]};
-            se_isect q;
-            if (!point_isect(g, xp, shift, t0, te, a.P, q)) continue;
-            R w = (R)0;
-            if (lane < q.ex[0])
-                w = se_pkb_eval<R>(s_pkb, a.nu, q.qoff[0] + lane, (R)(1.0 - q.t[0]));
-            else if (lane < q.ex[0] + q.ex[1])
-                w = se_pkb_eval<R>(s_pkb, a.nu, q.qoff[1] + lane - q.ex[0], (R)(1.0 - q.t[1]));
-            else if (lane < q.ex[0] + q.ex[1] + q.ex[2])
-                w = se_pkb_eval<R>(s_pkb, a.nu, q.qoff[2] + lane - q.ex[0] - q.ex[1], (R)(1.0 - q.t[2]));
-            const int nxy = q.ex[0] * q.ex[1];
-            const int zl = q.lo[2] - t0[2], yl = q.lo[1] - t0[1], xl = q.lo[0] - t0[0];
+    walk_points(a, t0, te, wave, lane, [&](uint64_t mask, int sc, const se_isect& q) {
+        const uint64_t own = mask;
+        double my0 = 0.0, my1 = 0.0, my2 = 0.0;
+        while (mask) {
+            const int j = __builtin_ctzll(mask);
+            mask &= mask - 1;
+            const int lo0 = rl_i(q.lo[0], j), lo1 = rl_i(q.lo[1], j), lo2 = rl_i(q.lo[2], j);
+            const int ex0 = rl_i(q.ex[0], j), ex1 = rl_i(q.ex[1], j), ex2 = rl_i(q.ex[2], j);
+            const int qo0 = rl_i(q.qoff[0], j), qo1 = rl_i(q.qoff[1], j), qo2 = rl_i(q.qoff[2], j);
+            int dim, qq;
+            if (lane < ex0) {
+                dim = 0;
+                qq = qo0 + lane;
+            } else if (lane < ex0 + ex1) {
+                dim = 1;
+                qq = qo1 + lane - ex0;
+            } else {
+                dim = 2;
+                qq = qo2 + min(lane - ex0 - ex1, ex2 - 1);
+            }
+            const double tj0 = se_readlane(q.t[0], j), tj1 = se_readlane(q.t[1], j), tj2 = se_readlane(q.t[2], j);
+            const double tt = dim == 0 ? tj0 : (dim == 1 ? tj1 : tj2);
+            const R w = pkb_weight<R>(s_pkb, qq, (R)(1.0 - tt));
+            const int nxy = ex0 * ex1;
+            const int zl = lo2 - t0[2], yl = lo1 - t0[1], xl = lo0 - t0[0];
             R acc0 = 0, acc1 = 0, acc2 = 0;
             for (int base = 0; base < nxy; base += 64) {
                 int idx = base + lane;
                 bool act = idx < nxy;
                 int idc = act ? idx : 0;
-                int iy = idc / q.ex[0];
-                int ix = idc - iy * q.ex[0];
+                int iy = idc / ex0;
+                int ix = idc - iy * ex0;
                 R wx = shfl_r(w, ix);
-                R wy = shfl_r(w, q.ex[0] + iy);
+                R wy = shfl_r(w, ex0 + iy);
                 R wxy = act ? wx * wy : (R)0;
                 int lb = (zl * TY + yl + iy) * TX + xl + ix;
-                for (int iz = 0; iz < q.ex[2]; iz++) {
-                    R wz = se_readlane(w, q.ex[0] + q.ex[1] + iz) * wxy;
+                for (int iz = 0; iz < ex2; iz++) {
+                    R wz = se_readlane(w, ex0 + ex1 + iz) * wxy;
                     int o = lb + iz * TX * TY;
                     acc0 += wz * tile[o];
                     acc1 += wz * tile[TV + o];
@@ -262,13 +345,18 @@ __global__ void __launch_bounds__(256) k_gather(se_tile_args a)
                 acc1 += __shfl_xor(acc1, off, 64);
                 acc2 += __shfl_xor(acc2, off, 64);
             }
-            if (lane == 0) {
-                atomicAdd(&a.u[s], (double)acc0);
-                atomicAdd(&a.u[n + s], (double)acc1);
-                atomicAdd(&a.u[2 * n + s], (double)acc2);
+            if (lane == j) {
+                my0 = (double)acc0;
+                my1 = (double)acc1;
+                my2 = (double)acc2;
             }
         }
-    }
+        if ((own >> lane) & 1ull) {
+            atomicAdd(&a.u[sc], my0);
+            atomicAdd(&a.u[n + sc], my1);
+            atomicAdd(&a.u[2 * n + sc], my2);
+        }
+    });
 }
 
 template <typename K>
@@ -302,7 +390,7 @@ void launch_spread(const se_plan* p, hipStream_t s)
     auto kern = k_spread<R, NC, TX, TY, TZ>;
     set_lds(kern, lds);
     unsigned nb = (unsigned)(p->ntile[0] * p->ntile[1] * p->ntile[2]);
-    hipLaunchKernelGGL(kern, dim3(nb), dim3(256), lds, s, a);
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(SE_TILE_THREADS), lds, s, a);
 }
 
 template <typename R, int TX, int TY, int TZ>
@@ -313,7 +401,7 @@ void launch_gather(const se_plan* p, hipStream_t s)
     auto kern = k_gather<R, TX, TY, TZ>;
     set_lds(kern, lds);
     unsigned nb = (unsigned)(p->ntile[0] * p->ntile[1] * p->ntile[2]);
-    hipLaunchKernelGGL(kern, dim3(nb), dim3(256), lds, s, a);
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(SE_TILE_THREADS), lds, s, a);
 }
 
 }  // namespace
