@@ -146,25 +146,27 @@ __device__ __forceinline__ void eval_queue(const se_real_args& a, const double* 
     }
 }
 
-// Targets [tb, tb + nt) of one cell with anchor bins (cbx, cby, cbz).
+// Targets [tb, tb + ntc) of one cell with bin coordinates cb.  Rows are
+// trimmed to the sources that can lie within rc of the cell's box: a row
+// (by, bz) is skipped when its y/z distance to the box reaches rc, otherwise
+// its x range is cut to the remaining reach sqrt(rc^2 - dy^2 - dz^2).
 template <int KER>
 __device__ __forceinline__ void real_cell(const se_real_args& a, const double* tab, se_real_lds& L, int cb[3],
                                           int64_t tb, int ntc, int lane)
 {
     const se_grid_geom& g = a.g;
-    // neighbour bin range of the whole cell
-    int blo[3], bhi[3];
+    int a0[3], a1[3], blo[3], bhi[3];
 #pragma unroll
     for (int d = 0; d < 3; d++) {
-        const int a0 = cb[d] * g.B[d], a1 = min(a0 + g.B[d] - 1, g.Mg[d] - 1);
-        blo[d] = se_floordiv(a0 - a.Ra[d], g.B[d]);
-        bhi[d] = se_floordiv(a1 + a.Ra[d], g.B[d]);
+        a0[d] = cb[d] * g.B[d];
+        a1[d] = min(a0[d] + g.B[d] - 1, g.Mg[d] - 1);
+        blo[d] = se_floordiv(a0[d] - a.Ra[d], g.B[d]);
+        bhi[d] = se_floordiv(a1[d] + a.Ra[d], g.B[d]);
         if (!g.periodic[d]) {
             blo[d] = max(blo[d], 0);
             bhi[d] = min(bhi[d], g.nb[d] - 1);
         }
     }
-    // stage the targets
     if (lane < ntc) {
         L.tp[lane] = a.xt[tb + lane];
         L.acc[0][lane] = 0.0;
@@ -174,71 +176,93 @@ __device__ __forceinline__ void real_cell(const se_real_args& a, const double* t
     wave_sync();
     const int ny = max(bhi[1] - blo[1] + 1, 0), nz = max(bhi[2] - blo[2] + 1, 0);
     const int nrows = ny * nz;
+    const double rc2 = a.rc2;
+    // cell box (grid index space, unwrapped): [a0, a1 + 1) per axis
     int qn = 0;
     int coinc = 0;
-    int ux = blo[0];
-    while (ux <= bhi[0]) {
-        const int kx = g.periodic[0] ? se_floordiv(ux, g.nb[0]) : 0;
-        const int wx0 = ux - kx * g.nb[0];
-        const int run = min(bhi[0] - ux + 1, g.nb[0] - wx0);
-        for (int rb = 0; rb < nrows; rb += 64) {
-            const int row = rb + lane;
-            int s = 0, e = 0, ky = 0, kz = 0;
-            if (row < nrows) {
-                const int by = blo[1] + row % ny, bz = blo[2] + row / ny;
-                ky = g.periodic[1] ? se_floordiv(by, g.nb[1]) : 0;
-                kz = g.periodic[2] ? se_floordiv(bz, g.nb[2]) : 0;
-                const int wy = by - ky * g.nb[1], wz = bz - kz * g.nb[2];
-                const int rowbase = (wz * g.nb[1] + wy) * g.nb[0] + wx0;
-                s = a.start[rowbase];
-                e = a.start[rowbase + run];
-            }
-            const double sx = kx * g.L[0], sy = ky * g.L[1], sz = kz * g.L[2];
-            const bool zero_row = kx == 0 && ky == 0 && kz == 0;
-            const int pk = pack_shift(kx, ky, kz);
-            while (__ballot(s < e)) {
-                const bool active = s < e;
-                const int sc = active ? s : 0;
-                const double4 p = a.xs[sc];
-                const double px = p.x + sx, py = p.y + sy, pz = p.z + sz;
-                for (int j = 0; j < ntc; j++) {
-                    const double4 tq = L.tp[j];
-                    const double d0 = tq.x - px, d1 = tq.y - py, d2 = tq.z - pz;
-                    const double rr = d0 * d0 + d1 * d1 + d2 * d2;
-                    bool hit = active && rr < a.rc2 && !(a.tas && zero_row && (int64_t)sc == tb + j);
-                    if (hit && rr == 0.0) {
-                        coinc = 1;
-                        hit = false;
-                    }
-                    const uint64_t m = __ballot(hit);
-                    if (m) {
-                        if (hit) {
-                            const int rank = __popcll(m & ((1ull << lane) - 1ull));
-                            L.qs[qn + rank] = sc;
-                            L.qk[qn + rank] = pk | (j << 21);
-                        }
-                        qn += __popcll(m);
-                        if (qn >= 64) {
-                            eval_queue<KER>(a, tab, L, 64, lane);
-                            const int rem = qn - 64;
-                            int ts = 0, tk = 0;
-                            if (lane < rem) {
-                                ts = L.qs[64 + lane];
-                                tk = L.qk[64 + lane];
-                            }
-                            wave_sync();
-                            if (lane < rem) {
-                                L.qs[lane] = ts;
-                                L.qk[lane] = tk;
-                            }
-                            qn = rem;
-                        }
-                    }
-                }
-                s += active ? 1 : 0;
+    for (int rb = 0; rb < nrows; rb += 64) {
+        const int row = rb + lane;
+        int ky = 0, kz = 0, rowbase = 0, uxl = 1, uxh = 0;
+        if (row < nrows) {
+            const int by = blo[1] + row % ny, bz = blo[2] + row / ny;
+            ky = g.periodic[1] ? se_floordiv(by, g.nb[1]) : 0;
+            kz = g.periodic[2] ? se_floordiv(bz, g.nb[2]) : 0;
+            const int wy = by - ky * g.nb[1], wz = bz - kz * g.nb[2];
+            rowbase = (wz * g.nb[1] + wy) * g.nb[0];
+            // distances (grid units) between the row's bins and the cell box in y and z
+            const int y0 = by * g.B[1], y1 = y0 + g.B[1];
+            const int z0 = bz * g.B[2], z1 = z0 + g.B[2];
+            const double dy = max(0, max(y0 - (a1[1] + 1), a0[1] - y1)) * g.h[1];
+            const double dz = max(0, max(z0 - (a1[2] + 1), a0[2] - z1)) * g.h[2];
+            const double rem2 = rc2 - dy * dy - dz * dz;
+            if (rem2 > 0.0) {
+                const int rx = (int)ceil(sqrt(rem2) * g.invh[0]) + 1;
+                uxl = se_floordiv(a0[0] - rx, g.B[0]);
+                uxh = se_floordiv(a1[0] + rx, g.B[0]);
+                uxl = max(uxl, blo[0]);
+                uxh = min(uxh, bhi[0]);
             }
         }
-        ux += run;
+        const double sy = ky * g.L[1], sz = kz * g.L[2];
+        int ux = uxl;
+        int s = 0, e = 0, pk = 0;
+        double sx = 0.0;
+        bool zero_row = false;
+        while (true) {
+            // refill exhausted lanes with their next run of consecutive bins
+            while (s == e && ux <= uxh) {
+                const int kx = g.periodic[0] ? se_floordiv(ux, g.nb[0]) : 0;
+                const int wx0 = ux - kx * g.nb[0];
+                const int run = min(uxh - ux + 1, g.nb[0] - wx0);
+                s = a.start[rowbase + wx0];
+                e = a.start[rowbase + wx0 + run];
+                sx = kx * g.L[0];
+                pk = pack_shift(kx, ky, kz);
+                zero_row = kx == 0 && ky == 0 && kz == 0;
+                ux += run;
+            }
+            const bool active = s < e;
+            if (!__ballot(active)) break;
+            const int sc = active ? s : 0;
+            const double4 p = a.xs[sc];
+            const double px = p.x + sx, py = p.y + sy, pz = p.z + sz;
+            for (int j = 0; j < ntc; j++) {
+                const double4 tq = L.tp[j];
+                const double d0 = tq.x - px, d1 = tq.y - py, d2 = tq.z - pz;
+                const double rr = d0 * d0 + d1 * d1 + d2 * d2;
+                bool hit = active && rr < rc2;
+                if (hit && rr == 0.0) {
+                    // the excluded self term (targets are sources) or a coincident pair
+                    if (!(a.tas && zero_row && (int64_t)sc == tb + j)) coinc = 1;
+                    hit = false;
+                }
+                const uint64_t m = __ballot(hit);
+                if (m) {
+                    if (hit) {
+                        const int rank = __popcll(m & ((1ull << lane) - 1ull));
+                        L.qs[qn + rank] = sc;
+                        L.qk[qn + rank] = pk | (j << 21);
+                    }
+                    qn += __popcll(m);
+                    if (qn >= 64) {
+                        eval_queue<KER>(a, tab, L, 64, lane);
+                        const int rem = qn - 64;
+                        int ts = 0, tk = 0;
+                        if (lane < rem) {
+                            ts = L.qs[64 + lane];
+                            tk = L.qk[64 + lane];
+                        }
+                        wave_sync();
+                        if (lane < rem) {
+                            L.qs[lane] = ts;
+                            L.qk[lane] = tk;
+                        }
+                        qn = rem;
+                    }
+                }
+            }
+            s += active ? 1 : 0;
+        }
     }
     eval_queue<KER>(a, tab, L, qn, lane);
     wave_sync();
