@@ -36,6 +36,7 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--safety", type=float, default=2.0)
     ap.add_argument("--seed", type=int, default=5000)
+    ap.add_argument("--nrc", type=float, default=0.0, help="expected sources within rc (0: the paper's table)")
     ap.add_argument("--cpu-sample", type=int, default=24, help="targets in the oracle sample (0: skip)")
     return ap.parse_args()
 
@@ -88,7 +89,7 @@ def main():
     f = torch.tensor(s["f"], device=dev)
     Q = float(np.sum(s["f"] ** 2))
     plan = se.Plan(kernel="stokeslet", periodicity=3, box=(1.0, 1.0, 1.0), tol=args.tol, tol_kind=se.TOL_REL,
-                   n_src=n, source_q=Q, safety=args.safety, precision=se.PREC_FP64)
+                   n_src=n, source_q=Q, safety=args.safety, precision=se.PREC_FP64, n_rc=args.nrc)
     par = plan.params
     u = torch.empty((n, 3), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
@@ -166,7 +167,7 @@ def main():
         "config": {"workload": "triply periodic stokeslet, unit cube, N=1e6 uniform sources = targets, "
                                "f~N(0,1)^3 zero mean, tol 1e-8 rms-rel (plain analytic parameters, 1 rhs, FP64)",
                    "form": "plain", "xi": round(par["xi"], 4), "rc": round(par["rc"], 5), "M": par["M"],
-                   "P": par["P"], "safety": args.safety},
+                   "P": par["P"], "safety": args.safety, "n_rc": args.nrc or 400.0},
         "phases_ms": {k: round(v, 4) for k, v in per_launch.items()},
         "roofline": roof,
         "cpu_baseline": cpu,

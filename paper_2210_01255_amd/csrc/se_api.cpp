@@ -39,7 +39,7 @@ void free_all(se_plan* p)
     void* ptrs[] = {p->d_flags, p->d_src, p->d_nrm, p->d_src_perm, p->d_src_start, p->d_tgt, p->d_tgt_perm,
                     p->d_tgt_start, p->d_keys_a, p->d_keys_b, p->d_vals_a, p->d_sort_tmp, p->d_fs, p->d_fs64,
                     p->d_red, p->d_grid, p->d_spec, p->d_uF, p->d_uR, p->d_pkb, p->d_invw2, p->d_tw,
-                    p->d_pos4, p->d_tpos4, p->d_str4, p->d_nrm4, p->d_rtab};
+                    p->d_pos4, p->d_tpos4, p->d_str4, p->d_nrm4, p->d_rtab, p->d_ktab};
     for (void* q : ptrs)
         if (q) hipFree(q);
 }
@@ -59,6 +59,29 @@ se_status check_hip(se_plan* p, hipError_t e, const char* what)
 }
 
 }  // namespace
+
+// Twiddle tables e^{-2 pi i k/N} (complex FP64, interleaved) for the R2C axis
+// (length N0/2, and the split factors for k = 0..N0/2) and the y and z axes.
+void se_fft_twiddles(const int* N, std::vector<double>* tw, int* off)
+{
+    tw->clear();
+    const int Nh = N[0] / 2;
+    auto push_table = [&](int n, int count) {
+        for (int k = 0; k < count; k++) {
+            long double ang = -2.0L * 3.141592653589793238462643383279502884L * k / n;
+            tw->push_back((double)std::cos(ang));
+            tw->push_back((double)std::sin(ang));
+        }
+    };
+    off[0] = 0;
+    push_table(Nh, Nh);
+    off[1] = Nh;
+    push_table(N[0], Nh + 1);
+    off[2] = 2 * Nh + 1;
+    push_table(N[1], N[1]);
+    off[3] = 2 * Nh + 1 + N[1];
+    push_table(N[2], N[2]);
+}
 
 extern "C" {
 
@@ -130,7 +153,7 @@ se_status se_plan_create(const se_problem* prob, const se_params* manual, se_pla
     p->tas = prob->targets_are_sources != 0;
     p->nt = p->tas ? prob->n_src : prob->n_tgt;
 
-    if (p->D != 3) {
+    if (p->D == 1 || p->D == 2) {
         delete p;
         return SE_ERR_UNSUPPORTED;
     }
@@ -178,6 +201,12 @@ se_status se_plan_create(const se_problem* prob, const se_params* manual, se_pla
     bool ok = (p->Nfft[0] % 2 == 0) && se_smooth_factors(p->Nfft[0] / 2, &rr) && p->Nfft[0] / 2 <= SE_FFT_LDS_ELEMS &&
               se_smooth_factors(p->Nfft[1], &rr) && p->Nfft[1] <= SE_FFT_LDS_ELEMS &&
               se_smooth_factors(p->Nfft[2], &rr) && p->ncomp * p->Nfft[2] <= (p->fp32 ? 6144 : 3072);
+    if (ok && p->D == 0) {
+        const int* n0 = p->par.n0_fft;
+        ok = (n0[0] % 2 == 0) && se_smooth_factors(n0[0] / 2, &rr) && n0[0] / 2 <= SE_FFT_LDS_ELEMS &&
+             se_smooth_factors(n0[1], &rr) && n0[1] <= SE_FFT_LDS_ELEMS && se_smooth_factors(n0[2], &rr) &&
+             n0[2] <= SE_FFT_LDS_ELEMS;
+    }
     if (!ok) {
         delete p;
         return SE_ERR_UNSUPPORTED;
@@ -208,7 +237,7 @@ se_status se_plan_create(const se_problem* prob, const se_params* manual, se_pla
     p->d_sort_tmp = A.get<char>(std::max<size_t>(p->sort_tmp_bytes, 256));
     p->d_fs = A.get<char>((size_t)p->ncomp * p->ns * rs);
     p->d_fs64 = A.get<double>(4 * p->ns);
-    p->d_red = A.get<double>(4);
+    p->d_red = A.get<double>(8);
     const size_t gv = (size_t)g.Mg[0] * g.Mg[1] * g.Mg[2];
     p->d_grid = A.get<char>((size_t)p->ncomp * gv * rs);
     const size_t sv = (size_t)p->Hx * p->Nfft[1] * g.Mg[2];
@@ -218,6 +247,7 @@ se_status se_plan_create(const se_problem* prob, const se_params* manual, se_pla
     p->d_str4 = A.get<double>(4 * p->ns);
     if (p->kernel == SE_STRESSLET) p->d_nrm4 = A.get<double>(4 * p->ns);
     p->d_rtab = A.get<double>((size_t)2 * SE_RTAB_N * (SE_RTAB_DEG + 1));
+    if (p->D == 0) p->d_ktab = A.get<double>((size_t)p->Hx * p->Nfft[1] * p->Nfft[2]);
     p->d_uF = A.get<double>(3 * p->nt);
     p->d_uR = A.get<double>(3 * p->nt);
     p->d_pkb = A.get<double>((size_t)par.P * (par.nu_deg + 1));
@@ -250,34 +280,27 @@ se_status se_plan_create(const se_problem* prob, const se_params* manual, se_pla
     std::vector<double> rtab;
     se_radial_table(&rtab);
     std::vector<double> tw;
-    tw.reserve(2 * ntw);
-    auto push_table = [&](int N, int count) {
-        for (int k = 0; k < count; k++) {
-            long double ang = -2.0L * 3.141592653589793238462643383279502884L * k / N;
-            tw.push_back((double)std::cos(ang));
-            tw.push_back((double)std::sin(ang));
-        }
-    };
-    p->tw_off[0] = 0;
-    push_table(Nh, Nh);
-    p->tw_off[1] = Nh;
-    push_table(p->Nfft[0], Nh + 1);
-    p->tw_off[2] = 2 * Nh + 1;
-    push_table(p->Nfft[1], p->Nfft[1]);
-    p->tw_off[3] = 2 * Nh + 1 + p->Nfft[1];
-    push_table(p->Nfft[2], p->Nfft[2]);
+    se_fft_twiddles(p->Nfft, &tw, p->tw_off);
 
     hipError_t e = hipMemcpy(p->d_pkb, pkb.data(), pkb.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p->d_invw2, iw.data(), iw.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p->d_tw, tw.data(), tw.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p->d_rtab, rtab.data(), rtab.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(p->d_flags, 0, sizeof(int));
-    if (e == hipSuccess) e = hipMemset(p->d_red, 0, 4 * sizeof(double));
+    if (e == hipSuccess) e = hipMemset(p->d_red, 0, 8 * sizeof(double));
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         free_all(p);
         delete p;
         return SE_ERR_HIP;
+    }
+    if (p->D == 0) {
+        se_status st0 = se_d0_precompute(p);
+        if (st0 != SE_OK) {
+            free_all(p);
+            delete p;
+            return st0;
+        }
     }
     *out = p;
     return SE_OK;

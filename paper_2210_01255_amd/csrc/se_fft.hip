@@ -42,6 +42,7 @@ struct se_fft_args {
     double scale;    // h1 h2 h3 / (N1 N2 N3)
     const double* invw2;  // 1/what0^2: [Hx | N1 | N2] per axis
     int iw_off[3];
+    const double* ktab;   // D = 0: precomputed truncated kernel on the half spectrum [z][y][x]
 };
 
 template <typename R>
@@ -342,65 +343,110 @@ __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_y(se_fft_args a, int dir
     }
 }
 
-// ------------------------------------------------ scaling (triply periodic)
-// Multiplier of eq. (SE-scaling-disc) with the D = 3 kernels of
-// eq. (mod-kernel-3p) (zero at k = 0) and the Fourier kernels
-// eqs. (stokeslet-fourier), (rotlet-fourier), (stresslet-fourier):
-//   S: u = c_H (k^2 F - k (k.F)),                 c_H = 8 pi gH / k^4
-//   Omega: u = -i (4 pi gE / k^2) (F x k)
-//   T: u = i c_H (k^2 (2 F k + k tr F) - 2 k (k^T F k)), F symmetric
-// times 1/what(k)^2 and the trapezoid/FFT normalisation.  Odd kernels are
-// set to zero on Nyquist indices (the real part of a non-Hermitian mode).
+// ------------------------------------------------------------------ scaling
+// Step (iii), eq. (SE-scaling-disc): multiply by Ghat_R(k) gammahat(k;xi) /
+// what(k)^2 and the trapezoid/FFT normalisation h1 h2 h3/(N1 N2 N3).  With
+// Ghat = Khat Ahat (eqs. diffop-rel-fourier-1..3) and the scalar Ahat the
+// biharmonic Bhat (stokeslet, stresslet) or harmonic Hhat (rotlet):
+//   S:     u = c (-k^2 F + k (k.F)),                      c = Bhat gH W
+//   Omega: u = -i c (F x k),                              c = Hhat gE W
+//   T:     u = i c (-k^2 (2 F k + k tr F) + 2 k (k^T F k)), c = Bhat gH W
+// (F symmetric for T).  Ahat is -8 pi/k^4 or 4 pi/k^2 for D = 3 with the
+// k = 0 mode set to zero (eq. mod-kernel-3p), and the precomputed truncated
+// kernel Ahat_{R,tr} for D = 0 (Sec. 3.5).  Odd kernels are zero on Nyquist
+// indices (the real part of a non-Hermitian mode).
+template <int KER>
+__device__ __forceinline__ double green_scalar(const se_fft_args& a, int ix, int iy, int iz, double k2)
+{
+    if (a.D == 0) return a.ktab[((int64_t)iz * a.N[1] + iy) * a.Hx + ix];
+    if (k2 == 0.0) return 0.0;
+    return KER == SE_ROTLET ? 4.0 * M_PI / k2 : -8.0 * M_PI / (k2 * k2);
+}
+
 template <typename R, int KER, int NC>
 __device__ __forceinline__ void scale_point(const se_fft_args& a, int ix, int iy, int iz, C<R>* F, C<R>* U)
 {
     const int kb[3] = {ix, iy < a.N[1] / 2 ? iy : iy - a.N[1], iz < a.N[2] / 2 ? iz : iz - a.N[2]};
     const double k[3] = {a.kfac[0] * kb[0], a.kfac[1] * kb[1], a.kfac[2] * kb[2]};
     const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
-    bool nyq = (2 * ix == a.N[0]) || (2 * iy == a.N[1]) || (2 * iz == a.N[2]);
-    if (k2 == 0.0 || (KER != SE_STOKESLET && nyq)) {
+    const bool nyq = (2 * ix == a.N[0]) || (2 * iy == a.N[1]) || (2 * iz == a.N[2]);
+    const double G = green_scalar<KER>(a, ix, iy, iz, k2);
+    if (G == 0.0 || (KER != SE_STOKESLET && nyq)) {
         U[0] = U[1] = U[2] = {(R)0, (R)0};
         return;
     }
     const double e = k2 / (4.0 * a.xi * a.xi);
     const double gE = exp(-e);
     const double iw = a.invw2[a.iw_off[0] + ix] * a.invw2[a.iw_off[1] + iy] * a.invw2[a.iw_off[2] + iz];
-    const double base = a.scale * iw;
+    const double W = a.scale * iw;
+    const R kr[3] = {(R)k[0], (R)k[1], (R)k[2]};
+    const R kk = (R)k2;
     if constexpr (KER == SE_STOKESLET) {
-        const R c = (R)(base * 8.0 * M_PI * gE * (1.0 + e) / (k2 * k2));
-        const R kr[3] = {(R)k[0], (R)k[1], (R)k[2]};
-        const R kk = (R)k2;
+        const R c = (R)(G * gE * (1.0 + e) * W);
         C<R> kf = {kr[0] * F[0].x + kr[1] * F[1].x + kr[2] * F[2].x, kr[0] * F[0].y + kr[1] * F[1].y + kr[2] * F[2].y};
 #pragma unroll
-        for (int j = 0; j < 3; j++) U[j] = {c * (kk * F[j].x - kr[j] * kf.x), c * (kk * F[j].y - kr[j] * kf.y)};
+        for (int j = 0; j < 3; j++) U[j] = {c * (kr[j] * kf.x - kk * F[j].x), c * (kr[j] * kf.y - kk * F[j].y)};
     } else if constexpr (KER == SE_ROTLET) {
-        const R c = (R)(base * 4.0 * M_PI * gE / k2);
-        const R kr[3] = {(R)k[0], (R)k[1], (R)k[2]};
-        // w = F x k
-        C<R> w[3];
+        const R c = (R)(G * gE * W);
+        C<R> w[3];  // F x k
         w[0] = {F[1].x * kr[2] - F[2].x * kr[1], F[1].y * kr[2] - F[2].y * kr[1]};
         w[1] = {F[2].x * kr[0] - F[0].x * kr[2], F[2].y * kr[0] - F[0].y * kr[2]};
         w[2] = {F[0].x * kr[1] - F[1].x * kr[0], F[0].y * kr[1] - F[1].y * kr[0]};
-        // U = -i c w
 #pragma unroll
-        for (int j = 0; j < 3; j++) U[j] = {c * w[j].y, -c * w[j].x};
+        for (int j = 0; j < 3; j++) U[j] = {c * w[j].y, -c * w[j].x};  // -i c w
     } else {
-        const R c = (R)(base * 8.0 * M_PI * gE * (1.0 + e) / (k2 * k2));
-        const R kr[3] = {(R)k[0], (R)k[1], (R)k[2]};
-        const R kk = (R)k2;
+        const R c = (R)(G * gE * (1.0 + e) * W);
         // symmetric F: 0 xx, 1 yy, 2 zz, 3 xy, 4 xz, 5 yz
         C<R> Fk[3];
         Fk[0] = {F[0].x * kr[0] + F[3].x * kr[1] + F[4].x * kr[2], F[0].y * kr[0] + F[3].y * kr[1] + F[4].y * kr[2]};
         Fk[1] = {F[3].x * kr[0] + F[1].x * kr[1] + F[5].x * kr[2], F[3].y * kr[0] + F[1].y * kr[1] + F[5].y * kr[2]};
         Fk[2] = {F[4].x * kr[0] + F[5].x * kr[1] + F[2].x * kr[2], F[4].y * kr[0] + F[5].y * kr[1] + F[2].y * kr[2]};
         C<R> tr = {F[0].x + F[1].x + F[2].x, F[0].y + F[1].y + F[2].y};
-        C<R> kFk = {kr[0] * Fk[0].x + kr[1] * Fk[1].x + kr[2] * Fk[2].x, kr[0] * Fk[0].y + kr[1] * Fk[1].y + kr[2] * Fk[2].y};
+        C<R> kFk = {kr[0] * Fk[0].x + kr[1] * Fk[1].x + kr[2] * Fk[2].x,
+                    kr[0] * Fk[0].y + kr[1] * Fk[1].y + kr[2] * Fk[2].y};
 #pragma unroll
         for (int j = 0; j < 3; j++) {
-            C<R> v = {kk * (2 * Fk[j].x + kr[j] * tr.x) - 2 * kr[j] * kFk.x,
-                      kk * (2 * Fk[j].y + kr[j] * tr.y) - 2 * kr[j] * kFk.y};
+            C<R> v = {2 * kr[j] * kFk.x - kk * (2 * Fk[j].x + kr[j] * tr.x),
+                      2 * kr[j] * kFk.y - kk * (2 * Fk[j].y + kr[j] * tr.y)};
             U[j] = {-c * v.y, c * v.x};  // i c v
         }
+    }
+}
+
+// Plain complex transform along z (no scaling) for `ncomp` components.
+template <typename R, int ELEMS>
+__global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_z(se_fft_args a, int dir)
+{
+    extern __shared__ double smem_d[];
+    const int Nz = a.N[2];
+    C<R>* tw = (C<R>*)smem_d;
+    C<R>* buf = tw + Nz;
+    load_tw(tw, a.tw + 2 * a.tw_z, Nz);
+    const int Cc = a.cols;
+    const int nbx = (a.Hx + Cc - 1) / Cc;
+    const int bx = blockIdx.x % nbx;
+    const int rest = blockIdx.x / nbx;
+    const int y = rest % a.N[1];
+    const int c = rest / a.N[1];
+    const int kx0 = bx * Cc;
+    const int Mz = a.Mg[2];
+    const int64_t zstride = (int64_t)a.N[1] * a.Hx;
+    C<R>* spec = (C<R>*)a.spec + (int64_t)c * Mz * zstride;
+    const int n_in = dir > 0 ? Mz : Nz;
+    const int n_out = dir > 0 ? Nz : Mz;
+    for (int i = threadIdx.x; i < Nz * Cc; i += blockDim.x) {
+        int z = i / Cc, col = i - z * Cc;
+        int kx = kx0 + col;
+        C<R> v = {(R)0, (R)0};
+        if (kx < a.Hx && z < n_in && z < Mz) v = spec[z * zstride + (int64_t)y * a.Hx + kx];
+        buf[i] = v;
+    }
+    __syncthreads();
+    fft_lines<R, ELEMS>(buf, Nz, Cc, Cc, 0, 1, Cc, true, tw, dir, a.rad_z, a.nrad_z);
+    for (int i = threadIdx.x; i < n_out * Cc; i += blockDim.x) {
+        int z = i / Cc, col = i - z * Cc;
+        int kx = kx0 + col;
+        if (kx < a.Hx && z < Mz) spec[z * zstride + (int64_t)y * a.Hx + kx] = buf[i];
     }
 }
 
@@ -457,67 +503,108 @@ __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_z_scale(se_fft_args a)
 template <typename R>
 constexpr int z_elems() { return sizeof(R) == 8 ? 3072 : 6144; }
 
-se_fft_args make_fft_args(const se_plan* p, int ncomp)
+void set_radices(int n, int* dst, int* cnt)
+{
+    std::vector<int> r;
+    se_smooth_factors(n, &r);
+    *cnt = (int)r.size();
+    for (size_t i = 0; i < r.size(); i++) dst[i] = r[i];
+}
+
+se_fft_args make_fft_args_geom(const int* Mg, const int* N, const double* h, void* grid, void* spec,
+                               const double* tw, const int* tw_off, int ncomp)
 {
     se_fft_args a;
     std::memset(&a, 0, sizeof(a));
     for (int d = 0; d < 3; d++) {
-        a.Mg[d] = p->g.Mg[d];
-        a.N[d] = p->Nfft[d];
+        a.Mg[d] = Mg[d];
+        a.N[d] = N[d];
     }
-    a.Hx = p->Hx;
+    a.Hx = N[0] / 2 + 1;
     a.ncomp = ncomp;
-    a.grid = p->d_grid;
-    a.spec = p->d_spec;
-    a.tw = p->d_tw;
-    a.tw_xh = p->tw_off[0];
-    a.tw_xp = p->tw_off[1];
-    a.tw_y = p->tw_off[2];
-    a.tw_z = p->tw_off[3];
-    std::vector<int> r;
-    se_smooth_factors(p->Nfft[0] / 2, &r);
-    a.nrad_xh = (int)r.size();
-    for (size_t i = 0; i < r.size(); i++) a.rad_xh[i] = r[i];
-    se_smooth_factors(p->Nfft[1], &r);
-    a.nrad_y = (int)r.size();
-    for (size_t i = 0; i < r.size(); i++) a.rad_y[i] = r[i];
-    se_smooth_factors(p->Nfft[2], &r);
-    a.nrad_z = (int)r.size();
-    for (size_t i = 0; i < r.size(); i++) a.rad_z[i] = r[i];
-    a.kernel = p->kernel;
-    a.D = p->D;
+    a.grid = grid;
+    a.spec = spec;
+    a.tw = tw;
+    a.tw_xh = tw_off[0];
+    a.tw_xp = tw_off[1];
+    a.tw_y = tw_off[2];
+    a.tw_z = tw_off[3];
+    set_radices(N[0] / 2, a.rad_xh, &a.nrad_xh);
+    set_radices(N[1], a.rad_y, &a.nrad_y);
+    set_radices(N[2], a.rad_z, &a.nrad_z);
     double hv = 1.0, nv = 1.0;
     for (int d = 0; d < 3; d++) {
-        a.kfac[d] = 2.0 * M_PI / (p->g.h[d] * p->Nfft[d]);
-        hv *= p->g.h[d];
-        nv *= p->Nfft[d];
+        a.kfac[d] = 2.0 * M_PI / (h[d] * N[d]);
+        hv *= h[d];
+        nv *= N[d];
     }
-    a.xi = p->par.xi;
     a.scale = hv / nv;
+    return a;
+}
+
+se_fft_args make_fft_args(const se_plan* p, int ncomp)
+{
+    se_fft_args a = make_fft_args_geom(p->g.Mg, p->Nfft, p->g.h, p->d_grid, p->d_spec, p->d_tw, p->tw_off, ncomp);
+    a.kernel = p->kernel;
+    a.D = p->D;
+    a.xi = p->par.xi;
     a.invw2 = p->d_invw2;
     a.iw_off[0] = 0;
     a.iw_off[1] = p->Hx;
     a.iw_off[2] = p->Hx + p->Nfft[1];
+    a.ktab = p->d_ktab;
     return a;
+}
+
+template <typename R>
+void run_x_r2c(se_fft_args a, int ncomp, hipStream_t s)
+{
+    const int Nh = a.N[0] / 2;
+    a.ncomp = ncomp;
+    a.lines = std::max(1, SE_FFT_LDS_ELEMS / Nh);
+    int64_t rows = (int64_t)ncomp * a.Mg[2] * a.Mg[1];
+    size_t lds = (size_t)(2 * Nh + 1 + a.lines * Nh) * sizeof(C<R>);
+    hipLaunchKernelGGL(k_fft_x_r2c<R>, dim3((unsigned)((rows + a.lines - 1) / a.lines)), dim3(SE_FFT_THREADS),
+                       lds, s, a);
+}
+
+template <typename R>
+void run_x_c2r(se_fft_args a, int ncomp, hipStream_t s)
+{
+    const int Nh = a.N[0] / 2;
+    a.ncomp = ncomp;
+    a.lines = std::max(1, SE_FFT_LDS_ELEMS / Nh);
+    int64_t rows = (int64_t)ncomp * a.Mg[2] * a.Mg[1];
+    size_t lds = (size_t)(2 * Nh + 1 + a.lines * Nh) * sizeof(C<R>);
+    hipLaunchKernelGGL(k_fft_x_c2r<R>, dim3((unsigned)((rows + a.lines - 1) / a.lines)), dim3(SE_FFT_THREADS),
+                       lds, s, a);
+}
+
+template <typename R>
+void run_y(se_fft_args a, int ncomp, int dir, hipStream_t s)
+{
+    a.cols = std::max(1, std::min(16, SE_FFT_LDS_ELEMS / a.N[1]));
+    int nbx = (a.Hx + a.cols - 1) / a.cols;
+    size_t lds = (size_t)(a.N[1] + a.cols * a.N[1]) * sizeof(C<R>);
+    hipLaunchKernelGGL(k_fft_y<R>, dim3((unsigned)(nbx * ncomp * a.Mg[2])), dim3(SE_FFT_THREADS), lds, s, a, dir);
+}
+
+template <typename R>
+void run_z_plain(se_fft_args a, int ncomp, int dir, hipStream_t s)
+{
+    a.cols = std::max(1, std::min(16, SE_FFT_LDS_ELEMS / a.N[2]));
+    int nbx = (a.Hx + a.cols - 1) / a.cols;
+    size_t lds = (size_t)(a.N[2] + a.cols * a.N[2]) * sizeof(C<R>);
+    hipLaunchKernelGGL((k_fft_z<R, SE_FFT_LDS_ELEMS>), dim3((unsigned)(nbx * a.N[1] * ncomp)), dim3(SE_FFT_THREADS),
+                       lds, s, a, dir);
 }
 
 template <typename R>
 void launch_fwd(const se_plan* p, hipStream_t s)
 {
-    // x pass
     se_fft_args a = make_fft_args(p, p->ncomp);
-    const int Nh = p->Nfft[0] / 2;
-    a.lines = std::max(1, SE_FFT_LDS_ELEMS / Nh);
-    int64_t rows = (int64_t)p->ncomp * p->g.Mg[2] * p->g.Mg[1];
-    size_t lds = (size_t)(2 * Nh + 1 + a.lines * Nh) * sizeof(C<R>);
-    hipLaunchKernelGGL(k_fft_x_r2c<R>, dim3((unsigned)((rows + a.lines - 1) / a.lines)), dim3(SE_FFT_THREADS),
-                       lds, s, a);
-    // y pass
-    a.cols = std::max(1, std::min(16, SE_FFT_LDS_ELEMS / p->Nfft[1]));
-    int nbx = (p->Hx + a.cols - 1) / a.cols;
-    lds = (size_t)(p->Nfft[1] + a.cols * p->Nfft[1]) * sizeof(C<R>);
-    hipLaunchKernelGGL(k_fft_y<R>, dim3((unsigned)(nbx * p->ncomp * p->g.Mg[2])), dim3(SE_FFT_THREADS), lds, s, a,
-                       1);
+    run_x_r2c<R>(a, p->ncomp, s);
+    run_y<R>(a, p->ncomp, 1, s);
 }
 
 template <typename R, int KER, int NC>
@@ -537,16 +624,8 @@ template <typename R>
 void launch_inv(const se_plan* p, hipStream_t s)
 {
     se_fft_args a = make_fft_args(p, 3);
-    a.cols = std::max(1, std::min(16, SE_FFT_LDS_ELEMS / p->Nfft[1]));
-    int nbx = (p->Hx + a.cols - 1) / a.cols;
-    size_t lds = (size_t)(p->Nfft[1] + a.cols * p->Nfft[1]) * sizeof(C<R>);
-    hipLaunchKernelGGL(k_fft_y<R>, dim3((unsigned)(nbx * 3 * p->g.Mg[2])), dim3(SE_FFT_THREADS), lds, s, a, -1);
-    const int Nh = p->Nfft[0] / 2;
-    a.lines = std::max(1, SE_FFT_LDS_ELEMS / Nh);
-    int64_t rows = (int64_t)3 * p->g.Mg[2] * p->g.Mg[1];
-    lds = (size_t)(2 * Nh + 1 + a.lines * Nh) * sizeof(C<R>);
-    hipLaunchKernelGGL(k_fft_x_c2r<R>, dim3((unsigned)((rows + a.lines - 1) / a.lines)), dim3(SE_FFT_THREADS),
-                       lds, s, a);
+    run_y<R>(a, 3, -1, s);
+    run_x_c2r<R>(a, 3, s);
 }
 
 template <typename R>
@@ -575,4 +654,23 @@ void se_launch_fft_inverse(const se_plan* p, hipStream_t s)
 {
     if (p->fp32) launch_inv<float>(p, s);
     else launch_inv<double>(p, s);
+}
+
+// FP64 3-D transform of ncomp components on an arbitrary grid:
+// dir > 0: real grid [c][Mg2][Mg1][Mg0] (zero padded to N) -> half spectrum
+// [c][Mg2][N1][N0/2+1] with z transformed in place over N2 (requires Mg2 == N2);
+// dir < 0: the reverse (C2R, truncated to Mg).  Unnormalised.
+void se_fft3d_f64(const int* Mg, const int* N, const double* h, double* grid, double* spec, const double* tw,
+                  const int* tw_off, int ncomp, int dir, hipStream_t s)
+{
+    se_fft_args a = make_fft_args_geom(Mg, N, h, grid, spec, tw, tw_off, ncomp);
+    if (dir > 0) {
+        run_x_r2c<double>(a, ncomp, s);
+        run_y<double>(a, ncomp, 1, s);
+        run_z_plain<double>(a, ncomp, 1, s);
+    } else {
+        run_z_plain<double>(a, ncomp, -1, s);
+        run_y<double>(a, ncomp, -1, s);
+        run_x_c2r<double>(a, ncomp, s);
+    }
 }

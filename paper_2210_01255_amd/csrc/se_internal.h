@@ -94,6 +94,7 @@ struct se_plan {
     double* d_str4 = nullptr;      // sorted strengths AoS [ns][4] (f or q, 0)
     double* d_nrm4 = nullptr;      // sorted normals AoS [ns][4] (stresslet)
     double* d_rtab = nullptr;      // radial-function table
+    double* d_ktab = nullptr;      // D = 0: truncated kernel Ahat_{R,tr} on the half spectrum
     double* d_uF = nullptr;        // [3][nt] sorted order
     double* d_uR = nullptr;        // [3][nt]
     double* d_pkb = nullptr;       // PKB coefficients [P][nu+1]
@@ -136,5 +137,9 @@ void se_launch_fft_inverse(const se_plan* p, hipStream_t s);
 void se_launch_gather(const se_plan* p, hipStream_t s);
 void se_launch_real_space(const se_plan* p, hipStream_t s);
 void se_launch_reductions(const se_plan* p, hipStream_t s);
+void se_fft3d_f64(const int* Mg, const int* N, const double* h, double* grid, double* spec, const double* tw,
+                  const int* tw_off, int ncomp, int dir, hipStream_t s);
+void se_fft_twiddles(const int* N, std::vector<double>* tw, int* off);
+se_status se_d0_precompute(se_plan* p);
 void se_launch_finalize(const se_plan* p, const double* f, double* u, double* u_real,
                         double* u_fourier, hipStream_t s);

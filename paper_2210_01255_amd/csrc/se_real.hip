@@ -334,31 +334,33 @@ __global__ void k_strengths(const double* __restrict__ f, const int* __restrict_
     }
 }
 
-// Deterministic single-workgroup reductions for the stresslet zero-mode term:
-// out[0] = sum_n q_n.nu_n, out[1..3] = sum_n x_n (q_n.nu_n).
-__global__ void __launch_bounds__(1024) k_reduce_qn(const double* __restrict__ qn, const double* __restrict__ xs,
-                                                    int64_t n, double* out)
+// Deterministic single-workgroup FP64 reductions over the sources:
+// out[0] = sum q.nu, out[1..3] = sum x (q.nu) (stresslet zero-mode term,
+// eq. k0-stresslet-3p), out[4..6] = sum f (gauge terms of the stokeslet).
+__global__ void __launch_bounds__(512) k_reduce_sources(const double* __restrict__ qn, const double* __restrict__ f,
+                                                        const double* __restrict__ xs, int64_t n, int have_qn,
+                                                        double* out)
 {
-    __shared__ double sm[4][1024];
-    double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-    for (int64_t i = threadIdx.x; i < n; i += 1024) {
-        double q = qn[i];
-        a0 += q;
-        a1 += xs[i] * q;
-        a2 += xs[n + i] * q;
-        a3 += xs[2 * n + i] * q;
+    __shared__ double sm[7][512];
+    double a[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int64_t i = threadIdx.x; i < n; i += 512) {
+        double q = have_qn ? qn[i] : 0.0;
+        a[0] += q;
+        a[1] += xs[i] * q;
+        a[2] += xs[n + i] * q;
+        a[3] += xs[2 * n + i] * q;
+        a[4] += f[i];
+        a[5] += f[n + i];
+        a[6] += f[2 * n + i];
     }
-    sm[0][threadIdx.x] = a0;
-    sm[1][threadIdx.x] = a1;
-    sm[2][threadIdx.x] = a2;
-    sm[3][threadIdx.x] = a3;
+    for (int c = 0; c < 7; c++) sm[c][threadIdx.x] = a[c];
     __syncthreads();
-    for (int w = 512; w > 0; w >>= 1) {
+    for (int w = 256; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w)
-            for (int c = 0; c < 4; c++) sm[c][threadIdx.x] += sm[c][threadIdx.x + w];
+            for (int c = 0; c < 7; c++) sm[c][threadIdx.x] += sm[c][threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x < 4) out[threadIdx.x] = sm[threadIdx.x][0];
+    if (threadIdx.x < 7) out[threadIdx.x] = sm[threadIdx.x][0];
 }
 
 struct se_fin_args {
@@ -371,6 +373,7 @@ struct se_fin_args {
     const double* red;    // stresslet sums
     double self_c;        // -4 xi/sqrt(pi) (stokeslet, targets are sources) or 0
     double k0_c;          // -8 pi/|B| (D = 3 stresslet) or 0
+    double gauge[3];      // constant added per component times sum f (stokeslet gauges)
     double* u;            // [nt][3] caller order (or null)
     double* u_real;
     double* u_four;
@@ -386,6 +389,7 @@ __global__ void k_finalize(se_fin_args a)
         double uf = a.uF[j * a.nt + t];
         if (a.self_c != 0.0) uf += a.self_c * a.f64[j * a.nt + t];
         if (a.k0_c != 0.0) uf += a.k0_c * (a.xt[j * a.nt + t] * a.red[0] - a.red[1 + j]);
+        uf += a.gauge[j] * a.red[4 + j];
         if (a.u) a.u[3 * o + j] = ur + uf;
         if (a.u_real) a.u_real[3 * o + j] = ur;
         if (a.u_four) a.u_four[3 * o + j] = uf;
@@ -410,8 +414,8 @@ void se_launch_strengths(const se_plan* p, const double* f, hipStream_t s)
 
 void se_launch_reductions(const se_plan* p, hipStream_t s)
 {
-    if (p->kernel == SE_STRESSLET && p->D == 3)
-        hipLaunchKernelGGL(k_reduce_qn, dim3(1), dim3(1024), 0, s, p->d_fs64 + 3 * p->ns, p->d_src, p->ns, p->d_red);
+    hipLaunchKernelGGL(k_reduce_sources, dim3(1), dim3(512), 0, s, p->d_fs64 + 3 * p->ns, p->d_fs64, p->d_src, p->ns,
+                       p->kernel == SE_STRESSLET ? 1 : 0, p->d_red);
 }
 
 void se_launch_real_space(const se_plan* p, hipStream_t s)
@@ -453,6 +457,11 @@ void se_launch_finalize(const se_plan* p, const double* f, double* u, double* u_
     a.red = p->d_red;
     a.self_c = (p->kernel == SE_STOKESLET && p->tas) ? -4.0 * p->par.xi / kSqrtPi : 0.0;
     a.k0_c = (p->kernel == SE_STRESSLET && p->D == 3) ? -8.0 * M_PI / (p->g.L[0] * p->g.L[1] * p->g.L[2]) : 0.0;
+    // D = 0 stokeslet: the optimal biharmonic b_B = -1/(2R) adds 4 b_B sum f
+    // (eq. 0p-stokeslet-extra-contribution); remove it so u decays at infinity.
+    for (int j = 0; j < 3; j++) a.gauge[j] = 0.0;
+    if (p->D == 0 && p->kernel == SE_STOKESLET)
+        for (int j = 0; j < 3; j++) a.gauge[j] = 2.0 / p->par.R;
     a.u = u;
     a.u_real = u_real;
     a.u_four = u_fourier;

@@ -224,3 +224,33 @@ def test_full_size_metric_config_sampled(env):
     err = oracle.rms_rel_error(u[idx], ref.total)
     print("full-size sampled rel err", err)
     assert err <= 1e-8
+
+
+# ------------------------------------------------------- D = 0 (free space)
+@pytest.mark.parametrize("kernel", ["stokeslet", "rotlet", "stresslet"])
+@pytest.mark.parametrize("tol", [1e-6, 1e-10])
+def test_free_space_matches_direct_sum(env, kernel, tol):
+    """Sec. 3.5 precomputed truncated kernels + 2x zero padding vs the direct sum
+    of eq. (periodic-potential) with p = 0 (the D = 0 definition)."""
+    _, oracle, _ = env
+    s = W.system(2000 + int(-np.log10(tol)), 1500, kernel=kernel)
+    _, u = _run(env, kernel, s, D=0, tol=tol)
+    err = oracle.rms_rel_error(u, _ref(env, kernel, s, D=0))
+    print("D=0", kernel, tol, "rel err", err)
+    assert err <= tol
+
+
+@pytest.mark.parametrize("kernel", ["stokeslet", "rotlet", "stresslet"])
+def test_free_space_box_aspect_and_targets(env, kernel):
+    """Elongated box (R from the diagonal, per-axis s0 M' rounding) and
+    off-source targets; the stokeslet with nonzero net force checks the
+    removal of the 4 b_B sum f gauge term (eq. 0p-stokeslet-extra-contribution)."""
+    _, oracle, _ = env
+    s = W.system(2100, 1200, box=(2.0, 1.0, 0.7), kernel=kernel)
+    if kernel != "stresslet":
+        s["f"] += 0.7  # net force
+    tg = W.uniform_points(W.rng(2101), 500, s["box"])
+    _, u = _run(env, kernel, s, D=0, tol=1e-8, targets=tg)
+    err = oracle.rms_rel_error(u, _ref(env, kernel, s, D=0, targets=tg))
+    print("D=0 aspect", kernel, "rel err", err)
+    assert err <= 1e-8
