@@ -11,7 +11,11 @@ What it computes (Bagge & Tornberg, Sec. 2):
     (k0-stresslet-3p) + self term (self-term);
   * D = 0: the free-space sum (periodic-potential) with the single image p=0,
     summed directly;
-  * D = 2, 1: see ``reduced.py`` (Appendices A and B).
+  * D = 2, 1: real part with images in the periodic directions only, the
+    nonsingular modes k^P != 0 of (2p-fourier-space) / (1p-fourier-space) by
+    the trapezoidal rule in the free wavenumbers (``virtual_cell``), and the
+    singular modes k^P = 0 in the closed forms of Appendices A.2 and B.2
+    (``reduced_oracle.c``), reported as 'k0'.
 
 The oracle chooses its own splitting parameter xi_o and truncations from a
 cost balance and a fixed damping margin (erfc(xi rc) and exp(-k^2/4xi^2)
@@ -76,9 +80,12 @@ def lib():
         L.oracle_free_kernel.restype = None
         L.oracle_real_kernel.argtypes = [i, d, dp, dp, dp, dp]
         L.oracle_real_kernel.restype = None
-        if hasattr(L, "oracle_reduced_fourier_part"):
-            L.oracle_reduced_fourier_part.argtypes = [i, i, dp, d, i, l, dp, dp, dp, l, dp, dp]
-            L.oracle_reduced_fourier_part.restype = l
+        L.oracle_reduced_fourier_part.argtypes = [i, i, dp, d, d, l, dp, dp, dp, l, dp, dp]
+        L.oracle_reduced_fourier_part.restype = l
+        L.oracle_zero_mode.argtypes = [i, i, dp, d, l, dp, dp, dp, l, dp, dp]
+        L.oracle_zero_mode.restype = None
+        L.oracle_e1.argtypes = [d]
+        L.oracle_e1.restype = d
         _lib = L
     return _lib
 
@@ -122,11 +129,13 @@ def real_kernel(kernel, xi, r, f, nu=None):
 
 
 class Parts(dict):
-    """Named contributions of one oracle evaluation (all [nt][3] arrays)."""
+    """Named contributions of one oracle evaluation plus scalar diagnostics."""
+
+    PARTS = ("real", "fourier", "k0", "self", "direct")
 
     @property
     def total(self):
-        return sum(v for k, v in self.items() if isinstance(v, np.ndarray) and k != "total")
+        return sum(self[k] for k in self.PARTS if k in self)
 
 
 def choose_xi(n_src, n_tgt, box, margin=6.0):
@@ -188,13 +197,18 @@ def ewald(D, kernel, box, x, f=None, q=None, nu=None, targets=None, self_src=Non
         nk = L.oracle_fourier_part_3p(kid, _d(box), float(xi), float(kmax), ns, _d(x), _d(a),
                                       _d(b) if b is not None else None, nt, _d(xt), _d(uf))
     else:
-        from . import reduced  # noqa: F401  (D = 1, 2: Appendices A, B)
-        nk = reduced.fourier_part(L, D, kid, box, float(xi), margin, x, a, b, xt, uf)
+        Lv = virtual_cell(D, box)
+        nk = L.oracle_reduced_fourier_part(D, kid, _d(Lv), float(xi), float(kmax), ns, _d(x), _d(a),
+                                           _d(b) if b is not None else None, nt, _d(xt), _d(uf))
+        out["virtual_cell"] = tuple(float(v) for v in Lv)
     out["fourier"] = uf
     out["n_k"] = int(nk)
     u0 = np.zeros((nt, 3))
     if D == 3 and kernel == "stresslet":
         L.oracle_k0_stresslet_3p(_d(box), ns, _d(x), _d(a), _d(b), nt, _d(xt), _d(u0))
+    elif D in (1, 2):
+        L.oracle_zero_mode(D, kid, _d(box), float(xi), ns, _d(x), _d(a), _d(b) if b is not None else None,
+                           nt, _d(xt), _d(u0))
     out["k0"] = u0
     us = np.zeros((nt, 3))
     if self_src is not None:
@@ -202,6 +216,29 @@ def ewald(D, kernel, box, x, f=None, q=None, nu=None, targets=None, self_src=Non
     out["self"] = us
     out["xi"] = float(xi)
     return out
+
+
+def virtual_cell(D, box, decay=7.0):
+    """Period P_v of the trapezoidal rule in the free directions (D = 2, 1).
+
+    For a mode with k^P != 0 the integrand over the free wavenumbers is
+    analytic in a strip of half-width |k^P| >= 2 pi / max(L_periodic), so the
+    trapezoidal rule with step 2 pi / P_v is in error by about
+    exp(-2 pi (P_v - extent) / max(L_periodic)); decay = 7 puts that below
+    e^{-43}.
+    """
+    box = np.asarray(box, dtype=np.float64)
+    lp = float(np.max(box[:D]))
+    ext = float(np.max(box[D:]))
+    pv = ext + decay * lp
+    Lv = box.copy()
+    Lv[D:] = pv
+    return np.ascontiguousarray(Lv)
+
+
+def e1(x):
+    """Exponential integral E1 as implemented in the oracle (pinned in tests)."""
+    return float(lib().oracle_e1(float(x)))
 
 
 def image_block_sum(D, kernel, box, x, f=None, q=None, nu=None, targets=None, self_src=None, K=10):

@@ -217,7 +217,7 @@ static void fourier_kernel_apply(int kernel, double xi, const double *k,
 }
 
 /* Enumerate k-bar in a half space with 0 < |k| <= kmax; k = 2 pi kbar_i / L_i. */
-static long list_halfspace_k(const double *L, double kmax, int *Kb, int **out)
+static long list_halfspace_k(const double *L, double kmax, int D, int *Kb, int **out)
 {
     for (int i = 0; i < 3; i++) Kb[i] = (int)floor(kmax * L[i] / (2.0 * OR_PI));
     long cap = (long)(2 * Kb[0] + 1) * (2 * Kb[1] + 1) * (Kb[2] + 1);
@@ -228,6 +228,9 @@ static long list_halfspace_k(const double *L, double kmax, int *Kb, int **out)
             for (int k1 = -Kb[0]; k1 <= Kb[0]; k1++) {
                 int upper = (k3 > 0) || (k3 == 0 && k2 > 0) || (k3 == 0 && k2 == 0 && k1 > 0);
                 if (!upper) continue;
+                /* D < 3: the modes with k^P = 0 are handled in closed form */
+                if (D == 2 && k1 == 0 && k2 == 0) continue;
+                if (D == 1 && k1 == 0) continue;
                 double kk[3] = {2.0 * OR_PI * k1 / L[0], 2.0 * OR_PI * k2 / L[1],
                                 2.0 * OR_PI * k3 / L[2]};
                 double kn2 = kk[0] * kk[0] + kk[1] * kk[1] + kk[2] * kk[2];
@@ -257,14 +260,19 @@ static void phase_table(double x, double L, int K, double complex *E)
 /*   S(k) = sum_n f_n e^{-i k.x_n}.                                          */
 /* The terms k and -k are complex conjugates, so the half space is summed    */
 /* and doubled (real part).  Returns the number of k-vectors used.           */
+/*                                                                           */
+/* With D = 2 or 1 the same sum over a cell whose free sides are L[i] = P_v  */
+/* and with the k^P = 0 modes left out is the trapezoidal rule, step         */
+/* 2 pi / P_v, of the integrals over the free wavenumbers in eqs.            */
+/* (2p-fourier-space) / (1p-fourier-space) for the nonsingular modes.        */
 /* ------------------------------------------------------------------------ */
-long oracle_fourier_part_3p(int kernel, const double *L, double xi, double kmax,
-                            long ns, const double *xs, const double *f, const double *nu,
-                            long nt, const double *xt, double *u)
+static long fourier_sum(int D, int kernel, const double *L, double xi, double kmax,
+                        long ns, const double *xs, const double *f, const double *nu,
+                        long nt, const double *xt, double *u)
 {
     int Kb[3];
     int *kl = NULL;
-    long nk = list_halfspace_k(L, kmax, Kb, &kl);
+    long nk = list_halfspace_k(L, kmax, D, Kb, &kl);
     int ncs = (kernel == OR_STRESSLET) ? 9 : 3;
     double complex *S = (double complex *)calloc((size_t)nk * ncs, sizeof(double complex));
     double V = L[0] * L[1] * L[2];
@@ -338,6 +346,22 @@ long oracle_fourier_part_3p(int kernel, const double *L, double xi, double kmax,
     free(S);
     free(kl);
     return nk;
+}
+
+long oracle_fourier_part_3p(int kernel, const double *L, double xi, double kmax,
+                            long ns, const double *xs, const double *f, const double *nu,
+                            long nt, const double *xt, double *u)
+{
+    return fourier_sum(3, kernel, L, xi, kmax, ns, xs, f, nu, nt, xt, u);
+}
+
+/* Nonsingular modes k^P != 0 for D = 2, 1; Lv = (L_1, L_2, P_v) or
+ * (L_1, P_v, P_v) (see fourier_sum). */
+long oracle_reduced_fourier_part(int D, int kernel, const double *Lv, double xi, double kmax,
+                                 long ns, const double *xs, const double *f, const double *nu,
+                                 long nt, const double *xt, double *u)
+{
+    return fourier_sum(D, kernel, Lv, xi, kmax, ns, xs, f, nu, nt, xt, u);
 }
 
 /* ------------------------------------------------------------------------ */

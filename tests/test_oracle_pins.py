@@ -179,7 +179,7 @@ def _sphere_quadrature(center, rho, n_t=24, n_p=48):
     return np.asarray(center)[None, :] + rho * nu, nu, w
 
 
-@pytest.mark.parametrize("D", [3, 0])
+@pytest.mark.parametrize("D", [3, 2, 1, 0])
 def test_stresslet_integral_identity(oracle_lib, D):
     """Eq. (stresslet-identity) for constant q0 on a sphere.
 
@@ -195,10 +195,76 @@ def test_stresslet_integral_identity(oracle_lib, D):
     inside = np.array([[0.5, 0.5, 0.5], [0.55, 0.45, 0.52]])
     outside = np.array([[0.5, 0.5, 0.93], [0.08, 0.9, 0.5]])
     t = np.concatenate([inside, outside])
-    r = oracle_lib.ewald(D, "stresslet", [1, 1, 1], y, q=q, nu=nu, targets=t, self_src=None)
+    xi = 4.0 if D in (1, 2) else None
+    r = oracle_lib.ewald(D, "stresslet", [1, 1, 1], y, q=q, nu=nu, targets=t, self_src=None, xi=xi)
     u = r.total if D else r["direct"]
     assert np.allclose(u[:2], 8 * np.pi * q0[None, :], rtol=0, atol=1e-8)
     assert np.allclose(u[2:], 0.0, atol=1e-8)
+
+
+# --------------------------------------------------------------------------
+# Doubly and singly periodic sums (Appendices A and B).
+# --------------------------------------------------------------------------
+def test_exponential_integral_matches_library(oracle_lib):
+    """E1 used by the singly periodic zero mode (eq. 1p-stokeslet-Q0) vs scipy."""
+    from scipy.special import exp1
+
+    for x in [1e-12, 1e-6, 1e-3, 0.1, 0.5, 0.999, 1.0, 1.001, 2.0, 7.5, 30.0, 200.0]:
+        assert abs(oracle_lib.e1(x) - exp1(x)) <= 4e-15 * exp1(x)
+
+
+@pytest.mark.parametrize("kernel", ["stokeslet", "rotlet", "stresslet"])
+@pytest.mark.parametrize("D", [2, 1])
+def test_xi_invariance_reduced(oracle_lib, D, kernel):
+    """Eqs. (2p-ewald-decomp) / (1p-ewald-decomp) do not depend on xi.
+
+    Net force is non-zero here, so the singly periodic stokeslet also checks
+    that the gauge of eq. (1p-stokeslet-Q0) is the same for every xi."""
+    box = (1.2, 0.9, 1.1)
+    s = W.system(23, 60, box=box, kernel=kernel, periodicity=D)
+    kw = dict(f=s.get("f"), q=s.get("q"), nu=s.get("nu"))
+    a = oracle_lib.ewald(D, kernel, box, s["x"], xi=3.5, **kw)
+    b = oracle_lib.ewald(D, kernel, box, s["x"], xi=6.0, **kw)
+    assert oracle_lib.rms_rel_error(a.total, b.total) < 1e-11
+    assert oracle_lib.rms_rel_error(a["real"], b["real"]) > 1e-3
+    assert oracle_lib.rms_rel_error(a["k0"], b["k0"]) > 1e-3
+    t = W.uniform_points(W.rng(24), 30, box)
+    a = oracle_lib.ewald(D, kernel, box, s["x"], targets=t, xi=3.5, **kw)
+    b = oracle_lib.ewald(D, kernel, box, s["x"], targets=t, xi=6.0, **kw)
+    assert oracle_lib.rms_rel_error(a.total, b.total) < 1e-11
+
+
+def _richardson(vals, Ks, p0):
+    """Repeated Richardson extrapolation for an error sum_j c_j K^{-(p0 + j)}, K doubling."""
+    T = [np.asarray(v) for v in vals]
+    p = p0
+    while len(T) > 1:
+        r = Ks[1] / Ks[0]
+        T = [(r ** p * T[i + 1] - T[i]) / (r ** p - 1) for i in range(len(T) - 1)]
+        p += 1
+    return T[0]
+
+
+@pytest.mark.parametrize("kernel", ["stokeslet", "rotlet", "stresslet"])
+@pytest.mark.parametrize("D", [1, 2])
+def test_reduced_matches_image_sums(oracle_lib, D, kernel):
+    """Direct image sums of eq. (periodic-potential) over the block |p_i| <= K.
+
+    The kernels decay as |r|^-2 (rotlet, stresslet; stokeslet with zero net
+    force), and the images at +p and -p cancel to leading order, so the sum
+    converges and its block truncation error is a power series in 1/K
+    (from K^-2 for D = 1 and K^-1 for D = 2), removed by Richardson
+    extrapolation.  Nothing here uses the Ewald split."""
+    box = (1.0, 1.0, 1.0)
+    s = W.system(12, 20, box=box, kernel=kernel, zero_mean=(kernel == "stokeslet"), periodicity=D)
+    kw = dict(f=s.get("f"), q=s.get("q"), nu=s.get("nu"))
+    ref = oracle_lib.ewald(D, kernel, box, s["x"], xi=5.0, **kw).total
+    if D == 1:
+        Ks, p0, tol = [250, 500, 1000, 2000], 2, 1e-12
+    else:
+        Ks, p0, tol = [8, 16, 32, 64, 128, 256], 1, 1e-9
+    vals = [oracle_lib.image_block_sum(D, kernel, box, s["x"], K=K, **kw) for K in Ks]
+    assert oracle_lib.rms_rel_error(_richardson(vals, Ks, p0), ref) < tol
 
 
 def test_direct_sum_is_translation_invariant_and_antisymmetric(oracle_lib):
