@@ -106,8 +106,8 @@ typedef struct se_params {
                             (M_i periodic, M'_i free for D = 1, 2, 2 M'_i for D = 0) */
     int32_t n0_fft[3];   /* free axes, k^P = 0 class: length s0 M'_i (D = 1, 2) */
     int32_t nstar_fft[3];/* free axes, K_* class: length s_* M'_i (D = 1, 2) */
-    int32_t kstar;       /* upsampling threshold kbar_* (periodic axes), 0: K_* empty */
-    int32_t reserved;
+    int32_t kstar[2];    /* upsampling threshold kbar_* per periodic axis (x, y; D = 1, 2),
+                            all 0: K_* empty */
     double xi;           /* splitting parameter */
     double rc;           /* real-space cut-off radius */
     double beta;         /* Kaiser-Bessel shape, eq. (PKB-parameters) */

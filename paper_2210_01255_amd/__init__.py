@@ -40,7 +40,7 @@ class se_params(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_int32), ("P", ctypes.c_int32), ("nu_deg", ctypes.c_int32),
                 ("f_M", ctypes.c_int32), ("M", ctypes.c_int32 * 3), ("n_fft", ctypes.c_int32 * 3),
                 ("n0_fft", ctypes.c_int32 * 3), ("nstar_fft", ctypes.c_int32 * 3),
-                ("kstar", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("kstar", ctypes.c_int32 * 2),
                 ("xi", ctypes.c_double), ("rc", ctypes.c_double), ("beta", ctypes.c_double),
                 ("h", ctypes.c_double * 3), ("L_ext", ctypes.c_double * 3), ("dL", ctypes.c_double * 3),
                 ("R", ctypes.c_double), ("s0", ctypes.c_double), ("s_star", ctypes.c_double),

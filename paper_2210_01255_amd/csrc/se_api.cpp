@@ -42,6 +42,130 @@ void free_all(se_plan* p)
                     p->d_pos4, p->d_tpos4, p->d_str4, p->d_nrm4, p->d_rtab, p->d_ktab};
     for (void* q : ptrs)
         if (q) hipFree(q);
+    for (se_aft_class& c : p->cls) {
+        void* cp[] = {c.buf, c.kv, c.iw, c.tw, c.mk};
+        for (void* q : cp)
+            if (q) hipFree(q);
+    }
+}
+
+// Class shapes of the adaptive transform (Sec. 3.4): [0] k^P = 0 with the
+// upsampled lengths s0 M'_i, [1] the set K_* (|k_i| <= k*, k^P != 0) with
+// s_* M'_i.  The threshold is clipped below the Nyquist index of each
+// periodic axis.
+void aft_shapes(se_plan* p)
+{
+    const se_params& par = p->par;
+    for (se_aft_class& c : p->cls) c = se_aft_class();
+    if (p->D != 1 && p->D != 2) return;
+    const int kx = std::max(0, std::min(par.kstar[0], p->Nfft[0] / 2 - 1));
+    const int ky = p->D == 2 ? std::max(0, std::min(par.kstar[1], p->Nfft[1] / 2 - 1)) : 0;
+    se_aft_class& c0 = p->cls[0];
+    c0.active = 1;
+    c0.zero = 1;
+    c0.nkx = 1;
+    c0.kx_lo = 0;
+    c0.ky_lo = 0;
+    se_aft_class& c1 = p->cls[1];
+    c1.active = p->D == 2 ? (kx >= 1 || ky >= 1) : kx >= 1;
+    if (p->D == 2) {
+        c0.ny = 1;
+        c0.nz = par.n0_fft[2];
+        c1.nkx = kx + 1;
+        c1.ny = 2 * ky + 1;
+        c1.nz = par.nstar_fft[2];
+        c1.kx_lo = 0;
+        c1.ky_lo = -ky;
+    } else {
+        c0.ny = par.n0_fft[1];
+        c0.nz = par.n0_fft[2];
+        c1.nkx = kx;
+        c1.ny = par.nstar_fft[1];
+        c1.nz = par.nstar_fft[2];
+        c1.kx_lo = 1;
+        c1.ky_lo = 0;
+    }
+    if (!c1.active) c1.nkx = c1.ny = c1.nz = 0;
+}
+
+// 1 - J0(x) and 1 - J0(x) - x J1(x)/2 (series for small x)
+void bessel_brackets(double x, double* h, double* b)
+{
+    if (x < 0.5) {
+        long double q = (long double)x * x / 4.0L, t = 1.0L, sh = 0.0L, sb = 0.0L;
+        for (int m = 1; m < 30; m++) {
+            t *= -q / ((long double)m * m);  // (-1)^m (x/2)^{2m} / (m!)^2
+            sh -= t;
+            sb += t * (m - 1);
+        }
+        *h = (double)sh;
+        *b = (double)sb;
+        return;
+    }
+    const double j0 = std::cyl_bessel_j(0.0, x), j1 = std::cyl_bessel_j(1.0, x);
+    *h = 1.0 - j0;
+    *b = 1.0 - j0 - 0.5 * x * j1;
+}
+
+// Wavenumbers, window deconvolution, twiddles and (D = 1, k^P = 0) the
+// modified kernels Hhat_R^{1P}, Bhat_R^{1P} (eqs. optimal-1p-harmonic,
+// optimal-1p-biharmonic with their limits) of each active class.
+hipError_t aft_tables(se_plan* p)
+{
+    const se_params& par = p->par;
+    const double twopi = 2.0 * M_PI;
+    for (se_aft_class& c : p->cls) {
+        if (!c.active) continue;
+        std::vector<double> kv, iw;
+        const int n[3] = {c.nkx, c.ny, c.nz};
+        double nv[3];
+        for (int d = 0; d < 3; d++) {
+            const double a = par.h[d] * par.P / 2.0;
+            const bool periodic = d < p->D;
+            for (int i = 0; i < n[d]; i++) {
+                double k;
+                if (d == 0) k = twopi * (c.kx_lo + i) / p->g.L[0];
+                else if (periodic) k = twopi * (c.ky_lo + i) / p->g.L[1];
+                else k = twopi * (i < n[d] / 2 ? i : i - n[d]) / (par.h[d] * n[d]);
+                kv.push_back(k);
+                double w = se_kb_fourier(k, a, par.beta);
+                iw.push_back(1.0 / (w * w));
+            }
+            nv[d] = periodic ? p->Nfft[d] : n[d];
+        }
+        c.scale = par.h[0] * par.h[1] * par.h[2] / (nv[0] * nv[1] * nv[2]);
+        std::vector<double> tw;
+        const int Nt[3] = {2, c.ny, c.nz};
+        se_fft_twiddles(Nt, &tw, c.tw_off);
+        hipError_t e = hipMemcpy(c.kv, kv.data(), kv.size() * sizeof(double), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(c.iw, iw.data(), iw.size() * sizeof(double), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(c.tw, tw.data(), tw.size() * sizeof(double), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return e;
+        if (c.mk) {
+            const double R = par.R;
+            std::vector<double> mk((size_t)2 * c.ny * c.nz);
+            for (int iz = 0; iz < c.nz; iz++)
+                for (int iy = 0; iy < c.ny; iy++) {
+                    const double ky = kv[c.nkx + iy], kz = kv[c.nkx + c.ny + iz];
+                    const double kk = std::sqrt(ky * ky + kz * kz);
+                    double hb, bb;
+                    bessel_brackets(R * kk, &hb, &bb);
+                    double H, B;
+                    if (kk == 0.0) {
+                        H = M_PI * R * R;
+                        B = -M_PI * R * R * R * R / 8.0;
+                    } else {
+                        H = 4.0 * M_PI / (kk * kk) * hb;
+                        B = -8.0 * M_PI / (kk * kk * kk * kk) * bb;
+                    }
+                    mk[2 * ((size_t)iz * c.ny + iy)] = H;
+                    mk[2 * ((size_t)iz * c.ny + iy) + 1] = B;
+                }
+            e = hipMemcpy(c.mk, mk.data(), mk.size() * sizeof(double), hipMemcpyHostToDevice);
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
 }
 
 int key_bits(int64_t nbins)
@@ -153,10 +277,6 @@ se_status se_plan_create(const se_problem* prob, const se_params* manual, se_pla
     p->tas = prob->targets_are_sources != 0;
     p->nt = p->tas ? prob->n_src : prob->n_tgt;
 
-    if (p->D == 1 || p->D == 2) {
-        delete p;
-        return SE_ERR_UNSUPPORTED;
-    }
     // precision: the FP32 grid path is for tolerances >= 1e-6
     if (prob->precision == SE_PREC_FP32) {
         double rel = prob->tol;
@@ -201,6 +321,14 @@ se_status se_plan_create(const se_problem* prob, const se_params* manual, se_pla
     bool ok = (p->Nfft[0] % 2 == 0) && se_smooth_factors(p->Nfft[0] / 2, &rr) && p->Nfft[0] / 2 <= SE_FFT_LDS_ELEMS &&
               se_smooth_factors(p->Nfft[1], &rr) && p->Nfft[1] <= SE_FFT_LDS_ELEMS &&
               se_smooth_factors(p->Nfft[2], &rr) && p->ncomp * p->Nfft[2] <= (p->fp32 ? 6144 : 3072);
+    if (ok && (p->D == 1 || p->D == 2)) {
+        aft_shapes(p);
+        for (const se_aft_class& c : p->cls) {
+            if (!c.active) continue;
+            if (p->D == 1) ok = ok && se_smooth_factors(c.ny, &rr) && c.ny <= SE_FFT_LDS_ELEMS;
+            ok = ok && se_smooth_factors(c.nz, &rr) && c.nz <= SE_FFT_LDS_ELEMS;
+        }
+    }
     if (ok && p->D == 0) {
         const int* n0 = p->par.n0_fft;
         ok = (n0[0] % 2 == 0) && se_smooth_factors(n0[0] / 2, &rr) && n0[0] / 2 <= SE_FFT_LDS_ELEMS &&
@@ -255,6 +383,15 @@ se_status se_plan_create(const se_problem* prob, const se_params* manual, se_pla
     const int Nh = p->Nfft[0] / 2;
     const size_t ntw = (size_t)Nh + (Nh + 1) + p->Nfft[1] + p->Nfft[2];
     p->d_tw = A.get<double>(2 * ntw);
+    for (se_aft_class& c : p->cls) {
+        if (!c.active) continue;
+        const size_t nel = (size_t)c.nkx * c.ny * c.nz;
+        c.buf = A.get<char>((size_t)p->ncomp * nel * 2 * rs);
+        c.kv = A.get<double>((size_t)c.nkx + c.ny + c.nz);
+        c.iw = A.get<double>((size_t)c.nkx + c.ny + c.nz);
+        c.tw = A.get<double>(2 * ((size_t)1 + 2 + c.ny + c.nz));
+        if (p->D == 1 && c.zero) c.mk = A.get<double>((size_t)2 * c.ny * c.nz);
+    }
     if (!A.ok) {
         free_all(p);
         delete p;
@@ -286,6 +423,7 @@ se_status se_plan_create(const se_problem* prob, const se_params* manual, se_pla
     if (e == hipSuccess) e = hipMemcpy(p->d_invw2, iw.data(), iw.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p->d_tw, tw.data(), tw.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p->d_rtab, rtab.data(), rtab.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = aft_tables(p);
     if (e == hipSuccess) e = hipMemset(p->d_flags, 0, sizeof(int));
     if (e == hipSuccess) e = hipMemset(p->d_red, 0, 8 * sizeof(double));
     if (e == hipSuccess) e = hipDeviceSynchronize();

@@ -43,6 +43,7 @@ struct se_fft_args {
     const double* invw2;  // 1/what0^2: [Hx | N1 | N2] per axis
     int iw_off[3];
     const double* ktab;   // D = 0: precomputed truncated kernel on the half spectrum [z][y][x]
+    int skip_kx, skip_ky; // D = 1, 2: main-grid modes handled by an upsampled class
 };
 
 template <typename R>
@@ -363,31 +364,18 @@ __device__ __forceinline__ double green_scalar(const se_fft_args& a, int ix, int
     return KER == SE_ROTLET ? 4.0 * M_PI / k2 : -8.0 * M_PI / (k2 * k2);
 }
 
-template <typename R, int KER, int NC>
-__device__ __forceinline__ void scale_point(const se_fft_args& a, int ix, int iy, int iz, C<R>* F, C<R>* U)
+// u = Khat(k) F with the scalar factor c = Ahat gammahat W already formed.
+template <typename R, int KER>
+__device__ __forceinline__ void apply_green(double cd, const double* k, double k2, const C<R>* F, C<R>* U)
 {
-    const int kb[3] = {ix, iy < a.N[1] / 2 ? iy : iy - a.N[1], iz < a.N[2] / 2 ? iz : iz - a.N[2]};
-    const double k[3] = {a.kfac[0] * kb[0], a.kfac[1] * kb[1], a.kfac[2] * kb[2]};
-    const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
-    const bool nyq = (2 * ix == a.N[0]) || (2 * iy == a.N[1]) || (2 * iz == a.N[2]);
-    const double G = green_scalar<KER>(a, ix, iy, iz, k2);
-    if (G == 0.0 || (KER != SE_STOKESLET && nyq)) {
-        U[0] = U[1] = U[2] = {(R)0, (R)0};
-        return;
-    }
-    const double e = k2 / (4.0 * a.xi * a.xi);
-    const double gE = exp(-e);
-    const double iw = a.invw2[a.iw_off[0] + ix] * a.invw2[a.iw_off[1] + iy] * a.invw2[a.iw_off[2] + iz];
-    const double W = a.scale * iw;
     const R kr[3] = {(R)k[0], (R)k[1], (R)k[2]};
     const R kk = (R)k2;
+    const R c = (R)cd;
     if constexpr (KER == SE_STOKESLET) {
-        const R c = (R)(G * gE * (1.0 + e) * W);
         C<R> kf = {kr[0] * F[0].x + kr[1] * F[1].x + kr[2] * F[2].x, kr[0] * F[0].y + kr[1] * F[1].y + kr[2] * F[2].y};
 #pragma unroll
         for (int j = 0; j < 3; j++) U[j] = {c * (kr[j] * kf.x - kk * F[j].x), c * (kr[j] * kf.y - kk * F[j].y)};
     } else if constexpr (KER == SE_ROTLET) {
-        const R c = (R)(G * gE * W);
         C<R> w[3];  // F x k
         w[0] = {F[1].x * kr[2] - F[2].x * kr[1], F[1].y * kr[2] - F[2].y * kr[1]};
         w[1] = {F[2].x * kr[0] - F[0].x * kr[2], F[2].y * kr[0] - F[0].y * kr[2]};
@@ -395,7 +383,6 @@ __device__ __forceinline__ void scale_point(const se_fft_args& a, int ix, int iy
 #pragma unroll
         for (int j = 0; j < 3; j++) U[j] = {c * w[j].y, -c * w[j].x};  // -i c w
     } else {
-        const R c = (R)(G * gE * (1.0 + e) * W);
         // symmetric F: 0 xx, 1 yy, 2 zz, 3 xy, 4 xz, 5 yz
         C<R> Fk[3];
         Fk[0] = {F[0].x * kr[0] + F[3].x * kr[1] + F[4].x * kr[2], F[0].y * kr[0] + F[3].y * kr[1] + F[4].y * kr[2]};
@@ -411,6 +398,29 @@ __device__ __forceinline__ void scale_point(const se_fft_args& a, int ix, int iy
             U[j] = {-c * v.y, c * v.x};  // i c v
         }
     }
+}
+
+template <typename R, int KER, int NC>
+__device__ __forceinline__ void scale_point(const se_fft_args& a, int ix, int iy, int iz, C<R>* F, C<R>* U)
+{
+    const int kb[3] = {ix, iy < a.N[1] / 2 ? iy : iy - a.N[1], iz < a.N[2] / 2 ? iz : iz - a.N[2]};
+    const double k[3] = {a.kfac[0] * kb[0], a.kfac[1] * kb[1], a.kfac[2] * kb[2]};
+    const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+    const bool nyq = (2 * ix == a.N[0]) || (2 * iy == a.N[1]) || (2 * iz == a.N[2]);
+    // D = 2: columns |kx|, |ky| <= k*; D = 1: planes kx <= k* (upsampled classes)
+    const bool moved = (a.D == 2 && ix <= a.skip_kx && kb[1] <= a.skip_ky && -kb[1] <= a.skip_ky) ||
+                       (a.D == 1 && ix <= a.skip_kx);
+    const double G = moved ? 0.0 : green_scalar<KER>(a, ix, iy, iz, k2);
+    if (G == 0.0 || (KER != SE_STOKESLET && nyq)) {
+        U[0] = U[1] = U[2] = {(R)0, (R)0};
+        return;
+    }
+    const double e = k2 / (4.0 * a.xi * a.xi);
+    const double gE = exp(-e);
+    const double iw = a.invw2[a.iw_off[0] + ix] * a.invw2[a.iw_off[1] + iy] * a.invw2[a.iw_off[2] + iz];
+    const double W = a.scale * iw;
+    const double screen = KER == SE_ROTLET ? gE : gE * (1.0 + e);
+    apply_green<R, KER>(G * screen * W, k, k2, F, U);
 }
 
 // Plain complex transform along z (no scaling) for `ncomp` components.
@@ -553,6 +563,14 @@ se_fft_args make_fft_args(const se_plan* p, int ncomp)
     a.iw_off[1] = p->Hx;
     a.iw_off[2] = p->Hx + p->Nfft[1];
     a.ktab = p->d_ktab;
+    a.skip_kx = -1;
+    a.skip_ky = -1;
+    if (p->D == 2) {
+        a.skip_kx = p->cls[1].active ? p->cls[1].nkx - 1 : 0;
+        a.skip_ky = p->cls[1].active ? (p->cls[1].ny - 1) / 2 : 0;
+    } else if (p->D == 1) {
+        a.skip_kx = p->cls[1].active ? p->cls[1].nkx : 0;
+    }
     return a;
 }
 
@@ -600,11 +618,18 @@ void run_z_plain(se_fft_args a, int ncomp, int dir, hipStream_t s)
 }
 
 template <typename R>
+void cls_gather(const se_plan* p, hipStream_t s);
+template <typename R>
+void cls_scatter(const se_plan* p, hipStream_t s);
+
+template <typename R>
 void launch_fwd(const se_plan* p, hipStream_t s)
 {
     se_fft_args a = make_fft_args(p, p->ncomp);
     run_x_r2c<R>(a, p->ncomp, s);
+    if (p->D == 1) cls_gather<R>(p, s);
     run_y<R>(a, p->ncomp, 1, s);
+    if (p->D == 2) cls_gather<R>(p, s);
 }
 
 template <typename R, int KER, int NC>
@@ -625,6 +650,7 @@ void launch_inv(const se_plan* p, hipStream_t s)
 {
     se_fft_args a = make_fft_args(p, 3);
     run_y<R>(a, 3, -1, s);
+    if (p->D == 1) cls_scatter<R>(p, s);
     run_x_c2r<R>(a, 3, s);
 }
 
@@ -636,8 +662,241 @@ void launch_z_dispatch(const se_plan* p, hipStream_t s)
     else launch_z<R, SE_STRESSLET, 6>(p, s);
 }
 
+// ------------------------------------------------- adaptive FFT: upsampled classes
+// Sec. 3.4 (AFT): modes k^P = 0 and k^P in K_* are transformed along the free
+// directions with upsampling s0 and s_* (zero padding in real space), scaled
+// with the modified kernels (eqs. mod-stokeslet-2p .. mod-stresslet-2p,
+// mod-rotlet-1p .. mod-stresslet-1p) or the regular ones, transformed back and
+// truncated to the extended grid.
+struct se_cls_args {
+    int D;
+    int zero;
+    int nkx, ny, nz;
+    int kx_lo, ky_lo;
+    int Hx, N1, Mg1, Mz;  // main half spectrum [c][Mz][N1][Hx], valid y rows Mg1
+    void* spec;
+    void* buf;
+    const double* kv;
+    const double* iw;
+    const double* mk;
+    double xi, R, scale;
+};
+
+se_cls_args make_cls_args(const se_plan* p, const se_aft_class& c)
+{
+    se_cls_args a;
+    std::memset(&a, 0, sizeof(a));
+    a.D = p->D;
+    a.zero = c.zero;
+    a.nkx = c.nkx;
+    a.ny = c.ny;
+    a.nz = c.nz;
+    a.kx_lo = c.kx_lo;
+    a.ky_lo = c.ky_lo;
+    a.Hx = p->Hx;
+    a.N1 = p->Nfft[1];
+    a.Mg1 = p->g.Mg[1];
+    a.Mz = p->g.Mg[2];
+    a.spec = p->d_spec;
+    a.buf = c.buf;
+    a.kv = c.kv;
+    a.iw = c.iw;
+    a.mk = c.mk;
+    a.xi = p->par.xi;
+    a.R = p->par.R;
+    a.scale = c.scale;
+    return a;
+}
+
+// main spectrum -> zero-padded class buffer (ncomp components)
+template <typename R>
+__global__ void k_cls_gather(se_cls_args a, int ncomp)
+{
+    const int64_t n = (int64_t)a.nkx * a.ny * a.nz;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * ncomp) return;
+    const int c = (int)(i / n);
+    const int64_t r = i - c * n;
+    const int ix = (int)(r % a.nkx);
+    const int iy = (int)((r / a.nkx) % a.ny);
+    const int iz = (int)(r / ((int64_t)a.nkx * a.ny));
+    const C<R>* spec = (const C<R>*)a.spec;
+    C<R> v = {(R)0, (R)0};
+    int y = -1;
+    if (a.D == 2) y = (a.ky_lo + iy + a.N1) % a.N1;
+    else if (iy < a.Mg1) y = iy;
+    if (y >= 0 && iz < a.Mz) v = spec[(((int64_t)c * a.Mz + iz) * a.N1 + y) * a.Hx + a.kx_lo + ix];
+    ((C<R>*)a.buf)[i] = v;
+}
+
+// class buffer (3 components) -> main spectrum, truncated to the extended grid
+template <typename R>
+__global__ void k_cls_scatter(se_cls_args a)
+{
+    const int rows = a.D == 2 ? a.ny : a.Mg1;
+    const int64_t n = (int64_t)a.nkx * rows * a.Mz;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 3 * n) return;
+    const int c = (int)(i / n);
+    const int64_t r = i - c * n;
+    const int ix = (int)(r % a.nkx);
+    const int iy = (int)((r / a.nkx) % rows);
+    const int iz = (int)(r / ((int64_t)a.nkx * rows));
+    int y = iy;
+    if (a.D == 2) {
+        if (!a.zero && a.kx_lo + ix == 0 && a.ky_lo + iy == 0) return;  // owned by the k^P = 0 class
+        y = (a.ky_lo + iy + a.N1) % a.N1;
+    }
+    const C<R>* buf = (const C<R>*)a.buf;
+    ((C<R>*)a.spec)[(((int64_t)c * a.Mz + iz) * a.N1 + y) * a.Hx + a.kx_lo + ix] =
+        buf[(((int64_t)c * a.nz + iz) * a.ny + iy) * a.nkx + ix];
+}
+
+template <typename R, int KER, int NC>
+__global__ void k_cls_scale(se_cls_args a)
+{
+    const int64_t n = (int64_t)a.nkx * a.ny * a.nz;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int ix = (int)(i % a.nkx);
+    const int iy = (int)((i / a.nkx) % a.ny);
+    const int iz = (int)(i / ((int64_t)a.nkx * a.ny));
+    C<R>* buf = (C<R>*)a.buf;
+    C<R> F[NC], U[3];
+#pragma unroll
+    for (int c = 0; c < NC; c++) F[c] = buf[c * n + i];
+    const double k[3] = {a.kv[ix], a.kv[a.nkx + iy], a.kv[a.nkx + a.ny + iz]};
+    const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+    const bool nyq = (2 * iz == a.nz) || (a.D == 1 && 2 * iy == a.ny);
+    const double e = k2 / (4.0 * a.xi * a.xi);
+    const double gE = exp(-e);
+    const double screen = KER == SE_ROTLET ? gE : gE * (1.0 + e);
+    const double W = a.scale * a.iw[ix] * a.iw[a.nkx + iy] * a.iw[a.nkx + a.ny + iz];
+    U[0] = U[1] = U[2] = {(R)0, (R)0};
+    const bool kp0 = (k[0] == 0.0) && (a.D == 1 || k[1] == 0.0);
+    if (KER != SE_STOKESLET && nyq) {
+        // odd kernels: no Hermitian partner on Nyquist indices
+    } else if (!a.zero) {
+        if (!kp0) {
+            const double G = KER == SE_ROTLET ? 4.0 * M_PI / k2 : -8.0 * M_PI / (k2 * k2);
+            apply_green<R, KER>(G * screen * W, k, k2, F, U);
+        }
+    } else if (a.D == 2) {
+        const double kz = k[2], Rk = a.R * kz;
+        if constexpr (KER == SE_STOKESLET) {
+            // Hhat_R^{2P} D^S, limit -2 pi R^2
+            const double H = kz == 0.0 ? -2.0 * M_PI * a.R * a.R
+                                       : 4.0 * M_PI / (kz * kz) * (1.0 - cos(Rk) - Rk * sin(Rk));
+            const R c = (R)(2.0 * H * screen * W);
+            U[0] = {c * F[0].x, c * F[0].y};
+            U[1] = {c * F[1].x, c * F[1].y};
+        } else {
+            // Zhat_R^{2P} = -i z, z = 4 pi (1 - cos(R k3))/k3, limit 0
+            const double z = kz == 0.0 ? 0.0 : 4.0 * M_PI * (1.0 - cos(Rk)) / kz;
+            const R c = (R)(z * screen * W);
+            if constexpr (KER == SE_ROTLET) {
+                U[0] = {c * F[1].y, -c * F[1].x};   // -i c F_2
+                U[1] = {-c * F[0].y, c * F[0].x};   // +i c F_1
+            } else {
+                // D^T: u1 = -4 Zhat F13, u2 = -4 Zhat F23, u3 = -2 Zhat tr F
+                U[0] = {-4 * c * F[4].y, 4 * c * F[4].x};
+                U[1] = {-4 * c * F[5].y, 4 * c * F[5].x};
+                C<R> tr = {F[0].x + F[1].x + F[2].x, F[0].y + F[1].y + F[2].y};
+                U[2] = {-2 * c * tr.y, 2 * c * tr.x};
+            }
+        }
+    } else {
+        const double H = a.mk[2 * (iz * (int64_t)a.ny + iy)];
+        const double B = a.mk[2 * (iz * (int64_t)a.ny + iy) + 1];
+        if constexpr (KER == SE_ROTLET) {
+            apply_green<R, KER>(H * screen * W, k, k2, F, U);
+        } else if constexpr (KER == SE_STOKESLET) {
+            apply_green<R, KER>(B * screen * W, k, k2, F, U);
+            const R c = (R)(2.0 * H * screen * W);
+            U[0] = {c * F[0].x, c * F[0].y};
+        } else {
+            const R cH = (R)(H * screen * W), cB = (R)(B * screen * W);
+            const R k2r = (R)k[1], k3r = (R)k[2], kk = (R)k2;
+            // 4 i cH (k2 F12 + k3 F13)
+            C<R> t0 = {4 * cH * (k2r * F[3].x + k3r * F[4].x), 4 * cH * (k2r * F[3].y + k3r * F[4].y)};
+            U[0] = {-t0.y, t0.x};
+            const R a22 = k2r * (3 * kk - 2 * k2r * k2r), a23 = 2 * k3r * (kk - 2 * k2r * k2r),
+                    a33 = k2r * (kk - 2 * k3r * k3r);
+            const R b22 = k3r * (kk - 2 * k2r * k2r), b23 = 2 * k2r * (kk - 2 * k3r * k3r),
+                    b33 = k3r * (3 * kk - 2 * k3r * k3r);
+            C<R> t1 = {2 * cH * k2r * F[0].x - cB * (a22 * F[1].x + a23 * F[5].x + a33 * F[2].x),
+                       2 * cH * k2r * F[0].y - cB * (a22 * F[1].y + a23 * F[5].y + a33 * F[2].y)};
+            C<R> t2 = {2 * cH * k3r * F[0].x - cB * (b22 * F[1].x + b23 * F[5].x + b33 * F[2].x),
+                       2 * cH * k3r * F[0].y - cB * (b22 * F[1].y + b23 * F[5].y + b33 * F[2].y)};
+            U[1] = {-t1.y, t1.x};
+            U[2] = {-t2.y, t2.x};
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 3; j++) buf[j * n + i] = U[j];
+}
+
+inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+se_fft_args cls_fft_args(const se_plan* p, const se_aft_class& c)
+{
+    const int Mg[3] = {2, c.ny, c.nz};
+    const int N[3] = {2, c.ny, c.nz};
+    se_fft_args a = make_fft_args_geom(Mg, N, p->g.h, nullptr, c.buf, c.tw, c.tw_off, p->ncomp);
+    a.Hx = c.nkx;
+    return a;
+}
+
+template <typename R>
+void cls_gather(const se_plan* p, hipStream_t s)
+{
+    for (const se_aft_class& c : p->cls) {
+        if (!c.active) continue;
+        se_cls_args a = make_cls_args(p, c);
+        int64_t n = (int64_t)c.nkx * c.ny * c.nz * p->ncomp;
+        hipLaunchKernelGGL(k_cls_gather<R>, dim3(nblk(n)), dim3(256), 0, s, a, p->ncomp);
+    }
+}
+
+template <typename R>
+void cls_scatter(const se_plan* p, hipStream_t s)
+{
+    for (const se_aft_class& c : p->cls) {
+        if (!c.active) continue;
+        se_cls_args a = make_cls_args(p, c);
+        int rows = p->D == 2 ? c.ny : p->g.Mg[1];
+        int64_t n = 3 * (int64_t)c.nkx * rows * p->g.Mg[2];
+        hipLaunchKernelGGL(k_cls_scatter<R>, dim3(nblk(n)), dim3(256), 0, s, a);
+    }
+}
+
+template <typename R, int KER, int NC>
+void cls_transform(const se_plan* p, hipStream_t s)
+{
+    for (const se_aft_class& c : p->cls) {
+        if (!c.active) continue;
+        se_fft_args f = cls_fft_args(p, c);
+        if (p->D == 1) run_y<R>(f, NC, 1, s);
+        run_z_plain<R>(f, NC, 1, s);
+        se_cls_args a = make_cls_args(p, c);
+        hipLaunchKernelGGL((k_cls_scale<R, KER, NC>), dim3(nblk((int64_t)c.nkx * c.ny * c.nz)), dim3(256), 0, s, a);
+        run_z_plain<R>(f, 3, -1, s);
+        if (p->D == 1) run_y<R>(f, 3, -1, s);
+    }
+}
+
+template <typename R>
+void cls_transform_dispatch(const se_plan* p, hipStream_t s)
+{
+    if (p->kernel == SE_STOKESLET) cls_transform<R, SE_STOKESLET, 3>(p, s);
+    else if (p->kernel == SE_ROTLET) cls_transform<R, SE_ROTLET, 3>(p, s);
+    else cls_transform<R, SE_STRESSLET, 6>(p, s);
+}
+
 }  // namespace
 
+// D = 1: the class planes are copied out after the x transform (before y);
+// D = 2: the class columns after the x and y transforms.
 void se_launch_fft_xy_forward(const se_plan* p, hipStream_t s)
 {
     if (p->fp32) launch_fwd<float>(p, s);
@@ -646,8 +905,15 @@ void se_launch_fft_xy_forward(const se_plan* p, hipStream_t s)
 
 void se_launch_fft_z_scale(const se_plan* p, hipStream_t s)
 {
-    if (p->fp32) launch_z_dispatch<float>(p, s);
-    else launch_z_dispatch<double>(p, s);
+    if (p->fp32) {
+        launch_z_dispatch<float>(p, s);
+        if (p->D == 1 || p->D == 2) cls_transform_dispatch<float>(p, s);
+        if (p->D == 2) cls_scatter<float>(p, s);
+    } else {
+        launch_z_dispatch<double>(p, s);
+        if (p->D == 1 || p->D == 2) cls_transform_dispatch<double>(p, s);
+        if (p->D == 2) cls_scatter<double>(p, s);
+    }
 }
 
 void se_launch_fft_inverse(const se_plan* p, hipStream_t s)

@@ -52,6 +52,26 @@ struct se_fft_axis {
     std::vector<int> radices;  // factorisation of n_fft (or n_fft/2 on the R2C axis)
 };
 
+// One upsampled mode class of the adaptive Fourier transform (D = 1, 2):
+// [0] the modes k^P = 0 (modified kernels, upsampling s0), [1] the set K_*
+// (regular kernels, upsampling s_*).  The class data lives in its own buffer
+// [c][nz][ny][nkx] (complex, grid precision), zero padded in the free
+// directions, so plain line FFTs of the padded lengths apply.
+struct se_aft_class {
+    int active = 0;
+    int zero = 0;            // 1: the k^P = 0 class
+    int nkx = 0, ny = 0, nz = 0;
+    int kx_lo = 0;           // main-spectrum kx index of local kx 0
+    int ky_lo = 0;           // D = 2: signed ky index of local row 0
+    void* buf = nullptr;
+    double* kv = nullptr;    // wavenumbers [nkx | ny | nz]
+    double* iw = nullptr;    // 1/what^2 [nkx | ny | nz]
+    double* tw = nullptr;    // twiddles for the (ny, nz) line FFTs
+    double* mk = nullptr;    // D = 1, k^P = 0: [ny*nz][2] = (Hhat_R, Bhat_R)
+    int tw_off[4] = {0, 0, 0, 0};
+    double scale = 0.0;      // h1 h2 h3 / (N1 N2 N3) with the class lengths
+};
+
 struct se_plan {
     se_problem prob{};
     se_params par{};
@@ -100,6 +120,7 @@ struct se_plan {
     double* d_pkb = nullptr;       // PKB coefficients [P][nu+1]
     double* d_invw2 = nullptr;     // 1/what0(k)^2 per axis, concatenated [Nx/2+1 | Ny | Nz]
     double* d_tw = nullptr;        // twiddles (complex FP64), see se_fft layout
+    se_aft_class cls[2];           // D = 1, 2 upsampled classes ([0] k^P = 0, [1] K_*)
     int tw_off[4] = {0, 0, 0, 0};  // offsets (complex elements) of x-half, x-post, y, z tables
     size_t ws_bytes = 0;
     bool timing = false;

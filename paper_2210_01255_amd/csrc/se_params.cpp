@@ -424,16 +424,23 @@ se_status se_select_params(const se_problem* p, const se_params* manual, se_para
         s0 = std::ceil(10.0 * s0 - 1e-9) / 10.0;
         par.s0 = s0;
         double lnterm = std::log(U / (2.0 * tau));
+        // eqs. (upsampling-factor-sstar), (estimate-kbarstar) are stated for a
+        // cube; they follow from requiring |k^P| (s L'_i - L_i) >= log(U/(2E))
+        // for the smallest |k^P| of a class, which for other boxes gives
+        //   s_*  = max_i (L_i + max_j L_j log(U/2E)/(2 pi)) / L'_i   (free i),
+        //   k*_j = ceil(L_j / min_i dL_i log(U/2E)/(2 pi) - 1)       (periodic j),
+        // and the cube formulas when all sides are equal.
+        double Lpmax = 0.0, dLmin = 1e300;
+        for (int j = 0; j < D; j++) Lpmax = std::max(Lpmax, p->box[j]);
+        for (int i = D; i < 3; i++) dLmin = std::min(dLmin, par.dL[i]);
         double sstar = 1.0;
-        int kstar = 0;
-        for (int i = D; i < 3; i++) {
-            double Meq = p->box[i] / par.h[i];
-            sstar = std::max(sstar, (Meq / par.M[i]) * (1.0 + lnterm / (2.0 * kPi)));
-            int ks = (int)std::ceil(Meq / (par.M[i] - Meq) * lnterm / (2.0 * kPi) - 1.0 - 1e-12);
-            kstar = std::max(kstar, ks);
-        }
+        for (int i = D; i < 3; i++)
+            sstar = std::max(sstar, (p->box[i] + Lpmax * lnterm / (2.0 * kPi)) / par.L_ext[i]);
         par.s_star = sstar;
-        par.kstar = D > 0 ? std::max(kstar, 0) : 0;
+        for (int j = 0; j < D && j < 2; j++) {
+            int ks = (int)std::ceil(p->box[j] / dLmin * lnterm / (2.0 * kPi) - 1.0 - 1e-12);
+            par.kstar[j] = std::max(ks, 0);
+        }
         for (int i = D; i < 3; i++) {
             if (D == 0) {
                 par.n_fft[i] = 2 * par.M[i];

@@ -3,6 +3,7 @@
 // self term (eq. 3p-stokeslet-self-term), the non-periodic stresslet term
 // (eq. k0-stresslet-3p) and scatters back to the caller's order.
 #include <algorithm>
+#include <cmath>
 
 #include "se_device.h"
 
@@ -462,6 +463,13 @@ void se_launch_finalize(const se_plan* p, const double* f, double* u, double* u_
     for (int j = 0; j < 3; j++) a.gauge[j] = 0.0;
     if (p->D == 0 && p->kernel == SE_STOKESLET)
         for (int j = 0; j < 3; j++) a.gauge[j] = 2.0 / p->par.R;
+    if (p->D == 1 && p->kernel == SE_STOKESLET) {
+        // eq. (1p-stokeslet-extra-contribution) for l_H = R, l_B = R sqrt(e),
+        // removed so that the result is in the gauge l_B = 1, l_H = 1/e
+        const double lr = std::log(p->par.R);
+        a.gauge[0] = -4.0 * (lr + 1.0) / p->g.L[0];
+        a.gauge[1] = a.gauge[2] = -(2.0 * lr + 1.0) / p->g.L[0];
+    }
     a.u = u;
     a.u_real = u_real;
     a.u_four = u_fourier;

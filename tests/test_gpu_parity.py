@@ -58,10 +58,12 @@ def _run(env, kernel, s, D=3, tol=1e-8, targets=None, precision=None, n_rhs=1, s
     return plan, u.cpu().numpy()
 
 
-def _ref(env, kernel, s, D=3, targets=None):
+def _ref(env, kernel, s, D=3, targets=None, xi=None):
     _, oracle, _ = env
+    if xi is None and D in (1, 2):
+        xi = 6.0 / float(np.max(s["box"][:D]))  # keeps the trapezoidal k-sums of the oracle small
     r = oracle.ewald(D, kernel, s["box"], s["x"], f=s.get("f"), q=s.get("q"), nu=s.get("nu"),
-                     targets=targets, self_src=None if targets is None else None)
+                     targets=targets, self_src=None if targets is None else None, xi=xi)
     return r.total if D else r["direct"]
 
 
@@ -83,15 +85,17 @@ def _cell_reference(x, par, box, D):
     return perm, start, list(nb), list(B)
 
 
-@pytest.mark.parametrize("n,box", [(1000, (1, 1, 1)), (20000, (1.3, 0.8, 1.9)), (7, (1, 1, 1))])
-def test_cell_list_bit_exact(env, n, box):
+@pytest.mark.parametrize("n,box,D", [(1000, (1, 1, 1), 3), (20000, (1.3, 0.8, 1.9), 3), (7, (1, 1, 1), 3),
+                                     (5000, (1.3, 0.8, 1.1), 2), (5000, (1.0, 1.2, 0.9), 1),
+                                     (3000, (1.0, 1.0, 1.0), 0)])
+def test_cell_list_bit_exact(env, n, box, D):
     se, _, torch = env
     s = W.system(100 + n, n, box=box)
     # put a few points exactly on grid lines / the lower faces
     s["x"][0] = 0.0
-    plan, _ = _run(env, "stokeslet", s, tol=1e-6)
+    plan, _ = _run(env, "stokeslet", s, D=D, tol=1e-6)
     perm, start, nb, cw = plan.cell_list(0)
-    rp, rs, rnb, rcw = _cell_reference(s["x"], plan.params, s["box"], 3)
+    rp, rs, rnb, rcw = _cell_reference(s["x"], plan.params, s["box"], D)
     assert nb == rnb and cw == rcw
     assert np.array_equal(perm, rp)
     assert np.array_equal(start, rs)
@@ -254,3 +258,61 @@ def test_free_space_box_aspect_and_targets(env, kernel):
     err = oracle.rms_rel_error(u, _ref(env, kernel, s, D=0, targets=tg))
     print("D=0 aspect", kernel, "rel err", err)
     assert err <= 1e-8
+
+
+# ------------------------------------------------------------ D = 2, 1 (AFT)
+@pytest.mark.parametrize("kernel", ["stokeslet", "rotlet", "stresslet"])
+@pytest.mark.parametrize("tol", [1e-6, 1e-10])
+@pytest.mark.parametrize("D", [2, 1])
+def test_reduced_periodicity_matches_oracle(env, D, kernel, tol):
+    """Adaptive FFT with the k^P = 0 class (modified kernels, s0) and the K_*
+    class (s_*), vs the oracle's Appendix A/B sums.  Net force is non-zero for
+    the stokeslet and rotlet, so the singly periodic stokeslet also checks the
+    gauge of eq. (1p-stokeslet-extra-contribution)."""
+    _, oracle, _ = env
+    s = W.system(2200 + 10 * D + int(-np.log10(tol)), 1200, kernel=kernel, periodicity=D)
+    if kernel != "stresslet":
+        s["f"] += 0.4
+    plan, u = _run(env, kernel, s, D=D, tol=tol)
+    err = oracle.rms_rel_error(u, _ref(env, kernel, s, D=D))
+    par = plan.params
+    print("D=%d" % D, kernel, tol, "rel err", err, "M", par["M"], "n0", par["n0_fft"], "n*", par["nstar_fft"],
+          "k*", par["kstar"])
+    assert err <= tol
+
+
+@pytest.mark.parametrize("kernel", ["stokeslet", "rotlet", "stresslet"])
+@pytest.mark.parametrize("D", [2, 1])
+def test_reduced_periodicity_box_aspect_and_targets(env, D, kernel):
+    """Non-cubic box (R from the free sides, per-axis padded lengths) and
+    off-source targets, some on the faces of the box."""
+    _, oracle, _ = env
+    box = (1.3, 0.8, 1.1) if D == 2 else (0.9, 1.2, 0.8)
+    s = W.system(2300 + D, 1000, box=box, kernel=kernel, periodicity=D)
+    tg = W.uniform_points(W.rng(2310 + D), 400, s["box"])
+    tg[:4, 2] = 0.0
+    tg[4:8, D] = 0.0
+    tg[8:12, 2] = np.nextafter(s["box"][2], 0.0)
+    _, u = _run(env, kernel, s, D=D, tol=1e-8, targets=tg)
+    err = oracle.rms_rel_error(u, _ref(env, kernel, s, D=D, targets=tg))
+    print("D=%d aspect" % D, kernel, "rel err", err)
+    assert err <= 1e-8
+
+
+@pytest.mark.parametrize("D", [2, 1])
+def test_reduced_periodicity_real_space_exact(env, D):
+    """The real-space part alone (images only along the periodic axes) vs the
+    oracle's at the same (xi, rc)."""
+    _, oracle, _ = env
+    s = W.system(2400 + D, 1500, kernel="stresslet", periodicity=D)
+    plan, ur, _ = _run(env, "stresslet", s, D=D, tol=1e-8, split=True)
+    par = plan.params
+    ref = np.zeros_like(ur)
+    L = oracle.lib()
+    a, b = s["q"], s["nu"]
+    L.oracle_real_part(D, 2, oracle._d(s["box"]), par["xi"], par["rc"], len(s["x"]), oracle._d(s["x"]),
+                       oracle._d(np.ascontiguousarray(a)), oracle._d(np.ascontiguousarray(b)), len(s["x"]),
+                       oracle._d(s["x"]), oracle._l(np.arange(len(s["x"]), dtype=np.int64)), oracle._d(ref))
+    err = oracle.rms_rel_error(ur, ref)
+    print("D=%d real part rel err" % D, err)
+    assert err <= 1e-12
