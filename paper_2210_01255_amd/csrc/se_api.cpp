@@ -365,7 +365,7 @@ se_status se_plan_create(const se_problem* prob, const se_params* manual, se_pla
     p->d_sort_tmp = A.get<char>(std::max<size_t>(p->sort_tmp_bytes, 256));
     p->d_fs = A.get<char>((size_t)p->ncomp * p->ns * rs);
     p->d_fs64 = A.get<double>(4 * p->ns);
-    p->d_red = A.get<double>(8);
+    p->d_red = A.get<double>(SE_RED_OUT + 7 * SE_RED_BLOCKS);
     const size_t gv = (size_t)g.Mg[0] * g.Mg[1] * g.Mg[2];
     p->d_grid = A.get<char>((size_t)p->ncomp * gv * rs);
     const size_t sv = (size_t)p->Hx * p->Nfft[1] * g.Mg[2];
@@ -425,7 +425,7 @@ se_status se_plan_create(const se_problem* prob, const se_params* manual, se_pla
     if (e == hipSuccess) e = hipMemcpy(p->d_rtab, rtab.data(), rtab.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = aft_tables(p);
     if (e == hipSuccess) e = hipMemset(p->d_flags, 0, sizeof(int));
-    if (e == hipSuccess) e = hipMemset(p->d_red, 0, 8 * sizeof(double));
+    if (e == hipSuccess) e = hipMemset(p->d_red, 0, (SE_RED_OUT + 7 * SE_RED_BLOCKS) * sizeof(double));
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         free_all(p);

@@ -27,6 +27,10 @@
 #define SE_RTAB_DEG 10
 #define SE_RTAB_X 8.0
 
+// Source reductions: SE_RED_OUT results followed by 7 x SE_RED_BLOCKS partials.
+#define SE_RED_OUT 8
+#define SE_RED_BLOCKS 256
+
 // Line FFT limits (LDS-resident lines).
 #define SE_FFT_MAX_LEN 4096
 #define SE_FFT_THREADS 256
@@ -106,7 +110,7 @@ struct se_plan {
     size_t sort_tmp_bytes = 0;
     void* d_fs = nullptr;          // sorted strengths in grid precision [ncomp][ns]
     double* d_fs64 = nullptr;      // sorted strengths FP64 [3][ns] (self term), q.nu [ns]
-    double* d_red = nullptr;       // reductions: [0] sum q.nu, [1..3] sum x (q.nu)
+    double* d_red = nullptr;       // reductions: [0] sum q.nu, [1..3] sum x (q.nu), [4..6] sum f; partials
     void* d_grid = nullptr;        // real grid [ncomp][Mz][My][Mx]
     void* d_spec = nullptr;        // half spectrum [ncomp][Mz][Ny][Hx] complex
     double* d_pos4 = nullptr;      // sorted sources AoS [ns][4] (x, y, z, 0)

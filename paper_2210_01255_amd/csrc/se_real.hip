@@ -335,16 +335,21 @@ __global__ void k_strengths(const double* __restrict__ f, const int* __restrict_
     }
 }
 
-// Deterministic single-workgroup FP64 reductions over the sources:
+// Deterministic FP64 reductions over the sources, in two fixed-order stages:
 // out[0] = sum q.nu, out[1..3] = sum x (q.nu) (stresslet zero-mode term,
 // eq. k0-stresslet-3p), out[4..6] = sum f (gauge terms of the stokeslet).
+// Stage 1: block b reduces the contiguous chunk b into part[c * SE_RED_BLOCKS + b];
+// stage 2: one block reduces the partials.
 __global__ void __launch_bounds__(512) k_reduce_sources(const double* __restrict__ qn, const double* __restrict__ f,
                                                         const double* __restrict__ xs, int64_t n, int have_qn,
-                                                        double* out)
+                                                        double* part)
 {
     __shared__ double sm[7][512];
     double a[7] = {0, 0, 0, 0, 0, 0, 0};
-    for (int64_t i = threadIdx.x; i < n; i += 512) {
+    const int64_t chunk = (n + SE_RED_BLOCKS - 1) / SE_RED_BLOCKS;
+    const int64_t lo = (int64_t)blockIdx.x * chunk;
+    const int64_t hi = lo + chunk < n ? lo + chunk : n;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += 512) {
         double q = have_qn ? qn[i] : 0.0;
         a[0] += q;
         a[1] += xs[i] * q;
@@ -357,6 +362,19 @@ __global__ void __launch_bounds__(512) k_reduce_sources(const double* __restrict
     for (int c = 0; c < 7; c++) sm[c][threadIdx.x] = a[c];
     __syncthreads();
     for (int w = 256; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int c = 0; c < 7; c++) sm[c][threadIdx.x] += sm[c][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 7) part[threadIdx.x * SE_RED_BLOCKS + blockIdx.x] = sm[threadIdx.x][0];
+}
+
+__global__ void __launch_bounds__(SE_RED_BLOCKS) k_reduce_final(const double* __restrict__ part, double* out)
+{
+    __shared__ double sm[7][SE_RED_BLOCKS];
+    for (int c = 0; c < 7; c++) sm[c][threadIdx.x] = part[c * SE_RED_BLOCKS + threadIdx.x];
+    __syncthreads();
+    for (int w = SE_RED_BLOCKS / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w)
             for (int c = 0; c < 7; c++) sm[c][threadIdx.x] += sm[c][threadIdx.x + w];
         __syncthreads();
@@ -415,8 +433,10 @@ void se_launch_strengths(const se_plan* p, const double* f, hipStream_t s)
 
 void se_launch_reductions(const se_plan* p, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_reduce_sources, dim3(1), dim3(512), 0, s, p->d_fs64 + 3 * p->ns, p->d_fs64, p->d_src, p->ns,
-                       p->kernel == SE_STRESSLET ? 1 : 0, p->d_red);
+    double* part = p->d_red + SE_RED_OUT;
+    hipLaunchKernelGGL(k_reduce_sources, dim3(SE_RED_BLOCKS), dim3(512), 0, s, p->d_fs64 + 3 * p->ns, p->d_fs64,
+                       p->d_src, p->ns, p->kernel == SE_STRESSLET ? 1 : 0, part);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(SE_RED_BLOCKS), 0, s, part, p->d_red);
 }
 
 void se_launch_real_space(const se_plan* p, hipStream_t s)
