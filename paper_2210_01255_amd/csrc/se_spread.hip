@@ -15,6 +15,8 @@
 // Periodic axes wrap through unwrapped bin indices (each image shift of a
 // point is visited once, so supports wider than the grid are handled too);
 // free axes are clipped.
+#include <algorithm>
+
 #include "se_device.h"
 
 #define SE_TILE_THREADS 512
@@ -359,6 +361,378 @@ __global__ void __launch_bounds__(SE_TILE_THREADS) k_gather(se_tile_args a)
     });
 }
 
+// ---------------------------------------------------------------------------
+// Register-tiled gridding and gathering.
+// A workgroup (4 waves) owns a 16 x 16 x 8 block of grid points; wave w owns
+// the 8 x 8 (x, y) columns at ((w & 1) 8, (w >> 1) 8) and keeps their 8 z
+// values of every component in registers, so gridding needs no atomics at
+// all and gathering reads the grid once per block.  The candidate points
+// (anchors in the halo bins) are enumerated as runs of the sorted order and
+// processed in batches of 64: the batch's 1-D weights restricted to the block
+// (16 + 16 + 8 per point, PKB by Horner) are evaluated once into LDS, then
+// every wave applies each point whose support meets its columns.
+#define SE_RT_THREADS 256
+#define SE_RT_KB 64
+#define SE_RT_MAXSLOTS 512
+#define SE_RT_TX 16
+#define SE_RT_TY 16
+#define SE_RT_TZ 8
+#define SE_RT_NW (SE_RT_TX + SE_RT_TY + SE_RT_TZ)
+
+template <typename R, int NC>
+struct se_rt_lds {
+    double pkb[SE_MAX_P * (SE_MAX_NU + 1)];
+    int run_beg[SE_RT_MAXSLOTS];
+    int run_pre[SE_RT_MAXSLOTS + 1];
+    int run_shift[SE_RT_MAXSLOTS][3];
+    R w[SE_RT_KB][SE_RT_NW];
+    double t[SE_RT_KB][3];
+    int o[SE_RT_KB][3];
+    int idx[SE_RT_KB];
+    int list[4][SE_RT_KB];   // per wave: the batch's points whose support meets its columns
+    int cnt[4];
+    R f[SE_RT_KB][NC];       // gridding: the batch's strengths
+    double u[SE_RT_KB][3];   // gathering: the batch's block partial sums
+};
+
+// Runs of sorted points whose anchor bins lie in the block's halo: one slot
+// per (bin row, periodic x segment).  Returns the number of candidates.
+template <typename L>
+__device__ int rt_build_runs(const se_tile_args& a, const int* t0, const int* te, L& s, int tid)
+{
+    const se_grid_geom& g = a.g;
+    int b0[3], nbr[3];
+    halo_bins(g, t0, te, a.P, b0, nbr);
+    const int nrows = nbr[1] * nbr[2];
+    int kx0 = 0, kx1 = 0;
+    if (g.periodic[0]) {
+        kx0 = se_floordiv(b0[0], g.nb[0]);
+        kx1 = se_floordiv(b0[0] + nbr[0] - 1, g.nb[0]);
+    }
+    const int nseg = nbr[0] > 0 ? kx1 - kx0 + 1 : 0;
+    const int nslots = nrows * nseg;
+    for (int slot = tid; slot < nslots; slot += SE_RT_THREADS) {
+        const int row = slot / nseg, k = kx0 + slot % nseg;
+        const int uy = b0[1] + row % nbr[1], uz = b0[2] + row / nbr[1];
+        int sy = 0, sz = 0, wy = uy, wz = uz;
+        if (g.periodic[1]) {
+            int kk = se_floordiv(uy, g.nb[1]);
+            wy = uy - kk * g.nb[1];
+            sy = kk * g.Mg[1];
+        }
+        if (g.periodic[2]) {
+            int kk = se_floordiv(uz, g.nb[2]);
+            wz = uz - kk * g.nb[2];
+            sz = kk * g.Mg[2];
+        }
+        int lo = b0[0], hi = b0[0] + nbr[0] - 1;
+        if (g.periodic[0]) {
+            lo = max(lo, k * g.nb[0]);
+            hi = min(hi, (k + 1) * g.nb[0] - 1);
+        }
+        const int wx0 = lo - k * g.nb[0];
+        const int rowbase = (wz * g.nb[1] + wy) * g.nb[0];
+        const int beg = a.start[rowbase + wx0], end = a.start[rowbase + wx0 + (hi - lo + 1)];
+        s.run_beg[slot] = beg;
+        s.run_pre[slot + 1] = end - beg;  // lengths, scanned below
+        s.run_shift[slot][0] = g.periodic[0] ? k * g.Mg[0] : 0;
+        s.run_shift[slot][1] = sy;
+        s.run_shift[slot][2] = sz;
+    }
+    __syncthreads();
+    if (tid < 64) {
+        // inclusive scan of the lengths by one wave: chunks per lane, then lanes
+        const int per = (nslots + 63) / 64;
+        const int c0 = tid * per, c1 = min(c0 + per, nslots);
+        int sum = 0;
+        for (int i = c0; i < c1; i++) sum += s.run_pre[i + 1];
+        int incl = sum;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            int v = __shfl_up(incl, off, 64);
+            if (tid >= off) incl += v;
+        }
+        int run = incl - sum;
+        for (int i = c0; i < c1; i++) {
+            run += s.run_pre[i + 1];
+            s.run_pre[i + 1] = run;
+        }
+        if (tid == 0) s.run_pre[0] = 0;
+    }
+    __syncthreads();
+    return nslots > 0 ? s.run_pre[nslots] : 0;
+}
+
+__device__ __forceinline__ bool rt_meets(const int* o, int P, int wxo, int wyo)
+{
+    return o[0] < wxo + 8 && o[0] + P > wxo && o[1] < wyo + 8 && o[1] + P > wyo && o[2] < SE_RT_TZ && o[2] + P > 0;
+}
+
+// One batch: locate candidates base .. base + KB - 1, anchor them, list them
+// per wave (the points whose support meets the wave's 8 x 8 x 8 columns) and
+// stage the block-restricted 1-D weights.  Returns the batch size.
+template <typename R, bool GATHER, int NC, typename L>
+__device__ int rt_stage_batch(const se_tile_args& a, const int* t0, int nslots, int total, int base, L& s, int tid)
+{
+    const se_grid_geom& g = a.g;
+    const int nb = min(SE_RT_KB, total - base);
+    if (tid < SE_RT_KB) {
+        int sidx = -1;
+        if (tid < nb) {
+            const int f = base + tid;
+            int lo = 0, hi = nslots;  // largest r with run_pre[r] <= f
+            while (hi - lo > 1) {
+                int mid = (lo + hi) >> 1;
+                if (s.run_pre[mid] <= f) lo = mid;
+                else hi = mid;
+            }
+            sidx = s.run_beg[lo] + (f - s.run_pre[lo]);
+            const int64_t n = a.n;
+            const double xp[3] = {a.xs[sidx], a.xs[n + sidx], a.xs[2 * n + sidx]};
+#pragma unroll
+            for (int d = 0; d < 3; d++) {
+                double u = se_gridcoord(g, d, xp[d]);
+                int an = (int)floor(u);
+                an = an < 0 ? 0 : (an > g.Mg[d] - 1 ? g.Mg[d] - 1 : an);
+                s.t[tid][d] = u - an;
+                s.o[tid][d] = an + s.run_shift[lo][d] - a.P / 2 + 1 - t0[d];
+            }
+            if constexpr (!GATHER) {
+                const R* fs = (const R*)a.fs;
+#pragma unroll
+                for (int c = 0; c < NC; c++) s.f[tid][c] = fs[c * n + sidx];
+            }
+        }
+        if constexpr (GATHER) s.u[tid][0] = s.u[tid][1] = s.u[tid][2] = 0.0;
+        // one wave: ballot per sub-block, compacted lists
+        int o[3] = {s.o[tid][0], s.o[tid][1], s.o[tid][2]};
+        bool any = false;
+#pragma unroll
+        for (int w = 0; w < 4; w++) {
+            const bool m = sidx >= 0 && rt_meets(o, a.P, (w & 1) * 8, (w >> 1) * 8);
+            any = any || m;
+            const uint64_t bal = __ballot(m);
+            const int pos = __builtin_popcountll(bal & ((1ull << tid) - 1ull));
+            if (m) s.list[w][pos] = tid;
+            if (tid == 0) s.cnt[w] = __builtin_popcountll(bal);
+        }
+        s.idx[tid] = any ? sidx : -1;  // -1: no weights needed
+    }
+    __syncthreads();
+    for (int i = tid; i < nb * SE_RT_NW; i += SE_RT_THREADS) {
+        const int p = i / SE_RT_NW, j = i - p * SE_RT_NW;
+        const int dim = j < SE_RT_TX ? 0 : (j < SE_RT_TX + SE_RT_TY ? 1 : 2);
+        const int coord = dim == 0 ? j : (dim == 1 ? j - SE_RT_TX : j - SE_RT_TX - SE_RT_TY);
+        const int q = coord - s.o[p][dim];
+        R w = (R)0;
+        if (q >= 0 && q < a.P && s.idx[p] >= 0) w = pkb_weight<R>(s.pkb, q, (R)(1.0 - s.t[p][dim]));
+        s.w[p][j] = w;
+    }
+    __syncthreads();
+    return nb;
+}
+
+template <typename R, int NC>
+__global__ void __launch_bounds__(SE_RT_THREADS) k_spread_rt(se_tile_args a)
+{
+    __shared__ se_rt_lds<R, NC> s;
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const se_grid_geom& g = a.g;
+    int t0[3], te[3];
+    tile_origin(a.ntile, SE_RT_TX, SE_RT_TY, SE_RT_TZ, g, t0, te);
+    for (int i = tid; i < SE_MAX_P * (SE_MAX_NU + 1); i += SE_RT_THREADS) {
+        int q = i / (SE_MAX_NU + 1), k = i - q * (SE_MAX_NU + 1);
+        s.pkb[i] = (q < a.P && k <= a.nu) ? a.pkb[q * (a.nu + 1) + k] : 0.0;
+    }
+    int b0[3], nbr[3];
+    halo_bins(g, t0, te, a.P, b0, nbr);
+    const int total = rt_build_runs(a, t0, te, s, tid);
+    int nseg = 1;
+    if (g.periodic[0]) nseg = se_floordiv(b0[0] + nbr[0] - 1, g.nb[0]) - se_floordiv(b0[0], g.nb[0]) + 1;
+    const int nslots = nbr[0] > 0 ? nbr[1] * nbr[2] * nseg : 0;
+    const int wxo = (wave & 1) * 8, wyo = (wave >> 1) * 8;
+    const int lx = lane & 7, ly = lane >> 3;
+    R acc[SE_RT_TZ][NC];
+#pragma unroll
+    for (int z = 0; z < SE_RT_TZ; z++)
+#pragma unroll
+        for (int c = 0; c < NC; c++) acc[z][c] = (R)0;
+    for (int base = 0; base < total; base += SE_RT_KB) {
+        (void)rt_stage_batch<R, false, NC>(a, t0, nslots, total, base, s, tid);
+        const int cnt = __builtin_amdgcn_readfirstlane(s.cnt[wave]);
+        // two points per step so that the LDS reads of the second overlap the
+        // arithmetic of the first
+        int i = 0;
+        for (; i + 1 < cnt; i += 2) {
+            const int pa = __builtin_amdgcn_readfirstlane(s.list[wave][i]);
+            const int pb = __builtin_amdgcn_readfirstlane(s.list[wave][i + 1]);
+            const R wa = s.w[pa][wxo + lx] * s.w[pa][SE_RT_TX + wyo + ly];
+            const R wb = s.w[pb][wxo + lx] * s.w[pb][SE_RT_TX + wyo + ly];
+            R ga[NC], gb[NC], za[SE_RT_TZ], zb[SE_RT_TZ];
+#pragma unroll
+            for (int c = 0; c < NC; c++) {
+                ga[c] = wa * s.f[pa][c];
+                gb[c] = wb * s.f[pb][c];
+            }
+#pragma unroll
+            for (int z = 0; z < SE_RT_TZ; z++) {
+                za[z] = s.w[pa][SE_RT_TX + SE_RT_TY + z];
+                zb[z] = s.w[pb][SE_RT_TX + SE_RT_TY + z];
+            }
+#pragma unroll
+            for (int z = 0; z < SE_RT_TZ; z++)
+#pragma unroll
+                for (int c = 0; c < NC; c++) {
+                    acc[z][c] += ga[c] * za[z];
+                    acc[z][c] += gb[c] * zb[z];
+                }
+        }
+        if (i < cnt) {
+            const int p = __builtin_amdgcn_readfirstlane(s.list[wave][i]);
+            const R wxy = s.w[p][wxo + lx] * s.w[p][SE_RT_TX + wyo + ly];
+            R gv[NC];
+#pragma unroll
+            for (int c = 0; c < NC; c++) gv[c] = wxy * s.f[p][c];
+#pragma unroll
+            for (int z = 0; z < SE_RT_TZ; z++) {
+                const R wz = s.w[p][SE_RT_TX + SE_RT_TY + z];
+#pragma unroll
+                for (int c = 0; c < NC; c++) acc[z][c] += gv[c] * wz;
+            }
+        }
+        __syncthreads();
+    }
+    R* grid = (R*)a.grid;
+    const int64_t plane = (int64_t)g.Mg[0] * g.Mg[1];
+    const int64_t vol = plane * g.Mg[2];
+    const int ix = wxo + lx, iy = wyo + ly;
+    if (ix < te[0] && iy < te[1]) {
+        const int64_t col = (int64_t)(t0[1] + iy) * g.Mg[0] + t0[0] + ix;
+#pragma unroll
+        for (int z = 0; z < SE_RT_TZ; z++) {
+            if (z < te[2]) {
+                const int64_t o = (int64_t)(t0[2] + z) * plane + col;
+#pragma unroll
+                for (int c = 0; c < NC; c++) grid[c * vol + o] = acc[z][c];
+            }
+        }
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ R rt_wave_sum(R v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(SE_RT_THREADS) k_gather_rt(se_tile_args a)
+{
+    __shared__ se_rt_lds<R, 3> s;
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const se_grid_geom& g = a.g;
+    int t0[3], te[3];
+    tile_origin(a.ntile, SE_RT_TX, SE_RT_TY, SE_RT_TZ, g, t0, te);
+    for (int i = tid; i < SE_MAX_P * (SE_MAX_NU + 1); i += SE_RT_THREADS) {
+        int q = i / (SE_MAX_NU + 1), k = i - q * (SE_MAX_NU + 1);
+        s.pkb[i] = (q < a.P && k <= a.nu) ? a.pkb[q * (a.nu + 1) + k] : 0.0;
+    }
+    const int wxo = (wave & 1) * 8, wyo = (wave >> 1) * 8;
+    const int lx = lane & 7, ly = lane >> 3;
+    R F[SE_RT_TZ][3];
+    {
+        const R* grid = (const R*)a.grid;
+        const int64_t plane = (int64_t)g.Mg[0] * g.Mg[1];
+        const int64_t vol = plane * g.Mg[2];
+        const int ix = wxo + lx, iy = wyo + ly;
+        const bool in = ix < te[0] && iy < te[1];
+        const int64_t col = in ? (int64_t)(t0[1] + iy) * g.Mg[0] + t0[0] + ix : 0;
+#pragma unroll
+        for (int z = 0; z < SE_RT_TZ; z++) {
+            const bool inz = in && z < te[2];
+            const int64_t o = inz ? (int64_t)(t0[2] + z) * plane + col : 0;
+#pragma unroll
+            for (int c = 0; c < 3; c++) F[z][c] = inz ? grid[c * vol + o] : (R)0;
+        }
+    }
+    int b0[3], nbr[3];
+    halo_bins(g, t0, te, a.P, b0, nbr);
+    const int total = rt_build_runs(a, t0, te, s, tid);
+    int nseg = 1;
+    if (g.periodic[0]) nseg = se_floordiv(b0[0] + nbr[0] - 1, g.nb[0]) - se_floordiv(b0[0], g.nb[0]) + 1;
+    const int nslots = nbr[0] > 0 ? nbr[1] * nbr[2] * nseg : 0;
+    const int64_t n = a.n;
+    for (int base = 0; base < total; base += SE_RT_KB) {
+        const int nb = rt_stage_batch<R, true, 3>(a, t0, nslots, total, base, s, tid);
+        // Groups of 8 points: per-lane partial sums v[3j + c], then one
+        // reduce-scatter over the wave (halving steps xor 32, 16, 8 leave lane
+        // group k = bits 5..3 with point k's three sums; xor 4, 2, 1 finish).
+        const int cnt = __builtin_amdgcn_readfirstlane(s.cnt[wave]);
+        for (int i0 = 0; i0 < cnt; i0 += 8) {
+            R v[24];
+#pragma unroll
+            for (int j = 0; j < 8; j++) {
+                v[3 * j] = v[3 * j + 1] = v[3 * j + 2] = (R)0;
+                if (i0 + j >= cnt) continue;
+                const int p = __builtin_amdgcn_readfirstlane(s.list[wave][i0 + j]);
+                const R wxy = s.w[p][wxo + lx] * s.w[p][SE_RT_TX + wyo + ly];
+                R v0 = 0, v1 = 0, v2 = 0;
+#pragma unroll
+                for (int z = 0; z < SE_RT_TZ; z++) {
+                    const R wz = s.w[p][SE_RT_TX + SE_RT_TY + z];
+                    v0 += wz * F[z][0];
+                    v1 += wz * F[z][1];
+                    v2 += wz * F[z][2];
+                }
+                v[3 * j] = v0 * wxy;
+                v[3 * j + 1] = v1 * wxy;
+                v[3 * j + 2] = v2 * wxy;
+            }
+            const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
+            R v12[12];
+#pragma unroll
+            for (int i = 0; i < 12; i++) {
+                const R mine = b5 ? v[12 + i] : v[i], oth = b5 ? v[i] : v[12 + i];
+                v12[i] = mine + __shfl_xor(oth, 32, 64);
+            }
+            R v6[6];
+#pragma unroll
+            for (int i = 0; i < 6; i++) {
+                const R mine = b4 ? v12[6 + i] : v12[i], oth = b4 ? v12[i] : v12[6 + i];
+                v6[i] = mine + __shfl_xor(oth, 16, 64);
+            }
+            R v3[3];
+#pragma unroll
+            for (int i = 0; i < 3; i++) {
+                const R mine = b3 ? v6[3 + i] : v6[i], oth = b3 ? v6[i] : v6[3 + i];
+                v3[i] = mine + __shfl_xor(oth, 8, 64);
+            }
+#pragma unroll
+            for (int off = 4; off > 0; off >>= 1)
+#pragma unroll
+                for (int i = 0; i < 3; i++) v3[i] += __shfl_xor(v3[i], off, 64);
+            if ((lane & 7) == 0) {
+                const int k = i0 + (b5 ? 4 : 0) + (b4 ? 2 : 0) + (b3 ? 1 : 0);
+                if (k < cnt) {
+                    const int p = s.list[wave][k];
+                    atomicAdd(&s.u[p][0], (double)v3[0]);
+                    atomicAdd(&s.u[p][1], (double)v3[1]);
+                    atomicAdd(&s.u[p][2], (double)v3[2]);
+                }
+            }
+        }
+        __syncthreads();
+        if (tid < 3 * nb) {
+            const int p = tid / 3, c = tid - 3 * p;
+            const double v = s.u[p][c];
+            if (v != 0.0) atomicAdd(&a.u[c * n + s.idx[p]], v);
+        }
+        __syncthreads();
+    }
+}
+
 template <typename K>
 void set_lds(K kern, size_t bytes)
 {
@@ -409,28 +783,75 @@ void launch_gather(const se_plan* p, hipStream_t s)
 // Tile shape used by both kernels (grid points per axis).
 void se_tile_shape(int ncomp, bool fp32, int* tile)
 {
-    tile[0] = 16;
-    tile[1] = 16;
-    tile[2] = (ncomp == 6 && !fp32) ? 4 : 8;
+    (void)ncomp;
+    (void)fp32;
+    tile[0] = SE_RT_TX;
+    tile[1] = SE_RT_TY;
+    tile[2] = SE_RT_TZ;
+}
+
+// The register-tiled kernels keep one slot per (halo bin row, x segment) in
+// LDS; bound the count for this grid.
+bool se_rt_fits(const se_plan* p)
+{
+    const se_grid_geom& g = p->g;
+    const int T[3] = {SE_RT_TX, SE_RT_TY, SE_RT_TZ};
+    int nbr[3];
+    for (int d = 0; d < 3; d++) {
+        nbr[d] = (T[d] + p->par.P - 2) / g.B[d] + 2;
+        if (!g.periodic[d]) nbr[d] = std::min(nbr[d], g.nb[d]);
+    }
+    const int nseg = g.periodic[0] ? (nbr[0] + g.nb[0] - 1) / g.nb[0] + 1 : 1;
+    return (int64_t)nbr[1] * nbr[2] * nseg <= SE_RT_MAXSLOTS && p->par.P <= SE_MAX_P;
+}
+
+template <typename R, int NC>
+void launch_spread_rt(const se_plan* p, hipStream_t s)
+{
+    se_tile_args a = make_args(p, false);
+    unsigned nb = (unsigned)(p->ntile[0] * p->ntile[1] * p->ntile[2]);
+    hipLaunchKernelGGL((k_spread_rt<R, NC>), dim3(nb), dim3(SE_RT_THREADS), 0, s, a);
+}
+
+template <typename R>
+void launch_gather_rt(const se_plan* p, hipStream_t s)
+{
+    se_tile_args a = make_args(p, true);
+    unsigned nb = (unsigned)(p->ntile[0] * p->ntile[1] * p->ntile[2]);
+    hipLaunchKernelGGL((k_gather_rt<R>), dim3(nb), dim3(SE_RT_THREADS), 0, s, a);
 }
 
 void se_launch_spread(const se_plan* p, hipStream_t s)
 {
+    if (se_rt_fits(p)) {
+        if (p->fp32) {
+            if (p->ncomp == 3) launch_spread_rt<float, 3>(p, s);
+            else launch_spread_rt<float, 6>(p, s);
+        } else {
+            if (p->ncomp == 3) launch_spread_rt<double, 3>(p, s);
+            else launch_spread_rt<double, 6>(p, s);
+        }
+        return;
+    }
     if (p->fp32) {
         if (p->ncomp == 3) launch_spread<float, 3, 16, 16, 8>(p, s);
         else launch_spread<float, 6, 16, 16, 8>(p, s);
     } else {
         if (p->ncomp == 3) launch_spread<double, 3, 16, 16, 8>(p, s);
-        else launch_spread<double, 6, 16, 16, 4>(p, s);
+        else launch_spread<double, 6, 16, 16, 8>(p, s);
     }
 }
 
 void se_launch_gather(const se_plan* p, hipStream_t s)
 {
+    if (se_rt_fits(p)) {
+        if (p->fp32) launch_gather_rt<float>(p, s);
+        else launch_gather_rt<double>(p, s);
+        return;
+    }
     if (p->fp32) {
         launch_gather<float, 16, 16, 8>(p, s);
     } else {
-        if (p->ncomp == 3) launch_gather<double, 16, 16, 8>(p, s);
-        else launch_gather<double, 16, 16, 4>(p, s);
+        launch_gather<double, 16, 16, 8>(p, s);
     }
 }
