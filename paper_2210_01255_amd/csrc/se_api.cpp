@@ -415,7 +415,7 @@ se_status se_plan_create(const se_problem* prob, const se_params* manual, se_pla
         }
     }
     std::vector<double> rtab;
-    se_radial_table(&rtab);
+    se_radial_table(se_rtab_xmax(par), &rtab);
     std::vector<double> tw;
     se_fft_twiddles(p->Nfft, &tw, p->tw_off);
 

@@ -23,9 +23,8 @@
 #define SE_MAX_NU 10
 
 // Real-space radial-function table (see se_radial_table)
-#define SE_RTAB_N 64
+#define SE_RTAB_N 32
 #define SE_RTAB_DEG 10
-#define SE_RTAB_X 8.0
 
 // Source reductions: SE_RED_OUT results followed by 7 x SE_RED_BLOCKS partials.
 #define SE_RED_OUT 8
@@ -140,7 +139,9 @@ se_status se_select_params(const se_problem* p, const se_params* manual, se_para
                            std::string* msg);
 bool se_smooth_factors(int n, std::vector<int>* radices);
 void se_pkb_coefficients(int P, int nu, double beta, std::vector<double>* coef);
-void se_radial_table(std::vector<double>* tab);
+void se_radial_table(double xmax, std::vector<double>* tab);
+// Range of the radial table: x = xi r for r < rc (slightly widened).
+inline double se_rtab_xmax(const se_params& par) { return par.xi * par.rc * (1.0 + 1e-9) + 1e-300; }
 double se_kb_fourier(double k, double a, double beta);
 
 // ---- kernels (se_*.hip): host-side launch wrappers

@@ -222,15 +222,16 @@ void se_pkb_coefficients(int P, int nu, double beta, std::vector<double>* coef)
 // Radial functions of the real-space kernels in x = xi r:
 //   G(x) = erfc(x) + (2x/sqrt(pi)) e^{-x^2},   E(x) = e^{-x^2},
 // (eqs. stokeslet-real, rotlet-real, stresslet-real are combinations of G/r
-// and E), as piecewise polynomials on SE_RTAB_N intervals of width
-// SE_RTAB_X/SE_RTAB_N, each interpolating at SE_RTAB_DEG+1 Chebyshev points
-// of the first kind; monomial basis in sigma = 2 s - 1 (s local in [0,1]).
+// and E), as piecewise polynomials on SE_RTAB_N intervals of [0, xmax]
+// (xmax = xi rc: only pairs inside the cut-off are evaluated), each
+// interpolating at SE_RTAB_DEG+1 Chebyshev points of the first kind; monomial
+// basis in sigma = 2 s - 1 (s local in [0,1]).
 // Layout tab[f][interval][SE_RTAB_DEG+1], f = 0: G, 1: E.
-void se_radial_table(std::vector<double>* tab)
+void se_radial_table(double xmax, std::vector<double>* tab)
 {
     const int n = SE_RTAB_DEG + 1;
     tab->assign((size_t)2 * SE_RTAB_N * n, 0.0);
-    const long double w = (long double)SE_RTAB_X / SE_RTAB_N;
+    const long double w = (long double)xmax / SE_RTAB_N;
     const long double sqpi = std::sqrt((long double)kPi);
     std::vector<long double> A(n * n), rhs(n), sig(n);
     for (int i = 0; i < n; i++) sig[i] = -std::cos((2.0L * i + 1.0L) * (long double)kPi / (2.0L * n));

@@ -23,6 +23,7 @@ struct se_real_args {
     const int* start;  // source cell starts
     const int* tstart; // target cell starts
     double xi, rc2;
+    double rscale;     // SE_RTAB_N / (table range in x = xi r)
     int Ra[3];         // anchor reach ceil(rc/h)+1
     int tas;
     double* u;         // [3][nt]
@@ -47,12 +48,12 @@ __device__ __forceinline__ double horner_tab(const double* c, double sg)
 //   T:     -2 r (r.q)(r.nu)/r^4 * (3G + (4x^3/sqrt(pi)) E)/r
 //          + (4 xi^3/sqrt(pi)) E (q (r.nu) + nu (r.q) + r (q.nu))
 template <int KER>
-__device__ __forceinline__ void real_pair(const double* tab, double xi, const double* r, double r2, const double* f,
-                                          const double* nu, double* u)
+__device__ __forceinline__ void real_pair(const double* tab, double xi, double rscale, const double* r, double r2,
+                                          const double* f, const double* nu, double* u)
 {
     const double inv = rsqrt(r2);
     const double x = xi * r2 * inv;
-    const double xs = x * (SE_RTAB_N / SE_RTAB_X);
+    const double xs = x * rscale;
     const int iv = min((int)xs, SE_RTAB_N - 1);
     const double sg = 2.0 * (xs - iv) - 1.0;
     const double G = horner_tab(tab + iv * kRn, sg);
@@ -140,7 +141,7 @@ __device__ __forceinline__ void eval_queue(const se_real_args& a, const double* 
             nu[2] = nv.z;
         }
         double u[3] = {0.0, 0.0, 0.0};
-        real_pair<KER>(tab, a.xi, r, r2, f, nu, u);
+        real_pair<KER>(tab, a.xi, a.rscale, r, r2, f, nu, u);
         atomicAdd(&L.acc[0][j], u[0]);
         atomicAdd(&L.acc[1][j], u[1]);
         atomicAdd(&L.acc[2][j], u[2]);
@@ -296,6 +297,301 @@ __global__ void __launch_bounds__(256) k_real(se_real_args a)
         int cb[3] = {(int)(c % g.nb[0]), (int)((c / g.nb[0]) % g.nb[1]), (int)(c / ((int64_t)g.nb[0] * g.nb[1]))};
         for (int t0 = tb; t0 < te; t0 += SE_RT) real_cell<KER>(a, tab, lds[wave], cb, t0, min(SE_RT, te - t0), lane);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Blocked real-space sum.  One wavefront per block of TB^3 target bins (about
+// 48 targets, one per lane).  The sources that can lie within rc of the
+// block's box form runs of the sorted order (rows of bins trimmed to the
+// remaining reach, split at periodic wraps); they are streamed through LDS 64
+// at a time, the next batch's loads in flight while the current one is used.
+// Each lane tests its target against the 64 staged sources (one broadcast
+// read each) and keeps a 64-bit hit mask, then walks its own mask evaluating
+// the pairs; the sums stay in registers, so there are no atomics and every
+// candidate is read from HBM/L2 once per block.
+#define SE_R2_SLOTS 320
+#define SE_R2_TROWS 16
+
+#define SE_R2_QCAP 512
+
+template <int KER>
+struct se_real2_lds {
+    double cx[64], cy[64], cz[64];  // shifted candidate positions
+    double fx[64], fy[64], fz[64];  // strengths
+    double nx[KER == SE_STRESSLET ? 64 : 1], ny[KER == SE_STRESSLET ? 64 : 1],
+        nz[KER == SE_STRESSLET ? 64 : 1];  // normals (stresslet)
+    double tx[64], ty[64], tz[64];  // target positions of the chunk
+    double acc[3][64];
+    unsigned short q[SE_R2_QCAP];   // queued pairs: (target lane << 6) | candidate slot
+    int cid[64];      // sorted index when unshifted, else -1
+    int run_beg[SE_R2_SLOTS];
+    int run_pre[SE_R2_SLOTS + 1];
+    int trow_beg[SE_R2_TROWS];
+    int trow_pre[SE_R2_TROWS + 1];
+};
+
+struct se_real2_geom {
+    int TB;          // target bins per block and axis
+    int nbk[3];      // blocks per axis
+    int64_t nblk;
+};
+
+__device__ __forceinline__ int wave_incl_scan(int v, int lane)
+{
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        int t = __shfl_up(v, off, 64);
+        if (lane >= off) v += t;
+    }
+    return v;
+}
+
+template <int KER>
+__device__ __forceinline__ void eval_queue2(const se_real_args& a, const double* tab, se_real2_lds<KER>& L, int qn,
+                                            int lane)
+{
+    wave_sync();
+    for (int e0 = 0; e0 < qn; e0 += 64) {
+        const int e = e0 + lane;
+        if (e < qn) {
+            const int qv = L.q[e];
+            const int tl = qv >> 6, c = qv & 63;
+            const double r[3] = {L.tx[tl] - L.cx[c], L.ty[tl] - L.cy[c], L.tz[tl] - L.cz[c]};
+            const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+            const double f[3] = {L.fx[c], L.fy[c], L.fz[c]};
+            double nu[3] = {0.0, 0.0, 0.0};
+            if constexpr (KER == SE_STRESSLET) {
+                nu[0] = L.nx[c];
+                nu[1] = L.ny[c];
+                nu[2] = L.nz[c];
+            }
+            double u[3] = {0.0, 0.0, 0.0};
+            real_pair<KER>(tab, a.xi, a.rscale, r, r2, f, nu, u);
+            atomicAdd(&L.acc[0][tl], u[0]);
+            atomicAdd(&L.acc[1][tl], u[1]);
+            atomicAdd(&L.acc[2][tl], u[2]);
+        }
+    }
+    wave_sync();
+}
+
+template <int KER>
+__global__ void __launch_bounds__(256) k_real2(se_real_args a, se_real2_geom bg)
+{
+    __shared__ double tab[2 * SE_RTAB_N * kRn];
+    __shared__ se_real2_lds<KER> lds[4];
+    for (int i = threadIdx.x; i < 2 * SE_RTAB_N * kRn; i += 256) tab[i] = a.rtab[i];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t blk = (int64_t)se_xcd_block(blockIdx.x, gridDim.x) * 4 + wave;
+    if (blk >= bg.nblk) return;
+    se_real2_lds<KER>& L = lds[wave];
+    const se_grid_geom& g = a.g;
+    const int ib[3] = {(int)(blk % bg.nbk[0]), (int)((blk / bg.nbk[0]) % bg.nbk[1]),
+                       (int)(blk / ((int64_t)bg.nbk[0] * bg.nbk[1]))};
+    int b0[3], b1[3], a0[3], a1[3], blo[3], bhi[3];
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        b0[d] = ib[d] * bg.TB;
+        b1[d] = min(b0[d] + bg.TB, g.nb[d]) - 1;
+        a0[d] = b0[d] * g.B[d];
+        a1[d] = min((b1[d] + 1) * g.B[d], g.Mg[d]) - 1;
+        blo[d] = se_floordiv(a0[d] - a.Ra[d], g.B[d]);
+        bhi[d] = se_floordiv(a1[d] + a.Ra[d], g.B[d]);
+        if (!g.periodic[d]) {
+            blo[d] = max(blo[d], 0);
+            bhi[d] = min(bhi[d], g.nb[d] - 1);
+        }
+    }
+    // ---- candidate runs
+    const int ny = bhi[1] - blo[1] + 1, nz = bhi[2] - blo[2] + 1;
+    int kx0 = 0, kx1 = 0;
+    if (g.periodic[0]) {
+        kx0 = se_floordiv(blo[0], g.nb[0]);
+        kx1 = se_floordiv(bhi[0], g.nb[0]);
+    }
+    const int nseg = kx1 - kx0 + 1;
+    const int nslots = ny * nz * nseg;
+    const double rc2 = a.rc2;
+    for (int slot = lane; slot < nslots; slot += 64) {
+        const int row = slot / nseg, k = kx0 + slot % nseg;
+        const int by = blo[1] + row % ny, bz = blo[2] + row / ny;
+        const int ky = g.periodic[1] ? se_floordiv(by, g.nb[1]) : 0;
+        const int kz = g.periodic[2] ? se_floordiv(bz, g.nb[2]) : 0;
+        const int wy = by - ky * g.nb[1], wz = bz - kz * g.nb[2];
+        const int y0 = by * g.B[1], y1 = y0 + g.B[1];
+        const int z0 = bz * g.B[2], z1 = z0 + g.B[2];
+        const double dy = max(0, max(y0 - (a1[1] + 1), a0[1] - y1)) * g.h[1];
+        const double dz = max(0, max(z0 - (a1[2] + 1), a0[2] - z1)) * g.h[2];
+        const double rem2 = rc2 - dy * dy - dz * dz;
+        int len = 0, beg = 0;
+        if (rem2 > 0.0) {
+            const int rx = (int)ceil(sqrt(rem2) * g.invh[0]) + 1;
+            int lo = max(se_floordiv(a0[0] - rx, g.B[0]), blo[0]);
+            int hi = min(se_floordiv(a1[0] + rx, g.B[0]), bhi[0]);
+            if (g.periodic[0]) {
+                lo = max(lo, k * g.nb[0]);
+                hi = min(hi, (k + 1) * g.nb[0] - 1);
+            }
+            if (lo <= hi) {
+                const int rowbase = (wz * g.nb[1] + wy) * g.nb[0];
+                const int wx0 = lo - k * g.nb[0];
+                beg = a.start[rowbase + wx0];
+                len = a.start[rowbase + wx0 + (hi - lo + 1)] - beg;
+            }
+        }
+        L.run_beg[slot] = beg;
+        L.run_pre[slot + 1] = len;
+    }
+    wave_sync();
+    {
+        const int per = (nslots + 63) / 64;
+        const int c0 = lane * per, c1 = min(c0 + per, nslots);
+        int sum = 0;
+        for (int i = c0; i < c1; i++) sum += L.run_pre[i + 1];
+        int run = wave_incl_scan(sum, lane) - sum;
+        for (int i = c0; i < c1; i++) {
+            run += L.run_pre[i + 1];
+            L.run_pre[i + 1] = run;
+        }
+        if (lane == 0) L.run_pre[0] = 0;
+    }
+    // ---- target rows of the block
+    const int tnx = b1[0] - b0[0] + 1, tny = b1[1] - b0[1] + 1, tnz = b1[2] - b0[2] + 1;
+    const int ntrows = tny * tnz;
+    {
+        int cnt = 0;
+        if (lane < ntrows) {
+            const int by = b0[1] + lane % tny, bz = b0[2] + lane / tny;
+            const int rowbase = (bz * g.nb[1] + by) * g.nb[0];
+            const int tb = a.tstart[rowbase + b0[0]];
+            L.trow_beg[lane] = tb;
+            cnt = a.tstart[rowbase + b0[0] + tnx] - tb;
+        }
+        const int incl = wave_incl_scan(cnt, lane);
+        if (lane < ntrows) L.trow_pre[lane + 1] = incl;
+        if (lane == 0) L.trow_pre[0] = 0;
+    }
+    wave_sync();
+    const int total = L.run_pre[nslots];
+    const int ntarg = L.trow_pre[ntrows];
+    int coinc = 0;
+    for (int tc = 0; tc < ntarg; tc += 64) {
+        const int ft = tc + lane;
+        const bool tvalid = ft < ntarg;
+        int tidx = 0;
+        if (tvalid) {
+            int r = 0;
+            while (r + 1 < ntrows && L.trow_pre[r + 1] <= ft) r++;
+            tidx = L.trow_beg[r] + (ft - L.trow_pre[r]);
+        }
+        const double4 tq = a.xt[tvalid ? tidx : 0];
+        L.tx[lane] = tq.x;
+        L.ty[lane] = tq.y;
+        L.tz[lane] = tq.z;
+        L.acc[0][lane] = L.acc[1][lane] = L.acc[2][lane] = 0.0;
+        // prefetch registers for one candidate per lane
+        double4 np = make_double4(0, 0, 0, 0), nf = np, nn = np;
+        int nid = -1;
+        auto load = [&](int cbase) {
+            const int f = cbase + lane;
+            if (f < total) {
+                int lo = 0, hi = nslots;
+                while (hi - lo > 1) {
+                    int mid = (lo + hi) >> 1;
+                    if (L.run_pre[mid] <= f) lo = mid;
+                    else hi = mid;
+                }
+                const int sidx = L.run_beg[lo] + (f - L.run_pre[lo]);
+                // image shift of the slot (row, x segment), as in the run table
+                const int row = lo / nseg;
+                const int kx = g.periodic[0] ? kx0 + lo % nseg : 0;
+                const int ky = g.periodic[1] ? se_floordiv(blo[1] + row % ny, g.nb[1]) : 0;
+                const int kz = g.periodic[2] ? se_floordiv(blo[2] + row / ny, g.nb[2]) : 0;
+                const double4 p = a.xs[sidx];
+                np = make_double4(p.x + kx * g.L[0], p.y + ky * g.L[1], p.z + kz * g.L[2], 0.0);
+                nf = a.f[sidx];
+                if (KER == SE_STRESSLET) nn = a.nrm[sidx];
+                nid = (kx == 0 && ky == 0 && kz == 0) ? sidx : -1;
+            }
+        };
+        load(0);
+        for (int cb = 0; cb < total; cb += 64) {
+            L.cx[lane] = np.x;
+            L.cy[lane] = np.y;
+            L.cz[lane] = np.z;
+            L.fx[lane] = nf.x;
+            L.fy[lane] = nf.y;
+            L.fz[lane] = nf.z;
+            if constexpr (KER == SE_STRESSLET) {
+                L.nx[lane] = nn.x;
+                L.ny[lane] = nn.y;
+                L.nz[lane] = nn.z;
+            }
+            L.cid[lane] = nid;
+            wave_sync();
+            if (cb + 64 < total) load(cb + 64);
+            const int n = min(64, total - cb);
+            // tests in groups of 8 (reads first, then arithmetic); the mask is
+            // built as two 32-bit words with compile-time bit positions
+            uint32_t mw[2] = {0u, 0u};
+            for (int c8 = 0; c8 < n; c8 += 8) {
+                double qx[8], qy[8], qz[8];
+#pragma unroll
+                for (int k = 0; k < 8; k++) {
+                    qx[k] = L.cx[c8 + k];
+                    qy[k] = L.cy[c8 + k];
+                    qz[k] = L.cz[c8 + k];
+                }
+                uint32_t bits = 0u, zbits = 0u;
+#pragma unroll
+                for (int k = 0; k < 8; k++) {
+                    const double d0 = tq.x - qx[k], d1 = tq.y - qy[k], d2 = tq.z - qz[k];
+                    const double rr = d0 * d0 + d1 * d1 + d2 * d2;
+                    const bool inb = tvalid && (c8 + k < n);
+                    bits |= (inb && rr < rc2 && rr != 0.0) ? (1u << k) : 0u;
+                    zbits |= (inb && rr == 0.0) ? (1u << k) : 0u;
+                }
+                if (__ballot(zbits != 0u)) {
+                    // the excluded self term (targets are sources) or a coincident pair
+#pragma unroll
+                    for (int k = 0; k < 8; k++)
+                        if (((zbits >> k) & 1u) && !(a.tas && L.cid[c8 + k] == tidx)) coinc = 1;
+                }
+                mw[c8 >> 5] |= bits << (c8 & 31);
+            }
+            uint64_t mask = ((uint64_t)mw[1] << 32) | mw[0];
+            // Queue the hits round-robin over the targets (the k-th hit of every
+            // target, then the (k+1)-th, ...), so a window of 64 queued pairs
+            // holds (nearly) distinct targets, and evaluate 64 pairs per step
+            // at full width with one LDS accumulation per component.
+            int qn = 0;
+            while (__ballot(mask != 0)) {
+                const bool has = mask != 0;
+                const uint64_t b = __ballot(has);
+                const int nb = __popcll(b);
+                if (qn + nb > SE_R2_QCAP) {
+                    eval_queue2<KER>(a, tab, L, qn, lane);
+                    qn = 0;
+                }
+                if (has) {
+                    const int c = __builtin_ctzll(mask);
+                    mask &= mask - 1;
+                    L.q[qn + __popcll(b & ((1ull << lane) - 1ull))] = (unsigned short)((lane << 6) | c);
+                }
+                qn += nb;
+            }
+            eval_queue2<KER>(a, tab, L, qn, lane);
+            wave_sync();
+        }
+        if (tvalid) {
+            a.u[tidx] = L.acc[0][lane];
+            a.u[a.nt + tidx] = L.acc[1][lane];
+            a.u[2 * a.nt + tidx] = L.acc[2][lane];
+        }
+        wave_sync();
+    }
+    if (__ballot(coinc) && lane == 0) atomicOr(a.flags, SE_FLAG_COINCIDENT);
 }
 
 // Sorted strengths: FP64 copy [3][ns] of f (or q) for the real-space sum and
@@ -454,10 +750,34 @@ void se_launch_real_space(const se_plan* p, hipStream_t s)
     a.tstart = p->tas ? p->d_src_start : p->d_tgt_start;
     a.xi = p->par.xi;
     a.rc2 = p->par.rc * p->par.rc;
+    a.rscale = SE_RTAB_N / se_rtab_xmax(p->par);
     for (int d = 0; d < 3; d++) a.Ra[d] = (int)std::ceil(p->par.rc / p->g.h[d]) + 1;
     a.tas = p->tas ? 1 : 0;
     a.u = p->d_uR;
     a.flags = p->d_flags;
+    // blocked kernel: TB^3 target bins per wavefront, about 48 targets
+    const se_grid_geom& g = p->g;
+    const int64_t nbins = (int64_t)g.nb[0] * g.nb[1] * g.nb[2];
+    const double per_bin = (double)p->nt / (double)nbins;
+    int TB = (int)std::lround(std::cbrt(48.0 / std::max(per_bin, 1e-9)));
+    TB = std::max(1, std::min(TB, 4));
+    se_real2_geom bg;
+    bg.TB = TB;
+    int span[3];
+    for (int d = 0; d < 3; d++) {
+        bg.nbk[d] = (g.nb[d] + TB - 1) / TB;
+        span[d] = (TB * g.B[d] + 2 * a.Ra[d]) / g.B[d] + 2;
+        if (!g.periodic[d]) span[d] = std::min(span[d], g.nb[d]);
+    }
+    bg.nblk = (int64_t)bg.nbk[0] * bg.nbk[1] * bg.nbk[2];
+    const int nseg = g.periodic[0] ? (span[0] + g.nb[0] - 1) / g.nb[0] + 1 : 1;
+    if ((int64_t)span[1] * span[2] * nseg <= SE_R2_SLOTS && TB * TB <= SE_R2_TROWS) {
+        unsigned nwg = (unsigned)((bg.nblk + 3) / 4);
+        if (p->kernel == SE_STOKESLET) hipLaunchKernelGGL(k_real2<SE_STOKESLET>, dim3(nwg), dim3(256), 0, s, a, bg);
+        else if (p->kernel == SE_ROTLET) hipLaunchKernelGGL(k_real2<SE_ROTLET>, dim3(nwg), dim3(256), 0, s, a, bg);
+        else hipLaunchKernelGGL(k_real2<SE_STRESSLET>, dim3(nwg), dim3(256), 0, s, a, bg);
+        return;
+    }
     unsigned nb = (unsigned)std::min<int64_t>((p->nt + 3) / 4, SE_REAL_BLOCKS);
     if (p->kernel == SE_STOKESLET) hipLaunchKernelGGL(k_real<SE_STOKESLET>, dim3(nb), dim3(256), 0, s, a);
     else if (p->kernel == SE_ROTLET) hipLaunchKernelGGL(k_real<SE_ROTLET>, dim3(nb), dim3(256), 0, s, a);
