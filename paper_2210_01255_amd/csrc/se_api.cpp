@@ -313,6 +313,7 @@ se_status se_plan_create(const se_problem* prob, const se_params* manual, se_pla
     }
     p->nbins = (int64_t)g.nb[0] * g.nb[1] * g.nb[2];
     p->Hx = p->Nfft[0] / 2 + 1;
+    p->Hp = (p->Hx + 7) / 8 * 8;
     se_tile_shape(p->ncomp, p->fp32, p->tile);
     for (int d = 0; d < 3; d++) p->ntile[d] = (g.Mg[d] + p->tile[d] - 1) / p->tile[d];
 
@@ -320,7 +321,8 @@ se_status se_plan_create(const se_problem* prob, const se_params* manual, se_pla
     std::vector<int> rr;
     bool ok = (p->Nfft[0] % 2 == 0) && se_smooth_factors(p->Nfft[0] / 2, &rr) && p->Nfft[0] / 2 <= SE_FFT_LDS_ELEMS &&
               se_smooth_factors(p->Nfft[1], &rr) && p->Nfft[1] <= SE_FFT_LDS_ELEMS &&
-              se_smooth_factors(p->Nfft[2], &rr) && p->ncomp * p->Nfft[2] <= (p->fp32 ? 6144 : 3072);
+              se_smooth_factors(p->Nfft[2], &rr) && p->Nfft[2] <= SE_FFT_LDS_ELEMS &&
+              se_fft_fits(p->Nfft, p->ncomp, p->fp32);
     if (ok && (p->D == 1 || p->D == 2)) {
         aft_shapes(p);
         for (const se_aft_class& c : p->cls) {
@@ -368,7 +370,7 @@ se_status se_plan_create(const se_problem* prob, const se_params* manual, se_pla
     p->d_red = A.get<double>(SE_RED_OUT + 7 * SE_RED_BLOCKS);
     const size_t gv = (size_t)g.Mg[0] * g.Mg[1] * g.Mg[2];
     p->d_grid = A.get<char>((size_t)p->ncomp * gv * rs);
-    const size_t sv = (size_t)p->Hx * p->Nfft[1] * g.Mg[2];
+    const size_t sv = (size_t)p->Hp * p->Nfft[1] * g.Mg[2];
     p->d_spec = A.get<char>((size_t)p->ncomp * sv * 2 * rs);
     p->d_pos4 = A.get<double>(4 * p->ns);
     if (!p->tas) p->d_tpos4 = A.get<double>(4 * p->nt);

@@ -23,15 +23,15 @@ namespace {
 struct se_fft_args {
     int Mg[3];
     int N[3];
-    int Hx;
+    int Hx;     // half-spectrum extent along x (kx = 0 .. Hx-1)
+    int Hp;     // row pitch of the half spectrum (complex elements, >= Hx)
     int ncomp;
     void* grid;
     void* spec;
     const double* tw;
     int tw_xh, tw_xp, tw_y, tw_z;
-    int rad_xh[SE_MAX_RAD], nrad_xh;
-    int rad_y[SE_MAX_RAD], nrad_y;
-    int rad_z[SE_MAX_RAD], nrad_z;
+    uint64_t rad_xh, rad_y, rad_z;  // radix sequences, 4 bits per stage (first stage lowest)
+    int nrad_xh, nrad_y, nrad_z;
     int lines;  // rows per workgroup (x passes)
     int cols;   // kx columns per workgroup (y, z passes)
     // scaling
@@ -49,170 +49,203 @@ struct se_fft_args {
 template <typename R>
 using C = se_cplx<R>;
 
-// ---------------------------------------------------------------- small DFTs
+// ---------------------------------------------------------------- butterflies
+// forward (dir = +1): out[k] = sum_n v[n] e^{-2 pi i n k / RAD}; inverse with +i
 template <typename R>
 __device__ __forceinline__ C<R> mul_mi(C<R> a, int dir)  // a * (-i dir)
 {
     return dir > 0 ? C<R>{a.y, -a.x} : C<R>{-a.y, a.x};
 }
+template <typename R>
+__device__ __forceinline__ C<R> cadd(C<R> a, C<R> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename R>
+__device__ __forceinline__ C<R> csub(C<R> a, C<R> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename R>
+__device__ __forceinline__ C<R> cscale(C<R> a, R s) { return {a.x * s, a.y * s}; }
 
-template <int RAD>
-struct se_dft_tab;
-template <>
-struct se_dft_tab<3> {
-    static constexpr double c[3] = {1.0, -0.5, -0.5};
-    static constexpr double s[3] = {0.0, 0.8660254037844386467637232, -0.8660254037844386467637232};
-};
-template <>
-struct se_dft_tab<5> {
-    static constexpr double c[5] = {1.0, 0.3090169943749474241022934, -0.8090169943749474241022934,
-                                    -0.8090169943749474241022934, 0.3090169943749474241022934};
-    static constexpr double s[5] = {0.0, 0.9510565162951535721164393, 0.587785252292473129168706,
-                                    -0.587785252292473129168706, -0.9510565162951535721164393};
-};
-template <>
-struct se_dft_tab<7> {
-    static constexpr double c[7] = {1.0, 0.6234898018587335305250049, -0.2225209339563144042889026,
-                                    -0.9009688679024191262361023, -0.9009688679024191262361023,
-                                    -0.2225209339563144042889026, 0.6234898018587335305250049};
-    static constexpr double s[7] = {0.0, 0.7818314824680298087084445, 0.9749279121818236070181317,
-                                    0.4338837391175581204757683, -0.4338837391175581204757683,
-                                    -0.9749279121818236070181317, -0.7818314824680298087084445};
-};
-
-// forward: out[k] = sum_n v[n] e^{-2 pi i n k / RAD}; inverse with +i
 template <typename R, int RAD>
 __device__ __forceinline__ void dft_small(C<R>* v, int dir)
 {
     if constexpr (RAD == 2) {
         C<R> a = v[0], b = v[1];
-        v[0] = {a.x + b.x, a.y + b.y};
-        v[1] = {a.x - b.x, a.y - b.y};
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    } else if constexpr (RAD == 3) {
+        const R s3 = (R)0.8660254037844386467637232;  // sin(2 pi/3)
+        C<R> t1 = cadd(v[1], v[2]);
+        C<R> t2 = csub(v[0], cscale(t1, (R)0.5));
+        C<R> t3 = mul_mi(cscale(csub(v[1], v[2]), s3), dir);
+        v[0] = cadd(v[0], t1);
+        v[1] = cadd(t2, t3);
+        v[2] = csub(t2, t3);
     } else if constexpr (RAD == 4) {
-        C<R> a0 = v[0], a1 = v[1], a2 = v[2], a3 = v[3];
-        C<R> s02 = {a0.x + a2.x, a0.y + a2.y}, d02 = {a0.x - a2.x, a0.y - a2.y};
-        C<R> s13 = {a1.x + a3.x, a1.y + a3.y}, d13 = {a1.x - a3.x, a1.y - a3.y};
+        C<R> s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+        C<R> s13 = cadd(v[1], v[3]), d13 = csub(v[1], v[3]);
         C<R> t = mul_mi(d13, dir);
-        v[0] = {s02.x + s13.x, s02.y + s13.y};
-        v[2] = {s02.x - s13.x, s02.y - s13.y};
-        v[1] = {d02.x + t.x, d02.y + t.y};
-        v[3] = {d02.x - t.x, d02.y - t.y};
-    } else if constexpr (RAD == 8) {
+        v[0] = cadd(s02, s13);
+        v[2] = csub(s02, s13);
+        v[1] = cadd(d02, t);
+        v[3] = csub(d02, t);
+    } else if constexpr (RAD == 5) {
+        const R c1 = (R)0.3090169943749474241022934, c2 = (R)-0.8090169943749474241022934;  // cos(2pi/5), cos(4pi/5)
+        const R s1 = (R)0.9510565162951535721164393, s2 = (R)0.5877852522924731291687060;   // sin(2pi/5), sin(4pi/5)
+        C<R> t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
+        C<R> t3 = csub(v[1], v[4]), t4 = csub(v[2], v[3]);
+        C<R> a1 = {v[0].x + c1 * t1.x + c2 * t2.x, v[0].y + c1 * t1.y + c2 * t2.y};
+        C<R> a2 = {v[0].x + c2 * t1.x + c1 * t2.x, v[0].y + c2 * t1.y + c1 * t2.y};
+        C<R> b1 = mul_mi(C<R>{s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y}, dir);
+        C<R> b2 = mul_mi(C<R>{s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y}, dir);
+        v[0] = {v[0].x + t1.x + t2.x, v[0].y + t1.y + t2.y};
+        v[1] = cadd(a1, b1);
+        v[4] = csub(a1, b1);
+        v[2] = cadd(a2, b2);
+        v[3] = csub(a2, b2);
+    } else if constexpr (RAD == 7) {
+        // pairs (n, 7 - n): y_k = x0 + sum_n [cos(2 pi n k/7)(x_n + x_{7-n})
+        //                               - i dir sin(2 pi n k/7)(x_n - x_{7-n})]
+        const R cc[3] = {(R)0.6234898018587335305250049, (R)-0.2225209339563144042889026,
+                         (R)-0.9009688679024191262361023};
+        const R ss[3] = {(R)0.7818314824680298087084445, (R)0.9749279121818236070181317,
+                         (R)0.4338837391175581204757683};
+        C<R> sp[3], sm[3];
+#pragma unroll
+        for (int n = 0; n < 3; n++) {
+            sp[n] = cadd(v[n + 1], v[6 - n]);
+            sm[n] = csub(v[n + 1], v[6 - n]);
+        }
+        C<R> y[7];
+        y[0] = {v[0].x + sp[0].x + sp[1].x + sp[2].x, v[0].y + sp[0].y + sp[1].y + sp[2].y};
+#pragma unroll
+        for (int k = 1; k <= 3; k++) {
+            C<R> a = v[0], b = {(R)0, (R)0};
+#pragma unroll
+            for (int n = 1; n <= 3; n++) {
+                const int m = (n * k) % 7;  // cos(2 pi m/7), sin(2 pi m/7) from the first half
+                const R c = m <= 3 ? cc[m - 1] : cc[7 - m - 1];
+                const R sn = m <= 3 ? ss[m - 1] : -ss[7 - m - 1];
+                a = {a.x + c * sp[n - 1].x, a.y + c * sp[n - 1].y};
+                b = {b.x + sn * sm[n - 1].x, b.y + sn * sm[n - 1].y};
+            }
+            C<R> t = mul_mi(b, dir);
+            y[k] = cadd(a, t);
+            y[7 - k] = csub(a, t);
+        }
+#pragma unroll
+        for (int k = 0; k < 7; k++) v[k] = y[k];
+    } else {
         C<R> e[4] = {v[0], v[2], v[4], v[6]};
         C<R> o[4] = {v[1], v[3], v[5], v[7]};
         dft_small<R, 4>(e, dir);
         dft_small<R, 4>(o, dir);
         const R h = (R)0.7071067811865475244008444;
-        // W8^k, k = 0..3 (forward e^{-i pi k/4})
         C<R> w1 = {h, dir > 0 ? -h : h};
         C<R> w3 = {-h, dir > 0 ? -h : h};
         C<R> o1 = cmul(o[1], w1);
         C<R> o2 = mul_mi(o[2], dir);
         C<R> o3 = cmul(o[3], w3);
-        v[0] = {e[0].x + o[0].x, e[0].y + o[0].y};
-        v[4] = {e[0].x - o[0].x, e[0].y - o[0].y};
-        v[1] = {e[1].x + o1.x, e[1].y + o1.y};
-        v[5] = {e[1].x - o1.x, e[1].y - o1.y};
-        v[2] = {e[2].x + o2.x, e[2].y + o2.y};
-        v[6] = {e[2].x - o2.x, e[2].y - o2.y};
-        v[3] = {e[3].x + o3.x, e[3].y + o3.y};
-        v[7] = {e[3].x - o3.x, e[3].y - o3.y};
-    } else {
-        C<R> out[RAD];
-#pragma unroll
-        for (int k = 0; k < RAD; k++) {
-            R ax = 0, ay = 0;
-#pragma unroll
-            for (int n = 0; n < RAD; n++) {
-                const int m = (n * k) % RAD;
-                const R c = (R)se_dft_tab<RAD>::c[m];
-                const R s = (R)se_dft_tab<RAD>::s[m] * (R)dir;
-                // v * (c - i s)
-                ax += v[n].x * c + v[n].y * s;
-                ay += v[n].y * c - v[n].x * s;
-            }
-            out[k] = {ax, ay};
-        }
-#pragma unroll
-        for (int k = 0; k < RAD; k++) v[k] = out[k];
+        v[0] = cadd(e[0], o[0]);
+        v[4] = csub(e[0], o[0]);
+        v[1] = cadd(e[1], o1);
+        v[5] = csub(e[1], o1);
+        v[2] = cadd(e[2], o2);
+        v[6] = csub(e[2], o2);
+        v[3] = cadd(e[3], o3);
+        v[7] = csub(e[3], o3);
     }
 }
 
-// One Stockham stage of radix RAD over `nl` lines of length N held in LDS.
-// Line l starts at (l / lpg) * gs + (l % lpg) * ls; element e at +e*es.
-// Work item idx -> (line, butterfly j); lines_fastest selects which index
-// varies fastest across threads (pick the one that is unit stride in LDS).
-template <typename R, int RAD, int ELEMS>
-__device__ __forceinline__ void fft_stage(C<R>* buf, int N, int nl, int lpg, int gs, int ls, int es,
-                                          bool lines_fastest, const C<R>* tw, int dir, int Ns)
+// q = a / d, r = a % d for 0 <= a < 2^20, 1 <= d < 2^12, through a float
+// reciprocal (one correction step covers its rounding).
+__device__ __forceinline__ int fdiv(int a, int d, float rd, int* rem)
 {
-    constexpr int MAXB = (ELEMS / RAD + SE_FFT_THREADS - 1) / SE_FFT_THREADS;
+    int q = (int)((float)a * rd);
+    int r = a - q * d;
+    if (r < 0) {
+        q--;
+        r += d;
+    } else if (r >= d) {
+        q++;
+        r -= d;
+    }
+    *rem = r;
+    return q;
+}
+
+// One out-of-place Stockham stage of radix RAD over `nl` lines of length N
+// held in LDS (src -> dst).  Line l starts at (l / lpg) * gs + (l % lpg) * ls,
+// element e at + e * es.  Each work item is one butterfly (no register arrays
+// across butterflies); with lines_fastest the line index varies fastest
+// across threads (nl must then be a power of two), otherwise the butterfly
+// index does (unit stride in LDS either way for the layouts used here).
+template <typename R, int RAD>
+__device__ __forceinline__ void stage_pp(const C<R>* __restrict__ src, C<R>* __restrict__ dst, int N, int nl, int lpg,
+                                         int gs, int ls, int es, bool lines_fastest, const C<R>* tw, int dir, int Ns)
+{
     const int nb = N / RAD;
     const int total = nb * nl;
     const int tstride = N / (Ns * RAD);
-    C<R> v[MAXB][RAD];
-    int base[MAXB], jj[MAXB];
-#pragma unroll
-    for (int b = 0; b < MAXB; b++) {
-        int idx = threadIdx.x + b * SE_FFT_THREADS;
-        base[b] = -1;
-        if (idx < total) {
-            int line, j;
-            if (lines_fastest) {
-                line = idx % nl;
-                j = idx / nl;
-            } else {
-                j = idx % nb;
-                line = idx / nb;
-            }
-            base[b] = (line / lpg) * gs + (line % lpg) * ls;
-            jj[b] = j;
-            const int jn = j % Ns;
-            const int ts = jn * tstride;
-#pragma unroll
-            for (int r = 0; r < RAD; r++) {
-                C<R> x = buf[base[b] + (j + r * nb) * es];
-                if (r > 0) {
-                    C<R> w = tw[r * ts];
-                    if (dir < 0) w.y = -w.y;
-                    x = cmul(x, w);
-                }
-                v[b][r] = x;
-            }
+    const float rnb = 1.0f / (float)nb, rns = 1.0f / (float)Ns, rlpg = 1.0f / (float)lpg;
+    const int lsh = __builtin_ctz((unsigned)nl);
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+        int line, j;
+        if (lines_fastest) {
+            line = idx & (nl - 1);
+            j = idx >> lsh;
+        } else {
+            line = fdiv(idx, nb, rnb, &j);
         }
-    }
-    __syncthreads();
+        int lr;
+        const int lq = fdiv(line, lpg, rlpg, &lr);
+        const int base = lq * gs + lr * ls;
+        int jn;
+        const int jq = fdiv(j, Ns, rns, &jn);
+        const int ts = jn * tstride;
+        C<R> v[RAD];
+        v[0] = src[base + j * es];
 #pragma unroll
-    for (int b = 0; b < MAXB; b++) {
-        if (base[b] >= 0) {
-            dft_small<R, RAD>(v[b], dir);
-            const int j = jj[b];
-            const int jn = j % Ns;
-            const int od = (j / Ns) * Ns * RAD + jn;
-#pragma unroll
-            for (int r = 0; r < RAD; r++) buf[base[b] + (od + r * Ns) * es] = v[b][r];
+        for (int r = 1; r < RAD; r++) {
+            C<R> w = tw[r * ts];
+            if (dir < 0) w.y = -w.y;
+            v[r] = cmul(src[base + (j + r * nb) * es], w);
         }
+        dft_small<R, RAD>(v, dir);
+        const int od = jq * Ns * RAD + jn;
+#pragma unroll
+        for (int r = 0; r < RAD; r++) dst[base + (od + r * Ns) * es] = v[r];
     }
-    __syncthreads();
 }
 
-template <typename R, int ELEMS>
-__device__ void fft_lines(C<R>* buf, int N, int nl, int lpg, int gs, int ls, int es, bool lines_fastest,
-                          const C<R>* tw, int dir, const int* rad, int nrad)
+// Full transform, alternating between the two buffers; returns the index
+// (0 or 1) of the buffer that holds the result.  The input must be complete
+// (synchronised) on entry; the result is synchronised on return.
+template <typename R>
+__device__ __forceinline__ int fft_pp(C<R>* b0, C<R>* b1, int N, int nl, int lpg, int gs, int ls, int es, bool lines_fastest,
+                      const C<R>* tw, int dir, const int* rad, int nrad)
 {
-    int Ns = 1;
+    int Ns = 1, cur = 0;
     for (int s = 0; s < nrad; s++) {
-        int r = rad[s];
+        const int r = rad[s];
+        C<R>* src = cur ? b1 : b0;
+        C<R>* dst = cur ? b0 : b1;
         switch (r) {
-            case 2: fft_stage<R, 2, ELEMS>(buf, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
-            case 3: fft_stage<R, 3, ELEMS>(buf, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
-            case 4: fft_stage<R, 4, ELEMS>(buf, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
-            case 5: fft_stage<R, 5, ELEMS>(buf, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
-            case 7: fft_stage<R, 7, ELEMS>(buf, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
-            default: fft_stage<R, 8, ELEMS>(buf, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
+            case 2: stage_pp<R, 2>(src, dst, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
+            case 3: stage_pp<R, 3>(src, dst, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
+            case 4: stage_pp<R, 4>(src, dst, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
+            case 5: stage_pp<R, 5>(src, dst, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
+            case 7: stage_pp<R, 7>(src, dst, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
+            default: stage_pp<R, 8>(src, dst, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
         }
+        __syncthreads();
         Ns *= r;
+        cur ^= 1;
     }
+    return cur;
+}
+
+// radix sequence (4 bits per stage) into an LDS array
+__device__ __forceinline__ void load_rad(int* dst, uint64_t code, int n)
+{
+    if ((int)threadIdx.x < n) dst[threadIdx.x] = (int)((code >> (4 * threadIdx.x)) & 15u);
 }
 
 template <typename R>
@@ -222,14 +255,19 @@ __device__ __forceinline__ void load_tw(C<R>* dst, const double* src, int n)
 }
 
 // ------------------------------------------------------------ x: real -> half
+// Rows of M0 reals (zero padded to N0) as N0/2 complex values, one FFT of
+// length N0/2, then the split into the half spectrum k = 0..N0/2.
 template <typename R>
 __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_x_r2c(se_fft_args a)
 {
     extern __shared__ double smem_d[];
+    __shared__ int s_rad[16];
+    load_rad(s_rad, a.rad_xh, a.nrad_xh);
     const int Nh = a.N[0] / 2;
     C<R>* tw = (C<R>*)smem_d;
     C<R>* twp = tw + Nh;
-    C<R>* buf = twp + Nh + 1;
+    C<R>* b0 = twp + Nh + 1;
+    C<R>* b1 = b0 + a.lines * Nh;
     load_tw(tw, a.tw + 2 * a.tw_xh, Nh);
     load_tw(twp, a.tw + 2 * a.tw_xp, Nh + 1);
     const int64_t rows = (int64_t)a.ncomp * a.Mg[2] * a.Mg[1];
@@ -243,14 +281,14 @@ __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_x_r2c(se_fft_args a)
         const R* row = grid + (row0 + l) * M0;
         R re = (2 * k < M0) ? row[2 * k] : (R)0;
         R im = (2 * k + 1 < M0) ? row[2 * k + 1] : (R)0;
-        buf[l * Nh + k] = {re, im};
+        b0[l * Nh + k] = {re, im};
     }
     __syncthreads();
-    fft_lines<R, SE_FFT_LDS_ELEMS>(buf, Nh, nl, nl, 0, Nh, 1, false, tw, 1, a.rad_xh, a.nrad_xh);
+    const C<R>* Z = fft_pp<R>(b0, b1, Nh, nl, nl, 0, Nh, 1, false, tw, 1, s_rad, a.nrad_xh) ? b1 : b0;
     for (int i = threadIdx.x; i < nl * (Nh + 1); i += blockDim.x) {
         int l = i / (Nh + 1), k = i - l * (Nh + 1);
-        C<R> zk = buf[l * Nh + (k % Nh)];
-        C<R> zn = buf[l * Nh + ((Nh - k) % Nh)];
+        C<R> zk = Z[l * Nh + (k % Nh)];
+        C<R> zn = Z[l * Nh + ((Nh - k) % Nh)];
         zn.y = -zn.y;  // conj(Z_{N-k})
         C<R> A = {(zk.x + zn.x) * (R)0.5, (zk.y + zn.y) * (R)0.5};
         C<R> Bm = {(zk.x - zn.x) * (R)0.5, (zk.y - zn.y) * (R)0.5};
@@ -260,7 +298,7 @@ __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_x_r2c(se_fft_args a)
         int64_t row = row0 + l;
         int64_t cz = row / a.Mg[1];
         int y = (int)(row - cz * a.Mg[1]);
-        spec[(cz * a.N[1] + y) * a.Hx + k] = X;
+        spec[(cz * a.N[1] + y) * a.Hp + k] = X;
     }
 }
 
@@ -269,10 +307,13 @@ template <typename R>
 __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_x_c2r(se_fft_args a)
 {
     extern __shared__ double smem_d[];
+    __shared__ int s_rad[16];
+    load_rad(s_rad, a.rad_xh, a.nrad_xh);
     const int Nh = a.N[0] / 2;
     C<R>* tw = (C<R>*)smem_d;
     C<R>* twp = tw + Nh;
-    C<R>* buf = twp + Nh + 1;
+    C<R>* b0 = twp + Nh + 1;
+    C<R>* b1 = b0 + a.lines * Nh;
     load_tw(tw, a.tw + 2 * a.tw_xh, Nh);
     load_tw(twp, a.tw + 2 * a.tw_xp, Nh + 1);
     __syncthreads();
@@ -286,7 +327,7 @@ __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_x_c2r(se_fft_args a)
         int64_t row = row0 + l;
         int64_t cz = row / a.Mg[1];
         int y = (int)(row - cz * a.Mg[1]);
-        const C<R>* X = spec + (cz * a.N[1] + y) * a.Hx;
+        const C<R>* X = spec + (cz * a.N[1] + y) * a.Hp;
         C<R> xk = X[k];
         C<R> xn = X[Nh - k];
         xn.y = -xn.y;  // conj(X_{N-k})
@@ -295,52 +336,57 @@ __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_x_c2r(se_fft_args a)
         C<R> w = twp[k];
         w.y = -w.y;  // e^{+2 pi i k/N0}
         C<R> Bp = cmul(d, w);
-        buf[l * Nh + k] = {Ap.x - Bp.y, Ap.y + Bp.x};  // A' + i B'
+        b0[l * Nh + k] = {Ap.x - Bp.y, Ap.y + Bp.x};  // A' + i B'
     }
     __syncthreads();
-    fft_lines<R, SE_FFT_LDS_ELEMS>(buf, Nh, nl, nl, 0, Nh, 1, false, tw, -1, a.rad_xh, a.nrad_xh);
+    const C<R>* Z = fft_pp<R>(b0, b1, Nh, nl, nl, 0, Nh, 1, false, tw, -1, s_rad, a.nrad_xh) ? b1 : b0;
     const int M0 = a.Mg[0];
     for (int i = threadIdx.x; i < nl * Nh; i += blockDim.x) {
         int l = i / Nh, k = i - l * Nh;
         R* row = grid + (row0 + l) * M0;
-        C<R> z = buf[l * Nh + k];
+        C<R> z = Z[l * Nh + k];
         if (2 * k < M0) row[2 * k] = z.x;
         if (2 * k + 1 < M0) row[2 * k + 1] = z.y;
     }
 }
 
 // ------------------------------------------------------------ y: complex
+// A bundle of `cols` adjacent kx columns (contiguous in a row) for one (c, z).
 template <typename R>
 __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_y(se_fft_args a, int dir)
 {
     extern __shared__ double smem_d[];
+    __shared__ int s_rad[16];
+    load_rad(s_rad, a.rad_y, a.nrad_y);
     const int Ny = a.N[1];
-    C<R>* tw = (C<R>*)smem_d;
-    C<R>* buf = tw + Ny;
-    load_tw(tw, a.tw + 2 * a.tw_y, Ny);
     const int Cc = a.cols;
+    C<R>* tw = (C<R>*)smem_d;
+    C<R>* b0 = tw + Ny;
+    C<R>* b1 = b0 + Ny * Cc;
+    load_tw(tw, a.tw + 2 * a.tw_y, Ny);
     const int nbx = (a.Hx + Cc - 1) / Cc;
     int bid = blockIdx.x;
     int bx = bid % nbx;
     int64_t cz = bid / nbx;  // c * Mz + z
     const int kx0 = bx * Cc;
     C<R>* spec = (C<R>*)a.spec;
-    C<R>* base = spec + cz * (int64_t)Ny * a.Hx;
+    C<R>* base = spec + cz * (int64_t)Ny * a.Hp;
     const int n_in = dir > 0 ? a.Mg[1] : Ny;
     const int n_out = dir > 0 ? Ny : a.Mg[1];
     for (int i = threadIdx.x; i < Ny * Cc; i += blockDim.x) {
         int y = i / Cc, col = i - y * Cc;
         int kx = kx0 + col;
-        C<R> v = {(R)0, (R)0};
-        if (kx < a.Hx && y < n_in) v = base[(int64_t)y * a.Hx + kx];
-        buf[y * Cc + col] = v;
+        // unconditional load from a valid address (kx0 < Hx), then select
+        const bool ok = kx < a.Hx && y < n_in;
+        const C<R> t = base[ok ? (int64_t)y * a.Hp + kx : (int64_t)kx0];
+        b0[y * Cc + col] = {ok ? t.x : (R)0, ok ? t.y : (R)0};
     }
     __syncthreads();
-    fft_lines<R, SE_FFT_LDS_ELEMS>(buf, Ny, Cc, Cc, 0, 1, Cc, true, tw, dir, a.rad_y, a.nrad_y);
+    const C<R>* Z = fft_pp<R>(b0, b1, Ny, Cc, Cc, 0, 1, Cc, true, tw, dir, s_rad, a.nrad_y) ? b1 : b0;
     for (int i = threadIdx.x; i < n_out * Cc; i += blockDim.x) {
         int y = i / Cc, col = i - y * Cc;
         int kx = kx0 + col;
-        if (kx < a.Hx) base[(int64_t)y * a.Hx + kx] = buf[y * Cc + col];
+        if (kx < a.Hx) base[(int64_t)y * a.Hp + kx] = Z[y * Cc + col];
     }
 }
 
@@ -424,15 +470,18 @@ __device__ __forceinline__ void scale_point(const se_fft_args& a, int ix, int iy
 }
 
 // Plain complex transform along z (no scaling) for `ncomp` components.
-template <typename R, int ELEMS>
+template <typename R>
 __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_z(se_fft_args a, int dir)
 {
     extern __shared__ double smem_d[];
+    __shared__ int s_rad[16];
+    load_rad(s_rad, a.rad_z, a.nrad_z);
     const int Nz = a.N[2];
-    C<R>* tw = (C<R>*)smem_d;
-    C<R>* buf = tw + Nz;
-    load_tw(tw, a.tw + 2 * a.tw_z, Nz);
     const int Cc = a.cols;
+    C<R>* tw = (C<R>*)smem_d;
+    C<R>* b0 = tw + Nz;
+    C<R>* b1 = b0 + Nz * Cc;
+    load_tw(tw, a.tw + 2 * a.tw_z, Nz);
     const int nbx = (a.Hx + Cc - 1) / Cc;
     const int bx = blockIdx.x % nbx;
     const int rest = blockIdx.x / nbx;
@@ -440,85 +489,108 @@ __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_z(se_fft_args a, int dir
     const int c = rest / a.N[1];
     const int kx0 = bx * Cc;
     const int Mz = a.Mg[2];
-    const int64_t zstride = (int64_t)a.N[1] * a.Hx;
+    const int64_t zstride = (int64_t)a.N[1] * a.Hp;
     C<R>* spec = (C<R>*)a.spec + (int64_t)c * Mz * zstride;
     const int n_in = dir > 0 ? Mz : Nz;
     const int n_out = dir > 0 ? Nz : Mz;
     for (int i = threadIdx.x; i < Nz * Cc; i += blockDim.x) {
         int z = i / Cc, col = i - z * Cc;
         int kx = kx0 + col;
-        C<R> v = {(R)0, (R)0};
-        if (kx < a.Hx && z < n_in && z < Mz) v = spec[z * zstride + (int64_t)y * a.Hx + kx];
-        buf[i] = v;
+        const bool ok = kx < a.Hx && z < n_in && z < Mz;
+        const C<R> t = spec[ok ? z * zstride + (int64_t)y * a.Hp + kx : (int64_t)y * a.Hp + kx0];
+        b0[i] = {ok ? t.x : (R)0, ok ? t.y : (R)0};
     }
     __syncthreads();
-    fft_lines<R, ELEMS>(buf, Nz, Cc, Cc, 0, 1, Cc, true, tw, dir, a.rad_z, a.nrad_z);
+    const C<R>* Z = fft_pp<R>(b0, b1, Nz, Cc, Cc, 0, 1, Cc, true, tw, dir, s_rad, a.nrad_z) ? b1 : b0;
     for (int i = threadIdx.x; i < n_out * Cc; i += blockDim.x) {
         int z = i / Cc, col = i - z * Cc;
         int kx = kx0 + col;
-        if (kx < a.Hx && z < Mz) spec[z * zstride + (int64_t)y * a.Hx + kx] = buf[i];
+        if (kx < a.Hx && z < Mz) spec[z * zstride + (int64_t)y * a.Hp + kx] = Z[i];
     }
 }
 
-template <typename R, int KER, int NC, int ELEMS>
+// Transform along z, scaling and inverse transform for one bundle of `cols`
+// kx columns at one y, all components resident in LDS.  NC + 1 column sets:
+// each component is transformed by ping-pong with the spare set, and the
+// roles follow the result (where[c] = set holding component c).
+template <typename R, int KER, int NC>
 __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_z_scale(se_fft_args a)
 {
     extern __shared__ double smem_d[];
+    __shared__ int s_rad[16];
+    load_rad(s_rad, a.rad_z, a.nrad_z);
     const int Nz = a.N[2];
-    C<R>* tw = (C<R>*)smem_d;
-    C<R>* buf = tw + Nz;
-    load_tw(tw, a.tw + 2 * a.tw_z, Nz);
     const int Cc = a.cols;
+    const int cs = Nz * Cc;  // LDS column-set size
+    C<R>* tw = (C<R>*)smem_d;
+    C<R>* sets = tw + Nz;
+    load_tw(tw, a.tw + 2 * a.tw_z, Nz);
     const int nbx = (a.Hx + Cc - 1) / Cc;
     const int bx = blockIdx.x % nbx;
     const int y = blockIdx.x / nbx;
     const int kx0 = bx * Cc;
     const int Mz = a.Mg[2];
-    const int64_t cstride = (int64_t)Mz * a.N[1] * a.Hx;
-    const int64_t zstride = (int64_t)a.N[1] * a.Hx;
+    const int64_t cstride = (int64_t)Mz * a.N[1] * a.Hp;
+    const int64_t zstride = (int64_t)a.N[1] * a.Hp;
     C<R>* spec = (C<R>*)a.spec;
-    const int cs = Nz * Cc;  // LDS component stride
     for (int i = threadIdx.x; i < NC * cs; i += blockDim.x) {
         int c = i / cs, rem = i - c * cs;
         int z = rem / Cc, col = rem - z * Cc;
         int kx = kx0 + col;
-        C<R> v = {(R)0, (R)0};
-        if (kx < a.Hx && z < Mz) v = spec[c * cstride + z * zstride + (int64_t)y * a.Hx + kx];
-        buf[i] = v;
+        const bool ok = kx < a.Hx && z < Mz;
+        const C<R> t = spec[c * cstride + (ok ? z * zstride + (int64_t)y * a.Hp + kx : (int64_t)y * a.Hp + kx0)];
+        sets[i] = {ok ? t.x : (R)0, ok ? t.y : (R)0};
     }
     __syncthreads();
-    fft_lines<R, ELEMS>(buf, Nz, NC * Cc, Cc, cs, 1, Cc, true, tw, 1, a.rad_z, a.nrad_z);
+    int where[NC];
+    int spare = NC;
+#pragma unroll
+    for (int c = 0; c < NC; c++) {
+        const int r = fft_pp<R>(sets + c * cs, sets + spare * cs, Nz, Cc, Cc, 0, 1, Cc, true, tw, 1, s_rad, a.nrad_z);
+        where[c] = r ? spare : c;
+        spare = r ? c : spare;
+    }
     for (int i = threadIdx.x; i < cs; i += blockDim.x) {
         int z = i / Cc, col = i - z * Cc;
         int kx = kx0 + col;
         if (kx >= a.Hx) continue;
         C<R> F[NC], U[3];
 #pragma unroll
-        for (int c = 0; c < NC; c++) F[c] = buf[c * cs + i];
+        for (int c = 0; c < NC; c++) F[c] = sets[where[c] * cs + i];
         scale_point<R, KER, NC>(a, kx, y, z, F, U);
 #pragma unroll
-        for (int j = 0; j < 3; j++) buf[j * cs + i] = U[j];
+        for (int j = 0; j < 3; j++) sets[where[j] * cs + i] = U[j];
     }
     __syncthreads();
-    fft_lines<R, ELEMS>(buf, Nz, 3 * Cc, Cc, cs, 1, Cc, true, tw, -1, a.rad_z, a.nrad_z);
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        const int r = fft_pp<R>(sets + where[c] * cs, sets + spare * cs, Nz, Cc, Cc, 0, 1, Cc, true, tw, -1, s_rad,
+                                a.nrad_z);
+        if (r) {
+            const int t = where[c];
+            where[c] = spare;
+            spare = t;
+        }
+    }
     for (int i = threadIdx.x; i < 3 * cs; i += blockDim.x) {
         int c = i / cs, rem = i - c * cs;
         int z = rem / Cc, col = rem - z * Cc;
         int kx = kx0 + col;
-        if (kx < a.Hx && z < Mz) spec[c * cstride + z * zstride + (int64_t)y * a.Hx + kx] = buf[i];
+        if (kx < a.Hx && z < Mz) spec[c * cstride + z * zstride + (int64_t)y * a.Hp + kx] = sets[where[c] * cs + rem];
     }
 }
 
-// z-pass LDS budget (complex elements) per precision
-template <typename R>
-constexpr int z_elems() { return sizeof(R) == 8 ? 3072 : 6144; }
+// LDS budgets (bytes) of the line kernels: two workgroups per CU.
+constexpr size_t kFftLds = 80 * 1024;
 
-void set_radices(int n, int* dst, int* cnt)
+void set_radices(int n, uint64_t* dst, int* cnt)
 {
     std::vector<int> r;
     se_smooth_factors(n, &r);
-    *cnt = (int)r.size();
-    for (size_t i = 0; i < r.size(); i++) dst[i] = r[i];
+    *cnt = (int)std::min<size_t>(r.size(), 16);
+    uint64_t code = 0;
+    for (int i = 0; i < *cnt; i++) code |= (uint64_t)r[i] << (4 * i);
+    *dst = code;
 }
 
 se_fft_args make_fft_args_geom(const int* Mg, const int* N, const double* h, void* grid, void* spec,
@@ -531,6 +603,7 @@ se_fft_args make_fft_args_geom(const int* Mg, const int* N, const double* h, voi
         a.N[d] = N[d];
     }
     a.Hx = N[0] / 2 + 1;
+    a.Hp = a.Hx;
     a.ncomp = ncomp;
     a.grid = grid;
     a.spec = spec;
@@ -539,9 +612,9 @@ se_fft_args make_fft_args_geom(const int* Mg, const int* N, const double* h, voi
     a.tw_xp = tw_off[1];
     a.tw_y = tw_off[2];
     a.tw_z = tw_off[3];
-    set_radices(N[0] / 2, a.rad_xh, &a.nrad_xh);
-    set_radices(N[1], a.rad_y, &a.nrad_y);
-    set_radices(N[2], a.rad_z, &a.nrad_z);
+    set_radices(N[0] / 2, &a.rad_xh, &a.nrad_xh);
+    set_radices(N[1], &a.rad_y, &a.nrad_y);
+    set_radices(N[2], &a.rad_z, &a.nrad_z);
     double hv = 1.0, nv = 1.0;
     for (int d = 0; d < 3; d++) {
         a.kfac[d] = 2.0 * M_PI / (h[d] * N[d]);
@@ -555,6 +628,7 @@ se_fft_args make_fft_args_geom(const int* Mg, const int* N, const double* h, voi
 se_fft_args make_fft_args(const se_plan* p, int ncomp)
 {
     se_fft_args a = make_fft_args_geom(p->g.Mg, p->Nfft, p->g.h, p->d_grid, p->d_spec, p->d_tw, p->tw_off, ncomp);
+    a.Hp = p->Hp;
     a.kernel = p->kernel;
     a.D = p->D;
     a.xi = p->par.xi;
@@ -575,13 +649,38 @@ se_fft_args make_fft_args(const se_plan* p, int ncomp)
 }
 
 template <typename R>
+int x_lines(int Nh)
+{
+    const int budget = (int)(kFftLds / sizeof(C<R>)) - (2 * Nh + 1);
+    return std::max(1, budget / (2 * Nh));
+}
+
+// columns per bundle for a pass holding `sets` column sets of length N plus
+// the twiddles within the LDS budget
+template <typename R>
+int bundle_cols(int N, int sets)
+{
+    const int budget = (int)(kFftLds / sizeof(C<R>)) - N;
+    int c = std::max(1, std::min(16, budget / (sets * N)));
+    while (c & (c - 1)) c &= c - 1;  // power of two (line index by shift)
+    return c;
+}
+
+template <typename K>
+void allow_lds(K kern, size_t bytes)
+{
+    if (bytes > 65536) (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <typename R>
 void run_x_r2c(se_fft_args a, int ncomp, hipStream_t s)
 {
     const int Nh = a.N[0] / 2;
     a.ncomp = ncomp;
-    a.lines = std::max(1, SE_FFT_LDS_ELEMS / Nh);
+    a.lines = x_lines<R>(Nh);
     int64_t rows = (int64_t)ncomp * a.Mg[2] * a.Mg[1];
-    size_t lds = (size_t)(2 * Nh + 1 + a.lines * Nh) * sizeof(C<R>);
+    size_t lds = (size_t)(2 * Nh + 1 + 2 * a.lines * Nh) * sizeof(C<R>);
+    allow_lds(k_fft_x_r2c<R>, lds);
     hipLaunchKernelGGL(k_fft_x_r2c<R>, dim3((unsigned)((rows + a.lines - 1) / a.lines)), dim3(SE_FFT_THREADS),
                        lds, s, a);
 }
@@ -591,9 +690,10 @@ void run_x_c2r(se_fft_args a, int ncomp, hipStream_t s)
 {
     const int Nh = a.N[0] / 2;
     a.ncomp = ncomp;
-    a.lines = std::max(1, SE_FFT_LDS_ELEMS / Nh);
+    a.lines = x_lines<R>(Nh);
     int64_t rows = (int64_t)ncomp * a.Mg[2] * a.Mg[1];
-    size_t lds = (size_t)(2 * Nh + 1 + a.lines * Nh) * sizeof(C<R>);
+    size_t lds = (size_t)(2 * Nh + 1 + 2 * a.lines * Nh) * sizeof(C<R>);
+    allow_lds(k_fft_x_c2r<R>, lds);
     hipLaunchKernelGGL(k_fft_x_c2r<R>, dim3((unsigned)((rows + a.lines - 1) / a.lines)), dim3(SE_FFT_THREADS),
                        lds, s, a);
 }
@@ -601,20 +701,21 @@ void run_x_c2r(se_fft_args a, int ncomp, hipStream_t s)
 template <typename R>
 void run_y(se_fft_args a, int ncomp, int dir, hipStream_t s)
 {
-    a.cols = std::max(1, std::min(16, SE_FFT_LDS_ELEMS / a.N[1]));
+    a.cols = bundle_cols<R>(a.N[1], 2);
     int nbx = (a.Hx + a.cols - 1) / a.cols;
-    size_t lds = (size_t)(a.N[1] + a.cols * a.N[1]) * sizeof(C<R>);
+    size_t lds = (size_t)(a.N[1] + 2 * a.cols * a.N[1]) * sizeof(C<R>);
+    allow_lds(k_fft_y<R>, lds);
     hipLaunchKernelGGL(k_fft_y<R>, dim3((unsigned)(nbx * ncomp * a.Mg[2])), dim3(SE_FFT_THREADS), lds, s, a, dir);
 }
 
 template <typename R>
 void run_z_plain(se_fft_args a, int ncomp, int dir, hipStream_t s)
 {
-    a.cols = std::max(1, std::min(16, SE_FFT_LDS_ELEMS / a.N[2]));
+    a.cols = bundle_cols<R>(a.N[2], 2);
     int nbx = (a.Hx + a.cols - 1) / a.cols;
-    size_t lds = (size_t)(a.N[2] + a.cols * a.N[2]) * sizeof(C<R>);
-    hipLaunchKernelGGL((k_fft_z<R, SE_FFT_LDS_ELEMS>), dim3((unsigned)(nbx * a.N[1] * ncomp)), dim3(SE_FFT_THREADS),
-                       lds, s, a, dir);
+    size_t lds = (size_t)(a.N[2] + 2 * a.cols * a.N[2]) * sizeof(C<R>);
+    allow_lds(k_fft_z<R>, lds);
+    hipLaunchKernelGGL(k_fft_z<R>, dim3((unsigned)(nbx * a.N[1] * ncomp)), dim3(SE_FFT_THREADS), lds, s, a, dir);
 }
 
 template <typename R>
@@ -636,12 +737,11 @@ template <typename R, int KER, int NC>
 void launch_z(const se_plan* p, hipStream_t s)
 {
     se_fft_args a = make_fft_args(p, NC);
-    constexpr int EL = z_elems<R>();
-    a.cols = std::max(1, std::min(8, EL / (NC * p->Nfft[2])));
+    a.cols = bundle_cols<R>(p->Nfft[2], NC + 1);
     int nbx = (p->Hx + a.cols - 1) / a.cols;
-    size_t lds = (size_t)(p->Nfft[2] + NC * a.cols * p->Nfft[2]) * sizeof(C<R>);
-    auto kern = k_fft_z_scale<R, KER, NC, EL>;
-    if (lds > 65536) (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    size_t lds = (size_t)(p->Nfft[2] + (NC + 1) * a.cols * p->Nfft[2]) * sizeof(C<R>);
+    auto kern = k_fft_z_scale<R, KER, NC>;
+    allow_lds(kern, lds);
     hipLaunchKernelGGL(kern, dim3((unsigned)(nbx * p->Nfft[1])), dim3(SE_FFT_THREADS), lds, s, a);
 }
 
@@ -673,7 +773,7 @@ struct se_cls_args {
     int zero;
     int nkx, ny, nz;
     int kx_lo, ky_lo;
-    int Hx, N1, Mg1, Mz;  // main half spectrum [c][Mz][N1][Hx], valid y rows Mg1
+    int Hp, N1, Mg1, Mz;  // main half spectrum [c][Mz][N1][Hp], valid y rows Mg1
     void* spec;
     void* buf;
     const double* kv;
@@ -693,7 +793,7 @@ se_cls_args make_cls_args(const se_plan* p, const se_aft_class& c)
     a.nz = c.nz;
     a.kx_lo = c.kx_lo;
     a.ky_lo = c.ky_lo;
-    a.Hx = p->Hx;
+    a.Hp = p->Hp;
     a.N1 = p->Nfft[1];
     a.Mg1 = p->g.Mg[1];
     a.Mz = p->g.Mg[2];
@@ -725,7 +825,7 @@ __global__ void k_cls_gather(se_cls_args a, int ncomp)
     int y = -1;
     if (a.D == 2) y = (a.ky_lo + iy + a.N1) % a.N1;
     else if (iy < a.Mg1) y = iy;
-    if (y >= 0 && iz < a.Mz) v = spec[(((int64_t)c * a.Mz + iz) * a.N1 + y) * a.Hx + a.kx_lo + ix];
+    if (y >= 0 && iz < a.Mz) v = spec[(((int64_t)c * a.Mz + iz) * a.N1 + y) * a.Hp + a.kx_lo + ix];
     ((C<R>*)a.buf)[i] = v;
 }
 
@@ -748,7 +848,7 @@ __global__ void k_cls_scatter(se_cls_args a)
         y = (a.ky_lo + iy + a.N1) % a.N1;
     }
     const C<R>* buf = (const C<R>*)a.buf;
-    ((C<R>*)a.spec)[(((int64_t)c * a.Mz + iz) * a.N1 + y) * a.Hx + a.kx_lo + ix] =
+    ((C<R>*)a.spec)[(((int64_t)c * a.Mz + iz) * a.N1 + y) * a.Hp + a.kx_lo + ix] =
         buf[(((int64_t)c * a.nz + iz) * a.ny + iy) * a.nkx + ix];
 }
 
@@ -844,6 +944,7 @@ se_fft_args cls_fft_args(const se_plan* p, const se_aft_class& c)
     const int N[3] = {2, c.ny, c.nz};
     se_fft_args a = make_fft_args_geom(Mg, N, p->g.h, nullptr, c.buf, c.tw, c.tw_off, p->ncomp);
     a.Hx = c.nkx;
+    a.Hp = c.nkx;
     return a;
 }
 
@@ -920,6 +1021,17 @@ void se_launch_fft_inverse(const se_plan* p, hipStream_t s)
 {
     if (p->fp32) launch_inv<float>(p, s);
     else launch_inv<double>(p, s);
+}
+
+// Whether the line kernels can hold the transforms of a plan in LDS
+// (one column at least per bundle, 160 KB per workgroup).
+bool se_fft_fits(const int* N, int ncomp, bool fp32)
+{
+    const size_t cb = fp32 ? 8 : 16;
+    const size_t lim = 160 * 1024;
+    const size_t nh = (size_t)N[0] / 2;
+    return (2 * nh + 1 + 2 * nh) * cb <= lim && (size_t)N[1] * 3 * cb <= lim && (size_t)N[2] * 3 * cb <= lim &&
+           (size_t)N[2] * (1 + (ncomp + 1)) * cb <= lim;
 }
 
 // FP64 3-D transform of ncomp components on an arbitrary grid:

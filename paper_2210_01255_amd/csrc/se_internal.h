@@ -90,6 +90,7 @@ struct se_plan {
     int64_t nbins = 0;
     int Nfft[3] = {0, 0, 0};
     int Hx = 0;              // R2C half-spectrum extent along x
+    int Hp = 0;              // half-spectrum row pitch (Hx rounded up to 8: 128-byte rows in FP64)
     int tile[3] = {16, 16, 8};  // spread/gather tile (grid points)
     int ntile[3] = {0, 0, 0};
 
@@ -111,7 +112,7 @@ struct se_plan {
     double* d_fs64 = nullptr;      // sorted strengths FP64 [3][ns] (self term), q.nu [ns]
     double* d_red = nullptr;       // reductions: [0] sum q.nu, [1..3] sum x (q.nu), [4..6] sum f; partials
     void* d_grid = nullptr;        // real grid [ncomp][Mz][My][Mx]
-    void* d_spec = nullptr;        // half spectrum [ncomp][Mz][Ny][Hx] complex
+    void* d_spec = nullptr;        // half spectrum [ncomp][Mz][Ny][Hp] complex
     double* d_pos4 = nullptr;      // sorted sources AoS [ns][4] (x, y, z, 0)
     double* d_tpos4 = nullptr;     // sorted targets AoS [nt][4] (null when tas)
     double* d_str4 = nullptr;      // sorted strengths AoS [ns][4] (f or q, 0)
@@ -167,5 +168,6 @@ void se_fft3d_f64(const int* Mg, const int* N, const double* h, double* grid, do
                   const int* tw_off, int ncomp, int dir, hipStream_t s);
 void se_fft_twiddles(const int* N, std::vector<double>* tw, int* off);
 se_status se_d0_precompute(se_plan* p);
+bool se_fft_fits(const int* N, int ncomp, bool fp32);
 void se_launch_finalize(const se_plan* p, const double* f, double* u, double* u_real,
                         double* u_fourier, hipStream_t s);
