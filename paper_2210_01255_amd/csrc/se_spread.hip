@@ -619,13 +619,46 @@ __global__ void __launch_bounds__(SE_RT_THREADS) k_spread_rt(se_tile_args a)
     }
 }
 
-template <typename R>
-__device__ __forceinline__ R rt_wave_sum(R v)
+// Cross-lane steps of the gathering reduce-scatter, on the VALU (gfx950
+// lane swaps and DPP), one helper per 32-bit width.
+//   sum32(a, b): lanes 0-31 get a[l] + a[l + 32], lanes 32-63 get b[l - 32] + b[l]
+//   sum16(a, b): even rows get a[l] + a[l + 16], odd rows get b[l - 16] + b[l]
+__device__ __forceinline__ float rt_sum32(float a, float b)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
+__device__ __forceinline__ double rt_sum32(double a, double b)
+{
+    auto lo = __builtin_amdgcn_permlane32_swap((unsigned)__double2loint(a), (unsigned)__double2loint(b), false, false);
+    auto hi = __builtin_amdgcn_permlane32_swap((unsigned)__double2hiint(a), (unsigned)__double2hiint(b), false, false);
+    return __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
+}
+__device__ __forceinline__ float rt_sum16(float a, float b)
+{
+    auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ double rt_sum16(double a, double b)
+{
+    auto lo = __builtin_amdgcn_permlane16_swap((unsigned)__double2loint(a), (unsigned)__double2loint(b), false, false);
+    auto hi = __builtin_amdgcn_permlane16_swap((unsigned)__double2hiint(a), (unsigned)__double2hiint(b), false, false);
+    return __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
+}
+// v from lane (l + 8) mod 16 (= l ^ 8) / row_half_mirror / quad_perm swaps
+template <int CTRL>
+__device__ __forceinline__ float rt_dpp(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double rt_dpp(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+constexpr int kDppRor8 = 0x128, kDppHalfMirror = 0x141, kDppXor2 = 0x4E, kDppXor1 = 0xB1;
 
 template <typename R>
 __global__ void __launch_bounds__(SE_RT_THREADS) k_gather_rt(se_tile_args a)
@@ -693,26 +726,22 @@ __global__ void __launch_bounds__(SE_RT_THREADS) k_gather_rt(se_tile_args a)
             const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
             R v12[12];
 #pragma unroll
-            for (int i = 0; i < 12; i++) {
-                const R mine = b5 ? v[12 + i] : v[i], oth = b5 ? v[i] : v[12 + i];
-                v12[i] = mine + __shfl_xor(oth, 32, 64);
-            }
+            for (int i = 0; i < 12; i++) v12[i] = rt_sum32(v[i], v[12 + i]);
             R v6[6];
 #pragma unroll
-            for (int i = 0; i < 6; i++) {
-                const R mine = b4 ? v12[6 + i] : v12[i], oth = b4 ? v12[i] : v12[6 + i];
-                v6[i] = mine + __shfl_xor(oth, 16, 64);
-            }
+            for (int i = 0; i < 6; i++) v6[i] = rt_sum16(v12[i], v12[6 + i]);
             R v3[3];
 #pragma unroll
             for (int i = 0; i < 3; i++) {
                 const R mine = b3 ? v6[3 + i] : v6[i], oth = b3 ? v6[i] : v6[3 + i];
-                v3[i] = mine + __shfl_xor(oth, 8, 64);
+                v3[i] = mine + rt_dpp<kDppRor8>(oth);
             }
 #pragma unroll
-            for (int off = 4; off > 0; off >>= 1)
-#pragma unroll
-                for (int i = 0; i < 3; i++) v3[i] += __shfl_xor(v3[i], off, 64);
+            for (int i = 0; i < 3; i++) {
+                v3[i] += rt_dpp<kDppHalfMirror>(v3[i]);
+                v3[i] += rt_dpp<kDppXor2>(v3[i]);
+                v3[i] += rt_dpp<kDppXor1>(v3[i]);
+            }
             if ((lane & 7) == 0) {
                 const int k = i0 + (b5 ? 4 : 0) + (b4 ? 2 : 0) + (b3 ? 1 : 0);
                 if (k < cnt) {
