@@ -41,6 +41,9 @@ def parse():
                     help="expected sources within rc (balances real space against the grid work on "
                          "this GPU; 0: the paper's CPU-tuned table value)")
     ap.add_argument("--cpu-sample", type=int, default=600, help="targets in the oracle sample (0: skip)")
+    ap.add_argument("--pollution", type=int, default=1,
+                    help="error-pollution rule: 0 (h/1.05, P+4) or 1 (h/1.1, P+2), both from the paper's "
+                         "error-pollution section; 1 suits this GPU (window work ~P^3 dominates)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="after the run, one plain device copy of this size (HBM counter calibration)")
     return ap.parse_args()
@@ -129,7 +132,8 @@ def main():
     f = torch.tensor(s["f"], device=dev)
     Q = float(np.sum(s["f"] ** 2))
     plan = se.Plan(kernel="stokeslet", periodicity=3, box=(1.0, 1.0, 1.0), tol=args.tol, tol_kind=se.TOL_REL,
-                   n_src=n, source_q=Q, safety=args.safety, precision=se.PREC_FP64, n_rc=args.nrc)
+                   n_src=n, source_q=Q, safety=args.safety, precision=se.PREC_FP64, n_rc=args.nrc,
+                   pollution=args.pollution)
     par = plan.params
     u = torch.empty((n, 3), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
@@ -223,7 +227,8 @@ def main():
                                "f~N(0,1)^3 zero mean, tol 1e-8 rms-rel (analytic parameters, N_rc re-tuned for the GPU, "
                                "1 rhs, FP64)",
                    "form": "plain", "xi": round(par["xi"], 4), "rc": round(par["rc"], 5), "M": par["M"],
-                   "P": par["P"], "safety": args.safety, "n_rc": args.nrc or 400.0},
+                   "P": par["P"], "safety": args.safety, "n_rc": args.nrc or 400.0,
+                   "pollution_rule": ["h/1.05,P+4", "h/1.1,P+2"][args.pollution]},
         "phases_ms": {k: round(v, 4) for k, v in per_launch.items()},
         "phases_roofline": phase_frac,
         "roofline": roof,

@@ -70,6 +70,11 @@ typedef int32_t se_status;
 #define SE_SELECT_LEARNED 1  /* reserved: learned selector with analytic fallback */
 #define SE_SELECT_MANUAL 2   /* caller supplies se_params */
 
+/* Error-pollution adjustment of the estimated (h, P), eq. (error-pollution-fix)
+ * and the alternative the same section reports as equally accurate. */
+#define SE_POLLUTION_PAPER 0 /* (h/1.1, P+2) for D = 0, (h/1.05, P+4) for D = 1, 2, 3 */
+#define SE_POLLUTION_FINE 1  /* (h/1.1, P+2) for every D: finer grid, narrower window */
+
 /* Problem statement (Algorithm 1 inputs plus the error tolerance). */
 typedef struct se_problem {
     int32_t struct_size;      /* sizeof(se_problem) */
@@ -92,7 +97,7 @@ typedef struct se_problem {
     int32_t targets_are_sources; /* 1: evaluate at the sources, starred sum */
     int32_t n_rhs;            /* strength sets sharing one geometry (>= 1) */
     int32_t device;           /* HIP device ordinal */
-    int32_t reserved;         /* must be 0 */
+    int32_t pollution;        /* SE_POLLUTION_PAPER or SE_POLLUTION_FINE */
 } se_problem;
 
 /* Resolved method parameters (Sec. 3 and 4). */

@@ -18,6 +18,7 @@ KERNELS = {"stokeslet": STOKESLET, "rotlet": ROTLET, "stresslet": STRESSLET}
 TOL_REL, TOL_ABS = 0, 1
 PREC_AUTO, PREC_FP64, PREC_FP32 = 0, 1, 2
 SELECT_ANALYTIC, SELECT_LEARNED, SELECT_MANUAL = 0, 1, 2
+POLLUTION_PAPER, POLLUTION_FINE = 0, 1
 
 SE_OK = 0
 STATUS = {0: "SE_OK", -1: "SE_ERR_ARG", -2: "SE_ERR_UNSUPPORTED", -3: "SE_ERR_OUT_OF_BOX",
@@ -33,7 +34,7 @@ class se_problem(ctypes.Structure):
                 ("safety", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("selector", ctypes.c_int32), ("n_src", ctypes.c_int64), ("n_tgt", ctypes.c_int64),
                 ("targets_are_sources", ctypes.c_int32), ("n_rhs", ctypes.c_int32),
-                ("device", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("device", ctypes.c_int32), ("pollution", ctypes.c_int32)]
 
 
 class se_params(ctypes.Structure):
@@ -125,7 +126,8 @@ se_debug_cell_list = lib.se_debug_cell_list
 
 def make_problem(kernel="stokeslet", periodicity=3, box=(1.0, 1.0, 1.0), tol=1e-8, tol_kind=TOL_REL,
                  n_src=1, n_tgt=0, targets_are_sources=True, n_rhs=1, source_q=0.0, xi=0.0, n_rc=0.0,
-                 safety=0.0, precision=PREC_FP64, selector=SELECT_ANALYTIC, device=0) -> se_problem:
+                 safety=0.0, precision=PREC_FP64, selector=SELECT_ANALYTIC, device=0,
+                 pollution=0) -> se_problem:
     p = se_problem()
     p.struct_size = ctypes.sizeof(se_problem)
     p.periodicity = int(periodicity)
@@ -145,7 +147,7 @@ def make_problem(kernel="stokeslet", periodicity=3, box=(1.0, 1.0, 1.0), tol=1e-
     p.targets_are_sources = 1 if targets_are_sources else 0
     p.n_rhs = int(n_rhs)
     p.device = int(device)
-    p.reserved = 0
+    p.pollution = int(pollution)
     return p
 
 

@@ -242,7 +242,7 @@ static se_status validate_problem(const se_problem* prob)
     if (prob->n_rhs < 1) return SE_ERR_ARG;
     if (prob->precision < SE_PREC_AUTO || prob->precision > SE_PREC_FP32) return SE_ERR_ARG;
     if (prob->selector < SE_SELECT_ANALYTIC || prob->selector > SE_SELECT_MANUAL) return SE_ERR_ARG;
-    if (prob->reserved != 0) return SE_ERR_ARG;
+    if (prob->pollution != SE_POLLUTION_PAPER && prob->pollution != SE_POLLUTION_FINE) return SE_ERR_ARG;
     return SE_OK;
 }
 

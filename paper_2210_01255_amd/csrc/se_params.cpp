@@ -363,8 +363,9 @@ se_status se_select_params(const se_problem* p, const se_params* manual, se_para
     double P_est = std::log(10.0 * U / tau) / 2.5;
     if (P_est < 0) P_est = 0;
     // step 4: pollution rule and grid rounding
-    double h_t = (D == 0) ? h_est / 1.1 : h_est / 1.05;
-    double P_t = (D == 0) ? P_est + 2.0 : P_est + 4.0;
+    const bool fine = D == 0 || p->pollution == SE_POLLUTION_FINE;
+    double h_t = fine ? h_est / 1.1 : h_est / 1.05;
+    double P_t = fine ? P_est + 2.0 : P_est + 4.0;
     // step 5: even window support, KB shape and PKB degree
     int P = 2 * (int)std::ceil(P_t / 2.0 - 1e-12);
     if (P < 4) P = 4;

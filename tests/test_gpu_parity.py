@@ -316,3 +316,21 @@ def test_reduced_periodicity_real_space_exact(env, D):
     err = oracle.rms_rel_error(ur, ref)
     print("D=%d real part rel err" % D, err)
     assert err <= 1e-12
+
+
+# ------------------------------------------- alternative pollution adjustment
+@pytest.mark.parametrize("kernel", ["stokeslet", "rotlet", "stresslet"])
+@pytest.mark.parametrize("D,tol", [(3, 1e-6), (3, 1e-10), (2, 1e-8), (1, 1e-8)])
+def test_fine_pollution_rule_meets_tolerance(env, kernel, D, tol):
+    """(h/1.1, P+2) for every D, the second adjustment the error-pollution
+    section reports as restoring the estimates' accuracy."""
+    se, oracle, _ = env
+    s = W.system(2500 + D, 1500, kernel=kernel, periodicity=D)
+    plan, u = _run(env, kernel, s, D=D, tol=tol, pollution=se.POLLUTION_FINE)
+    par = plan.params
+    ref = se.select_params(kernel=kernel, periodicity=D, box=tuple(s["box"]), tol=tol, n_src=1500,
+                           source_q=_q_of(kernel, s), safety=SAFETY)
+    assert par["P"] == ref["P"] - 2  # P + 2 instead of P + 4
+    err = oracle.rms_rel_error(u, _ref(env, kernel, s, D=D))
+    print("fine pollution D=%d" % D, kernel, tol, "P", par["P"], "M", par["M"], "rel err", err)
+    assert err <= tol

@@ -89,3 +89,19 @@ def test_bad_arguments_are_rejected(se):
     with pytest.raises(se.SEError):
         # window support above 32 points
         se.select_params(kernel="stokeslet", periodicity=3, tol=1e-30, tol_kind=se.TOL_ABS, n_src=10)
+
+
+def test_pollution_rules(se):
+    """Eq. (error-pollution-fix) and its alternative: P drops by 2, h by 1.05/1.1."""
+    for D in (3, 2, 1):
+        a = se.select_params(kernel="stokeslet", periodicity=D, tol=1e-8, n_src=10_000, safety=10)
+        b = se.select_params(kernel="stokeslet", periodicity=D, tol=1e-8, n_src=10_000, safety=10,
+                             pollution=se.POLLUTION_FINE)
+        assert b["P"] == a["P"] - 2
+        assert b["M"][0] >= a["M"][0]
+    a = se.select_params(kernel="stokeslet", periodicity=0, tol=1e-8, n_src=10_000, safety=10)
+    b = se.select_params(kernel="stokeslet", periodicity=0, tol=1e-8, n_src=10_000, safety=10,
+                         pollution=se.POLLUTION_FINE)
+    assert a["P"] == b["P"] and a["M"] == b["M"]  # D = 0 uses (h/1.1, P+2) either way
+    with pytest.raises(se.SEError):
+        se.select_params(kernel="stokeslet", periodicity=3, tol=1e-8, n_src=10, pollution=7)
