@@ -271,7 +271,7 @@ __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_x_r2c(se_fft_args a)
     load_tw(tw, a.tw + 2 * a.tw_xh, Nh);
     load_tw(twp, a.tw + 2 * a.tw_xp, Nh + 1);
     const int64_t rows = (int64_t)a.ncomp * a.Mg[2] * a.Mg[1];
-    const int64_t row0 = (int64_t)blockIdx.x * a.lines;
+    const int64_t row0 = (int64_t)se_xcd_block(blockIdx.x, gridDim.x) * a.lines;
     const int nl = (int)min((int64_t)a.lines, rows - row0);
     const R* grid = (const R*)a.grid;
     C<R>* spec = (C<R>*)a.spec;
@@ -318,7 +318,7 @@ __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_x_c2r(se_fft_args a)
     load_tw(twp, a.tw + 2 * a.tw_xp, Nh + 1);
     __syncthreads();
     const int64_t rows = (int64_t)a.ncomp * a.Mg[2] * a.Mg[1];
-    const int64_t row0 = (int64_t)blockIdx.x * a.lines;
+    const int64_t row0 = (int64_t)se_xcd_block(blockIdx.x, gridDim.x) * a.lines;
     const int nl = (int)min((int64_t)a.lines, rows - row0);
     R* grid = (R*)a.grid;
     const C<R>* spec = (const C<R>*)a.spec;
@@ -365,7 +365,7 @@ __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_y(se_fft_args a, int dir
     C<R>* b1 = b0 + Ny * Cc;
     load_tw(tw, a.tw + 2 * a.tw_y, Ny);
     const int nbx = (a.Hx + Cc - 1) / Cc;
-    int bid = blockIdx.x;
+    int bid = se_xcd_block(blockIdx.x, gridDim.x);  // neighbouring bundles share an XCD (L2)
     int bx = bid % nbx;
     int64_t cz = bid / nbx;  // c * Mz + z
     const int kx0 = bx * Cc;
@@ -483,8 +483,9 @@ __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_z(se_fft_args a, int dir
     C<R>* b1 = b0 + Nz * Cc;
     load_tw(tw, a.tw + 2 * a.tw_z, Nz);
     const int nbx = (a.Hx + Cc - 1) / Cc;
-    const int bx = blockIdx.x % nbx;
-    const int rest = blockIdx.x / nbx;
+    const int blk = se_xcd_block(blockIdx.x, gridDim.x);
+    const int bx = blk % nbx;
+    const int rest = blk / nbx;
     const int y = rest % a.N[1];
     const int c = rest / a.N[1];
     const int kx0 = bx * Cc;
@@ -526,8 +527,9 @@ __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_z_scale(se_fft_args a)
     C<R>* sets = tw + Nz;
     load_tw(tw, a.tw + 2 * a.tw_z, Nz);
     const int nbx = (a.Hx + Cc - 1) / Cc;
-    const int bx = blockIdx.x % nbx;
-    const int y = blockIdx.x / nbx;
+    const int blk = se_xcd_block(blockIdx.x, gridDim.x);
+    const int bx = blk % nbx;
+    const int y = blk / nbx;
     const int kx0 = bx * Cc;
     const int Mz = a.Mg[2];
     const int64_t cstride = (int64_t)Mz * a.N[1] * a.Hp;
