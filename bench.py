@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--nrc", type=float, default=280.0,
                     help="expected sources within rc (balances real space against the grid work on "
                          "this GPU; 0: the paper's CPU-tuned table value)")
-    ap.add_argument("--cpu-sample", type=int, default=600, help="targets in the oracle sample (0: skip)")
+    ap.add_argument("--cpu-sample", type=int, default=2000, help="targets in the oracle sample (0: skip)")
     ap.add_argument("--pollution", type=int, default=1,
                     help="error-pollution rule: 0 (h/1.05, P+4) or 1 (h/1.1, P+2), both from the paper's "
                          "error-pollution section; 1 suits this GPU (window work ~P^3 dominates)")
