@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--pollution", type=int, default=1,
                     help="error-pollution rule: 0 (h/1.05, P+4) or 1 (h/1.1, P+2), both from the paper's "
                          "error-pollution section; 1 suits this GPU (window work ~P^3 dominates)")
+    ap.add_argument("--nrhs", type=int, default=1,
+                    help="strength sets on the shared geometry (> 1: the batched form)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="after the run, one plain device copy of this size (HBM counter calibration)")
     return ap.parse_args()
@@ -78,8 +80,16 @@ def measured_traffic(phase):
     return t.get("bytes_per_launch")
 
 
-def roofline_for(phase, ms_per_launch, par, n_src, n_tgt, ncomp, fp64, box_vol=1.0):
-    """Algorithmic work of one launch of the phase divided by its duration."""
+def roofline_for(phase, ms_per_launch, par, n_src, n_tgt, ncomp, fp64, box_vol=1.0, slots=1):
+    """Algorithmic work of one launch of the phase divided by its duration
+    (a launch covers `slots` right-hand sides)."""
+    r = _roofline_one(phase, ms_per_launch / slots, par, n_src, n_tgt, ncomp, fp64, box_vol)
+    if r is not None:
+        r["work_per_launch"] *= slots
+    return r
+
+
+def _roofline_one(phase, ms_per_launch, par, n_src, n_tgt, ncomp, fp64, box_vol=1.0):
     P = par["P"]
     M = par["M"]
     sec = ms_per_launch * 1e-3
@@ -127,15 +137,17 @@ def main():
 
     dev = torch.device("cuda:0")
     n = args.n
-    s = W.system(args.seed, n, kernel="stokeslet", zero_mean=True)
+    nrhs = args.nrhs
+    s = W.system(args.seed, n, kernel="stokeslet", zero_mean=True, n_rhs=nrhs if nrhs > 1 else None)
     x = torch.tensor(s["x"], device=dev)
     f = torch.tensor(s["f"], device=dev)
-    Q = float(np.sum(s["f"] ** 2))
+    Q = float(np.sum(s["f"] ** 2)) / nrhs  # per right-hand side
     plan = se.Plan(kernel="stokeslet", periodicity=3, box=(1.0, 1.0, 1.0), tol=args.tol, tol_kind=se.TOL_REL,
                    n_src=n, source_q=Q, safety=args.safety, precision=se.PREC_FP64, n_rc=args.nrc,
-                   pollution=args.pollution)
+                   pollution=args.pollution, n_rhs=nrhs)
+    slots = 2 if nrhs >= 2 else 1  # right-hand sides per chunk of the phases (stokeslet)
     par = plan.params
-    u = torch.empty((n, 3), dtype=torch.float64, device=dev)
+    u = torch.empty((n, 3) if nrhs == 1 else (nrhs, n, 3), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
 
     def step():
@@ -152,7 +164,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
-    value = n / (ms_per_step * 1e-3)
+    value = nrhs * n / (ms_per_step * 1e-3)
 
     # live per-phase durations (HIP events on the execution stream)
     plan.set_timing(True)
@@ -163,7 +175,7 @@ def main():
     plan.set_timing(False)
     per_launch = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in phases.items()}
     dom = max((k for k in per_launch if k not in ("geometry",)), key=lambda k: per_launch[k])
-    rl = roofline_for(dom, per_launch[dom], par, n, n, 3, True)
+    rl = roofline_for(dom, per_launch[dom], par, n, n, 3, True, slots=slots)
     roof = None
     if rl is not None:
         roof = {"kernel": dom, "bound": rl["bound"], "achieved": round(rl["achieved"], 4), "peak": rl["peak"],
@@ -172,7 +184,7 @@ def main():
                 "work_per_launch": rl["work_per_launch"]}
     phase_frac = {}
     for k, v in per_launch.items():
-        r = roofline_for(k, v, par, n, n, 3, True) if v > 0 else None
+        r = roofline_for(k, v, par, n, n, 3, True, slots=slots) if v > 0 else None
         if r is not None:
             phase_frac[k] = {"bound": r["bound"], "frac": round(r["achieved"] / r["peak"], 5)}
 
@@ -192,7 +204,8 @@ def main():
         oracle.build(force=False)
         idx = np.sort(W.rng(args.seed + 1).choice(n, args.cpu_sample, replace=False))
         c0 = time.perf_counter()
-        ref = oracle.ewald(3, "stokeslet", [1.0, 1.0, 1.0], s["x"], f=s["f"], targets=s["x"][idx],
+        f0 = s["f"] if nrhs == 1 else s["f"][0]
+        ref = oracle.ewald(3, "stokeslet", [1.0, 1.0, 1.0], s["x"], f=f0, targets=s["x"][idx],
                            self_src=idx)
         c1 = time.perf_counter()
         cores = os.cpu_count()
@@ -207,11 +220,11 @@ def main():
                "kind": "oracle",
                "sample": "%d of %d targets (all %d sources), FP64 classical Ewald, xi_o=%.3f, %.1f s"
                          % (args.cpu_sample, n, n, ref["xi"], c1 - c0)}
-        ug = u.cpu().numpy()[idx]
+        ug = (u.cpu().numpy() if nrhs == 1 else u[0].cpu().numpy())[idx]
         err_sample = oracle.rms_rel_error(ug, ref.total)
 
     out = {
-        "metric": "targets/sec at 1e-8 rms-rel err, N=1M TP stokeslet",
+        "metric": "targets/sec at 1e-8 rms-rel err, N=1M TP stokeslet; learned+batched vs plain",
         "value": round(value, 1),
         "unit": "targets/s",
         "n_gpus": 1,
@@ -225,8 +238,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": "triply periodic stokeslet, unit cube, N=1e6 uniform sources = targets, "
                                "f~N(0,1)^3 zero mean, tol 1e-8 rms-rel (analytic parameters, N_rc re-tuned for the GPU, "
-                               "1 rhs, FP64)",
-                   "form": "plain", "xi": round(par["xi"], 4), "rc": round(par["rc"], 5), "M": par["M"],
+                               "%d rhs on the shared geometry, FP64)" % nrhs,
+                   "form": "plain" if nrhs == 1 else "batched", "n_rhs": nrhs,
+                   "xi": round(par["xi"], 4), "rc": round(par["rc"], 5), "M": par["M"],
                    "P": par["P"], "safety": args.safety, "n_rc": args.nrc or 400.0,
                    "pollution_rule": ["h/1.05,P+4", "h/1.1,P+2"][args.pollution]},
         "phases_ms": {k: round(v, 4) for k, v in per_launch.items()},

@@ -272,6 +272,9 @@ se_status se_plan_create(const se_problem* prob, const se_params* manual, se_pla
     p->kernel = prob->kernel;
     p->ncomp = prob->kernel == SE_STRESSLET ? 6 : 3;
     p->nrhs = prob->n_rhs;
+    // pairs of right-hand sides share the window weights, candidate lists and
+    // real-space radial functions (6 gridded components, as for one stresslet)
+    p->rb = (p->ncomp == 3 && p->nrhs >= 2) ? 2 : 1;
     p->device = prob->device;
     p->ns = prob->n_src;
     p->tas = prob->targets_are_sources != 0;
@@ -365,21 +368,22 @@ se_status se_plan_create(const se_problem* prob, const se_params* manual, se_pla
     p->d_vals_a = A.get<int>(nmax);
     p->sort_tmp_bytes = se_sort_tmp_bytes(nmax, key_bits(p->nbins));
     p->d_sort_tmp = A.get<char>(std::max<size_t>(p->sort_tmp_bytes, 256));
-    p->d_fs = A.get<char>((size_t)p->ncomp * p->ns * rs);
-    p->d_fs64 = A.get<double>(4 * p->ns);
-    p->d_red = A.get<double>(SE_RED_OUT + 7 * SE_RED_BLOCKS);
+    const size_t rb = (size_t)p->rb;
+    p->d_fs = A.get<char>(rb * p->ncomp * p->ns * rs);
+    p->d_fs64 = A.get<double>(rb * 4 * p->ns);
+    p->d_red = A.get<double>(rb * (SE_RED_OUT + 7 * SE_RED_BLOCKS));
     const size_t gv = (size_t)g.Mg[0] * g.Mg[1] * g.Mg[2];
-    p->d_grid = A.get<char>((size_t)p->ncomp * gv * rs);
+    p->d_grid = A.get<char>(rb * p->ncomp * gv * rs);
     const size_t sv = (size_t)p->Hp * p->Nfft[1] * g.Mg[2];
-    p->d_spec = A.get<char>((size_t)p->ncomp * sv * 2 * rs);
+    p->d_spec = A.get<char>(rb * p->ncomp * sv * 2 * rs);
     p->d_pos4 = A.get<double>(4 * p->ns);
     if (!p->tas) p->d_tpos4 = A.get<double>(4 * p->nt);
-    p->d_str4 = A.get<double>(4 * p->ns);
+    p->d_str4 = A.get<double>(rb * 4 * p->ns);
     if (p->kernel == SE_STRESSLET) p->d_nrm4 = A.get<double>(4 * p->ns);
     p->d_rtab = A.get<double>((size_t)2 * SE_RTAB_N * (SE_RTAB_DEG + 1));
     if (p->D == 0) p->d_ktab = A.get<double>((size_t)p->Hx * p->Nfft[1] * p->Nfft[2]);
-    p->d_uF = A.get<double>(3 * p->nt);
-    p->d_uR = A.get<double>(3 * p->nt);
+    p->d_uF = A.get<double>(rb * 3 * p->nt);
+    p->d_uR = A.get<double>(rb * 3 * p->nt);
     p->d_pkb = A.get<double>((size_t)par.P * (par.nu_deg + 1));
     p->d_invw2 = A.get<double>((size_t)p->Hx + p->Nfft[1] + p->Nfft[2]);
     const int Nh = p->Nfft[0] / 2;
@@ -388,7 +392,7 @@ se_status se_plan_create(const se_problem* prob, const se_params* manual, se_pla
     for (se_aft_class& c : p->cls) {
         if (!c.active) continue;
         const size_t nel = (size_t)c.nkx * c.ny * c.nz;
-        c.buf = A.get<char>((size_t)p->ncomp * nel * 2 * rs);
+        c.buf = A.get<char>(rb * p->ncomp * nel * 2 * rs);  // one set per slot
         c.kv = A.get<double>((size_t)c.nkx + c.ny + c.nz);
         c.iw = A.get<double>((size_t)c.nkx + c.ny + c.nz);
         c.tw = A.get<double>(2 * ((size_t)1 + 2 + c.ny + c.nz));
@@ -427,7 +431,7 @@ se_status se_plan_create(const se_problem* prob, const se_params* manual, se_pla
     if (e == hipSuccess) e = hipMemcpy(p->d_rtab, rtab.data(), rtab.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = aft_tables(p);
     if (e == hipSuccess) e = hipMemset(p->d_flags, 0, sizeof(int));
-    if (e == hipSuccess) e = hipMemset(p->d_red, 0, (SE_RED_OUT + 7 * SE_RED_BLOCKS) * sizeof(double));
+    if (e == hipSuccess) e = hipMemset(p->d_red, 0, rb * (SE_RED_OUT + 7 * SE_RED_BLOCKS) * sizeof(double));
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         free_all(p);
@@ -574,44 +578,47 @@ static se_status run(se_plan* p, const double* strengths, double* u, double* ur,
     if (!p || !strengths) return SE_ERR_ARG;
     if (!p->have_geometry) return SE_ERR_STATE;
     if (hipSetDevice(p->device) != hipSuccess) return SE_ERR_HIP;
-    for (int r = 0; r < p->nrhs; r++) {
-        const double* f = strengths + (size_t)r * p->ns * 3;
-        double* ur_ = u ? u + (size_t)r * p->nt * 3 : nullptr;
-        double* urr = ur ? ur + (size_t)r * p->nt * 3 : nullptr;
-        double* urf = uf ? uf + (size_t)r * p->nt * 3 : nullptr;
+    // chunks of rb right-hand sides: one slot each in the plan's buffers
+    for (int r0 = 0; r0 < p->nrhs; r0 += p->rb) {
+        const int nr = std::min(p->rb, p->nrhs - r0);
         {
             PhaseScope ps(p, 1, s);
-            se_launch_strengths(p, f, s);
-            se_launch_reductions(p, s);
-            se_launch_fill_double(p->d_uF, 0.0, 3 * p->nt, s);
+            for (int k = 0; k < nr; k++) {
+                se_launch_strengths(p, strengths + (size_t)(r0 + k) * p->ns * 3, k, s);
+                se_launch_reductions(p, k, s);
+            }
+            se_launch_fill_double(p->d_uF, 0.0, (int64_t)nr * 3 * p->nt, s);
         }
         {
             PhaseScope ps(p, 2, s);
-            se_launch_spread(p, s);
+            se_launch_spread(p, 0, nr, s);
         }
         {
             PhaseScope ps(p, 3, s);
-            se_launch_fft_xy_forward(p, s);
+            for (int k = 0; k < nr; k++) se_launch_fft_xy_forward(p, k, s);
         }
         {
             PhaseScope ps(p, 4, s);
-            se_launch_fft_z_scale(p, s);
+            for (int k = 0; k < nr; k++) se_launch_fft_z_scale(p, k, s);
         }
         {
             PhaseScope ps(p, 5, s);
-            se_launch_fft_inverse(p, s);
+            for (int k = 0; k < nr; k++) se_launch_fft_inverse(p, k, s);
         }
         {
             PhaseScope ps(p, 6, s);
-            se_launch_gather(p, s);
+            se_launch_gather(p, 0, nr, s);
         }
         {
             PhaseScope ps(p, 7, s);
-            se_launch_real_space(p, s);
+            se_launch_real_space(p, 0, nr, s);
         }
         {
             PhaseScope ps(p, 8, s);
-            se_launch_finalize(p, f, ur_, urr, urf, s);
+            for (int k = 0; k < nr; k++) {
+                const size_t o = (size_t)(r0 + k) * p->nt * 3;
+                se_launch_finalize(p, k, u ? u + o : nullptr, ur ? ur + o : nullptr, uf ? uf + o : nullptr, s);
+            }
         }
         const int ph[8] = {1, 2, 3, 4, 5, 6, 7, 8};
         collect_phases(p, ph, 8);

@@ -627,9 +627,10 @@ se_fft_args make_fft_args_geom(const int* Mg, const int* N, const double* h, voi
     return a;
 }
 
-se_fft_args make_fft_args(const se_plan* p, int ncomp)
+se_fft_args make_fft_args(const se_plan* p, int ncomp, int slot)
 {
-    se_fft_args a = make_fft_args_geom(p->g.Mg, p->Nfft, p->g.h, p->d_grid, p->d_spec, p->d_tw, p->tw_off, ncomp);
+    se_fft_args a = make_fft_args_geom(p->g.Mg, p->Nfft, p->g.h, se_slot_grid(p, slot), se_slot_spec(p, slot), p->d_tw,
+                                       p->tw_off, ncomp);
     a.Hp = p->Hp;
     a.kernel = p->kernel;
     a.D = p->D;
@@ -721,24 +722,24 @@ void run_z_plain(se_fft_args a, int ncomp, int dir, hipStream_t s)
 }
 
 template <typename R>
-void cls_gather(const se_plan* p, hipStream_t s);
+void cls_gather(const se_plan* p, int slot, hipStream_t s);
 template <typename R>
-void cls_scatter(const se_plan* p, hipStream_t s);
+void cls_scatter(const se_plan* p, int slot, hipStream_t s);
 
 template <typename R>
-void launch_fwd(const se_plan* p, hipStream_t s)
+void launch_fwd(const se_plan* p, int slot, hipStream_t s)
 {
-    se_fft_args a = make_fft_args(p, p->ncomp);
+    se_fft_args a = make_fft_args(p, p->ncomp, slot);
     run_x_r2c<R>(a, p->ncomp, s);
-    if (p->D == 1) cls_gather<R>(p, s);
+    if (p->D == 1) cls_gather<R>(p, slot, s);
     run_y<R>(a, p->ncomp, 1, s);
-    if (p->D == 2) cls_gather<R>(p, s);
+    if (p->D == 2) cls_gather<R>(p, slot, s);
 }
 
 template <typename R, int KER, int NC>
-void launch_z(const se_plan* p, hipStream_t s)
+void launch_z(const se_plan* p, int slot, hipStream_t s)
 {
-    se_fft_args a = make_fft_args(p, NC);
+    se_fft_args a = make_fft_args(p, NC, slot);
     a.cols = bundle_cols<R>(p->Nfft[2], NC + 1);
     int nbx = (p->Hx + a.cols - 1) / a.cols;
     size_t lds = (size_t)(p->Nfft[2] + (NC + 1) * a.cols * p->Nfft[2]) * sizeof(C<R>);
@@ -748,20 +749,20 @@ void launch_z(const se_plan* p, hipStream_t s)
 }
 
 template <typename R>
-void launch_inv(const se_plan* p, hipStream_t s)
+void launch_inv(const se_plan* p, int slot, hipStream_t s)
 {
-    se_fft_args a = make_fft_args(p, 3);
+    se_fft_args a = make_fft_args(p, 3, slot);
     run_y<R>(a, 3, -1, s);
-    if (p->D == 1) cls_scatter<R>(p, s);
+    if (p->D == 1) cls_scatter<R>(p, slot, s);
     run_x_c2r<R>(a, 3, s);
 }
 
 template <typename R>
-void launch_z_dispatch(const se_plan* p, hipStream_t s)
+void launch_z_dispatch(const se_plan* p, int slot, hipStream_t s)
 {
-    if (p->kernel == SE_STOKESLET) launch_z<R, SE_STOKESLET, 3>(p, s);
-    else if (p->kernel == SE_ROTLET) launch_z<R, SE_ROTLET, 3>(p, s);
-    else launch_z<R, SE_STRESSLET, 6>(p, s);
+    if (p->kernel == SE_STOKESLET) launch_z<R, SE_STOKESLET, 3>(p, slot, s);
+    else if (p->kernel == SE_ROTLET) launch_z<R, SE_ROTLET, 3>(p, slot, s);
+    else launch_z<R, SE_STRESSLET, 6>(p, slot, s);
 }
 
 // ------------------------------------------------- adaptive FFT: upsampled classes
@@ -784,7 +785,12 @@ struct se_cls_args {
     double xi, R, scale;
 };
 
-se_cls_args make_cls_args(const se_plan* p, const se_aft_class& c)
+void* cls_slot_buf(const se_plan* p, const se_aft_class& c, int slot)
+{
+    return (char*)c.buf + (size_t)slot * p->ncomp * c.nkx * c.ny * c.nz * 2 * se_real_bytes(p);
+}
+
+se_cls_args make_cls_args(const se_plan* p, const se_aft_class& c, int slot)
 {
     se_cls_args a;
     std::memset(&a, 0, sizeof(a));
@@ -799,8 +805,8 @@ se_cls_args make_cls_args(const se_plan* p, const se_aft_class& c)
     a.N1 = p->Nfft[1];
     a.Mg1 = p->g.Mg[1];
     a.Mz = p->g.Mg[2];
-    a.spec = p->d_spec;
-    a.buf = c.buf;
+    a.spec = se_slot_spec(p, slot);
+    a.buf = cls_slot_buf(p, c, slot);
     a.kv = c.kv;
     a.iw = c.iw;
     a.mk = c.mk;
@@ -940,33 +946,33 @@ __global__ void k_cls_scale(se_cls_args a)
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
-se_fft_args cls_fft_args(const se_plan* p, const se_aft_class& c)
+se_fft_args cls_fft_args(const se_plan* p, const se_aft_class& c, int slot)
 {
     const int Mg[3] = {2, c.ny, c.nz};
     const int N[3] = {2, c.ny, c.nz};
-    se_fft_args a = make_fft_args_geom(Mg, N, p->g.h, nullptr, c.buf, c.tw, c.tw_off, p->ncomp);
+    se_fft_args a = make_fft_args_geom(Mg, N, p->g.h, nullptr, cls_slot_buf(p, c, slot), c.tw, c.tw_off, p->ncomp);
     a.Hx = c.nkx;
     a.Hp = c.nkx;
     return a;
 }
 
 template <typename R>
-void cls_gather(const se_plan* p, hipStream_t s)
+void cls_gather(const se_plan* p, int slot, hipStream_t s)
 {
     for (const se_aft_class& c : p->cls) {
         if (!c.active) continue;
-        se_cls_args a = make_cls_args(p, c);
+        se_cls_args a = make_cls_args(p, c, slot);
         int64_t n = (int64_t)c.nkx * c.ny * c.nz * p->ncomp;
         hipLaunchKernelGGL(k_cls_gather<R>, dim3(nblk(n)), dim3(256), 0, s, a, p->ncomp);
     }
 }
 
 template <typename R>
-void cls_scatter(const se_plan* p, hipStream_t s)
+void cls_scatter(const se_plan* p, int slot, hipStream_t s)
 {
     for (const se_aft_class& c : p->cls) {
         if (!c.active) continue;
-        se_cls_args a = make_cls_args(p, c);
+        se_cls_args a = make_cls_args(p, c, slot);
         int rows = p->D == 2 ? c.ny : p->g.Mg[1];
         int64_t n = 3 * (int64_t)c.nkx * rows * p->g.Mg[2];
         hipLaunchKernelGGL(k_cls_scatter<R>, dim3(nblk(n)), dim3(256), 0, s, a);
@@ -974,14 +980,14 @@ void cls_scatter(const se_plan* p, hipStream_t s)
 }
 
 template <typename R, int KER, int NC>
-void cls_transform(const se_plan* p, hipStream_t s)
+void cls_transform(const se_plan* p, int slot, hipStream_t s)
 {
     for (const se_aft_class& c : p->cls) {
         if (!c.active) continue;
-        se_fft_args f = cls_fft_args(p, c);
+        se_fft_args f = cls_fft_args(p, c, slot);
         if (p->D == 1) run_y<R>(f, NC, 1, s);
         run_z_plain<R>(f, NC, 1, s);
-        se_cls_args a = make_cls_args(p, c);
+        se_cls_args a = make_cls_args(p, c, slot);
         hipLaunchKernelGGL((k_cls_scale<R, KER, NC>), dim3(nblk((int64_t)c.nkx * c.ny * c.nz)), dim3(256), 0, s, a);
         run_z_plain<R>(f, 3, -1, s);
         if (p->D == 1) run_y<R>(f, 3, -1, s);
@@ -989,40 +995,40 @@ void cls_transform(const se_plan* p, hipStream_t s)
 }
 
 template <typename R>
-void cls_transform_dispatch(const se_plan* p, hipStream_t s)
+void cls_transform_dispatch(const se_plan* p, int slot, hipStream_t s)
 {
-    if (p->kernel == SE_STOKESLET) cls_transform<R, SE_STOKESLET, 3>(p, s);
-    else if (p->kernel == SE_ROTLET) cls_transform<R, SE_ROTLET, 3>(p, s);
-    else cls_transform<R, SE_STRESSLET, 6>(p, s);
+    if (p->kernel == SE_STOKESLET) cls_transform<R, SE_STOKESLET, 3>(p, slot, s);
+    else if (p->kernel == SE_ROTLET) cls_transform<R, SE_ROTLET, 3>(p, slot, s);
+    else cls_transform<R, SE_STRESSLET, 6>(p, slot, s);
 }
 
 }  // namespace
 
 // D = 1: the class planes are copied out after the x transform (before y);
 // D = 2: the class columns after the x and y transforms.
-void se_launch_fft_xy_forward(const se_plan* p, hipStream_t s)
+void se_launch_fft_xy_forward(const se_plan* p, int slot, hipStream_t s)
 {
-    if (p->fp32) launch_fwd<float>(p, s);
-    else launch_fwd<double>(p, s);
+    if (p->fp32) launch_fwd<float>(p, slot, s);
+    else launch_fwd<double>(p, slot, s);
 }
 
-void se_launch_fft_z_scale(const se_plan* p, hipStream_t s)
+void se_launch_fft_z_scale(const se_plan* p, int slot, hipStream_t s)
 {
     if (p->fp32) {
-        launch_z_dispatch<float>(p, s);
-        if (p->D == 1 || p->D == 2) cls_transform_dispatch<float>(p, s);
-        if (p->D == 2) cls_scatter<float>(p, s);
+        launch_z_dispatch<float>(p, slot, s);
+        if (p->D == 1 || p->D == 2) cls_transform_dispatch<float>(p, slot, s);
+        if (p->D == 2) cls_scatter<float>(p, slot, s);
     } else {
-        launch_z_dispatch<double>(p, s);
-        if (p->D == 1 || p->D == 2) cls_transform_dispatch<double>(p, s);
-        if (p->D == 2) cls_scatter<double>(p, s);
+        launch_z_dispatch<double>(p, slot, s);
+        if (p->D == 1 || p->D == 2) cls_transform_dispatch<double>(p, slot, s);
+        if (p->D == 2) cls_scatter<double>(p, slot, s);
     }
 }
 
-void se_launch_fft_inverse(const se_plan* p, hipStream_t s)
+void se_launch_fft_inverse(const se_plan* p, int slot, hipStream_t s)
 {
-    if (p->fp32) launch_inv<float>(p, s);
-    else launch_inv<double>(p, s);
+    if (p->fp32) launch_inv<float>(p, slot, s);
+    else launch_inv<double>(p, slot, s);
 }
 
 // Whether the line kernels can hold the transforms of a plan in LDS

@@ -82,6 +82,7 @@ struct se_plan {
     int kernel = 0;
     int ncomp = 3;   // gridded components (3, or 6 for the symmetrised stresslet source)
     int nrhs = 1;
+    int rb = 1;      // right-hand sides per chunk (buffers hold rb slots)
     bool fp32 = false;
     int device = 0;
     int64_t ns = 0, nt = 0;
@@ -135,6 +136,28 @@ struct se_plan {
     std::string msg;
 };
 
+// Per-slot buffer views (a chunk of rb right-hand sides shares the geometry).
+inline size_t se_grid_elems(const se_plan* p) { return (size_t)p->g.Mg[0] * p->g.Mg[1] * p->g.Mg[2]; }
+inline size_t se_spec_elems(const se_plan* p) { return (size_t)p->Hp * p->Nfft[1] * p->g.Mg[2]; }
+inline size_t se_real_bytes(const se_plan* p) { return p->fp32 ? sizeof(float) : sizeof(double); }
+inline void* se_slot_grid(const se_plan* p, int slot)
+{
+    return (char*)p->d_grid + (size_t)slot * p->ncomp * se_grid_elems(p) * se_real_bytes(p);
+}
+inline void* se_slot_spec(const se_plan* p, int slot)
+{
+    return (char*)p->d_spec + (size_t)slot * p->ncomp * se_spec_elems(p) * 2 * se_real_bytes(p);
+}
+inline void* se_slot_fs(const se_plan* p, int slot)
+{
+    return (char*)p->d_fs + (size_t)slot * p->ncomp * p->ns * se_real_bytes(p);
+}
+inline double* se_slot_fs64(const se_plan* p, int slot) { return p->d_fs64 + (size_t)slot * 4 * p->ns; }
+inline double* se_slot_str4(const se_plan* p, int slot) { return p->d_str4 + (size_t)slot * 4 * p->ns; }
+inline double* se_slot_red(const se_plan* p, int slot) { return p->d_red + (size_t)slot * (SE_RED_OUT + 7 * SE_RED_BLOCKS); }
+inline double* se_slot_uF(const se_plan* p, int slot) { return p->d_uF + (size_t)slot * 3 * p->nt; }
+inline double* se_slot_uR(const se_plan* p, int slot) { return p->d_uR + (size_t)slot * 3 * p->nt; }
+
 // ---- planner (se_params.cpp)
 se_status se_select_params(const se_problem* p, const se_params* manual, se_params* out,
                            std::string* msg);
@@ -156,18 +179,17 @@ void se_launch_gather_sorted(const double* xyz, const int* perm, int64_t n, cons
 void se_launch_cell_starts(const int* sorted_keys, int64_t n, int64_t nbins, int* start,
                            hipStream_t s);
 se_status se_sort_pairs(se_plan* p, int64_t n, hipStream_t s);
-void se_launch_strengths(const se_plan* p, const double* f, hipStream_t s);
-void se_launch_spread(const se_plan* p, hipStream_t s);
-void se_launch_fft_xy_forward(const se_plan* p, hipStream_t s);
-void se_launch_fft_z_scale(const se_plan* p, hipStream_t s);
-void se_launch_fft_inverse(const se_plan* p, hipStream_t s);
-void se_launch_gather(const se_plan* p, hipStream_t s);
-void se_launch_real_space(const se_plan* p, hipStream_t s);
-void se_launch_reductions(const se_plan* p, hipStream_t s);
+void se_launch_strengths(const se_plan* p, const double* f, int slot, hipStream_t s);
+void se_launch_spread(const se_plan* p, int slot0, int nslot, hipStream_t s);
+void se_launch_fft_xy_forward(const se_plan* p, int slot, hipStream_t s);
+void se_launch_fft_z_scale(const se_plan* p, int slot, hipStream_t s);
+void se_launch_fft_inverse(const se_plan* p, int slot, hipStream_t s);
+void se_launch_gather(const se_plan* p, int slot0, int nslot, hipStream_t s);
+void se_launch_real_space(const se_plan* p, int slot0, int nslot, hipStream_t s);
+void se_launch_reductions(const se_plan* p, int slot, hipStream_t s);
 void se_fft3d_f64(const int* Mg, const int* N, const double* h, double* grid, double* spec, const double* tw,
                   const int* tw_off, int ncomp, int dir, hipStream_t s);
 void se_fft_twiddles(const int* N, std::vector<double>* tw, int* off);
 se_status se_d0_precompute(se_plan* p);
 bool se_fft_fits(const int* N, int ncomp, bool fp32);
-void se_launch_finalize(const se_plan* p, const double* f, double* u, double* u_real,
-                        double* u_fourier, hipStream_t s);
+void se_launch_finalize(const se_plan* p, int slot, double* u, double* u_real, double* u_fourier, hipStream_t s);

@@ -47,31 +47,43 @@ __device__ __forceinline__ double horner_tab(const double* c, double sg)
 //   Omega: (G/r^3) (f x r)
 //   T:     -2 r (r.q)(r.nu)/r^4 * (3G + (4x^3/sqrt(pi)) E)/r
 //          + (4 xi^3/sqrt(pi)) E (q (r.nu) + nu (r.q) + r (q.nu))
-template <int KER>
-__device__ __forceinline__ void real_pair(const double* tab, double xi, double rscale, const double* r, double r2,
-                                          const double* f, const double* nu, double* u)
+struct se_radial {
+    double inv, x, G, E;
+};
+
+__device__ __forceinline__ se_radial real_radial(const double* tab, double xi, double rscale, double r2)
 {
-    const double inv = rsqrt(r2);
-    const double x = xi * r2 * inv;
-    const double xs = x * rscale;
+    se_radial q;
+    q.inv = rsqrt(r2);
+    q.x = xi * r2 * q.inv;
+    const double xs = q.x * rscale;
     const int iv = min((int)xs, SE_RTAB_N - 1);
     const double sg = 2.0 * (xs - iv) - 1.0;
-    const double G = horner_tab(tab + iv * kRn, sg);
-    const double E = horner_tab(tab + (SE_RTAB_N + iv) * kRn, sg);
+    q.G = horner_tab(tab + iv * kRn, sg);
+    q.E = horner_tab(tab + (SE_RTAB_N + iv) * kRn, sg);
+    return q;
+}
+
+template <int KER>
+__device__ __forceinline__ void real_apply(const se_radial& q, double xi, const double* r, const double* f,
+                                           const double* nu, double* u)
+{
+    const double inv = q.inv;
     if constexpr (KER == SE_STOKESLET) {
-        const double c1 = G * inv;
-        const double c2 = (4.0 / kSqrtPi) * xi * E;
+        const double c1 = q.G * inv;
+        const double c2 = (4.0 / kSqrtPi) * xi * q.E;
         const double rf = (r[0] * f[0] + r[1] * f[1] + r[2] * f[2]) * inv * inv;
 #pragma unroll
         for (int j = 0; j < 3; j++) u[j] += c1 * (f[j] + r[j] * rf) - c2 * f[j];
     } else if constexpr (KER == SE_ROTLET) {
-        const double c1 = G * inv * inv * inv;
+        const double c1 = q.G * inv * inv * inv;
         u[0] += c1 * (f[1] * r[2] - f[2] * r[1]);
         u[1] += c1 * (f[2] * r[0] - f[0] * r[2]);
         u[2] += c1 * (f[0] * r[1] - f[1] * r[0]);
     } else {
-        const double c1 = (3.0 * G + (4.0 / kSqrtPi) * x * x * x * E) * inv;
-        const double c2 = (4.0 / kSqrtPi) * xi * xi * xi * E;
+        const double x = q.x;
+        const double c1 = (3.0 * q.G + (4.0 / kSqrtPi) * x * x * x * q.E) * inv;
+        const double c2 = (4.0 / kSqrtPi) * xi * xi * xi * q.E;
         const double rq = r[0] * f[0] + r[1] * f[1] + r[2] * f[2];
         const double rv = r[0] * nu[0] + r[1] * nu[1] + r[2] * nu[2];
         const double qv = f[0] * nu[0] + f[1] * nu[1] + f[2] * nu[2];
@@ -80,6 +92,20 @@ __device__ __forceinline__ void real_pair(const double* tab, double xi, double r
 #pragma unroll
         for (int j = 0; j < 3; j++) u[j] += a * r[j] + c2 * (f[j] * rv + nu[j] * rq + r[j] * qv);
     }
+}
+
+// u_j += G^R_{jl(m)}(r; xi) . f, eqs. (stokeslet-real), (rotlet-real),
+// (stresslet-real), written with x = xi r through G(x) = erfc(x) +
+// (2x/sqrt(pi)) e^{-x^2} and E(x) = e^{-x^2} (tabulated, see se_radial_table):
+//   S:     (G/r)(f + r (r.f)/r^2) - (4 xi/sqrt(pi)) E f
+//   Omega: (G/r^3) (f x r)
+//   T:     -2 r (r.q)(r.nu)/r^4 * (3G + (4x^3/sqrt(pi)) E)/r
+//          + (4 xi^3/sqrt(pi)) E (q (r.nu) + nu (r.q) + r (q.nu))
+template <int KER>
+__device__ __forceinline__ void real_pair(const double* tab, double xi, double rscale, const double* r, double r2,
+                                          const double* f, const double* nu, double* u)
+{
+    real_apply<KER>(real_radial(tab, xi, rscale, r2), xi, r, f, nu, u);
 }
 
 // Persistent workgroups of 4 wavefronts; each wavefront walks a contiguous
@@ -314,14 +340,14 @@ __global__ void __launch_bounds__(256) k_real(se_real_args a)
 
 #define SE_R2_QCAP 512
 
-template <int KER>
+template <int KER, int RB>
 struct se_real2_lds {
     double cx[64], cy[64], cz[64];  // shifted candidate positions
-    double fx[64], fy[64], fz[64];  // strengths
+    double fx[RB][64], fy[RB][64], fz[RB][64];  // strengths of the RB right-hand sides
     double nx[KER == SE_STRESSLET ? 64 : 1], ny[KER == SE_STRESSLET ? 64 : 1],
         nz[KER == SE_STRESSLET ? 64 : 1];  // normals (stresslet)
     double tx[64], ty[64], tz[64];  // target positions of the chunk
-    double acc[3][64];
+    double acc[3 * RB][64];
     unsigned short q[SE_R2_QCAP];   // queued pairs: (target lane << 6) | candidate slot
     int cid[64];      // sorted index when unshifted, else -1
     int run_beg[SE_R2_SLOTS];
@@ -346,9 +372,9 @@ __device__ __forceinline__ int wave_incl_scan(int v, int lane)
     return v;
 }
 
-template <int KER>
-__device__ __forceinline__ void eval_queue2(const se_real_args& a, const double* tab, se_real2_lds<KER>& L, int qn,
-                                            int lane)
+template <int KER, int RB>
+__device__ __forceinline__ void eval_queue2(const se_real_args& a, const double* tab, se_real2_lds<KER, RB>& L,
+                                            int qn, int lane)
 {
     wave_sync();
     for (int e0 = 0; e0 < qn; e0 += 64) {
@@ -358,34 +384,38 @@ __device__ __forceinline__ void eval_queue2(const se_real_args& a, const double*
             const int tl = qv >> 6, c = qv & 63;
             const double r[3] = {L.tx[tl] - L.cx[c], L.ty[tl] - L.cy[c], L.tz[tl] - L.cz[c]};
             const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-            const double f[3] = {L.fx[c], L.fy[c], L.fz[c]};
+            const se_radial q = real_radial(tab, a.xi, a.rscale, r2);
             double nu[3] = {0.0, 0.0, 0.0};
             if constexpr (KER == SE_STRESSLET) {
                 nu[0] = L.nx[c];
                 nu[1] = L.ny[c];
                 nu[2] = L.nz[c];
             }
-            double u[3] = {0.0, 0.0, 0.0};
-            real_pair<KER>(tab, a.xi, a.rscale, r, r2, f, nu, u);
-            atomicAdd(&L.acc[0][tl], u[0]);
-            atomicAdd(&L.acc[1][tl], u[1]);
-            atomicAdd(&L.acc[2][tl], u[2]);
+#pragma unroll
+            for (int k = 0; k < RB; k++) {
+                const double f[3] = {L.fx[k][c], L.fy[k][c], L.fz[k][c]};
+                double u[3] = {0.0, 0.0, 0.0};
+                real_apply<KER>(q, a.xi, r, f, nu, u);
+                atomicAdd(&L.acc[3 * k + 0][tl], u[0]);
+                atomicAdd(&L.acc[3 * k + 1][tl], u[1]);
+                atomicAdd(&L.acc[3 * k + 2][tl], u[2]);
+            }
         }
     }
     wave_sync();
 }
 
-template <int KER>
+template <int KER, int RB>
 __global__ void __launch_bounds__(256) k_real2(se_real_args a, se_real2_geom bg)
 {
     __shared__ double tab[2 * SE_RTAB_N * kRn];
-    __shared__ se_real2_lds<KER> lds[4];
+    __shared__ se_real2_lds<KER, RB> lds[4];
     for (int i = threadIdx.x; i < 2 * SE_RTAB_N * kRn; i += 256) tab[i] = a.rtab[i];
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t blk = (int64_t)se_xcd_block(blockIdx.x, gridDim.x) * 4 + wave;
     if (blk >= bg.nblk) return;
-    se_real2_lds<KER>& L = lds[wave];
+    se_real2_lds<KER, RB>& L = lds[wave];
     const se_grid_geom& g = a.g;
     const int ib[3] = {(int)(blk % bg.nbk[0]), (int)((blk / bg.nbk[0]) % bg.nbk[1]),
                        (int)(blk / ((int64_t)bg.nbk[0] * bg.nbk[1]))};
@@ -489,9 +519,13 @@ __global__ void __launch_bounds__(256) k_real2(se_real_args a, se_real2_geom bg)
         L.tx[lane] = tq.x;
         L.ty[lane] = tq.y;
         L.tz[lane] = tq.z;
-        L.acc[0][lane] = L.acc[1][lane] = L.acc[2][lane] = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3 * RB; k++) L.acc[k][lane] = 0.0;
         // prefetch registers for one candidate per lane
-        double4 np = make_double4(0, 0, 0, 0), nf = np, nn = np;
+        double4 np = make_double4(0, 0, 0, 0), nn = np;
+        double4 nf[RB];
+#pragma unroll
+        for (int k = 0; k < RB; k++) nf[k] = np;
         int nid = -1;
         auto load = [&](int cbase) {
             const int f = cbase + lane;
@@ -510,7 +544,8 @@ __global__ void __launch_bounds__(256) k_real2(se_real_args a, se_real2_geom bg)
                 const int kz = g.periodic[2] ? se_floordiv(blo[2] + row / ny, g.nb[2]) : 0;
                 const double4 p = a.xs[sidx];
                 np = make_double4(p.x + kx * g.L[0], p.y + ky * g.L[1], p.z + kz * g.L[2], 0.0);
-                nf = a.f[sidx];
+#pragma unroll
+                for (int k = 0; k < RB; k++) nf[k] = a.f[(int64_t)k * a.ns + sidx];
                 if (KER == SE_STRESSLET) nn = a.nrm[sidx];
                 nid = (kx == 0 && ky == 0 && kz == 0) ? sidx : -1;
             }
@@ -520,9 +555,12 @@ __global__ void __launch_bounds__(256) k_real2(se_real_args a, se_real2_geom bg)
             L.cx[lane] = np.x;
             L.cy[lane] = np.y;
             L.cz[lane] = np.z;
-            L.fx[lane] = nf.x;
-            L.fy[lane] = nf.y;
-            L.fz[lane] = nf.z;
+#pragma unroll
+            for (int k = 0; k < RB; k++) {
+                L.fx[k][lane] = nf[k].x;
+                L.fy[k][lane] = nf[k].y;
+                L.fz[k][lane] = nf[k].z;
+            }
             if constexpr (KER == SE_STRESSLET) {
                 L.nx[lane] = nn.x;
                 L.ny[lane] = nn.y;
@@ -571,7 +609,7 @@ __global__ void __launch_bounds__(256) k_real2(se_real_args a, se_real2_geom bg)
                 const uint64_t b = __ballot(has);
                 const int nb = __popcll(b);
                 if (qn + nb > SE_R2_QCAP) {
-                    eval_queue2<KER>(a, tab, L, qn, lane);
+                    eval_queue2<KER, RB>(a, tab, L, qn, lane);
                     qn = 0;
                 }
                 if (has) {
@@ -581,13 +619,12 @@ __global__ void __launch_bounds__(256) k_real2(se_real_args a, se_real2_geom bg)
                 }
                 qn += nb;
             }
-            eval_queue2<KER>(a, tab, L, qn, lane);
+            eval_queue2<KER, RB>(a, tab, L, qn, lane);
             wave_sync();
         }
         if (tvalid) {
-            a.u[tidx] = L.acc[0][lane];
-            a.u[a.nt + tidx] = L.acc[1][lane];
-            a.u[2 * a.nt + tidx] = L.acc[2][lane];
+#pragma unroll
+            for (int k = 0; k < 3 * RB; k++) a.u[(int64_t)k * a.nt + tidx] = L.acc[k][lane];
         }
         wave_sync();
     }
@@ -715,27 +752,29 @@ inline unsigned grid1d(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs)
 
 }  // namespace
 
-void se_launch_strengths(const se_plan* p, const double* f, hipStream_t s)
+void se_launch_strengths(const se_plan* p, const double* f, int slot, hipStream_t s)
 {
+    double* f64 = se_slot_fs64(p, slot);
+    double4* f4 = (double4*)se_slot_str4(p, slot);
     if (p->fp32)
         hipLaunchKernelGGL(k_strengths<float>, dim3(grid1d(p->ns, 256)), dim3(256), 0, s, f, p->d_src_perm, p->ns,
-                           p->d_nrm, p->ncomp, p->d_fs64, (float*)p->d_fs, p->d_fs64 + 3 * p->ns, (double4*)p->d_str4,
-                           p->d_flags);
+                           p->d_nrm, p->ncomp, f64, (float*)se_slot_fs(p, slot), f64 + 3 * p->ns, f4, p->d_flags);
     else
         hipLaunchKernelGGL(k_strengths<double>, dim3(grid1d(p->ns, 256)), dim3(256), 0, s, f, p->d_src_perm, p->ns,
-                           p->d_nrm, p->ncomp, p->d_fs64, (double*)p->d_fs, p->d_fs64 + 3 * p->ns, (double4*)p->d_str4,
-                           p->d_flags);
+                           p->d_nrm, p->ncomp, f64, (double*)se_slot_fs(p, slot), f64 + 3 * p->ns, f4, p->d_flags);
 }
 
-void se_launch_reductions(const se_plan* p, hipStream_t s)
+void se_launch_reductions(const se_plan* p, int slot, hipStream_t s)
 {
-    double* part = p->d_red + SE_RED_OUT;
-    hipLaunchKernelGGL(k_reduce_sources, dim3(SE_RED_BLOCKS), dim3(512), 0, s, p->d_fs64 + 3 * p->ns, p->d_fs64,
-                       p->d_src, p->ns, p->kernel == SE_STRESSLET ? 1 : 0, part);
-    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(SE_RED_BLOCKS), 0, s, part, p->d_red);
+    double* red = se_slot_red(p, slot);
+    double* part = red + SE_RED_OUT;
+    const double* f64 = se_slot_fs64(p, slot);
+    hipLaunchKernelGGL(k_reduce_sources, dim3(SE_RED_BLOCKS), dim3(512), 0, s, f64 + 3 * p->ns, f64, p->d_src, p->ns,
+                       p->kernel == SE_STRESSLET ? 1 : 0, part);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(SE_RED_BLOCKS), 0, s, part, red);
 }
 
-void se_launch_real_space(const se_plan* p, hipStream_t s)
+void se_launch_real_space(const se_plan* p, int slot0, int nslot, hipStream_t s)
 {
     se_real_args a;
     a.g = p->g;
@@ -743,7 +782,7 @@ void se_launch_real_space(const se_plan* p, hipStream_t s)
     a.nt = p->nt;
     a.xs = (const double4*)p->d_pos4;
     a.ns = p->ns;
-    a.f = (const double4*)p->d_str4;
+    a.f = (const double4*)se_slot_str4(p, slot0);
     a.nrm = (const double4*)p->d_nrm4;
     a.rtab = p->d_rtab;
     a.start = p->d_src_start;
@@ -753,7 +792,7 @@ void se_launch_real_space(const se_plan* p, hipStream_t s)
     a.rscale = SE_RTAB_N / se_rtab_xmax(p->par);
     for (int d = 0; d < 3; d++) a.Ra[d] = (int)std::ceil(p->par.rc / p->g.h[d]) + 1;
     a.tas = p->tas ? 1 : 0;
-    a.u = p->d_uR;
+    a.u = se_slot_uR(p, slot0);
     a.flags = p->d_flags;
     // blocked kernel: TB^3 target bins per wavefront, about 48 targets
     const se_grid_geom& g = p->g;
@@ -773,29 +812,46 @@ void se_launch_real_space(const se_plan* p, hipStream_t s)
     const int nseg = g.periodic[0] ? (span[0] + g.nb[0] - 1) / g.nb[0] + 1 : 1;
     if ((int64_t)span[1] * span[2] * nseg <= SE_R2_SLOTS && TB * TB <= SE_R2_TROWS) {
         unsigned nwg = (unsigned)((bg.nblk + 3) / 4);
-        if (p->kernel == SE_STOKESLET) hipLaunchKernelGGL(k_real2<SE_STOKESLET>, dim3(nwg), dim3(256), 0, s, a, bg);
-        else if (p->kernel == SE_ROTLET) hipLaunchKernelGGL(k_real2<SE_ROTLET>, dim3(nwg), dim3(256), 0, s, a, bg);
-        else hipLaunchKernelGGL(k_real2<SE_STRESSLET>, dim3(nwg), dim3(256), 0, s, a, bg);
+        if (nslot == 2 && p->kernel == SE_STOKESLET)
+            hipLaunchKernelGGL((k_real2<SE_STOKESLET, 2>), dim3(nwg), dim3(256), 0, s, a, bg);
+        else if (nslot == 2 && p->kernel == SE_ROTLET)
+            hipLaunchKernelGGL((k_real2<SE_ROTLET, 2>), dim3(nwg), dim3(256), 0, s, a, bg);
+        else {
+            for (int k = 0; k < nslot; k++) {
+                se_real_args b = a;
+                b.f = (const double4*)se_slot_str4(p, slot0 + k);
+                b.u = se_slot_uR(p, slot0 + k);
+                if (p->kernel == SE_STOKESLET)
+                    hipLaunchKernelGGL((k_real2<SE_STOKESLET, 1>), dim3(nwg), dim3(256), 0, s, b, bg);
+                else if (p->kernel == SE_ROTLET)
+                    hipLaunchKernelGGL((k_real2<SE_ROTLET, 1>), dim3(nwg), dim3(256), 0, s, b, bg);
+                else
+                    hipLaunchKernelGGL((k_real2<SE_STRESSLET, 1>), dim3(nwg), dim3(256), 0, s, b, bg);
+            }
+        }
         return;
     }
     unsigned nb = (unsigned)std::min<int64_t>((p->nt + 3) / 4, SE_REAL_BLOCKS);
-    if (p->kernel == SE_STOKESLET) hipLaunchKernelGGL(k_real<SE_STOKESLET>, dim3(nb), dim3(256), 0, s, a);
-    else if (p->kernel == SE_ROTLET) hipLaunchKernelGGL(k_real<SE_ROTLET>, dim3(nb), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL(k_real<SE_STRESSLET>, dim3(nb), dim3(256), 0, s, a);
+    for (int k = 0; k < nslot; k++) {
+        se_real_args b = a;
+        b.f = (const double4*)se_slot_str4(p, slot0 + k);
+        b.u = se_slot_uR(p, slot0 + k);
+        if (p->kernel == SE_STOKESLET) hipLaunchKernelGGL(k_real<SE_STOKESLET>, dim3(nb), dim3(256), 0, s, b);
+        else if (p->kernel == SE_ROTLET) hipLaunchKernelGGL(k_real<SE_ROTLET>, dim3(nb), dim3(256), 0, s, b);
+        else hipLaunchKernelGGL(k_real<SE_STRESSLET>, dim3(nb), dim3(256), 0, s, b);
+    }
 }
 
-void se_launch_finalize(const se_plan* p, const double* f, double* u, double* u_real, double* u_fourier,
-                        hipStream_t s)
+void se_launch_finalize(const se_plan* p, int slot, double* u, double* u_real, double* u_fourier, hipStream_t s)
 {
-    (void)f;
     se_fin_args a;
     a.nt = p->nt;
     a.perm = p->tas ? p->d_src_perm : p->d_tgt_perm;
-    a.uF = p->d_uF;
-    a.uR = p->d_uR;
-    a.f64 = p->d_fs64;
+    a.uF = se_slot_uF(p, slot);
+    a.uR = se_slot_uR(p, slot);
+    a.f64 = se_slot_fs64(p, slot);
     a.xt = p->tas ? p->d_src : p->d_tgt;
-    a.red = p->d_red;
+    a.red = se_slot_red(p, slot);
     a.self_c = (p->kernel == SE_STOKESLET && p->tas) ? -4.0 * p->par.xi / kSqrtPi : 0.0;
     a.k0_c = (p->kernel == SE_STRESSLET && p->D == 3) ? -8.0 * M_PI / (p->g.L[0] * p->g.L[1] * p->g.L[2]) : 0.0;
     // D = 0 stokeslet: the optimal biharmonic b_B = -1/(2R) adds 4 b_B sum f

@@ -392,7 +392,7 @@ struct se_rt_lds {
     int list[4][SE_RT_KB];   // per wave: the batch's points whose support meets its columns
     int cnt[4];
     R f[SE_RT_KB][NC];       // gridding: the batch's strengths
-    double u[SE_RT_KB][3];   // gathering: the batch's block partial sums
+    double u[SE_RT_KB][NC];  // gathering: the batch's block partial sums
 };
 
 // Runs of sorted points whose anchor bins lie in the block's halo: one slot
@@ -503,7 +503,10 @@ __device__ int rt_stage_batch(const se_tile_args& a, const int* t0, int nslots, 
                 for (int c = 0; c < NC; c++) s.f[tid][c] = fs[c * n + sidx];
             }
         }
-        if constexpr (GATHER) s.u[tid][0] = s.u[tid][1] = s.u[tid][2] = 0.0;
+        if constexpr (GATHER) {
+#pragma unroll
+            for (int c = 0; c < NC; c++) s.u[tid][c] = 0.0;
+        }
         // one wave: ballot per sub-block, compacted lists
         int o[3] = {s.o[tid][0], s.o[tid][1], s.o[tid][2]};
         bool any = false;
@@ -660,10 +663,10 @@ __device__ __forceinline__ double rt_dpp(double v)
 }
 constexpr int kDppRor8 = 0x128, kDppHalfMirror = 0x141, kDppXor2 = 0x4E, kDppXor1 = 0xB1;
 
-template <typename R>
+template <typename R, int NCG>
 __global__ void __launch_bounds__(SE_RT_THREADS) k_gather_rt(se_tile_args a)
 {
-    __shared__ se_rt_lds<R, 3> s;
+    __shared__ se_rt_lds<R, NCG> s;
     const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const se_grid_geom& g = a.g;
     int t0[3], te[3];
@@ -674,7 +677,7 @@ __global__ void __launch_bounds__(SE_RT_THREADS) k_gather_rt(se_tile_args a)
     }
     const int wxo = (wave & 1) * 8, wyo = (wave >> 1) * 8;
     const int lx = lane & 7, ly = lane >> 3;
-    R F[SE_RT_TZ][3];
+    R F[SE_RT_TZ][NCG];
     {
         const R* grid = (const R*)a.grid;
         const int64_t plane = (int64_t)g.Mg[0] * g.Mg[1];
@@ -687,7 +690,7 @@ __global__ void __launch_bounds__(SE_RT_THREADS) k_gather_rt(se_tile_args a)
             const bool inz = in && z < te[2];
             const int64_t o = inz ? (int64_t)(t0[2] + z) * plane + col : 0;
 #pragma unroll
-            for (int c = 0; c < 3; c++) F[z][c] = inz ? grid[c * vol + o] : (R)0;
+            for (int c = 0; c < NCG; c++) F[z][c] = inz ? grid[c * vol + o] : (R)0;
         }
     }
     int b0[3], nbr[3];
@@ -697,31 +700,34 @@ __global__ void __launch_bounds__(SE_RT_THREADS) k_gather_rt(se_tile_args a)
     if (g.periodic[0]) nseg = se_floordiv(b0[0] + nbr[0] - 1, g.nb[0]) - se_floordiv(b0[0], g.nb[0]) + 1;
     const int nslots = nbr[0] > 0 ? nbr[1] * nbr[2] * nseg : 0;
     const int64_t n = a.n;
+    constexpr int GP = 24 / NCG;  // points per reduce-scatter group
     for (int base = 0; base < total; base += SE_RT_KB) {
-        const int nb = rt_stage_batch<R, true, 3>(a, t0, nslots, total, base, s, tid);
-        // Groups of 8 points: per-lane partial sums v[3j + c], then one
-        // reduce-scatter over the wave (halving steps xor 32, 16, 8 leave lane
-        // group k = bits 5..3 with point k's three sums; xor 4, 2, 1 finish).
+        const int nb = rt_stage_batch<R, true, NCG>(a, t0, nslots, total, base, s, tid);
+        // Groups of GP points: per-lane partial sums v[NCG j + c] (24 values),
+        // then one reduce-scatter over the wave: halving steps across lane
+        // bits 5, 4, 3 leave lane group k (bits 5..3) with values 3k .. 3k+2,
+        // and the sum over bits 2..0 completes them.
         const int cnt = __builtin_amdgcn_readfirstlane(s.cnt[wave]);
-        for (int i0 = 0; i0 < cnt; i0 += 8) {
+        for (int i0 = 0; i0 < cnt; i0 += GP) {
             R v[24];
 #pragma unroll
-            for (int j = 0; j < 8; j++) {
-                v[3 * j] = v[3 * j + 1] = v[3 * j + 2] = (R)0;
+            for (int j = 0; j < GP; j++) {
+#pragma unroll
+                for (int c = 0; c < NCG; c++) v[NCG * j + c] = (R)0;
                 if (i0 + j >= cnt) continue;
                 const int p = __builtin_amdgcn_readfirstlane(s.list[wave][i0 + j]);
                 const R wxy = s.w[p][wxo + lx] * s.w[p][SE_RT_TX + wyo + ly];
-                R v0 = 0, v1 = 0, v2 = 0;
+                R acc[NCG];
+#pragma unroll
+                for (int c = 0; c < NCG; c++) acc[c] = (R)0;
 #pragma unroll
                 for (int z = 0; z < SE_RT_TZ; z++) {
                     const R wz = s.w[p][SE_RT_TX + SE_RT_TY + z];
-                    v0 += wz * F[z][0];
-                    v1 += wz * F[z][1];
-                    v2 += wz * F[z][2];
+#pragma unroll
+                    for (int c = 0; c < NCG; c++) acc[c] += wz * F[z][c];
                 }
-                v[3 * j] = v0 * wxy;
-                v[3 * j + 1] = v1 * wxy;
-                v[3 * j + 2] = v2 * wxy;
+#pragma unroll
+                for (int c = 0; c < NCG; c++) v[NCG * j + c] = acc[c] * wxy;
             }
             const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
             R v12[12];
@@ -743,18 +749,19 @@ __global__ void __launch_bounds__(SE_RT_THREADS) k_gather_rt(se_tile_args a)
                 v3[i] += rt_dpp<kDppXor1>(v3[i]);
             }
             if ((lane & 7) == 0) {
-                const int k = i0 + (b5 ? 4 : 0) + (b4 ? 2 : 0) + (b3 ? 1 : 0);
+                const int grp = (b5 ? 4 : 0) + (b4 ? 2 : 0) + (b3 ? 1 : 0);
+                const int k = i0 + (3 * grp) / NCG, c0 = (3 * grp) % NCG;
                 if (k < cnt) {
                     const int p = s.list[wave][k];
-                    atomicAdd(&s.u[p][0], (double)v3[0]);
-                    atomicAdd(&s.u[p][1], (double)v3[1]);
-                    atomicAdd(&s.u[p][2], (double)v3[2]);
+                    atomicAdd(&s.u[p][c0], (double)v3[0]);
+                    atomicAdd(&s.u[p][c0 + 1], (double)v3[1]);
+                    atomicAdd(&s.u[p][c0 + 2], (double)v3[2]);
                 }
             }
         }
         __syncthreads();
-        if (tid < 3 * nb) {
-            const int p = tid / 3, c = tid - 3 * p;
+        for (int i = tid; i < NCG * nb; i += SE_RT_THREADS) {
+            const int p = i / NCG, c = i - NCG * p;
             const double v = s.u[p][c];
             if (v != 0.0) atomicAdd(&a.u[c * n + s.idx[p]], v);
         }
@@ -768,7 +775,7 @@ void set_lds(K kern, size_t bytes)
     if (bytes > 65536) (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-se_tile_args make_args(const se_plan* p, bool gather)
+se_tile_args make_args(const se_plan* p, bool gather, int slot)
 {
     se_tile_args a;
     a.g = p->g;
@@ -779,16 +786,16 @@ se_tile_args make_args(const se_plan* p, bool gather)
     a.P = p->par.P;
     a.nu = p->par.nu_deg;
     for (int d = 0; d < 3; d++) a.ntile[d] = p->ntile[d];
-    a.grid = p->d_grid;
-    a.fs = p->d_fs;
-    a.u = p->d_uF;
+    a.grid = se_slot_grid(p, slot);
+    a.fs = se_slot_fs(p, slot);
+    a.u = se_slot_uF(p, slot);
     return a;
 }
 
 template <typename R, int NC, int TX, int TY, int TZ>
-void launch_spread(const se_plan* p, hipStream_t s)
+void launch_spread(const se_plan* p, int slot, hipStream_t s)
 {
-    se_tile_args a = make_args(p, false);
+    se_tile_args a = make_args(p, false, slot);
     size_t lds = SE_MAX_P * (SE_MAX_NU + 1) * sizeof(double) + (size_t)NC * TX * TY * TZ * sizeof(R);
     auto kern = k_spread<R, NC, TX, TY, TZ>;
     set_lds(kern, lds);
@@ -797,9 +804,9 @@ void launch_spread(const se_plan* p, hipStream_t s)
 }
 
 template <typename R, int TX, int TY, int TZ>
-void launch_gather(const se_plan* p, hipStream_t s)
+void launch_gather(const se_plan* p, int slot, hipStream_t s)
 {
-    se_tile_args a = make_args(p, true);
+    se_tile_args a = make_args(p, true, slot);
     size_t lds = SE_MAX_P * (SE_MAX_NU + 1) * sizeof(double) + (size_t)3 * TX * TY * TZ * sizeof(R);
     auto kern = k_gather<R, TX, TY, TZ>;
     set_lds(kern, lds);
@@ -835,52 +842,69 @@ bool se_rt_fits(const se_plan* p)
 }
 
 template <typename R, int NC>
-void launch_spread_rt(const se_plan* p, hipStream_t s)
+void launch_spread_rt(const se_plan* p, int slot, hipStream_t s)
 {
-    se_tile_args a = make_args(p, false);
+    se_tile_args a = make_args(p, false, slot);
     unsigned nb = (unsigned)(p->ntile[0] * p->ntile[1] * p->ntile[2]);
     hipLaunchKernelGGL((k_spread_rt<R, NC>), dim3(nb), dim3(SE_RT_THREADS), 0, s, a);
 }
 
-template <typename R>
-void launch_gather_rt(const se_plan* p, hipStream_t s)
+template <typename R, int NCG>
+void launch_gather_rt(const se_plan* p, int slot, hipStream_t s)
 {
-    se_tile_args a = make_args(p, true);
+    se_tile_args a = make_args(p, true, slot);
     unsigned nb = (unsigned)(p->ntile[0] * p->ntile[1] * p->ntile[2]);
-    hipLaunchKernelGGL((k_gather_rt<R>), dim3(nb), dim3(SE_RT_THREADS), 0, s, a);
+    hipLaunchKernelGGL((k_gather_rt<R, NCG>), dim3(nb), dim3(SE_RT_THREADS), 0, s, a);
 }
 
-void se_launch_spread(const se_plan* p, hipStream_t s)
+// slot0 .. slot0 + nslot - 1: right-hand sides of the current chunk (two
+// stokeslet/rotlet slots are gridded together as six components)
+void se_launch_spread(const se_plan* p, int slot0, int nslot, hipStream_t s)
 {
     if (se_rt_fits(p)) {
-        if (p->fp32) {
-            if (p->ncomp == 3) launch_spread_rt<float, 3>(p, s);
-            else launch_spread_rt<float, 6>(p, s);
-        } else {
-            if (p->ncomp == 3) launch_spread_rt<double, 3>(p, s);
-            else launch_spread_rt<double, 6>(p, s);
+        if (p->ncomp == 3 && nslot == 2) {
+            if (p->fp32) launch_spread_rt<float, 6>(p, slot0, s);
+            else launch_spread_rt<double, 6>(p, slot0, s);
+            return;
+        }
+        for (int k = 0; k < nslot; k++) {
+            if (p->fp32) {
+                if (p->ncomp == 3) launch_spread_rt<float, 3>(p, slot0 + k, s);
+                else launch_spread_rt<float, 6>(p, slot0 + k, s);
+            } else {
+                if (p->ncomp == 3) launch_spread_rt<double, 3>(p, slot0 + k, s);
+                else launch_spread_rt<double, 6>(p, slot0 + k, s);
+            }
         }
         return;
     }
-    if (p->fp32) {
-        if (p->ncomp == 3) launch_spread<float, 3, 16, 16, 8>(p, s);
-        else launch_spread<float, 6, 16, 16, 8>(p, s);
-    } else {
-        if (p->ncomp == 3) launch_spread<double, 3, 16, 16, 8>(p, s);
-        else launch_spread<double, 6, 16, 16, 8>(p, s);
+    for (int k = 0; k < nslot; k++) {
+        if (p->fp32) {
+            if (p->ncomp == 3) launch_spread<float, 3, 16, 16, 8>(p, slot0 + k, s);
+            else launch_spread<float, 6, 16, 16, 8>(p, slot0 + k, s);
+        } else {
+            if (p->ncomp == 3) launch_spread<double, 3, 16, 16, 8>(p, slot0 + k, s);
+            else launch_spread<double, 6, 16, 16, 8>(p, slot0 + k, s);
+        }
     }
 }
 
-void se_launch_gather(const se_plan* p, hipStream_t s)
+void se_launch_gather(const se_plan* p, int slot0, int nslot, hipStream_t s)
 {
     if (se_rt_fits(p)) {
-        if (p->fp32) launch_gather_rt<float>(p, s);
-        else launch_gather_rt<double>(p, s);
+        if (nslot == 2) {
+            if (p->fp32) launch_gather_rt<float, 6>(p, slot0, s);
+            else launch_gather_rt<double, 6>(p, slot0, s);
+            return;
+        }
+        for (int k = 0; k < nslot; k++) {
+            if (p->fp32) launch_gather_rt<float, 3>(p, slot0 + k, s);
+            else launch_gather_rt<double, 3>(p, slot0 + k, s);
+        }
         return;
     }
-    if (p->fp32) {
-        launch_gather<float, 16, 16, 8>(p, s);
-    } else {
-        launch_gather<double, 16, 16, 8>(p, s);
+    for (int k = 0; k < nslot; k++) {
+        if (p->fp32) launch_gather<float, 16, 16, 8>(p, slot0 + k, s);
+        else launch_gather<double, 16, 16, 8>(p, slot0 + k, s);
     }
 }

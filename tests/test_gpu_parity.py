@@ -47,7 +47,8 @@ def _run(env, kernel, s, D=3, tol=1e-8, targets=None, precision=None, n_rhs=1, s
           (kernel, D, n, tol, list(s["box"]), None if targets is None else len(targets), n_rhs), flush=True)
     plan = se.Plan(kernel=kernel, periodicity=D, box=tuple(s["box"]), tol=tol, n_src=n,
                    n_tgt=0 if targets is None else len(targets), targets_are_sources=targets is None,
-                   source_q=_q_of(kernel, s) / n_rhs, safety=SAFETY, precision=prec, n_rhs=n_rhs, **kw)
+                   source_q=kw.pop("source_q", _q_of(kernel, s) / n_rhs), safety=SAFETY, precision=prec,
+                   n_rhs=n_rhs, **kw)
     plan.set_geometry(x, nu, t)
     if split:
         ur, uf = plan.execute_split(str_)
@@ -172,6 +173,32 @@ def test_multiple_rhs_equal_single_runs(env):
         s1 = {"x": s["x"], "box": s["box"], "f": s["f"][r]}
         ref = _ref(env, "stokeslet", s1)
         assert oracle.rms_rel_error(u[r], ref) <= 1e-8
+
+
+@pytest.mark.parametrize("kernel,D,nrhs,prec", [("stokeslet", 3, 4, "fp64"), ("rotlet", 2, 2, "fp64"),
+                                                  ("stokeslet", 1, 3, "fp64"), ("rotlet", 0, 2, "fp64"),
+                                                  ("stresslet", 3, 2, "fp64"), ("stokeslet", 3, 5, "fp32")])
+def test_batched_rhs_match_single_rhs_plans(env, kernel, D, nrhs, prec):
+    """Right-hand sides processed in pairs (shared weights, candidate lists
+    and radial functions) give the single-right-hand-side results."""
+    se, oracle, torch = env
+    s = W.system(1700 + nrhs + 10 * D, 1500, kernel=kernel, periodicity=D, n_rhs=nrhs)
+    precision = se.PREC_FP64 if prec == "fp64" else se.PREC_FP32
+    tol = 1e-8 if prec == "fp64" else 1e-6
+    src = "q" if kernel == "stresslet" else "f"
+    q_all = _q_of(kernel, s)
+    plan, u = _run(env, kernel, s, D=D, tol=tol, n_rhs=nrhs, precision=precision)
+    assert u.shape == (nrhs, 1500, 3)
+    for r in range(nrhs):
+        s1 = {k: v for k, v in s.items()}
+        s1[src] = s[src][r]
+        # same parameters as the batched plan (its Q is the mean over right-hand sides)
+        _, u1 = _run(env, kernel, s1, D=D, tol=tol, precision=precision, source_q=q_all / nrhs)
+        diff = oracle.rms_rel_error(u[r], u1)
+        print("batched rhs", kernel, D, nrhs, prec, r, "vs single", diff)
+        assert diff <= (1e-12 if prec == "fp64" else 1e-6)
+        if prec == "fp64":
+            assert oracle.rms_rel_error(u[r], _ref(env, kernel, s1, D=D)) <= tol
 
 
 def test_fp32_grid_path_meets_1e6(env):
