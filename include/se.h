@@ -210,6 +210,38 @@ se_status se_debug_cell_list(const se_plan* plan, int32_t which, const int32_t**
                              const int32_t** cell_start, int32_t* nbins_xyz,
                              int32_t* cell_width);
 
+/* ---- Batches of independent systems (uneven sizes, any periodicity).
+ *
+ * A batch owns one plan per system (same rules as se_plan_create, selector
+ * ANALYTIC or LEARNED).  se_batch_execute evaluates every system on one
+ * stream; the first call with a given set of pointers runs the launches
+ * eagerly, then records the same sequence into a HIP graph (relaxed stream
+ * capture, no memset nodes) and later calls with the same pointers replay
+ * that graph as one launch.  A null stream always runs eagerly.  The graph
+ * is dropped by se_batch_set_geometry, se_batch_tune and pointer changes.
+ * Arrays of pointers are host arrays of n_sys device pointers, laid out as
+ * for the single-system calls.  Errors: as the single-system calls; a
+ * failing system stops the call and reports its status. */
+typedef struct se_batch se_batch;
+se_status se_batch_create(const se_problem* probs, int32_t n_sys, se_batch** out);
+se_status se_batch_destroy(se_batch* batch);
+/* Member plan i (owned by the batch): parameters, timing, debug access. */
+se_status se_batch_plan(se_batch* batch, int32_t i, se_plan** plan);
+se_status se_batch_set_geometry(se_batch* batch, const double* const* src_xyz, const double* const* nrm_xyz,
+                                const double* const* tgt_xyz, void* stream);
+se_status se_batch_execute(se_batch* batch, const double* const* strengths, double* const* u_out, void* stream);
+/* Autotuner: for every member plan, times the candidate launch shapes of the
+ * real-space blocking (target bins per block) and the FFT column bundles on
+ * the bound geometry with the given strengths (synchronous, HIP events) and
+ * keeps the fastest.  The results are the same for every candidate up to
+ * rounding. */
+se_status se_batch_tune(se_batch* batch, const double* const* strengths, double* const* u_out, void* stream);
+
+/* Launch-shape knobs of one plan (0 = automatic): real-space target bins per
+ * block axis (1..4) and the cap on FFT column bundles (1..16, power of 2). */
+se_status se_plan_set_shape(se_plan* plan, int32_t real_tb, int32_t fft_cols);
+se_status se_plan_get_shape(const se_plan* plan, int32_t* real_tb, int32_t* fft_cols);
+
 #ifdef __cplusplus
 }
 #endif

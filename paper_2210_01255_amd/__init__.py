@@ -52,7 +52,8 @@ class se_params(ctypes.Structure):
 EXPORTS = ["se_version", "se_status_string", "se_params_select", "se_plan_create", "se_plan_destroy",
            "se_plan_get_params", "se_plan_workspace_bytes", "se_plan_last_message", "se_set_geometry",
            "se_execute", "se_execute_split", "se_sync_status", "se_plan_set_timing", "se_plan_phase_times",
-           "se_debug_cell_list"]
+           "se_debug_cell_list", "se_plan_set_shape", "se_plan_get_shape", "se_batch_create", "se_batch_destroy",
+           "se_batch_plan", "se_batch_set_geometry", "se_batch_execute", "se_batch_tune"]
 
 PHASES = ["geometry", "strengths", "spread", "fft_fwd_xy", "fft_z_scale", "fft_inv_yx", "gather", "real_space",
           "epilogue"]
@@ -101,6 +102,22 @@ def _load():
     L.se_plan_phase_times.argtypes = [vp, P(ctypes.c_double), P(i32), i32]
     L.se_debug_cell_list.restype = i32
     L.se_debug_cell_list.argtypes = [vp, i32, P(vp), P(vp), P(i32 * 3), P(i32 * 3)]
+    L.se_plan_set_shape.restype = i32
+    L.se_plan_set_shape.argtypes = [vp, i32, i32]
+    L.se_plan_get_shape.restype = i32
+    L.se_plan_get_shape.argtypes = [vp, P(i32), P(i32)]
+    L.se_batch_create.restype = i32
+    L.se_batch_create.argtypes = [P(se_problem), i32, P(vp)]
+    L.se_batch_destroy.restype = i32
+    L.se_batch_destroy.argtypes = [vp]
+    L.se_batch_plan.restype = i32
+    L.se_batch_plan.argtypes = [vp, i32, P(vp)]
+    L.se_batch_set_geometry.restype = i32
+    L.se_batch_set_geometry.argtypes = [vp, P(vp), P(vp), P(vp), vp]
+    L.se_batch_execute.restype = i32
+    L.se_batch_execute.argtypes = [vp, P(vp), P(vp), vp]
+    L.se_batch_tune.restype = i32
+    L.se_batch_tune.argtypes = [vp, P(vp), P(vp), vp]
     return L
 
 
@@ -122,6 +139,14 @@ se_sync_status = lib.se_sync_status
 se_plan_set_timing = lib.se_plan_set_timing
 se_plan_phase_times = lib.se_plan_phase_times
 se_debug_cell_list = lib.se_debug_cell_list
+se_plan_set_shape = lib.se_plan_set_shape
+se_plan_get_shape = lib.se_plan_get_shape
+se_batch_create = lib.se_batch_create
+se_batch_destroy = lib.se_batch_destroy
+se_batch_plan = lib.se_batch_plan
+se_batch_set_geometry = lib.se_batch_set_geometry
+se_batch_execute = lib.se_batch_execute
+se_batch_tune = lib.se_batch_tune
 
 
 def make_problem(kernel="stokeslet", periodicity=3, box=(1.0, 1.0, 1.0), tol=1e-8, tol_kind=TOL_REL,
@@ -192,6 +217,10 @@ class Plan:
                                 ctypes.byref(manual) if manual is not None else None, ctypes.byref(h))
         if st != SE_OK:
             raise SEError(st, "se_plan_create")
+        self._owned = True
+        self._attach(h)
+
+    def _attach(self, h):
         self.handle = h
         par = se_params()
         lib.se_plan_get_params(self.handle, ctypes.byref(par))
@@ -201,10 +230,32 @@ class Plan:
         self.n_tgt = self.problem.n_src if self.problem.targets_are_sources else self.problem.n_tgt
         self.n_rhs = self.problem.n_rhs
 
+    @classmethod
+    def _member(cls, handle, problem):
+        """View of a plan owned by a Batch (not destroyed by close())."""
+        self = cls.__new__(cls)
+        self.problem = problem
+        self._owned = False
+        self._attach(handle)
+        return self
+
     def close(self):
         if getattr(self, "handle", None):
-            lib.se_plan_destroy(self.handle)
+            if getattr(self, "_owned", True):
+                lib.se_plan_destroy(self.handle)
             self.handle = None
+
+    def set_shape(self, real_tb=0, fft_cols=0):
+        st = lib.se_plan_set_shape(self.handle, int(real_tb), int(fft_cols))
+        if st != SE_OK:
+            raise SEError(st, "se_plan_set_shape")
+
+    def get_shape(self):
+        tb, fc = ctypes.c_int32(), ctypes.c_int32()
+        st = lib.se_plan_get_shape(self.handle, ctypes.byref(tb), ctypes.byref(fc))
+        if st != SE_OK:
+            raise SEError(st, "se_plan_get_shape")
+        return tb.value, fc.value
 
     def __del__(self):
         try:
@@ -296,3 +347,94 @@ class Plan:
         hip.hipMemcpy(perm.ctypes.data, pp, perm.nbytes, 2)
         hip.hipMemcpy(start.ctypes.data, cs, start.nbytes, 2)
         return perm, start, list(nb), list(cw)
+
+
+def _ptrs(ts):
+    return (ctypes.c_void_p * len(ts))(*[t.data_ptr() if t is not None else 0 for t in ts])
+
+
+class Batch:
+    """Independent systems (uneven sizes, any periodicity) evaluated together.
+
+    ``problems`` is a list of keyword dicts for make_problem.  On a non-default
+    stream, the first execute with a given set of tensors runs eagerly and
+    records a HIP graph that later calls with the same tensors replay.
+    """
+
+    def __init__(self, problems):
+        n = len(problems)
+        if n == 0:
+            raise ValueError("empty batch")
+        arr = (se_problem * n)(*[make_problem(**kw) for kw in problems])
+        h = ctypes.c_void_p()
+        st = lib.se_batch_create(arr, n, ctypes.byref(h))
+        if st != SE_OK:
+            raise SEError(st, "se_batch_create")
+        self.handle = h
+        self.plans = []
+        for i in range(n):
+            ph = ctypes.c_void_p()
+            st = lib.se_batch_plan(self.handle, i, ctypes.byref(ph))
+            if st != SE_OK:
+                raise SEError(st, "se_batch_plan")
+            self.plans.append(Plan._member(ph, arr[i]))
+
+    def __len__(self):
+        return len(self.plans)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            for p in self.plans:
+                p.handle = None
+            lib.se_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_geometry(self, srcs, normals=None, targets=None, stream=None):
+        n = len(self.plans)
+        normals = normals if normals is not None else [None] * n
+        targets = targets if targets is not None else [None] * n
+        for p, a, b, c in zip(self.plans, srcs, normals, targets):
+            Plan._check(a, (p.n_src, 3), "src")
+            Plan._check(b, (p.n_src, 3), "normals")
+            if not p.problem.targets_are_sources:
+                Plan._check(c, (p.n_tgt, 3), "targets")
+        self._keep_geom = (list(srcs), list(normals), list(targets))
+        st = lib.se_batch_set_geometry(self.handle, _ptrs(srcs), _ptrs(normals), _ptrs(targets), _stream(stream))
+        if st != SE_OK:
+            raise SEError(st, "se_batch_set_geometry")
+
+    def _outs(self, strengths, outs):
+        import torch
+        if outs is None:
+            outs = []
+            for p, f in zip(self.plans, strengths):
+                shp = (p.n_rhs, p.n_tgt, 3) if p.n_rhs > 1 else (p.n_tgt, 3)
+                outs.append(torch.empty(shp, dtype=torch.float64, device=f.device))
+        for p, f, o in zip(self.plans, strengths, outs):
+            shp = (p.n_rhs, p.n_src, 3) if p.n_rhs > 1 else (p.n_src, 3)
+            Plan._check(f, shp, "strengths")
+            Plan._check(o, (p.n_rhs, p.n_tgt, 3) if p.n_rhs > 1 else (p.n_tgt, 3), "out")
+        return outs
+
+    def execute(self, strengths, outs=None, stream=None):
+        if len(strengths) != len(self.plans):
+            raise ValueError("one strengths tensor per system")
+        outs = self._outs(strengths, outs)
+        st = lib.se_batch_execute(self.handle, _ptrs(strengths), _ptrs(outs), _stream(stream))
+        if st != SE_OK:
+            raise SEError(st, "se_batch_execute")
+        return outs
+
+    def tune(self, strengths, outs=None, stream=None):
+        """Autotune every member's launch shapes; returns [(real_tb, fft_cols)]."""
+        outs = self._outs(strengths, outs)
+        st = lib.se_batch_tune(self.handle, _ptrs(strengths), _ptrs(outs), _stream(stream))
+        if st != SE_OK:
+            raise SEError(st, "se_batch_tune")
+        return [p.get_shape() for p in self.plans]

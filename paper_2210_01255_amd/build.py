@@ -34,9 +34,9 @@ def _sources():
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + COMMON
+    cmd = [HIPCC] + COMMON + DEVICE
     if src.endswith(".hip"):
-        cmd += DEVICE + ["-x", "hip"]
+        cmd += ["-x", "hip"]
     cmd += ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

@@ -551,6 +551,7 @@ se_status se_set_geometry(se_plan* plan, const double* src_xyz, const double* nr
     hipStream_t s = (hipStream_t)stream;
     if (hipSetDevice(plan->device) != hipSuccess) return SE_ERR_HIP;
     plan->have_geometry = false;
+    plan->geom_gen++;
     se_status st;
     {
         PhaseScope ps(plan, 0, s);
@@ -573,7 +574,7 @@ se_status se_set_geometry(se_plan* plan, const double* src_xyz, const double* nr
     return st;
 }
 
-static se_status run(se_plan* p, const double* strengths, double* u, double* ur, double* uf, hipStream_t s)
+se_status se_run_plan(se_plan* p, const double* strengths, double* u, double* ur, double* uf, hipStream_t s)
 {
     if (!p || !strengths) return SE_ERR_ARG;
     if (!p->have_geometry) return SE_ERR_STATE;
@@ -629,13 +630,30 @@ static se_status run(se_plan* p, const double* strengths, double* u, double* ur,
 se_status se_execute(se_plan* plan, const double* strengths, double* u_out, void* stream)
 {
     if (!u_out) return SE_ERR_ARG;
-    return run(plan, strengths, u_out, nullptr, nullptr, (hipStream_t)stream);
+    return se_run_plan(plan, strengths, u_out, nullptr, nullptr, (hipStream_t)stream);
 }
 
 se_status se_execute_split(se_plan* plan, const double* strengths, double* u_real, double* u_fourier, void* stream)
 {
     if (!u_real || !u_fourier) return SE_ERR_ARG;
-    return run(plan, strengths, nullptr, u_real, u_fourier, (hipStream_t)stream);
+    return se_run_plan(plan, strengths, nullptr, u_real, u_fourier, (hipStream_t)stream);
+}
+
+se_status se_plan_set_shape(se_plan* plan, int32_t real_tb, int32_t fft_cols)
+{
+    if (!plan || real_tb < 0 || real_tb > 4 || fft_cols < 0 || fft_cols > 16) return SE_ERR_ARG;
+    if (fft_cols & (fft_cols - 1)) return SE_ERR_ARG;
+    plan->shape_real_tb = real_tb;
+    plan->shape_fft_cols = fft_cols;
+    return SE_OK;
+}
+
+se_status se_plan_get_shape(const se_plan* plan, int32_t* real_tb, int32_t* fft_cols)
+{
+    if (!plan || !real_tb || !fft_cols) return SE_ERR_ARG;
+    *real_tb = plan->shape_real_tb;
+    *fft_cols = plan->shape_fft_cols;
+    return SE_OK;
 }
 
 se_status se_sync_status(se_plan* plan)

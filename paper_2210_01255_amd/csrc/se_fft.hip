@@ -34,6 +34,7 @@ struct se_fft_args {
     int nrad_xh, nrad_y, nrad_z;
     int lines;  // rows per workgroup (x passes)
     int cols;   // kx columns per workgroup (y, z passes)
+    int cols_cap;  // upper bound on cols (0: automatic)
     // scaling
     int kernel;
     int D;
@@ -632,6 +633,7 @@ se_fft_args make_fft_args(const se_plan* p, int ncomp, int slot)
     se_fft_args a = make_fft_args_geom(p->g.Mg, p->Nfft, p->g.h, se_slot_grid(p, slot), se_slot_spec(p, slot), p->d_tw,
                                        p->tw_off, ncomp);
     a.Hp = p->Hp;
+    a.cols_cap = p->shape_fft_cols;
     a.kernel = p->kernel;
     a.D = p->D;
     a.xi = p->par.xi;
@@ -661,10 +663,10 @@ int x_lines(int Nh)
 // columns per bundle for a pass holding `sets` column sets of length N plus
 // the twiddles within the LDS budget
 template <typename R>
-int bundle_cols(int N, int sets)
+int bundle_cols(int N, int sets, int cap = 16)
 {
     const int budget = (int)(kFftLds / sizeof(C<R>)) - N;
-    int c = std::max(1, std::min(16, budget / (sets * N)));
+    int c = std::max(1, std::min(cap > 0 ? cap : 16, budget / (sets * N)));
     while (c & (c - 1)) c &= c - 1;  // power of two (line index by shift)
     return c;
 }
@@ -704,7 +706,7 @@ void run_x_c2r(se_fft_args a, int ncomp, hipStream_t s)
 template <typename R>
 void run_y(se_fft_args a, int ncomp, int dir, hipStream_t s)
 {
-    a.cols = bundle_cols<R>(a.N[1], 2);
+    a.cols = bundle_cols<R>(a.N[1], 2, a.cols_cap);
     int nbx = (a.Hx + a.cols - 1) / a.cols;
     size_t lds = (size_t)(a.N[1] + 2 * a.cols * a.N[1]) * sizeof(C<R>);
     allow_lds(k_fft_y<R>, lds);
@@ -714,7 +716,7 @@ void run_y(se_fft_args a, int ncomp, int dir, hipStream_t s)
 template <typename R>
 void run_z_plain(se_fft_args a, int ncomp, int dir, hipStream_t s)
 {
-    a.cols = bundle_cols<R>(a.N[2], 2);
+    a.cols = bundle_cols<R>(a.N[2], 2, a.cols_cap);
     int nbx = (a.Hx + a.cols - 1) / a.cols;
     size_t lds = (size_t)(a.N[2] + 2 * a.cols * a.N[2]) * sizeof(C<R>);
     allow_lds(k_fft_z<R>, lds);
@@ -740,7 +742,7 @@ template <typename R, int KER, int NC>
 void launch_z(const se_plan* p, int slot, hipStream_t s)
 {
     se_fft_args a = make_fft_args(p, NC, slot);
-    a.cols = bundle_cols<R>(p->Nfft[2], NC + 1);
+    a.cols = bundle_cols<R>(p->Nfft[2], NC + 1, p->shape_fft_cols);
     int nbx = (p->Hx + a.cols - 1) / a.cols;
     size_t lds = (size_t)(p->Nfft[2] + (NC + 1) * a.cols * p->Nfft[2]) * sizeof(C<R>);
     auto kern = k_fft_z_scale<R, KER, NC>;
@@ -953,6 +955,7 @@ se_fft_args cls_fft_args(const se_plan* p, const se_aft_class& c, int slot)
     se_fft_args a = make_fft_args_geom(Mg, N, p->g.h, nullptr, cls_slot_buf(p, c, slot), c.tw, c.tw_off, p->ncomp);
     a.Hx = c.nkx;
     a.Hp = c.nkx;
+    a.cols_cap = p->shape_fft_cols;
     return a;
 }
 

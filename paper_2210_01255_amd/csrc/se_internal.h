@@ -83,6 +83,9 @@ struct se_plan {
     int ncomp = 3;   // gridded components (3, or 6 for the symmetrised stresslet source)
     int nrhs = 1;
     int rb = 1;      // right-hand sides per chunk (buffers hold rb slots)
+    uint64_t geom_gen = 0;   // counts geometry bindings (recorded graphs depend on them)
+    int shape_real_tb = 0;   // launch-shape knobs (0: automatic), see se_plan_set_shape
+    int shape_fft_cols = 0;
     bool fp32 = false;
     int device = 0;
     int64_t ns = 0, nt = 0;
@@ -193,3 +196,8 @@ void se_fft_twiddles(const int* N, std::vector<double>* tw, int* off);
 se_status se_d0_precompute(se_plan* p);
 bool se_fft_fits(const int* N, int ncomp, bool fp32);
 void se_launch_finalize(const se_plan* p, int slot, double* u, double* u_real, double* u_fourier, hipStream_t s);
+
+// One evaluation of all right-hand sides of a plan on stream s (kernel
+// launches only, so it can be recorded into a graph when timing is off).
+extern "C" __attribute__((visibility("hidden"))) se_status se_run_plan(se_plan* p, const double* strengths, double* u,
+                                                                        double* ur, double* uf, hipStream_t s);

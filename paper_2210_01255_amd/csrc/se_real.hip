@@ -799,6 +799,7 @@ void se_launch_real_space(const se_plan* p, int slot0, int nslot, hipStream_t s)
     const int64_t nbins = (int64_t)g.nb[0] * g.nb[1] * g.nb[2];
     const double per_bin = (double)p->nt / (double)nbins;
     int TB = (int)std::lround(std::cbrt(48.0 / std::max(per_bin, 1e-9)));
+    if (p->shape_real_tb > 0) TB = p->shape_real_tb;
     TB = std::max(1, std::min(TB, 4));
     se_real2_geom bg;
     bg.TB = TB;

@@ -1,0 +1,182 @@
+"""Batches of independent systems (uneven N, periodicity 3/2/1/0, elongated
+boxes) through se_batch_*: the eager pass, every HIP-graph replay and the
+autotuned launch shapes against single-plan runs and the FP64 oracle.
+
+Floating-point bar: the requested rms-relative tolerance against the oracle
+(safety factor 10 as in the single-system parity tests); replays against the
+eager pass within 1e-12 relative (only the order of the atomic additions in
+spreading and gathering may differ between launches).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+SAFETY = 10.0
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    import oracle
+    import paper_2210_01255_amd as se
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    oracle.build(force=False)
+    return se, oracle, torch
+
+
+def _systems(seed, count, lo, hi, kernel="stokeslet"):
+    """Uneven systems: N log-uniform in [lo, hi], D uniform in {3,2,1,0},
+    one box axis stretched by a ~ U[1, 4]."""
+    g = W.rng(seed)
+    sizes = W.loguniform_sizes(g, count, lo, hi)
+    out = []
+    for i, n in enumerate(sizes):
+        D = int(g.integers(0, 4))
+        box = W.aspect_box(g)
+        s = W.system(seed * 1000 + i, int(n), box=tuple(box), kernel=kernel, zero_mean=(D == 3),
+                     layout="uniform")
+        s["D"] = D
+        out.append(s)
+    return out
+
+
+def _problem(s, kernel, tol):
+    q = float(np.sum(s["f"] ** 2)) if kernel != "stresslet" else float(
+        np.sum((s["q"][:, :, None] * s["nu"][:, None, :]) ** 2))
+    return dict(kernel=kernel, periodicity=s["D"], box=tuple(s["box"]), tol=tol, n_src=len(s["x"]),
+                source_q=q, safety=SAFETY)
+
+
+def _dev(env, systems, key):
+    _, _, torch = env
+    return [torch.tensor(s[key], device="cuda:0") if key in s else None for s in systems]
+
+
+def _oracle_ref(env, s, kernel, idx=None):
+    _, oracle, _ = env
+    D = s["D"]
+    xi = 6.0 / float(np.max(s["box"][:D])) if D in (1, 2) else None
+    tg = None if idx is None else s["x"][idx]
+    r = oracle.ewald(D, kernel, s["box"], s["x"], f=s.get("f"), q=s.get("q"), nu=s.get("nu"),
+                     targets=tg, self_src=idx, xi=xi)
+    return r.total if D else r["direct"]
+
+
+def test_batch_graph_replays_match_eager_and_oracle(env):
+    se, oracle, torch = env
+    tol = 1e-6
+    systems = _systems(41, 8, 200, 1500)
+    print("batch Ns", [len(s["x"]) for s in systems], "Ds", [s["D"] for s in systems], flush=True)
+    b = se.Batch([_problem(s, "stokeslet", tol) for s in systems])
+    x = _dev(env, systems, "x")
+    f = _dev(env, systems, "f")
+    outs = [torch.empty_like(t) for t in f]
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(st):
+        b.set_geometry(x, stream=st)
+        b.execute(f, outs, stream=st)  # eager pass (records the graph)
+    st.synchronize()
+    eager = [o.cpu().numpy() for o in outs]
+    for s, u in zip(systems, eager):
+        err = oracle.rms_rel_error(u, _oracle_ref(env, s, "stokeslet"))
+        print("D=%d N=%d err %.3g" % (s["D"], len(s["x"]), err), flush=True)
+        assert err <= tol
+
+    for rep in range(4):
+        # unrelated eager work and host synchronisation between the replays
+        junk = torch.randn(1 << 16, device="cuda:0", dtype=torch.float64)
+        (junk * 2.0).sum().item()
+        for o in outs:
+            o.fill_(float("nan"))
+        st.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(st):
+            b.execute(f, outs, stream=st)  # graph replay
+        st.synchronize()
+        for u0, o in zip(eager, outs):
+            u = o.cpu().numpy()
+            assert np.all(np.isfinite(u)), "replay %d left unwritten outputs" % rep
+            assert oracle.rms_rel_error(u, u0) <= 1e-12, rep
+
+    # new output tensors: a fresh eager pass and a new graph
+    outs2 = [torch.empty_like(t) for t in f]
+    st.wait_stream(torch.cuda.current_stream())
+    for _ in range(2):
+        with torch.cuda.stream(st):
+            b.execute(f, outs2, stream=st)
+        st.synchronize()
+        for u0, o in zip(eager, outs2):
+            assert oracle.rms_rel_error(o.cpu().numpy(), u0) <= 1e-12
+
+    # each member equals a single plan of the same problem
+    for s, u0, p in zip(systems, eager, b.plans):
+        single = se.Plan(**_problem(s, "stokeslet", tol))
+        assert single.params == p.params
+        xs = torch.tensor(s["x"], device="cuda:0")
+        single.set_geometry(xs)
+        u = single.execute(torch.tensor(s["f"], device="cuda:0"))
+        single.sync()
+        assert oracle.rms_rel_error(u.cpu().numpy(), u0) <= 1e-12
+    b.close()
+
+
+def test_batch_of_64_uneven_systems_with_tuning(env):
+    """64 systems, N log-uniform in [1e3, 5e4], D uniform in {3,2,1,0}, box
+    aspect in [1,4], tol 1e-6: autotuned shapes, graph replay; every member
+    against the replayed eager pass, and against the oracle on 24 sampled
+    targets (singly periodic members up to N = 1e4 only: the oracle's
+    trapezoidal k-sums over the virtual cell take seconds per 1e4 sources)."""
+    se, oracle, torch = env
+    tol = 1e-6
+    systems = _systems(64, 64, 1e3, 5e4)
+    print("64 systems, total N", sum(len(s["x"]) for s in systems), flush=True)
+    b = se.Batch([_problem(s, "stokeslet", tol) for s in systems])
+    x = _dev(env, systems, "x")
+    f = _dev(env, systems, "f")
+    outs = [torch.empty_like(t) for t in f]
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(st):
+        b.set_geometry(x, stream=st)
+        b.execute(f, outs, stream=st)
+    st.synchronize()
+    before = [o.cpu().numpy() for o in outs]
+    with torch.cuda.stream(st):
+        shapes = b.tune(f, outs, stream=st)
+    st.synchronize()
+    print("tuned shapes", shapes, flush=True)
+    assert all(0 <= tb <= 4 and fc in (0, 2, 4, 8, 16) for tb, fc in shapes)
+    for _ in range(3):
+        for o in outs:
+            o.fill_(float("nan"))
+        st.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(st):
+            b.execute(f, outs, stream=st)
+        st.synchronize()
+    g = W.rng(6400)
+    for i, (s, o, u0) in enumerate(zip(systems, outs, before)):
+        u = o.cpu().numpy()
+        assert oracle.rms_rel_error(u, u0) <= 1e-12, i
+        if s["D"] == 1 and len(s["x"]) > 10000:
+            continue
+        idx = np.sort(g.choice(len(s["x"]), size=24, replace=False)).astype(np.int64)
+        # sampled error: normalised by the rms of the full result (eq. rel-rms-error)
+        ref = _oracle_ref(env, s, "stokeslet", idx)
+        err = np.sqrt(np.mean(np.sum((u[idx] - ref) ** 2, axis=1))) / np.sqrt(np.mean(np.sum(u ** 2, axis=1)))
+        print("sys %d D=%d N=%d sampled err %.3g" % (i, s["D"], len(s["x"]), err), flush=True)
+        assert err <= 3 * tol
+    b.close()
+
+
+def test_batch_rejects_bad_arguments(env):
+    se, _, torch = env
+    with pytest.raises(se.SEError):
+        se.Batch([dict(kernel="stokeslet", periodicity=5, n_src=10)])
+    b = se.Batch([dict(kernel="stokeslet", periodicity=3, n_src=100, tol=1e-6, source_q=300.0)])
+    f = torch.zeros(100, 3, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(se.SEError):
+        b.execute([f])  # no geometry bound
+    b.close()
