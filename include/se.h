@@ -67,7 +67,7 @@ typedef int32_t se_status;
 #define SE_PREC_FP32 2
 
 #define SE_SELECT_ANALYTIC 0 /* the paper's estimate-based procedure, Sec. 4.6 */
-#define SE_SELECT_LEARNED 1  /* reserved: learned selector with analytic fallback */
+#define SE_SELECT_LEARNED 1  /* learned selector (se_selector_*) with analytic fallback */
 #define SE_SELECT_MANUAL 2   /* caller supplies se_params */
 
 /* Error-pollution adjustment of the estimated (h, P), eq. (error-pollution-fix)
@@ -241,6 +241,69 @@ se_status se_batch_tune(se_batch* batch, const double* const* strengths, double*
  * block axis (1..4) and the cap on FFT column bundles (1..16, power of 2). */
 se_status se_plan_set_shape(se_plan* plan, int32_t real_tb, int32_t fft_cols);
 se_status se_plan_get_shape(const se_plan* plan, int32_t* real_tb, int32_t* fft_cols);
+
+/* ---- Learned parameter selector.
+ *
+ * A fully connected FP32 network: SE_MLP_IN inputs, two tanh layers of
+ * SE_MLP_HID units, SE_MLP_OUT linear outputs.  Features of a problem (raw,
+ * before the normalisation stored with the weights): log10 N, ln(L_max/L_min),
+ * one-hot periodicity D = 0..3, one-hot kernel (stokeslet, rotlet, stresslet),
+ * log10 of the rms-relative tolerance.  Outputs: ln(xi Lc), ln(Lc/h), P and
+ * ln(xi rc), with Lc = (L1 L2 L3)^(1/3) and h the target grid spacing; the
+ * rest of the parameters follow by steps 5-7 of Sec. 4.6.  A proposal is
+ * rejected if a truncation estimate of Sec. 4 at the completed parameters
+ * exceeds ten times the tolerance (the estimates are within a factor 10 of
+ * the measured error); then, and when no weights are
+ * loaded, selection falls back to SE_SELECT_ANALYTIC (se_plan_last_message
+ * says which was used).  Weights are process-wide: the latest of
+ * se_selector_train / se_selector_load, else the file named by the environment
+ * variable SE_SELECTOR_WEIGHTS, else se_selector_weights.bin beside this
+ * library.  Parameter vector (SE_MLP_NPARAM floats, row-major, output index
+ * first): W1[64][10], b1[64], W2[64][64], b2[64], W3[4][64], b3[4]. */
+#define SE_MLP_IN 10
+#define SE_MLP_HID 64
+#define SE_MLP_OUT 4
+#define SE_MLP_NPARAM 5124
+#define SE_MLP_NORM (2 * SE_MLP_IN + 2 * SE_MLP_OUT) /* x mean, x std, y mean, y std */
+
+typedef struct se_train_cfg {
+    int32_t struct_size; /* sizeof(se_train_cfg) */
+    int32_t epochs;      /* passes over the records (>= 1) */
+    int32_t batch;       /* minibatch size (>= 1) */
+    int32_t device;      /* HIP device ordinal */
+    float lr, beta1, beta2, eps; /* Adam; lr > 0, 0 <= beta < 1, eps > 0 */
+    uint64_t seed;       /* initial weights (Glorot-uniform) and sample order */
+} se_train_cfg;
+
+/* Feature row of a problem (host; x has SE_MLP_IN entries). */
+se_status se_selector_features(const se_problem* prob, float* x);
+/* Trains the process-wide network on n host records X[n][SE_MLP_IN] (raw
+ * features) and Y[n][SE_MLP_OUT] (raw outputs): normalisation to zero mean and
+ * unit variance from the records, then epochs of shuffled minibatches through
+ * the device kernels.  loss_history (host, may be null) receives the mean
+ * normalised loss of each epoch.  Synchronous. */
+se_status se_selector_train(const se_train_cfg* cfg, const float* X, const float* Y, int64_t n, float* loss_history);
+/* Versioned binary file (magic, sizes, normalisation, weights, checksum);
+ * a corrupt or mismatched file is rejected with SE_ERR_ARG and changes nothing. */
+se_status se_selector_save(const char* path);
+se_status se_selector_load(const char* path);
+/* 1 when weights are present (loading the default file if needed), else 0. */
+int32_t se_selector_ready(void);
+/* Copies out the weights (SE_MLP_NPARAM floats) and normalisation (SE_MLP_NORM). */
+se_status se_selector_get(float* theta, float* norm);
+/* Raw outputs for n raw feature rows (device pointers, stream-ordered). */
+se_status se_selector_predict(const float* X, float* Y, int64_t n, void* stream);
+
+/* Training building blocks on device buffers of normalised data, for checks:
+ * loss = sum_i |mlp(theta, x_i) - y_i|^2 / (n SE_MLP_OUT) and grad = d loss / d
+ * theta (n >= 1; grad SE_MLP_NPARAM floats, loss one float); forward gives
+ * mlp(theta, x_i); adam applies one Adam step with bias corrections at step
+ * t >= 1 to n parameters. */
+se_status se_mlp_loss_grad(const float* theta, const float* X, const float* Y, int64_t n, float* grad, float* loss,
+                           void* stream);
+se_status se_mlp_forward(const float* theta, const float* X, int64_t n, float* Y, void* stream);
+se_status se_mlp_adam(float* theta, float* m, float* v, const float* grad, int64_t n, int32_t t, float lr, float beta1,
+                      float beta2, float eps, void* stream);
 
 #ifdef __cplusplus
 }

@@ -21,6 +21,8 @@ SELECT_ANALYTIC, SELECT_LEARNED, SELECT_MANUAL = 0, 1, 2
 POLLUTION_PAPER, POLLUTION_FINE = 0, 1
 
 SE_OK = 0
+SE_ERR_ARG, SE_ERR_UNSUPPORTED, SE_ERR_OUT_OF_BOX, SE_ERR_NONFINITE = -1, -2, -3, -4
+SE_ERR_COINCIDENT, SE_ERR_TOL_UNREACHABLE, SE_ERR_NOMEM, SE_ERR_HIP, SE_ERR_STATE = -5, -6, -7, -8, -9
 STATUS = {0: "SE_OK", -1: "SE_ERR_ARG", -2: "SE_ERR_UNSUPPORTED", -3: "SE_ERR_OUT_OF_BOX",
           -4: "SE_ERR_NONFINITE", -5: "SE_ERR_COINCIDENT", -6: "SE_ERR_TOL_UNREACHABLE",
           -7: "SE_ERR_NOMEM", -8: "SE_ERR_HIP", -9: "SE_ERR_STATE"}
@@ -53,10 +55,22 @@ EXPORTS = ["se_version", "se_status_string", "se_params_select", "se_plan_create
            "se_plan_get_params", "se_plan_workspace_bytes", "se_plan_last_message", "se_set_geometry",
            "se_execute", "se_execute_split", "se_sync_status", "se_plan_set_timing", "se_plan_phase_times",
            "se_debug_cell_list", "se_plan_set_shape", "se_plan_get_shape", "se_batch_create", "se_batch_destroy",
-           "se_batch_plan", "se_batch_set_geometry", "se_batch_execute", "se_batch_tune"]
+           "se_batch_plan", "se_batch_set_geometry", "se_batch_execute", "se_batch_tune", "se_selector_features",
+           "se_selector_train", "se_selector_save", "se_selector_load", "se_selector_ready", "se_selector_get",
+           "se_selector_predict", "se_mlp_loss_grad", "se_mlp_forward", "se_mlp_adam"]
 
 PHASES = ["geometry", "strengths", "spread", "fft_fwd_xy", "fft_z_scale", "fft_inv_yx", "gather", "real_space",
           "epilogue"]
+
+
+class se_train_cfg(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_int32), ("epochs", ctypes.c_int32), ("batch", ctypes.c_int32),
+                ("device", ctypes.c_int32), ("lr", ctypes.c_float), ("beta1", ctypes.c_float),
+                ("beta2", ctypes.c_float), ("eps", ctypes.c_float), ("seed", ctypes.c_uint64)]
+
+
+MLP_IN, MLP_HID, MLP_OUT, MLP_NPARAM = 10, 64, 4, 5124
+MLP_NORM = 2 * 10 + 2 * 4
 
 
 class SEError(RuntimeError):
@@ -69,6 +83,16 @@ def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libse_mi355x.so is not built (run __graft_entry__.build() or "
                           "python -m paper_2210_01255_amd.build)")
+    # One HIP runtime per process: torch's extension libraries ask for
+    # libamdhip64.so and load the copy torch ships, whose soname is the
+    # libamdhip64.so.7 this library links against.  Loading torch first makes
+    # the library bind to that same copy, so that device pointers and streams
+    # from torch are valid here; loaded the other way round the process would
+    # hold two runtimes.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     vp, i32 = ctypes.c_void_p, ctypes.c_int32
     P = ctypes.POINTER
@@ -118,6 +142,28 @@ def _load():
     L.se_batch_execute.argtypes = [vp, P(vp), P(vp), vp]
     L.se_batch_tune.restype = i32
     L.se_batch_tune.argtypes = [vp, P(vp), P(vp), vp]
+    f32p = P(ctypes.c_float)
+    L.se_selector_features.restype = i32
+    L.se_selector_features.argtypes = [P(se_problem), f32p]
+    L.se_selector_train.restype = i32
+    L.se_selector_train.argtypes = [P(se_train_cfg), f32p, f32p, ctypes.c_int64, f32p]
+    L.se_selector_save.restype = i32
+    L.se_selector_save.argtypes = [ctypes.c_char_p]
+    L.se_selector_load.restype = i32
+    L.se_selector_load.argtypes = [ctypes.c_char_p]
+    L.se_selector_ready.restype = i32
+    L.se_selector_ready.argtypes = []
+    L.se_selector_get.restype = i32
+    L.se_selector_get.argtypes = [f32p, f32p]
+    L.se_selector_predict.restype = i32
+    L.se_selector_predict.argtypes = [vp, vp, ctypes.c_int64, vp]
+    L.se_mlp_loss_grad.restype = i32
+    L.se_mlp_loss_grad.argtypes = [vp, vp, vp, ctypes.c_int64, vp, vp, vp]
+    L.se_mlp_forward.restype = i32
+    L.se_mlp_forward.argtypes = [vp, vp, ctypes.c_int64, vp, vp]
+    L.se_mlp_adam.restype = i32
+    L.se_mlp_adam.argtypes = [vp, vp, vp, vp, ctypes.c_int64, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                              ctypes.c_float, vp]
     return L
 
 
@@ -147,6 +193,16 @@ se_batch_plan = lib.se_batch_plan
 se_batch_set_geometry = lib.se_batch_set_geometry
 se_batch_execute = lib.se_batch_execute
 se_batch_tune = lib.se_batch_tune
+se_selector_features = lib.se_selector_features
+se_selector_train = lib.se_selector_train
+se_selector_save = lib.se_selector_save
+se_selector_load = lib.se_selector_load
+se_selector_ready = lib.se_selector_ready
+se_selector_get = lib.se_selector_get
+se_selector_predict = lib.se_selector_predict
+se_mlp_loss_grad = lib.se_mlp_loss_grad
+se_mlp_forward = lib.se_mlp_forward
+se_mlp_adam = lib.se_mlp_adam
 
 
 def make_problem(kernel="stokeslet", periodicity=3, box=(1.0, 1.0, 1.0), tol=1e-8, tol_kind=TOL_REL,
@@ -225,6 +281,7 @@ class Plan:
         par = se_params()
         lib.se_plan_get_params(self.handle, ctypes.byref(par))
         self.params = params_to_dict(par)
+        self.message = (lib.se_plan_last_message(self.handle) or b"").decode()
         self.kernel = self.problem.kernel
         self.n_src = self.problem.n_src
         self.n_tgt = self.problem.n_src if self.problem.targets_are_sources else self.problem.n_tgt

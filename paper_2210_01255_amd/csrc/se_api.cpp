@@ -228,6 +228,16 @@ const char* se_status_string(se_status s)
     }
 }
 
+// Transform-size limits of the LDS-resident line FFTs.
+static bool fft_sizes_ok(const int32_t* N, int ncomp, bool fp32)
+{
+    std::vector<int> rr;
+    const int n[3] = {N[0], N[1], N[2]};
+    return (n[0] % 2 == 0) && se_smooth_factors(n[0] / 2, &rr) && n[0] / 2 <= SE_FFT_LDS_ELEMS &&
+           se_smooth_factors(n[1], &rr) && n[1] <= SE_FFT_LDS_ELEMS && se_smooth_factors(n[2], &rr) &&
+           n[2] <= SE_FFT_LDS_ELEMS && se_fft_fits(n, ncomp, fp32);
+}
+
 static se_status validate_problem(const se_problem* prob)
 {
     if (prob->struct_size != (int32_t)sizeof(se_problem)) return SE_ERR_ARG;
@@ -253,6 +263,7 @@ se_status se_params_select(const se_problem* prob, se_params* out)
     if (st != SE_OK) return st;
     if (prob->selector == SE_SELECT_MANUAL) return SE_ERR_ARG;
     std::string msg;
+    if (prob->selector == SE_SELECT_LEARNED) return se_select_learned(prob, out, &msg);
     return se_select_params(prob, nullptr, out, &msg);
 }
 
@@ -292,11 +303,17 @@ se_status se_plan_create(const se_problem* prob, const se_params* manual, se_pla
         p->fp32 = (prob->tol_kind == SE_TOL_REL && prob->tol >= 1e-6);
     }
     std::string msg;
-    se_status st = se_select_params(prob, manual, &p->par, &msg);
+    se_status st = prob->selector == SE_SELECT_LEARNED ? se_select_learned(prob, &p->par, &msg)
+                                                       : se_select_params(prob, manual, &p->par, &msg);
+    if (st == SE_OK && prob->selector == SE_SELECT_LEARNED && !fft_sizes_ok(p->par.n_fft, p->ncomp, p->fp32)) {
+        st = se_select_params(prob, nullptr, &p->par, &msg);
+        msg = "learned selector: grid beyond the FFT limits; analytic parameters";
+    }
     if (st != SE_OK) {
         delete p;
         return st;
     }
+    p->msg = msg;
     const se_params& par = p->par;
 
     // grid geometry
@@ -322,10 +339,7 @@ se_status se_plan_create(const se_problem* prob, const se_params* manual, se_pla
 
     // transform-size limits of the LDS-resident line FFTs
     std::vector<int> rr;
-    bool ok = (p->Nfft[0] % 2 == 0) && se_smooth_factors(p->Nfft[0] / 2, &rr) && p->Nfft[0] / 2 <= SE_FFT_LDS_ELEMS &&
-              se_smooth_factors(p->Nfft[1], &rr) && p->Nfft[1] <= SE_FFT_LDS_ELEMS &&
-              se_smooth_factors(p->Nfft[2], &rr) && p->Nfft[2] <= SE_FFT_LDS_ELEMS &&
-              se_fft_fits(p->Nfft, p->ncomp, p->fp32);
+    bool ok = fft_sizes_ok(p->Nfft, p->ncomp, p->fp32);
     if (ok && (p->D == 1 || p->D == 2)) {
         aft_shapes(p);
         for (const se_aft_class& c : p->cls) {

@@ -164,6 +164,11 @@ inline double* se_slot_uR(const se_plan* p, int slot) { return p->d_uR + (size_t
 // ---- planner (se_params.cpp)
 se_status se_select_params(const se_problem* p, const se_params* manual, se_params* out,
                            std::string* msg);
+se_status se_complete_params(const se_problem* p, double xi, double rc, double h_t, int P, se_params* out,
+                             std::string* msg);
+// Learned selection (MLP proposal, then completion and the estimate check);
+// falls back to se_select_params and says so in msg.
+se_status se_select_learned(const se_problem* p, se_params* out, std::string* msg);
 bool se_smooth_factors(int n, std::vector<int>* radices);
 void se_pkb_coefficients(int P, int nu, double beta, std::vector<double>* coef);
 void se_radial_table(double xmax, std::vector<double>* tab);
@@ -201,3 +206,12 @@ void se_launch_finalize(const se_plan* p, int slot, double* u, double* u_real, d
 // launches only, so it can be recorded into a graph when timing is off).
 extern "C" __attribute__((visibility("hidden"))) se_status se_run_plan(se_plan* p, const double* strengths, double* u,
                                                                         double* ur, double* uf, hipStream_t s);
+
+// Learned-selector kernels (se_mlp.hip).
+size_t se_mlp_part_floats(int cnt);
+void se_mlp_launch_grad(const float* th, const float* X, const float* Y, int64_t n, uint64_t a, uint64_t c,
+                        int64_t start, int cnt, float* part, float* grad, float* loss, hipStream_t s);
+void se_mlp_launch_adam(float* th, float* m, float* v, const float* g, int64_t n, int t, float lr, float b1,
+                        float b2, float eps, hipStream_t s);
+void se_mlp_launch_forward(const float* th, const float* X, int64_t n, float* Y, const float* norm, hipStream_t s);
+void se_mlp_launch_fill(float* p, int64_t n, float v, hipStream_t s);

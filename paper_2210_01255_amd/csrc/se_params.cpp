@@ -349,30 +349,60 @@ se_status se_select_params(const se_problem* p, const se_params* manual, se_para
         }
     }
     const double tau = tau_of(xi);
-    const double U = pot_rms(kernel, b, Q, xi);
-    par.xi = xi;
-    par.tau_abs = tau;
-    par.U = U;
 
     // step 1: real-space cut-off
-    par.rc = solve_rc(kernel, b, Q, xi, tau);
+    const double rc = solve_rc(kernel, b, Q, xi, tau);
     // step 2: grid spacing from the Fourier truncation estimate
     double kinf = solve_kinf(kernel, b, Q, xi, tau);
     double h_est = kPi / kinf;
     // step 3: window support from 10 U exp(-2.5 P) = tau
-    double P_est = std::log(10.0 * U / tau) / 2.5;
+    double P_est = std::log(10.0 * pot_rms(kernel, b, Q, xi) / tau) / 2.5;
     if (P_est < 0) P_est = 0;
-    // step 4: pollution rule and grid rounding
+    // step 4: pollution rule
     const bool fine = D == 0 || p->pollution == SE_POLLUTION_FINE;
     double h_t = fine ? h_est / 1.1 : h_est / 1.05;
     double P_t = fine ? P_est + 2.0 : P_est + 4.0;
-    // step 5: even window support, KB shape and PKB degree
+    // step 5: even window support
     int P = 2 * (int)std::ceil(P_t / 2.0 - 1e-12);
     if (P < 4) P = 4;
+    return se_complete_params(p, xi, rc, h_t, P, out, msg);
+}
+
+// Steps 5-7 of Sec. 4.6 from (xi, rc, target spacing h_t, window support P):
+// KB shape and PKB degree, grid rounding eq. (grid-adjustment), the extended
+// grid of the free directions eq. (extended-grid-size), the truncation radius
+// eq. (truncation-radius), the upsampling factors eqs. (upsampling-factor-s0),
+// (upsampling-factor-sstar), (estimate-kbarstar), and the three truncation
+// estimates at the final parameters.
+se_status se_complete_params(const se_problem* p, double xi, double rc, double h_t, int P, se_params* out,
+                             std::string* msg)
+{
+    const int D = p->periodicity, kernel = p->kernel;
+    Box b;
+    b.V = p->box[0] * p->box[1] * p->box[2];
+    b.Lc = std::cbrt(b.V);
+    const double N = (double)p->n_src;
+    const double Q = p->source_q > 0 ? p->source_q : 3.0 * N;
+    const double safety = p->safety > 0 ? p->safety : 1.0;
+    const int fM = 4;
+    if (!(xi > 0) || !(rc > 0) || !(h_t > 0) || !std::isfinite(xi) || !std::isfinite(rc) || !std::isfinite(h_t)) {
+        *msg = "parameters: need finite xi, rc, h > 0";
+        return SE_ERR_ARG;
+    }
     if (P > SE_MAX_P) {
         *msg = "tolerance needs a window support above 32 grid points";
         return SE_ERR_TOL_UNREACHABLE;
     }
+    se_params par;
+    std::memset(&par, 0, sizeof(par));
+    par.struct_size = sizeof(se_params);
+    par.f_M = fM;
+    const double U = pot_rms(kernel, b, Q, xi);
+    const double tau = p->tol_kind == SE_TOL_ABS ? p->tol / safety : p->tol * U / safety;
+    par.xi = xi;
+    par.tau_abs = tau;
+    par.U = U;
+    par.rc = rc;
     par.P = P;
     par.beta = 2.5 * P;
     par.nu_deg = std::min(P / 2 + 2, 10);

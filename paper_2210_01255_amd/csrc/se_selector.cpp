@@ -1,0 +1,455 @@
+// se_selector.cpp -- the learned parameter selector: features of a problem,
+// process-wide weights (train, save, load), device inference, and the
+// learned path of parameter selection with its fallback to the analytic
+// procedure of Sec. 4.6.
+#include "se_internal.h"
+
+#include <dlfcn.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <vector>
+
+namespace {
+
+const char kMagic[8] = {'S', 'E', 'M', 'L', 'P', 0, 'v', '1'};
+
+struct Selector {
+    std::mutex mu;
+    bool ready = false;
+    bool tried_default = false;
+    std::vector<float> theta = std::vector<float>(SE_MLP_NPARAM, 0.f);
+    float norm[SE_MLP_NORM] = {};
+    std::map<int, float*> dev;  // device copies of theta
+};
+
+Selector& sel()
+{
+    static Selector s;
+    return s;
+}
+
+uint64_t splitmix64(uint64_t* state)
+{
+    uint64_t z = (*state += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+double uniform01(uint64_t* state) { return (double)(splitmix64(state) >> 11) * (1.0 / 9007199254740992.0); }
+
+uint32_t fnv1a(const unsigned char* p, size_t n)
+{
+    uint32_t h = 2166136261u;
+    for (size_t i = 0; i < n; i++) {
+        h ^= p[i];
+        h *= 16777619u;
+    }
+    return h;
+}
+
+void drop_device_copies(Selector& S)
+{
+    int cur = 0;
+    hipGetDevice(&cur);
+    for (auto& kv : S.dev) {
+        hipSetDevice(kv.first);
+        hipFree(kv.second);
+    }
+    S.dev.clear();
+    hipSetDevice(cur);
+}
+
+void install(Selector& S, const float* theta, const float* norm)
+{
+    drop_device_copies(S);
+    S.theta.assign(theta, theta + SE_MLP_NPARAM);
+    std::memcpy(S.norm, norm, sizeof(S.norm));
+    S.ready = true;
+}
+
+se_status load_file(Selector& S, const char* path)
+{
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return SE_ERR_ARG;
+    std::vector<unsigned char> buf;
+    unsigned char tmp[4096];
+    size_t r;
+    while ((r = std::fread(tmp, 1, sizeof(tmp), f)) > 0) buf.insert(buf.end(), tmp, tmp + r);
+    std::fclose(f);
+    const size_t body = 8 + 4 * sizeof(int32_t) + sizeof(float) * (SE_MLP_NORM + SE_MLP_NPARAM);
+    if (buf.size() != body + sizeof(uint32_t)) return SE_ERR_ARG;
+    if (std::memcmp(buf.data(), kMagic, 8) != 0) return SE_ERR_ARG;
+    int32_t dims[4];
+    std::memcpy(dims, buf.data() + 8, sizeof(dims));
+    if (dims[0] != SE_MLP_IN || dims[1] != SE_MLP_HID || dims[2] != SE_MLP_OUT || dims[3] != SE_MLP_NPARAM)
+        return SE_ERR_ARG;
+    uint32_t sum;
+    std::memcpy(&sum, buf.data() + body, sizeof(sum));
+    if (sum != fnv1a(buf.data(), body)) return SE_ERR_ARG;
+    std::vector<float> norm(SE_MLP_NORM), theta(SE_MLP_NPARAM);
+    const unsigned char* q = buf.data() + 8 + sizeof(dims);
+    std::memcpy(norm.data(), q, sizeof(float) * SE_MLP_NORM);
+    std::memcpy(theta.data(), q + sizeof(float) * SE_MLP_NORM, sizeof(float) * SE_MLP_NPARAM);
+    for (float v : norm)
+        if (!std::isfinite(v)) return SE_ERR_ARG;
+    for (int i = SE_MLP_IN; i < 2 * SE_MLP_IN; i++)
+        if (!(norm[i] > 0.f)) return SE_ERR_ARG;
+    for (int o = 0; o < SE_MLP_OUT; o++)
+        if (!(norm[2 * SE_MLP_IN + SE_MLP_OUT + o] > 0.f)) return SE_ERR_ARG;
+    for (float v : theta)
+        if (!std::isfinite(v)) return SE_ERR_ARG;
+    install(S, theta.data(), norm.data());
+    return SE_OK;
+}
+
+std::string default_path()
+{
+    Dl_info info;
+    if (dladdr((void*)&se_selector_ready, &info) && info.dli_fname) {
+        std::string p(info.dli_fname);
+        size_t k = p.rfind('/');
+        return (k == std::string::npos ? std::string(".") : p.substr(0, k)) + "/se_selector_weights.bin";
+    }
+    return "se_selector_weights.bin";
+}
+
+// Caller holds S.mu.
+bool ensure_ready(Selector& S)
+{
+    if (S.ready) return true;
+    if (S.tried_default) return false;
+    S.tried_default = true;
+    const char* env = std::getenv("SE_SELECTOR_WEIGHTS");
+    if (env && *env && load_file(S, env) == SE_OK) return true;
+    return load_file(S, default_path().c_str()) == SE_OK;
+}
+
+// Caller holds S.mu; the device is current.
+float* device_theta(Selector& S)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    auto it = S.dev.find(dev);
+    if (it != S.dev.end()) return it->second;
+    float* p = nullptr;
+    if (hipMalloc(&p, sizeof(float) * SE_MLP_NPARAM) != hipSuccess) return nullptr;
+    if (hipMemcpy(p, S.theta.data(), sizeof(float) * SE_MLP_NPARAM, hipMemcpyHostToDevice) != hipSuccess) {
+        hipFree(p);
+        return nullptr;
+    }
+    S.dev[dev] = p;
+    return p;
+}
+
+bool features(const se_problem* p, float* x)
+{
+    if (!p || !x) return false;
+    if (p->periodicity < 0 || p->periodicity > 3 || p->kernel < SE_STOKESLET || p->kernel > SE_STRESSLET) return false;
+    if (!(p->tol > 0) || p->n_src < 1) return false;
+    double lmax = 0.0, lmin = 1e300;
+    for (int i = 0; i < 3; i++) {
+        if (!(p->box[i] > 0)) return false;
+        lmax = std::max(lmax, p->box[i]);
+        lmin = std::min(lmin, p->box[i]);
+    }
+    for (int i = 0; i < SE_MLP_IN; i++) x[i] = 0.f;
+    x[0] = (float)std::log10((double)p->n_src);
+    x[1] = (float)std::log(lmax / lmin);
+    x[2 + p->periodicity] = 1.f;
+    x[6 + p->kernel] = 1.f;
+    x[9] = (float)std::log10(p->tol);
+    return true;
+}
+
+}  // namespace
+
+// Learned path of parameter selection.  The network proposes (xi, h, P, rc)
+// for the problem; steps 5-7 of Sec. 4.6 complete them, and the proposal is
+// kept unless one of the real-space, Fourier and window estimates of Sec. 4 at
+// the completed parameters exceeds ten times the tolerance.
+se_status se_select_learned(const se_problem* p, se_params* out, std::string* msg)
+{
+    auto fallback = [&](const char* why) {
+        se_status st = se_select_params(p, nullptr, out, msg);
+        *msg = std::string("learned selector: ") + why + "; analytic parameters";
+        return st;
+    };
+    if (p->tol_kind != SE_TOL_REL) return fallback("absolute tolerance");
+    float x[SE_MLP_IN], y[SE_MLP_OUT];
+    if (!features(p, x)) return fallback("no features");
+    {
+        Selector& S = sel();
+        std::lock_guard<std::mutex> lk(S.mu);
+        if (!ensure_ready(S)) return fallback("no weights");
+        if (hipSetDevice(p->device) != hipSuccess) return SE_ERR_HIP;
+        float* th = device_theta(S);
+        float* buf = nullptr;
+        if (!th || hipMalloc(&buf, sizeof(float) * (SE_MLP_IN + SE_MLP_OUT)) != hipSuccess) return SE_ERR_NOMEM;
+        hipError_t e = hipMemcpy(buf, x, sizeof(x), hipMemcpyHostToDevice);
+        if (e == hipSuccess) {
+            se_mlp_launch_forward(th, buf, 1, buf + SE_MLP_IN, S.norm, nullptr);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipMemcpy(y, buf + SE_MLP_IN, sizeof(y), hipMemcpyDeviceToHost);
+        hipFree(buf);
+        if (e != hipSuccess) return SE_ERR_HIP;
+    }
+    for (float v : y)
+        if (!std::isfinite(v)) return fallback("non-finite proposal");
+    const double Lc = std::cbrt(p->box[0] * p->box[1] * p->box[2]);
+    const double xi = std::exp((double)y[0]) / Lc;
+    // FP32 outputs: a spacing L/M read back lies within a few ulp of the grid
+    // boundary; the slack keeps it from rounding up to the next grid size
+    const double h = Lc / std::exp((double)y[1]) * (1.0 + 1e-5);
+    int P = 2 * (int)std::lround((double)y[2] / 2.0);
+    P = std::max(4, std::min(P, SE_MAX_P));
+    const double rc = std::exp((double)y[3]) / xi;
+    se_problem q = *p;
+    q.safety = 1.0;  // the estimates are checked against the tolerance itself
+    se_params par;
+    std::string m2;
+    if (se_complete_params(&q, xi, rc, h, P, &par, &m2) != SE_OK) return fallback("proposal not completed");
+    // the estimates are within a factor 10 of the measured error (Sec. 4):
+    // a proposal they put above 10 tol cannot meet tol
+    const double lim = 10.0 * par.tau_abs;
+    if (par.est_real > lim || par.est_fourier > lim || par.est_window > lim)
+        return fallback("estimates above ten times the tolerance");
+    *out = par;
+    *msg = "learned parameters";
+    return SE_OK;
+}
+
+extern "C" {
+
+se_status se_selector_features(const se_problem* prob, float* x) { return features(prob, x) ? SE_OK : SE_ERR_ARG; }
+
+int32_t se_selector_ready(void)
+{
+    Selector& S = sel();
+    std::lock_guard<std::mutex> lk(S.mu);
+    return ensure_ready(S) ? 1 : 0;
+}
+
+se_status se_selector_get(float* theta, float* norm)
+{
+    Selector& S = sel();
+    std::lock_guard<std::mutex> lk(S.mu);
+    if (!ensure_ready(S)) return SE_ERR_STATE;
+    if (theta) std::memcpy(theta, S.theta.data(), sizeof(float) * SE_MLP_NPARAM);
+    if (norm) std::memcpy(norm, S.norm, sizeof(S.norm));
+    return SE_OK;
+}
+
+se_status se_selector_save(const char* path)
+{
+    if (!path) return SE_ERR_ARG;
+    Selector& S = sel();
+    std::lock_guard<std::mutex> lk(S.mu);
+    if (!S.ready) return SE_ERR_STATE;
+    std::vector<unsigned char> buf(kMagic, kMagic + 8);
+    const int32_t dims[4] = {SE_MLP_IN, SE_MLP_HID, SE_MLP_OUT, SE_MLP_NPARAM};
+    auto put = [&](const void* p, size_t n) {
+        const unsigned char* c = (const unsigned char*)p;
+        buf.insert(buf.end(), c, c + n);
+    };
+    put(dims, sizeof(dims));
+    put(S.norm, sizeof(S.norm));
+    put(S.theta.data(), sizeof(float) * SE_MLP_NPARAM);
+    const uint32_t sum = fnv1a(buf.data(), buf.size());
+    put(&sum, sizeof(sum));
+    FILE* f = std::fopen(path, "wb");
+    if (!f) return SE_ERR_ARG;
+    const bool ok = std::fwrite(buf.data(), 1, buf.size(), f) == buf.size();
+    return (std::fclose(f) == 0 && ok) ? SE_OK : SE_ERR_ARG;
+}
+
+se_status se_selector_load(const char* path)
+{
+    if (!path) return SE_ERR_ARG;
+    Selector& S = sel();
+    std::lock_guard<std::mutex> lk(S.mu);
+    return load_file(S, path);
+}
+
+se_status se_selector_predict(const float* X, float* Y, int64_t n, void* stream)
+{
+    if (n < 0 || (n > 0 && (!X || !Y))) return SE_ERR_ARG;
+    Selector& S = sel();
+    std::lock_guard<std::mutex> lk(S.mu);
+    if (!ensure_ready(S)) return SE_ERR_STATE;
+    float* th = device_theta(S);
+    if (!th) return SE_ERR_NOMEM;
+    se_mlp_launch_forward(th, X, n, Y, S.norm, (hipStream_t)stream);
+    return hipGetLastError() == hipSuccess ? SE_OK : SE_ERR_HIP;
+}
+
+se_status se_mlp_forward(const float* theta, const float* X, int64_t n, float* Y, void* stream)
+{
+    if (!theta || n < 0 || (n > 0 && (!X || !Y))) return SE_ERR_ARG;
+    se_mlp_launch_forward(theta, X, n, Y, nullptr, (hipStream_t)stream);
+    return hipGetLastError() == hipSuccess ? SE_OK : SE_ERR_HIP;
+}
+
+se_status se_mlp_loss_grad(const float* theta, const float* X, const float* Y, int64_t n, float* grad, float* loss,
+                           void* stream)
+{
+    if (!theta || !X || !Y || !grad || !loss || n < 1 || n > ((int64_t)1 << 30)) return SE_ERR_ARG;
+    float* part = nullptr;
+    if (hipMalloc(&part, sizeof(float) * se_mlp_part_floats((int)n)) != hipSuccess) return SE_ERR_NOMEM;
+    hipStream_t s = (hipStream_t)stream;
+    se_mlp_launch_grad(theta, X, Y, n, 1, 0, 0, (int)n, part, grad, loss, s);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    hipFree(part);
+    return e == hipSuccess ? SE_OK : SE_ERR_HIP;
+}
+
+se_status se_mlp_adam(float* theta, float* m, float* v, const float* grad, int64_t n, int32_t t, float lr, float beta1,
+                      float beta2, float eps, void* stream)
+{
+    if (!theta || !m || !v || !grad || n < 0 || t < 1 || !(lr > 0) || !(beta1 >= 0 && beta1 < 1) ||
+        !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
+        return SE_ERR_ARG;
+    if (n == 0) return SE_OK;
+    se_mlp_launch_adam(theta, m, v, grad, n, t, lr, beta1, beta2, eps, (hipStream_t)stream);
+    return hipGetLastError() == hipSuccess ? SE_OK : SE_ERR_HIP;
+}
+
+se_status se_selector_train(const se_train_cfg* cfg, const float* X, const float* Y, int64_t n, float* loss_history)
+{
+    if (!cfg || cfg->struct_size != (int32_t)sizeof(se_train_cfg) || !X || !Y || n < 1 || n > ((int64_t)1 << 30))
+        return SE_ERR_ARG;
+    if (cfg->epochs < 1 || cfg->batch < 1 || !(cfg->lr > 0) || !(cfg->beta1 >= 0 && cfg->beta1 < 1) ||
+        !(cfg->beta2 >= 0 && cfg->beta2 < 1) || !(cfg->eps > 0))
+        return SE_ERR_ARG;
+    if (hipSetDevice(cfg->device) != hipSuccess) return SE_ERR_HIP;
+    const int B = (int)std::min<int64_t>(cfg->batch, n);
+
+    // normalisation: zero mean, unit variance per column (constant columns: scale 1)
+    float norm[SE_MLP_NORM];
+    std::vector<float> Xn((size_t)n * SE_MLP_IN), Yn((size_t)n * SE_MLP_OUT);
+    auto column_stats = [&](const float* A, int w, int c, float* mean, float* sd) {
+        double s = 0.0, s2 = 0.0;
+        for (int64_t i = 0; i < n; i++) s += A[i * w + c];
+        const double mu = s / (double)n;
+        for (int64_t i = 0; i < n; i++) {
+            const double d = A[i * w + c] - mu;
+            s2 += d * d;
+        }
+        const double sdv = std::sqrt(s2 / (double)n);
+        *mean = (float)mu;
+        *sd = sdv > 1e-6 ? (float)sdv : 1.f;
+    };
+    for (int c = 0; c < SE_MLP_IN; c++) {
+        column_stats(X, SE_MLP_IN, c, &norm[c], &norm[SE_MLP_IN + c]);
+        for (int64_t i = 0; i < n; i++)
+            Xn[i * SE_MLP_IN + c] = (X[i * SE_MLP_IN + c] - norm[c]) / norm[SE_MLP_IN + c];
+    }
+    for (int o = 0; o < SE_MLP_OUT; o++) {
+        float* ym = &norm[2 * SE_MLP_IN + o];
+        float* ys = &norm[2 * SE_MLP_IN + SE_MLP_OUT + o];
+        column_stats(Y, SE_MLP_OUT, o, ym, ys);
+        for (int64_t i = 0; i < n; i++) Yn[i * SE_MLP_OUT + o] = (Y[i * SE_MLP_OUT + o] - *ym) / *ys;
+    }
+    for (float v : Xn)
+        if (!std::isfinite(v)) return SE_ERR_ARG;
+    for (float v : Yn)
+        if (!std::isfinite(v)) return SE_ERR_ARG;
+
+    // Glorot-uniform weights, zero biases
+    uint64_t rs = cfg->seed;
+    std::vector<float> th(SE_MLP_NPARAM, 0.f);
+    {
+        const int fan[3][2] = {{SE_MLP_IN, SE_MLP_HID}, {SE_MLP_HID, SE_MLP_HID}, {SE_MLP_HID, SE_MLP_OUT}};
+        int off = 0;
+        for (int l = 0; l < 3; l++) {
+            const double lim = std::sqrt(6.0 / (fan[l][0] + fan[l][1]));
+            const int nw = fan[l][0] * fan[l][1];
+            for (int i = 0; i < nw; i++) th[off + i] = (float)((2.0 * uniform01(&rs) - 1.0) * lim);
+            off += nw + fan[l][1];
+        }
+    }
+
+    const int64_t steps = (n + B - 1) / B;
+    const int64_t total = steps * (int64_t)cfg->epochs;
+    float *dX = nullptr, *dY = nullptr, *dth = nullptr, *dm = nullptr, *dv = nullptr, *dg = nullptr, *dpart = nullptr,
+          *dloss = nullptr;
+    hipStream_t s = nullptr;
+    auto cleanup = [&]() {
+        for (float* q : {dX, dY, dth, dm, dv, dg, dpart, dloss})
+            if (q) hipFree(q);
+        if (s) hipStreamDestroy(s);
+    };
+    bool ok = hipMalloc(&dX, sizeof(float) * Xn.size()) == hipSuccess &&
+              hipMalloc(&dY, sizeof(float) * Yn.size()) == hipSuccess &&
+              hipMalloc(&dth, sizeof(float) * SE_MLP_NPARAM) == hipSuccess &&
+              hipMalloc(&dm, sizeof(float) * SE_MLP_NPARAM) == hipSuccess &&
+              hipMalloc(&dv, sizeof(float) * SE_MLP_NPARAM) == hipSuccess &&
+              hipMalloc(&dg, sizeof(float) * SE_MLP_NPARAM) == hipSuccess &&
+              hipMalloc(&dpart, sizeof(float) * se_mlp_part_floats(B)) == hipSuccess &&
+              hipMalloc(&dloss, sizeof(float) * total) == hipSuccess && hipStreamCreate(&s) == hipSuccess;
+    if (!ok) {
+        cleanup();
+        return SE_ERR_NOMEM;
+    }
+    hipError_t e = hipMemcpy(dX, Xn.data(), sizeof(float) * Xn.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dY, Yn.data(), sizeof(float) * Yn.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dth, th.data(), sizeof(float) * SE_MLP_NPARAM, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        cleanup();
+        return SE_ERR_HIP;
+    }
+    se_mlp_launch_fill(dm, SE_MLP_NPARAM, 0.f, s);
+    se_mlp_launch_fill(dv, SE_MLP_NPARAM, 0.f, s);
+    int64_t step = 0;
+    for (int ep = 0; ep < cfg->epochs; ep++) {
+        // sample order of this epoch: pos -> (a pos + c) mod n with gcd(a, n) = 1
+        uint64_t a = 1, c = 0;
+        if (n > 1) {
+            do {
+                a = 1 + splitmix64(&rs) % (uint64_t)(n - 1);
+            } while (std::gcd(a, (uint64_t)n) != 1);
+            c = splitmix64(&rs) % (uint64_t)n;
+        }
+        for (int64_t k = 0; k < steps; k++, step++) {
+            const int64_t start = k * B;
+            const int cnt = (int)std::min<int64_t>(B, n - start);
+            se_mlp_launch_grad(dth, dX, dY, n, a, c, start, cnt, dpart, dg, dloss + step, s);
+            se_mlp_launch_adam(dth, dm, dv, dg, SE_MLP_NPARAM, (int)std::min<int64_t>(step + 1, 1 << 30), cfg->lr,
+                               cfg->beta1, cfg->beta2, cfg->eps, s);
+        }
+    }
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    std::vector<float> lossv(total);
+    if (e == hipSuccess) e = hipMemcpy(lossv.data(), dloss, sizeof(float) * total, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(th.data(), dth, sizeof(float) * SE_MLP_NPARAM, hipMemcpyDeviceToHost);
+    cleanup();
+    if (e != hipSuccess) return SE_ERR_HIP;
+    for (float v : th)
+        if (!std::isfinite(v)) return SE_ERR_NONFINITE;
+    if (loss_history) {
+        for (int ep = 0; ep < cfg->epochs; ep++) {
+            double acc = 0.0;
+            for (int64_t k = 0; k < steps; k++) {
+                const int cnt = (int)std::min<int64_t>(B, n - k * B);
+                acc += (double)lossv[ep * steps + k] * cnt;
+            }
+            loss_history[ep] = (float)(acc / (double)n);
+        }
+    }
+    Selector& S = sel();
+    std::lock_guard<std::mutex> lk(S.mu);
+    install(S, th.data(), norm);
+    return SE_OK;
+}
+
+}  // extern "C"

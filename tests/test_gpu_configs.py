@@ -1,0 +1,94 @@
+"""Full-size parity for the FP32 grid path on the paper-shaped workloads.
+
+* Doubly periodic stokeslet and stresslet, unit box, N = 2e4 uniform:
+  FP64 and FP32 at rms-relative tolerances 1e-4, 1e-6, 1e-8 against the
+  oracle on 1000 sampled targets (FP32 below 1e-6 is refused with
+  SE_ERR_TOL_UNREACHABLE, the documented limit of the FP32 grid path).
+* Singly periodic (x) and free-space rotlet and stresslet, box 4 x 1 x 1,
+  N = 1e5 (half uniform, half in 10 Gaussian clusters, sigma = 0.02), 16
+  right-hand sides on shared geometry, FP32 at 1e-6: every rhs against an
+  FP64 run at 1e-9 on all targets; that run and the FP32 result against the
+  oracle on sampled targets (D = 0: all 16 rhs, 500 targets; D = 1: the
+  oracle's trapezoidal k-sums over N = 1e5 sources take tens of seconds per
+  rhs, so rhs 0 (and 15 for the rotlet) on 200 targets).
+
+Bars: the requested tolerance (safety factor 10 as everywhere in the GPU
+tests); the sampled error is the rms over the sample relative to the
+oracle's rms over it.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from test_gpu_parity import SAFETY, _q_of, env  # noqa: F401  (shared fixture)
+
+pytestmark = pytest.mark.gpu
+
+
+def _plan_run(env, kernel, s, D, tol, prec, n_rhs=1):
+    se, _, torch = env
+    dev = torch.device("cuda:0")
+    n = s["x"].shape[0]
+    print("case kernel=%s D=%d n=%d tol=%g prec=%d rhs=%d" % (kernel, D, n, tol, prec, n_rhs), flush=True)
+    plan = se.Plan(kernel=kernel, periodicity=D, box=tuple(s["box"]), tol=tol, n_src=n,
+                   source_q=_q_of(kernel, s) / n_rhs, safety=SAFETY, precision=prec, n_rhs=n_rhs)
+    x = torch.tensor(s["x"], device=dev)
+    nu = torch.tensor(s["nu"], device=dev) if kernel == "stresslet" else None
+    plan.set_geometry(x, nu)
+    u = plan.execute(torch.tensor(s["q"] if kernel == "stresslet" else s["f"], device=dev))
+    plan.sync()
+    return u.cpu().numpy()
+
+
+def _oracle(env, kernel, s, D, idx, r=None):
+    _, oracle, _ = env
+    pick = (lambda a: a) if r is None else (lambda a: a[r])
+    xi = 6.0 / float(np.max(s["box"][:D])) if D in (1, 2) else None
+    res = oracle.ewald(D, kernel, s["box"], s["x"], f=pick(s["f"]) if "f" in s else None,
+                       q=pick(s["q"]) if "q" in s else None, nu=s.get("nu"), targets=s["x"][idx], self_src=idx,
+                       xi=xi)
+    return res.total if D else res["direct"]
+
+
+@pytest.mark.parametrize("kernel", ["stokeslet", "stresslet"])
+def test_doubly_periodic_fp32_and_fp64(env, kernel):
+    se, oracle, _ = env
+    n = 20000
+    s = W.system(2650 + len(kernel), n, kernel=kernel)
+    idx = np.sort(W.rng(2651).choice(n, 1000, replace=False)).astype(np.int64)
+    ref = _oracle(env, kernel, s, 2, idx)
+    for tol in (1e-4, 1e-6, 1e-8):
+        for prec in (se.PREC_FP64, se.PREC_FP32):
+            if prec == se.PREC_FP32 and tol < 1e-6:
+                with pytest.raises(se.SEError) as e:
+                    _plan_run(env, kernel, s, 2, tol, prec)
+                assert e.value.status == se.SE_ERR_TOL_UNREACHABLE
+                continue
+            u = _plan_run(env, kernel, s, 2, tol, prec)
+            err = oracle.rms_rel_error(u[idx], ref)
+            print("D=2 %s tol %g %s sampled err %.3g" % (kernel, tol, "fp32" if prec == se.PREC_FP32 else "fp64",
+                                                           err), flush=True)
+            assert err <= tol
+
+
+@pytest.mark.parametrize("D,kernel", [(1, "rotlet"), (1, "stresslet"), (0, "rotlet"), (0, "stresslet")])
+def test_elongated_clustered_16_rhs_fp32(env, D, kernel):
+    se, oracle, _ = env
+    n, nrhs, tol = 100000, 16, 1e-6
+    s = W.system(2700 + 10 * D + len(kernel), n, box=(4.0, 1.0, 1.0), kernel=kernel, layout="mixed",
+                 periodicity=D, n_rhs=nrhs)
+    u32 = _plan_run(env, kernel, s, D, tol, se.PREC_FP32, nrhs)
+    u64 = _plan_run(env, kernel, s, D, 1e-9, se.PREC_FP64, nrhs)
+    for r in range(nrhs):
+        err = oracle.rms_rel_error(u32[r], u64[r])
+        assert err <= tol, (r, err)
+    nt = 500 if D == 0 else 200
+    idx = np.sort(W.rng(2701 + D).choice(n, nt, replace=False)).astype(np.int64)
+    rhs = range(nrhs) if D == 0 else ([0, nrhs - 1] if kernel == "rotlet" else [0])
+    for r in rhs:
+        ref = _oracle(env, kernel, s, D, idx, r)
+        e64 = oracle.rms_rel_error(u64[r][idx], ref)
+        e32 = oracle.rms_rel_error(u32[r][idx], ref)
+        print("D=%d %s rhs %d sampled err fp64 %.3g fp32 %.3g" % (D, kernel, r, e64, e32), flush=True)
+        assert e64 <= 1e-8
+        assert e32 <= tol

@@ -4,6 +4,7 @@ import math
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -105,3 +106,77 @@ def test_pollution_rules(se):
     assert a["P"] == b["P"] and a["M"] == b["M"]  # D = 0 uses (h/1.1, P+2) either way
     with pytest.raises(se.SEError):
         se.select_params(kernel="stokeslet", periodicity=3, tol=1e-8, n_src=10, pollution=7)
+
+
+def _weights_file(path, theta, norm, magic=b"SEMLP\x00v1", dims=(10, 64, 4, 5124)):
+    import struct
+    body = magic + struct.pack("<4i", *dims) + np.asarray(norm, "<f4").tobytes() + np.asarray(theta, "<f4").tobytes()
+    h = 2166136261
+    for b in body:
+        h = ((h ^ b) * 16777619) & 0xFFFFFFFF
+    with open(path, "wb") as f:
+        f.write(body + struct.pack("<I", h))
+
+
+def test_selector_weights_file_roundtrip_and_rejection(tmp_path):
+    """A well-formed file loads (host only) and reads back; a flipped byte,
+    a wrong size or a non-positive scale is rejected and changes nothing."""
+    import ctypes
+    import paper_2210_01255_amd as se
+    g = np.random.default_rng(1)
+    theta = g.normal(size=se.MLP_NPARAM).astype(np.float32)
+    norm = np.concatenate([g.normal(size=10), g.uniform(0.5, 2, 10), g.normal(size=4),
+                           g.uniform(0.5, 2, 4)]).astype(np.float32)
+    good = str(tmp_path / "good.bin")
+    _weights_file(good, theta, norm)
+    assert se.se_selector_load(good.encode()) == se.SE_OK
+    t2 = np.zeros_like(theta)
+    n2 = np.zeros_like(norm)
+    fp = ctypes.POINTER(ctypes.c_float)
+    assert se.se_selector_get(t2.ctypes.data_as(fp), n2.ctypes.data_as(fp)) == se.SE_OK
+    assert np.array_equal(t2, theta) and np.array_equal(n2, norm)
+    raw = open(good, "rb").read()
+    bad = str(tmp_path / "bad.bin")
+    for blob in (raw[:100] + bytes([raw[100] ^ 1]) + raw[101:], raw[:-5], raw + b"\x00"):
+        open(bad, "wb").write(blob)
+        assert se.se_selector_load(bad.encode()) == se.SE_ERR_ARG
+    norm_bad = norm.copy()
+    norm_bad[12] = 0.0
+    _weights_file(bad, theta, norm_bad)
+    assert se.se_selector_load(bad.encode()) == se.SE_ERR_ARG
+    _weights_file(bad, theta, norm, dims=(10, 32, 4, 5124))
+    assert se.se_selector_load(bad.encode()) == se.SE_ERR_ARG
+    assert se.se_selector_get(t2.ctypes.data_as(fp), None) == se.SE_OK
+    assert np.array_equal(t2, theta)
+
+
+def test_selector_features():
+    import paper_2210_01255_amd as se
+    from paper_2210_01255_amd import selector as S
+    x = S.features(25000, 1, se.KERNELS["rotlet"], (1.0, 3.0, 1.5), 1e-7)
+    expect = np.zeros(10, dtype=np.float32)
+    expect[0] = np.log10(25000)
+    expect[1] = np.log(3.0)
+    expect[2 + 1] = 1
+    expect[6 + 1] = 1
+    expect[9] = -7
+    assert np.allclose(x, expect, rtol=1e-6, atol=1e-6)
+
+
+def test_selector_targets_map_back_to_parameters():
+    """Network outputs of a parameter set, ln(xi Lc), ln(Lc/h), P, ln(xi rc),
+    give back (xi, h, P, rc) the way the learned path reads them."""
+    import paper_2210_01255_amd as se
+    from paper_2210_01255_amd import selector as S
+    for D, kernel, box, tol in [(3, 0, (1, 1, 1), 1e-8), (0, 0, (1, 2, 1), 1e-6), (2, 2, (1, 1, 1.5), 1e-7),
+                                (1, 1, (2.5, 1, 1), 1e-5)]:
+        ref = se.select_params(kernel=kernel, periodicity=D, box=box, tol=tol, n_src=20000, safety=3.0,
+                               pollution=se.POLLUTION_FINE)
+        hmin = min(ref["h"][i] for i in range(3) if (i < D or D == 0))
+        y = S.targets_of(ref["xi"], hmin, ref["P"], ref["rc"], np.array(box, dtype=float)).astype(np.float64)
+        Lc = float(np.prod(box)) ** (1 / 3)
+        xi = np.exp(y[0]) / Lc
+        assert abs(xi - ref["xi"]) <= 1e-6 * ref["xi"]
+        assert abs(Lc / np.exp(y[1]) - hmin) <= 1e-6 * hmin
+        assert y[2] == ref["P"]
+        assert abs(np.exp(y[3]) / xi - ref["rc"]) <= 1e-6 * ref["rc"]

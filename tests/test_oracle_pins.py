@@ -282,3 +282,68 @@ def test_direct_sum_is_translation_invariant_and_antisymmetric(oracle_lib):
     assert np.allclose(oracle_lib.free_kernel("stresslet", -r, f, nu),
                        -oracle_lib.free_kernel("stresslet", r, f, nu))
     assert np.allclose(oracle_lib.free_kernel("stokeslet", -r, f), oracle_lib.free_kernel("stokeslet", r, f))
+
+
+# ------------------------------------------------ learned selector network
+def _mlp_case(seed, n):
+    from oracle import mlp
+    g = np.random.default_rng(seed)
+    theta = g.normal(0.0, 0.3, mlp.N_PARAM)
+    X = g.normal(size=(n, mlp.N_IN))
+    T = g.normal(size=(n, mlp.N_OUT))
+    return theta, X, T
+
+
+def test_mlp_gradient_matches_finite_differences():
+    """Backpropagated gradient against central differences of the loss on
+    every parameter block (all of b3, b1; strided entries of the weights)."""
+    from oracle import mlp
+    theta, X, T = _mlp_case(7, 9)
+    L, g = mlp.loss_grad(theta, X, T)
+    assert abs(L - mlp.loss(theta, X, T)) < 1e-15
+    idx = list(range(0, mlp.N_PARAM, 37)) + list(range(mlp.N_PARAM - 4, mlp.N_PARAM)) + [640, 703, 704, 4864]
+    h = 1e-6
+    for i in idx:
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += h
+        tm[i] -= h
+        fd = (mlp.loss(tp, X, T) - mlp.loss(tm, X, T)) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-8 * max(1.0, abs(g[i])), i
+
+
+def test_mlp_forward_known_values():
+    """Zero first-layer weights make the output W3 tanh(W2 tanh(b1) + b2) + b3
+    for every input; a single active path gives tanh(tanh(w x)) scaled."""
+    from oracle import mlp
+    p = {name: np.zeros(shp) for name, shp in mlp.SHAPES}
+    p["b1"][:] = 0.5
+    p["W2"][3, :] = 0.1
+    p["W3"][2, 3] = 2.0
+    p["b3"][:] = [1.0, -1.0, 0.25, 0.0]
+    X = np.random.default_rng(3).normal(size=(5, mlp.N_IN))
+    y = mlp.forward(mlp.pack(p), X)
+    expect = np.array([1.0, -1.0, 0.25 + 2.0 * np.tanh(64 * 0.1 * np.tanh(0.5)), 0.0])
+    assert np.allclose(y, expect[None, :], rtol=0, atol=1e-15)
+    q = {name: np.zeros(shp) for name, shp in mlp.SHAPES}
+    q["W1"][0, 4] = 0.7
+    q["W2"][1, 0] = 1.3
+    q["W3"][0, 1] = 1.0
+    y = mlp.forward(mlp.pack(q), X)
+    assert np.allclose(y[:, 0], np.tanh(1.3 * np.tanh(0.7 * X[:, 4])), rtol=0, atol=1e-15)
+    assert np.all(y[:, 1:] == 0.0)
+
+
+def test_adam_first_step_closed_form():
+    """At t = 1 from zero moments the bias corrections give m_hat = g and
+    v_hat = g^2, so the step is -lr g / (|g| + eps)."""
+    from oracle import mlp
+    g = np.random.default_rng(4).normal(size=50)
+    th0 = np.linspace(-1, 1, 50)
+    th1, m, v = mlp.adam_step(th0, np.zeros(50), np.zeros(50), g, 1, 1e-3, 0.9, 0.999, 1e-8)
+    assert np.allclose(th1, th0 - 1e-3 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
+    assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
+    # a constant gradient keeps m_hat = g and v_hat = g^2 at every step
+    th, m, v = th0, np.zeros(50), np.zeros(50)
+    for t in range(1, 6):
+        th, m, v = mlp.adam_step(th, m, v, g, t, 1e-3, 0.9, 0.999, 0.0)
+    assert np.allclose(th, th0 - 5e-3 * np.sign(g), rtol=0, atol=1e-12)
