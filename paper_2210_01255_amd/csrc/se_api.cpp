@@ -4,6 +4,7 @@
 #include <complex>
 #include <cstring>
 #include <new>
+#include <thread>
 
 #include "se_internal.h"
 
@@ -142,25 +143,46 @@ hipError_t aft_tables(se_plan* p)
         if (e == hipSuccess) e = hipMemcpy(c.tw, tw.data(), tw.size() * sizeof(double), hipMemcpyHostToDevice);
         if (e != hipSuccess) return e;
         if (c.mk) {
+            // the multipliers depend on |k| only and the free-axis wavenumbers
+            // of index i and n - i are opposite: evaluate one quadrant (the
+            // Bessel functions dominate plan creation) on host threads, then
+            // mirror it
             const double R = par.R;
-            std::vector<double> mk((size_t)2 * c.ny * c.nz);
-            for (int iz = 0; iz < c.nz; iz++)
-                for (int iy = 0; iy < c.ny; iy++) {
-                    const double ky = kv[c.nkx + iy], kz = kv[c.nkx + c.ny + iz];
-                    const double kk = std::sqrt(ky * ky + kz * kz);
-                    double hb, bb;
-                    bessel_brackets(R * kk, &hb, &bb);
-                    double H, B;
-                    if (kk == 0.0) {
-                        H = M_PI * R * R;
-                        B = -M_PI * R * R * R * R / 8.0;
-                    } else {
-                        H = 4.0 * M_PI / (kk * kk) * hb;
-                        B = -8.0 * M_PI / (kk * kk * kk * kk) * bb;
+            const int qy = c.ny / 2 + 1, qz = c.nz / 2 + 1;
+            std::vector<double> quad((size_t)2 * qy * qz);
+            auto rows = [&](int z0, int z1) {
+                for (int iz = z0; iz < z1; iz++)
+                    for (int iy = 0; iy < qy; iy++) {
+                        const double ky = kv[c.nkx + iy], kz = kv[c.nkx + c.ny + iz];
+                        const double kk = std::sqrt(ky * ky + kz * kz);
+                        double hb, bb;
+                        bessel_brackets(R * kk, &hb, &bb);
+                        double H, B;
+                        if (kk == 0.0) {
+                            H = M_PI * R * R;
+                            B = -M_PI * R * R * R * R / 8.0;
+                        } else {
+                            H = 4.0 * M_PI / (kk * kk) * hb;
+                            B = -8.0 * M_PI / (kk * kk * kk * kk) * bb;
+                        }
+                        quad[2 * ((size_t)iz * qy + iy)] = H;
+                        quad[2 * ((size_t)iz * qy + iy) + 1] = B;
                     }
-                    mk[2 * ((size_t)iz * c.ny + iy)] = H;
-                    mk[2 * ((size_t)iz * c.ny + iy) + 1] = B;
+            };
+            const int nth = std::max(1, std::min<int>(16, (int)std::thread::hardware_concurrency()));
+            std::vector<std::thread> pool;
+            for (int t = 0; t < nth; t++) pool.emplace_back(rows, (int)((int64_t)qz * t / nth),
+                                                            (int)((int64_t)qz * (t + 1) / nth));
+            for (auto& th : pool) th.join();
+            std::vector<double> mk((size_t)2 * c.ny * c.nz);
+            for (int iz = 0; iz < c.nz; iz++) {
+                const int jz = std::min(iz, c.nz - iz);
+                for (int iy = 0; iy < c.ny; iy++) {
+                    const int jy = std::min(iy, c.ny - iy);
+                    mk[2 * ((size_t)iz * c.ny + iy)] = quad[2 * ((size_t)jz * qy + jy)];
+                    mk[2 * ((size_t)iz * c.ny + iy) + 1] = quad[2 * ((size_t)jz * qy + jy) + 1];
                 }
+            }
             e = hipMemcpy(c.mk, mk.data(), mk.size() * sizeof(double), hipMemcpyHostToDevice);
             if (e != hipSuccess) return e;
         }

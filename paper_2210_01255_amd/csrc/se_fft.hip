@@ -585,6 +585,7 @@ __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_z_scale(se_fft_args a)
 
 // LDS budgets (bytes) of the line kernels: two workgroups per CU.
 constexpr size_t kFftLds = 80 * 1024;
+constexpr size_t kFftLdsStatic = 256;  // static LDS of the line kernels (radix table), rounded up
 
 void set_radices(int n, uint64_t* dst, int* cnt)
 {
@@ -1036,10 +1037,13 @@ void se_launch_fft_inverse(const se_plan* p, int slot, hipStream_t s)
 
 // Whether the line kernels can hold the transforms of a plan in LDS
 // (one column at least per bundle, 160 KB per workgroup).
+// The dynamic LDS of a line kernel plus its static part (the radix table)
+// must fit the 160 KiB a workgroup may hold: a dispatch asking for more is
+// refused by the runtime and takes the queue down with it.
 bool se_fft_fits(const int* N, int ncomp, bool fp32)
 {
     const size_t cb = fp32 ? 8 : 16;
-    const size_t lim = 160 * 1024;
+    const size_t lim = 160 * 1024 - kFftLdsStatic;
     const size_t nh = (size_t)N[0] / 2;
     return (2 * nh + 1 + 2 * nh) * cb <= lim && (size_t)N[1] * 3 * cb <= lim && (size_t)N[2] * 3 * cb <= lim &&
            (size_t)N[2] * (1 + (ncomp + 1)) * cb <= lim;

@@ -180,3 +180,21 @@ def test_selector_targets_map_back_to_parameters():
         assert abs(Lc / np.exp(y[1]) - hmin) <= 1e-6 * hmin
         assert y[2] == ref["P"]
         assert abs(np.exp(y[3]) / xi - ref["rc"]) <= 1e-6 * ref["rc"]
+
+
+def test_fft_pass_beyond_lds_is_refused_at_plan_creation():
+    """A z pass whose dynamic LDS alone is the full 160 KiB (1280 points, six
+    stresslet components, FP64) leaves no room for the kernels' static LDS:
+    plan creation refuses it (SE_ERR_UNSUPPORTED) before any device call."""
+    import ctypes
+    import paper_2210_01255_amd as se
+    par = se.se_params()
+    par.struct_size = ctypes.sizeof(se.se_params)
+    par.P, par.xi, par.rc = 8, 10.0, 0.2
+    for i, m in enumerate((8, 8, 1280)):
+        par.M[i] = m
+    prob = se.make_problem(kernel="stresslet", periodicity=3, tol=1e-8, n_src=100, selector=se.SELECT_MANUAL,
+                           precision=se.PREC_FP64)
+    h = ctypes.c_void_p()
+    st = se.lib.se_plan_create(ctypes.byref(prob), ctypes.byref(par), ctypes.byref(h))
+    assert st == se.SE_ERR_UNSUPPORTED
