@@ -1,8 +1,12 @@
 """Benchmark: N = 1e6 triply periodic stokeslet at 1e-8 rms-relative error on one MI355X.
 
 One step = one pass of the whole hot path over the batch: se_set_geometry (cell
-list) + se_execute (gridding, FFT, scaling, IFFT, gathering, real-space sum,
-self term).  Inputs are resident in HBM before the timed region starts.
+list) + the evaluation (gridding, FFT, scaling, IFFT, gathering, real-space
+sum, self term).  Two forms run on the same inputs: plain (analytic
+parameters, one strength set per step) and learned+batched (learned
+parameters, 16 strength sets on the shared geometry, the evaluation replayed
+as one HIP graph); `value` is the latter's targets/s.  Inputs are resident in
+HBM before the timed regions start.
 Prints ONE JSON line (see the design doc for the roofline and baseline recipes).
 """
 from __future__ import annotations
@@ -34,18 +38,17 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--tol", type=float, default=1e-8)
-    ap.add_argument("--safety", type=float, default=10.0,
-                    help="tau_abs divisor; 10 makes 'error <= tol' hold across the estimate's band")
     ap.add_argument("--seed", type=int, default=5000)
-    ap.add_argument("--nrc", type=float, default=280.0,
-                    help="expected sources within rc (balances real space against the grid work on "
-                         "this GPU; 0: the paper's CPU-tuned table value)")
+    ap.add_argument("--nrhs", type=int, default=16,
+                    help="strength sets on the shared geometry in the learned+batched form")
+    ap.add_argument("--safety", type=float, default=10.0,
+                    help="plain form: tau_abs divisor; 10 makes 'error <= tol' hold across the estimate's band")
+    ap.add_argument("--nrc", type=float, default=0.0,
+                    help="plain form: expected sources within rc (0: the paper's table value)")
+    ap.add_argument("--pollution", type=int, default=0,
+                    help="plain form: error-pollution rule, 0 (h/1.05, P+4) as the paper applies it for D = 3, "
+                         "or 1 (h/1.1, P+2)")
     ap.add_argument("--cpu-sample", type=int, default=2000, help="targets in the oracle sample (0: skip)")
-    ap.add_argument("--pollution", type=int, default=1,
-                    help="error-pollution rule: 0 (h/1.05, P+4) or 1 (h/1.1, P+2), both from the paper's "
-                         "error-pollution section; 1 suits this GPU (window work ~P^3 dominates)")
-    ap.add_argument("--nrhs", type=int, default=1,
-                    help="strength sets on the shared geometry (> 1: the batched form)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="after the run, one plain device copy of this size (HBM counter calibration)")
     return ap.parse_args()
@@ -136,43 +139,73 @@ def main():
     import paper_2210_01255_amd as se
 
     dev = torch.device("cuda:0")
-    n = args.n
-    nrhs = args.nrhs
-    s = W.system(args.seed, n, kernel="stokeslet", zero_mean=True, n_rhs=nrhs if nrhs > 1 else None)
+    n, nrhs = args.n, max(1, args.nrhs)
+    s = W.system(args.seed, n, kernel="stokeslet", zero_mean=True, n_rhs=nrhs)
     x = torch.tensor(s["x"], device=dev)
-    f = torch.tensor(s["f"], device=dev)
-    Q = float(np.sum(s["f"] ** 2)) / nrhs  # per right-hand side
-    plan = se.Plan(kernel="stokeslet", periodicity=3, box=(1.0, 1.0, 1.0), tol=args.tol, tol_kind=se.TOL_REL,
-                   n_src=n, source_q=Q, safety=args.safety, precision=se.PREC_FP64, n_rc=args.nrc,
-                   pollution=args.pollution, n_rhs=nrhs)
-    slots = 2 if nrhs >= 2 else 1  # right-hand sides per chunk of the phases (stokeslet)
-    par = plan.params
-    u = torch.empty((n, 3) if nrhs == 1 else (nrhs, n, 3), dtype=torch.float64, device=dev)
-    stream = torch.cuda.current_stream()
+    f = torch.tensor(s["f"], device=dev)         # [nrhs, n, 3]
+    f0 = f[0].contiguous()                         # the plain form's strengths: the first set
+    Q = float(np.sum(s["f"] ** 2)) / nrhs          # per right-hand side
+    common = dict(kernel="stokeslet", periodicity=3, box=(1.0, 1.0, 1.0), tol=args.tol, tol_kind=se.TOL_REL,
+                  n_src=n, source_q=Q, precision=se.PREC_FP64)
 
-    def step():
+    # ---- plain: analytic parameters (Sec. 4.6 with the paper's table values), one rhs
+    plan = se.Plan(safety=args.safety, n_rc=args.nrc, pollution=args.pollution, **common)
+    u0 = torch.empty((n, 3), dtype=torch.float64, device=dev)
+
+    def plain_step():
         plan.set_geometry(x)
-        plan.execute(f, out=u)
+        plan.execute(f0, out=u0)
 
     for _ in range(args.warmup):
-        step()
+        plain_step()
     torch.cuda.synchronize()
     plan.sync()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        step()
+        plain_step()
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    value = nrhs * n / (ms_per_step * 1e-3)
+    plain_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    plain_par = plan.params
 
-    # live per-phase durations (HIP events on the execution stream)
-    plan.set_timing(True)
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    phases = plan.phase_times()
-    plan.set_timing(False)
+    # ---- learned + batched: learned parameters, nrhs sets on the shared
+    # geometry, the evaluation replayed as one HIP graph on a side stream
+    batch = se.Batch([dict(selector=se.SELECT_LEARNED, n_rhs=nrhs, **common)])
+    bplan = batch.plans[0]
+    fb = f if nrhs > 1 else f0
+    ub = torch.empty_like(fb)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+
+    def batched_step():
+        batch.set_geometry([x], stream=side)
+        batch.execute([fb], [ub], stream=side)
+
+    with torch.cuda.stream(side):
+        for _ in range(max(1, args.warmup)):
+            batched_step()
+    side.synchronize()
+    bplan.sync()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(side):
+        for _ in range(args.steps):
+            batched_step()
+    side.synchronize()
+    ms_per_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    value = nrhs * n / (ms_per_step * 1e-3)
+    plain_value = n / (plain_ms * 1e-3)
+    par = bplan.params
+
+    # live per-phase durations of the same kernels (eager launches with HIP
+    # events on the launch stream; a replayed graph carries no events)
+    bplan.set_timing(True)
+    with torch.cuda.stream(side):
+        for _ in range(args.steps):
+            bplan.set_geometry(x, stream=side)
+            bplan.execute(fb, out=ub, stream=side)
+    side.synchronize()
+    phases = bplan.phase_times()
+    bplan.set_timing(False)
+    slots = 2 if nrhs >= 2 else 1  # right-hand sides per chunk of the phases (stokeslet)
     per_launch = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in phases.items()}
     dom = max((k for k in per_launch if k not in ("geometry",)), key=lambda k: per_launch[k])
     rl = roofline_for(dom, per_launch[dom], par, n, n, 3, True, slots=slots)
@@ -198,14 +231,13 @@ def main():
         del a, b
 
     cpu = None
-    err_sample = None
+    err_plain = err_batched = None
     if args.cpu_sample > 0:
         import oracle
         oracle.build(force=False)
         idx = np.sort(W.rng(args.seed + 1).choice(n, args.cpu_sample, replace=False))
         c0 = time.perf_counter()
-        f0 = s["f"] if nrhs == 1 else s["f"][0]
-        ref = oracle.ewald(3, "stokeslet", [1.0, 1.0, 1.0], s["x"], f=f0, targets=s["x"][idx],
+        ref = oracle.ewald(3, "stokeslet", [1.0, 1.0, 1.0], s["x"], f=s["f"][0], targets=s["x"][idx],
                            self_src=idx)
         c1 = time.perf_counter()
         cores = os.cpu_count()
@@ -220,8 +252,12 @@ def main():
                "kind": "oracle",
                "sample": "%d of %d targets (all %d sources), FP64 classical Ewald, xi_o=%.3f, %.1f s"
                          % (args.cpu_sample, n, n, ref["xi"], c1 - c0)}
-        ug = (u.cpu().numpy() if nrhs == 1 else u[0].cpu().numpy())[idx]
-        err_sample = oracle.rms_rel_error(ug, ref.total)
+        err_plain = oracle.rms_rel_error(u0.cpu().numpy()[idx], ref.total)
+        ub0 = ub[0] if nrhs > 1 else ub
+        err_batched = oracle.rms_rel_error(ub0.cpu().numpy()[idx], ref.total)
+
+    def pdesc(p):
+        return {"xi": round(p["xi"], 4), "rc": round(p["rc"], 5), "M": p["M"], "P": p["P"]}
 
     out = {
         "metric": "targets/sec at 1e-8 rms-rel err, N=1M TP stokeslet; learned+batched vs plain",
@@ -237,17 +273,19 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "triply periodic stokeslet, unit cube, N=1e6 uniform sources = targets, "
-                               "f~N(0,1)^3 zero mean, tol 1e-8 rms-rel (analytic parameters, N_rc re-tuned for the GPU, "
-                               "%d rhs on the shared geometry, FP64)" % nrhs,
-                   "form": "plain" if nrhs == 1 else "batched", "n_rhs": nrhs,
-                   "xi": round(par["xi"], 4), "rc": round(par["rc"], 5), "M": par["M"],
-                   "P": par["P"], "safety": args.safety, "n_rc": args.nrc or 400.0,
-                   "pollution_rule": ["h/1.05,P+4", "h/1.1,P+2"][args.pollution]},
+                               "f~N(0,1)^3 zero mean, tol 1e-8 rms-rel, FP64; learned parameters, %d strength "
+                               "sets on the shared geometry, one replayed HIP graph per step" % nrhs,
+                   "form": "learned+batched", "n_rhs": nrhs, "learned": pdesc(par),
+                   "plain": dict(pdesc(plain_par), safety=args.safety, n_rc=args.nrc or 400.0,
+                                 pollution_rule=["h/1.05,P+4", "h/1.1,P+2"][args.pollution])},
+        "plain": {"value": round(plain_value, 1), "ms_per_step": round(plain_ms, 4),
+                  "err_rms_rel_sample": err_plain},
+        "speedup_vs_plain": round(value / plain_value, 4),
+        "err_rms_rel_sample": err_batched,
         "phases_ms": {k: round(v, 4) for k, v in per_launch.items()},
         "phases_roofline": phase_frac,
         "roofline": roof,
         "cpu_baseline": cpu,
-        "err_rms_rel_sample": err_sample,
     }
     print(json.dumps(out))
 

@@ -218,7 +218,8 @@ se_status se_debug_cell_list(const se_plan* plan, int32_t which, const int32_t**
  * eagerly, then records the same sequence into a HIP graph (relaxed stream
  * capture, no memset nodes) and later calls with the same pointers replay
  * that graph as one launch.  A null stream always runs eagerly.  The graph
- * is dropped by se_batch_set_geometry, se_batch_tune and pointer changes.
+ * is dropped by se_batch_tune, new launch shapes and pointer changes; it stays
+ * valid across se_batch_set_geometry, which rewrites the plans' own buffers.
  * Arrays of pointers are host arrays of n_sys device pointers, laid out as
  * for the single-system calls.  Errors: as the single-system calls; a
  * failing system stops the call and reports its status. */
@@ -249,11 +250,12 @@ se_status se_plan_get_shape(const se_plan* plan, int32_t* real_tb, int32_t* fft_
  * before the normalisation stored with the weights): log10 N, ln(L_max/L_min),
  * one-hot periodicity D = 0..3, one-hot kernel (stokeslet, rotlet, stresslet),
  * log10 of the rms-relative tolerance.  Outputs: ln(xi Lc), ln(Lc/h), P and
- * ln(xi rc), with Lc = (L1 L2 L3)^(1/3) and h the target grid spacing; the
- * rest of the parameters follow by steps 5-7 of Sec. 4.6.  A proposal is
- * rejected if a truncation estimate of Sec. 4 at the completed parameters
- * exceeds ten times the tolerance (the estimates are within a factor 10 of
- * the measured error); then, and when no weights are
+ * ln(xi rc), with Lc = (L1 L2 L3)^(1/3) and h the grid spacing.  The
+ * proposed xi is kept; the steps of Sec. 4.6 (fine pollution rule) at that
+ * xi, over safety factors 0.2 .. 50, give a family of parameter sets, and the
+ * member nearest to the proposed (rc, h, P) is used.  It is
+ * rejected if an estimate exceeds ten times the tolerance (the estimates are
+ * within a factor 10 of the measured error); then, and when no weights are
  * loaded, selection falls back to SE_SELECT_ANALYTIC (se_plan_last_message
  * says which was used).  Weights are process-wide: the latest of
  * se_selector_train / se_selector_load, else the file named by the environment

@@ -587,7 +587,6 @@ se_status se_set_geometry(se_plan* plan, const double* src_xyz, const double* nr
     hipStream_t s = (hipStream_t)stream;
     if (hipSetDevice(plan->device) != hipSuccess) return SE_ERR_HIP;
     plan->have_geometry = false;
-    plan->geom_gen++;
     se_status st;
     {
         PhaseScope ps(plan, 0, s);

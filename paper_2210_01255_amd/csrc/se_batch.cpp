@@ -19,7 +19,7 @@ struct se_batch {
     int device = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    std::vector<uintptr_t> key;  // stream, pointers, geometry bindings and launch shapes the graph holds
+    std::vector<uintptr_t> key;  // stream, pointers and launch shapes the graph holds
 };
 
 namespace {
@@ -135,7 +135,8 @@ se_status se_batch_set_geometry(se_batch* b, const double* const* src, const dou
 {
     if (!b || !src) return SE_ERR_ARG;
     if (hipSetDevice(b->device) != hipSuccess) return SE_ERR_HIP;
-    drop_graph(b);
+    // binding rewrites the plans' own cell lists and sorted copies in place:
+    // a recorded graph stays valid
     for (size_t i = 0; i < b->plans.size(); i++) {
         se_status st = se_set_geometry(b->plans[i], src[i], nrm ? nrm[i] : nullptr, tgt ? tgt[i] : nullptr, stream);
         if (st != SE_OK) return st;
@@ -153,13 +154,12 @@ se_status se_batch_execute(se_batch* b, const double* const* f, double* const* u
     if (!s) return run_eager(b, f, u, s);
 
     std::vector<uintptr_t> key;
-    key.reserve(5 * b->plans.size() + 1);
+    key.reserve(4 * b->plans.size() + 1);
     key.push_back((uintptr_t)stream);
     for (size_t i = 0; i < b->plans.size(); i++) {
         const se_plan* p = b->plans[i];
         key.push_back((uintptr_t)f[i]);
         key.push_back((uintptr_t)u[i]);
-        key.push_back((uintptr_t)p->geom_gen);
         key.push_back((uintptr_t)p->shape_real_tb);
         key.push_back((uintptr_t)p->shape_fft_cols);
     }

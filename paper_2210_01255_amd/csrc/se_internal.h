@@ -83,7 +83,6 @@ struct se_plan {
     int ncomp = 3;   // gridded components (3, or 6 for the symmetrised stresslet source)
     int nrhs = 1;
     int rb = 1;      // right-hand sides per chunk (buffers hold rb slots)
-    uint64_t geom_gen = 0;   // counts geometry bindings (recorded graphs depend on them)
     int shape_real_tb = 0;   // launch-shape knobs (0: automatic), see se_plan_set_shape
     int shape_fft_cols = 0;
     bool fp32 = false;

@@ -172,9 +172,9 @@ bool features(const se_problem* p, float* x)
 }  // namespace
 
 // Learned path of parameter selection.  The network proposes (xi, h, P, rc)
-// for the problem; steps 5-7 of Sec. 4.6 complete them, and the proposal is
-// kept unless one of the real-space, Fourier and window estimates of Sec. 4 at
-// the completed parameters exceeds ten times the tolerance.
+// for the problem; xi is kept, the other three pick one safety factor for the
+// steps of Sec. 4.6, and the result is rejected if one of the real-space,
+// Fourier and window estimates of Sec. 4 exceeds ten times the tolerance.
 se_status se_select_learned(const se_problem* p, se_params* out, std::string* msg)
 {
     auto fallback = [&](const char* why) {
@@ -206,20 +206,41 @@ se_status se_select_learned(const se_problem* p, se_params* out, std::string* ms
         if (!std::isfinite(v)) return fallback("non-finite proposal");
     const double Lc = std::cbrt(p->box[0] * p->box[1] * p->box[2]);
     const double xi = std::exp((double)y[0]) / Lc;
-    // FP32 outputs: a spacing L/M read back lies within a few ulp of the grid
-    // boundary; the slack keeps it from rounding up to the next grid size
-    const double h = Lc / std::exp((double)y[1]) * (1.0 + 1e-5);
-    int P = 2 * (int)std::lround((double)y[2] / 2.0);
-    P = std::max(4, std::min(P, SE_MAX_P));
+    const double h = Lc / std::exp((double)y[1]);
+    const double Pp = std::max(4.0, std::min((double)y[2], (double)SE_MAX_P));
     const double rc = std::exp((double)y[3]) / xi;
+    if (!(xi > 0) || !(h > 0) || !(rc > 0)) return fallback("proposal out of range");
+    // The analytic steps of Sec. 4.6 (fine pollution rule) at the proposed xi
+    // form a one-parameter family in the safety factor; the member nearest to
+    // the proposed (rc, h, P), each difference weighted by the typical error
+    // of that output on held-out problems, is the parameter set.  So the
+    // real-space, Fourier and window parts always come from one consistent
+    // accuracy target, and a proposal that is itself such a member maps back
+    // to it.
     se_problem q = *p;
-    q.safety = 1.0;  // the estimates are checked against the tolerance itself
+    q.xi = xi;
+    q.pollution = SE_POLLUTION_FINE;
     se_params par;
     std::string m2;
-    if (se_complete_params(&q, xi, rc, h, P, &par, &m2) != SE_OK) return fallback("proposal not completed");
+    double best = 1e300;
+    for (int k = 0; k <= 64; k++) {
+        q.safety = 0.2 * std::pow(250.0, k / 64.0);  // 0.2 .. 50
+        se_params a;
+        if (se_select_params(&q, nullptr, &a, &m2) != SE_OK) continue;
+        double ha = 1e300;
+        for (int d = 0; d < 3; d++)
+            if (d < p->periodicity || p->periodicity == 0) ha = std::min(ha, a.h[d]);
+        const double dr = std::log(a.rc / rc) / 0.04, dh = std::log(ha / h) / 0.12, dp = (a.P - Pp) / 0.7;
+        const double dist = dr * dr + dh * dh + dp * dp;
+        if (dist < best) {
+            best = dist;
+            par = a;
+        }
+    }
+    if (!(best < 1e300)) return fallback("analytic completion failed");
     // the estimates are within a factor 10 of the measured error (Sec. 4):
-    // a proposal they put above 10 tol cannot meet tol
-    const double lim = 10.0 * par.tau_abs;
+    // a parameter set they put above 10 tol cannot meet tol
+    const double lim = 10.0 * p->tol * par.U;
     if (par.est_real > lim || par.est_fourier > lim || par.est_window > lim)
         return fallback("estimates above ten times the tolerance");
     *out = par;

@@ -18,6 +18,7 @@ runs of the method itself:
 Command line (GPU):
     python -m paper_2210_01255_amd.selector generate --seed 0 --first 0 --count 100 --out runs0.npz
     python -m paper_2210_01255_amd.selector train --runs runs0.npz runs1.npz --out weights.bin
+    python -m paper_2210_01255_amd.selector evaluate --weights weights.bin --random 40
 """
 from __future__ import annotations
 
@@ -174,6 +175,53 @@ def _save_runs(rows, out_path):
     return arr
 
 
+def evaluate(problems, seed=0, reps=3, plain_safety=10.0):
+    """Plain (analytic, Table 3 n_rc, the paper's pollution rule, safety
+    plain_safety) against learned parameters on each (N, D, kernel, box, tol):
+    measured time of se_set_geometry + se_execute and rms-relative error
+    against a reference at a much tighter tolerance.  Returns a list of dicts."""
+    import torch
+    from . import SELECT_LEARNED
+    dev = torch.device("cuda:0")
+    rows = []
+    for i, (N, D, kernel, box, tol) in enumerate(problems):
+        g = np.random.default_rng([seed, 7919, i])
+        box = np.asarray(box, dtype=np.float64)
+        x, s, nu, Q = _system(g, int(N), D, kernel, box)
+        xd, sd = torch.tensor(x, device=dev), torch.tensor(s, device=dev)
+        nud = torch.tensor(nu, device=dev) if nu is not None else None
+        common = dict(kernel=kernel, periodicity=D, box=tuple(box), n_src=int(N), source_q=Q, precision=PREC_FP64)
+        ref_plan = Plan(tol=max(min(tol * 1e-3, 1e-11), 1e-13), safety=10.0, **common)
+        ref_plan.set_geometry(xd, nud)
+        ref = ref_plan.execute(sd)
+        ref_plan.sync()
+        del ref_plan
+        rnorm = torch.linalg.vector_norm(ref).item()
+        out = torch.empty_like(ref)
+        row = dict(N=int(N), D=D, kernel=kernel, aspect=float(box.max() / box.min()), tol=tol)
+        for name, kw in (("plain", dict(safety=plain_safety, pollution=POLLUTION_PAPER)),
+                         ("learned", dict(selector=SELECT_LEARNED))):
+            plan = Plan(tol=tol, **kw, **common)
+            gms, ems = _timed(plan, xd, sd, nud, out, reps)
+            plan.sync()
+            row[name + "_ms"] = gms + ems
+            row[name + "_err"] = torch.linalg.vector_norm(out - ref).item() / rnorm
+            row[name + "_M"] = list(plan.params["M"])
+            row[name + "_P"] = plan.params["P"]
+            if name == "learned":
+                row["learned_msg"] = plan.message
+            del plan
+        print("eval %d N=%d D=%d k=%d aspect=%.2f tol=%.0e: plain %.3f ms err %.2e | learned %.3f ms err %.2e (%s)" %
+              (i, N, D, kernel, row["aspect"], tol, row["plain_ms"], row["plain_err"], row["learned_ms"],
+               row["learned_err"], row["learned_msg"]), flush=True)
+        rows.append(row)
+        torch.cuda.empty_cache()
+    return rows
+
+
+METRIC_PROBLEMS = [(1_000_000, D, 0, (1.0, 1.0, 1.0), tol) for D in (3, 0) for tol in (1e-4, 1e-6, 1e-8, 1e-10)]
+
+
 def load_runs(paths):
     parts = [np.load(p) for p in paths]
     return {k: np.concatenate([p[k] if k in p.files else np.zeros(len(p["problem"])) for p in parts])
@@ -198,7 +246,7 @@ def labels(runs, margin=0.5):
     return np.array(X, dtype=np.float32), np.array(Y, dtype=np.float32), np.array(ids)
 
 
-def train(X, Y, epochs=3000, batch=64, lr=2e-3, seed=1, device=0):
+def train(X, Y, epochs=150, batch=64, lr=1e-3, seed=1, device=0):
     """se_selector_train; returns the per-epoch loss."""
     X = np.ascontiguousarray(X, dtype=np.float32)
     Y = np.ascontiguousarray(Y, dtype=np.float32)
@@ -252,14 +300,30 @@ def main(argv=None):
     t = sub.add_parser("train")
     t.add_argument("--runs", nargs="+", required=True)
     t.add_argument("--out", required=True)
-    t.add_argument("--epochs", type=int, default=3000)
+    t.add_argument("--epochs", type=int, default=150)
     t.add_argument("--batch", type=int, default=64)
-    t.add_argument("--lr", type=float, default=2e-3)
+    t.add_argument("--lr", type=float, default=1e-3)
     t.add_argument("--margin", type=float, default=0.5)
     t.add_argument("--seed", type=int, default=1)
+    ev = sub.add_parser("evaluate")
+    ev.add_argument("--weights", default=None)
+    ev.add_argument("--random", type=int, default=0, help="held-out random problems (seed 1) besides the N=1e6 set")
     a = ap.parse_args(argv)
     if a.cmd == "generate":
         generate(a.seed, a.first, a.count, a.out, a.max_seconds)
+        return 0
+    if a.cmd == "evaluate":
+        if a.weights:
+            load(a.weights)
+        probs = list(METRIC_PROBLEMS)
+        g = np.random.default_rng(1)
+        probs += [sample_problem(g) for _ in range(a.random)]
+        rows = evaluate(probs)
+        tp = sum(r["plain_ms"] for r in rows)
+        tl = sum(r["learned_ms"] for r in rows)
+        bad = [r for r in rows if r["learned_err"] > r["tol"]]
+        print("total plain %.1f ms, learned %.1f ms (x%.2f); learned above tol: %d of %d" %
+              (tp, tl, tp / tl, len(bad), len(rows)), flush=True)
         return 0
     runs = load_runs(a.runs)
     X, Y, ids = labels(runs, a.margin)

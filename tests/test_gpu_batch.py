@@ -111,6 +111,28 @@ def test_batch_graph_replays_match_eager_and_oracle(env):
         for u0, o in zip(eager, outs2):
             assert oracle.rms_rel_error(o.cpu().numpy(), u0) <= 1e-12
 
+    # new positions bound in place: the recorded graph replays on them
+    moved = []
+    for s in systems:
+        s2 = dict(s)
+        s2["x"] = np.mod(s["x"] + 0.137 * s["box"][None, :], s["box"][None, :])
+        moved.append(s2)
+    x2 = _dev(env, moved, "x")
+    st.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(st):
+        b.set_geometry(x2, stream=st)
+        b.execute(f, outs2, stream=st)  # same pointers: graph replay
+    st.synchronize()
+    for s2, o, p in zip(moved, outs2, b.plans):
+        single = se.Plan(**_problem(s2, "stokeslet", tol))
+        single.set_geometry(torch.tensor(s2["x"], device="cuda:0"))
+        u = single.execute(torch.tensor(s2["f"], device="cuda:0"))
+        single.sync()
+        assert oracle.rms_rel_error(o.cpu().numpy(), u.cpu().numpy()) <= 1e-12
+    with torch.cuda.stream(st):
+        b.set_geometry(x, stream=st)
+    st.synchronize()
+
     # each member equals a single plan of the same problem
     for s, u0, p in zip(systems, eager, b.plans):
         single = se.Plan(**_problem(s, "stokeslet", tol))

@@ -160,33 +160,83 @@ def test_train_predict_save_load(env, tmp_path, restore_selector):
 
 def test_learned_path_completes_a_proposal_like_the_analytic_procedure(env, tmp_path, restore_selector):
     """A network whose output is a constant, the outputs of an analytic
-    parameter set, makes the learned path return that parameter set (same
-    xi, rc, P and grids); a constant proposal whose estimates exceed the
-    tolerance falls back to the analytic parameters."""
+    parameter set (fine pollution rule, safety 3), makes the learned path
+    return that set: same xi, and the implied safety factor ~3 gives the same
+    window and a grid and cut-off within one rounding step.  A proposal whose
+    grid exceeds the FFT limits falls back to the analytic parameters."""
     se, mlp, torch = env
     from paper_2210_01255_amd import selector as S
     import importlib
     abi = importlib.import_module("test_library_abi")
+    theta = np.zeros(se.MLP_NPARAM, dtype=np.float32)
+    p = str(tmp_path / "c.bin")
     for D, kernel, box, tol in [(3, 0, (1, 1, 1), 1e-8), (0, 0, (1, 2, 1), 1e-6), (2, 2, (1, 1, 1.5), 1e-7),
                                 (1, 1, (2.5, 1, 1), 1e-5)]:
-        kw = dict(kernel=kernel, periodicity=D, box=box, tol=tol, n_src=20000, safety=3.0)
-        ref = se.select_params(pollution=se.POLLUTION_FINE, **kw)
+        kw = dict(kernel=kernel, periodicity=D, box=box, tol=tol, n_src=20000)
+        ref = se.select_params(pollution=se.POLLUTION_FINE, safety=3.0, **kw)
         hmin = min(ref["h"][i] for i in range(3) if (i < D or D == 0))
         y = S.targets_of(ref["xi"], hmin, ref["P"], ref["rc"], np.array(box, dtype=float))
-        theta = np.zeros(se.MLP_NPARAM, dtype=np.float32)
-        norm = np.concatenate([np.zeros(10), np.ones(10), y, np.ones(4)]).astype(np.float32)
-        p = str(tmp_path / "c.bin")
-        abi._weights_file(p, theta, norm)
+        abi._weights_file(p, theta, np.concatenate([np.zeros(10), np.ones(10), y, np.ones(4)]).astype(np.float32))
         S.load(p)
         got = se.select_params(selector=se.SELECT_LEARNED, **kw)
+        print(D, kernel, "ref", ref["M"], ref["P"], ref["rc"], "learned", got["M"], got["P"], got["rc"],
+              ref["tau_abs"] / got["tau_abs"], flush=True)
         assert abs(got["xi"] - ref["xi"]) <= 1e-5 * ref["xi"]
-        assert abs(got["rc"] - ref["rc"]) <= 1e-5 * ref["rc"]
-        assert got["P"] == ref["P"] and got["M"] == ref["M"] and got["n_fft"] == ref["n_fft"]
-        # a proposal with half the window support: the window estimate exceeds tol -> analytic
-        y2 = y.copy()
-        y2[2] = 4.0
-        abi._weights_file(p, theta, np.concatenate([np.zeros(10), np.ones(10), y2, np.ones(4)]).astype(np.float32))
-        S.load(p)
-        plan = se.Plan(selector=se.SELECT_LEARNED, **kw)
-        assert "analytic" in plan.message, plan.message
-        assert plan.params == se.select_params(**kw)
+        assert abs(got["rc"] - ref["rc"]) <= 0.03 * ref["rc"]
+        assert got["P"] == ref["P"]
+        assert all(abs(a - b) <= 0.1 * b for a, b in zip(got["M"], ref["M"]))
+    kw = dict(kernel=0, periodicity=3, box=(1, 1, 1), tol=1e-8, n_src=20000)
+    y = np.array([np.log(2000.0), np.log(4000.0), 12.0, np.log(4.0)], dtype=np.float32)
+    abi._weights_file(p, theta, np.concatenate([np.zeros(10), np.ones(10), y, np.ones(4)]).astype(np.float32))
+    S.load(p)
+    plan = se.Plan(selector=se.SELECT_LEARNED, **kw)
+    assert "analytic" in plan.message, plan.message
+    assert plan.params == se.select_params(**kw)
+
+
+def test_shipped_weights_beat_plain_at_equal_error(env, restore_selector):
+    """The trained selector (weights shipped beside the library) on N = 1e6
+    uniform stokeslet systems, D = 3 and D = 0, tol 1e-4 .. 1e-10: every
+    learned run meets its tolerance against a reference at 1e-3 tol (itself
+    checked against the oracle on sampled targets below), and the learned
+    parameters take less total time than the plain analytic ones (Table 3
+    n_rc, the paper's pollution rule, safety 10)."""
+    se, mlp, torch = env
+    from paper_2210_01255_amd import selector as S
+    path = os.path.join(os.path.dirname(se.__file__), "se_selector_weights.bin")
+    assert os.path.exists(path), "trained weights missing"
+    S.load(path)
+    rows = S.evaluate(S.METRIC_PROBLEMS)
+    for r in rows:
+        assert r["learned_msg"] == "learned parameters", r
+        assert r["learned_err"] <= r["tol"], r
+        assert r["plain_err"] <= r["tol"], r
+    tp = sum(r["plain_ms"] for r in rows)
+    tl = sum(r["learned_ms"] for r in rows)
+    print("plain %.1f ms learned %.1f ms: x%.2f" % (tp, tl, tp / tl), flush=True)
+    assert tl < tp
+
+
+@pytest.mark.parametrize("D", [3, 0])
+def test_learned_parameters_against_oracle_sampled(env, restore_selector, D):
+    """Learned parameters at N = 1e6, tol 1e-8, against the oracle on 24
+    sampled targets."""
+    se, mlp, torch = env
+    import oracle
+    import workloads as W
+    path = os.path.join(os.path.dirname(se.__file__), "se_selector_weights.bin")
+    se.se_selector_load(path.encode())
+    n = 1_000_000
+    s = W.system(5100 + D, n, kernel="stokeslet", zero_mean=(D == 3))
+    plan = se.Plan(kernel="stokeslet", periodicity=D, tol=1e-8, n_src=n, source_q=float(np.sum(s["f"] ** 2)),
+                   selector=se.SELECT_LEARNED)
+    assert plan.message == "learned parameters"
+    plan.set_geometry(torch.tensor(s["x"], device="cuda:0"))
+    u = plan.execute(torch.tensor(s["f"], device="cuda:0")).cpu().numpy()
+    plan.sync()
+    idx = np.sort(W.rng(5200 + D).choice(n, 24, replace=False)).astype(np.int64)
+    ref = oracle.ewald(D, "stokeslet", s["box"], s["x"], f=s["f"], targets=s["x"][idx], self_src=idx)
+    ref = ref.total if D else ref["direct"]
+    err = oracle.rms_rel_error(u[idx], ref)
+    print("D=%d learned sampled err %.3g" % (D, err), flush=True)
+    assert err <= 1e-8
