@@ -215,8 +215,9 @@ se_status se_debug_cell_list(const se_plan* plan, int32_t which, const int32_t**
  * A batch owns one plan per system (same rules as se_plan_create, selector
  * ANALYTIC or LEARNED).  se_batch_execute evaluates every system on one
  * stream; the first call with a given set of pointers runs the launches
- * eagerly, then records the same sequence into a HIP graph (relaxed stream
- * capture, no memset nodes) and later calls with the same pointers replay
+ * eagerly, then records them into a HIP graph (relaxed stream capture, no
+ * memset nodes; the systems forked over four internal streams, so that they
+ * form parallel branches) and later calls with the same pointers replay
  * that graph as one launch.  A null stream always runs eagerly.  The graph
  * is dropped by se_batch_tune, new launch shapes and pointer changes; it stays
  * valid across se_batch_set_geometry, which rewrites the plans' own buffers.

@@ -14,12 +14,18 @@
 #include <cstdint>
 #include <vector>
 
+// Independent systems are recorded on up to kLanes forked streams, so the
+// graph holds them as parallel branches and small systems share the chip.
+constexpr int kLanes = 4;
+
 struct se_batch {
     std::vector<se_plan*> plans;
     int device = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<uintptr_t> key;  // stream, pointers and launch shapes the graph holds
+    hipStream_t lane[kLanes] = {};
+    hipEvent_t fork = nullptr, join[kLanes] = {};
 };
 
 namespace {
@@ -42,22 +48,45 @@ se_status run_eager(se_batch* b, const double* const* f, double* const* u, hipSt
     return SE_OK;
 }
 
-// Records every member's launches into a graph (timing events off: they
+bool make_lanes(se_batch* b)
+{
+    if (b->fork) return true;
+    if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) return false;
+    for (int l = 0; l < kLanes; l++) {
+        if (hipStreamCreateWithFlags(&b->lane[l], hipStreamNonBlocking) != hipSuccess) return false;
+        if (hipEventCreateWithFlags(&b->join[l], hipEventDisableTiming) != hipSuccess) return false;
+    }
+    return true;
+}
+
+// Records every member's launches into a graph: fork from s onto the lanes,
+// system i on lane i mod kLanes, join back on s (timing events off: they
 // would need host synchronisation inside the capture).
 se_status record(se_batch* b, const double* const* f, double* const* u, hipStream_t s)
 {
+    if (!make_lanes(b)) return SE_ERR_HIP;
     std::vector<bool> timing(b->plans.size());
     for (size_t i = 0; i < b->plans.size(); i++) {
         timing[i] = b->plans[i]->timing;
         b->plans[i]->timing = false;
     }
+    const int lanes = (int)std::min<size_t>(kLanes, b->plans.size());
     se_status st = SE_OK;
     hipGraph_t g = nullptr;
     if (hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) != hipSuccess) {
         st = SE_ERR_HIP;
     } else {
-        st = run_eager(b, f, u, s);
-        hipError_t e = hipStreamEndCapture(s, &g);
+        hipError_t e = hipEventRecord(b->fork, s);
+        for (int l = 0; l < lanes && e == hipSuccess; l++) e = hipStreamWaitEvent(b->lane[l], b->fork, 0);
+        if (e != hipSuccess) st = SE_ERR_HIP;
+        for (size_t i = 0; i < b->plans.size() && st == SE_OK; i++)
+            st = se_run_plan(b->plans[i], f[i], u[i], nullptr, nullptr, b->lane[i % lanes]);
+        for (int l = 0; l < lanes; l++) {
+            hipError_t e1 = hipEventRecord(b->join[l], b->lane[l]);
+            if (e1 == hipSuccess) e1 = hipStreamWaitEvent(s, b->join[l], 0);
+            if (e1 != hipSuccess && st == SE_OK) st = SE_ERR_HIP;
+        }
+        e = hipStreamEndCapture(s, &g);
         if (st == SE_OK && (e != hipSuccess || !g)) st = SE_ERR_HIP;
     }
     for (size_t i = 0; i < b->plans.size(); i++) b->plans[i]->timing = timing[i];
@@ -118,6 +147,11 @@ se_status se_batch_destroy(se_batch* b)
     hipSetDevice(b->device);
     hipDeviceSynchronize();
     drop_graph(b);
+    if (b->fork) hipEventDestroy(b->fork);
+    for (int l = 0; l < kLanes; l++) {
+        if (b->lane[l]) hipStreamDestroy(b->lane[l]);
+        if (b->join[l]) hipEventDestroy(b->join[l]);
+    }
     for (se_plan* p : b->plans) se_plan_destroy(p);
     delete b;
     return SE_OK;
