@@ -70,15 +70,16 @@ def source_digest(phase):
 
 
 def measured_traffic(phase):
-    """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE counter
-    runs (scaled by the copy-kernel calibration), or None when they were taken
-    on another version of the kernel's source."""
+    """HBM bytes per launch of the phase's kernel in the learned+batched form,
+    from the committed FETCH_SIZE / WRITE_SIZE counter runs (scaled by the
+    copy-kernel calibration), or None when they were taken on another version
+    of the kernel's source."""
     try:
         with open(TRAFFIC_FILE) as fh:
-            t = json.load(fh)
-    except (OSError, ValueError):
+            t = json.load(fh).get("phases", {}).get(phase)
+    except (OSError, ValueError, AttributeError):
         return None
-    if t.get("phase") != phase or t.get("source_sha") != source_digest(phase):
+    if not t or t.get("source_sha") != source_digest(phase):
         return None
     return t.get("bytes_per_launch")
 
