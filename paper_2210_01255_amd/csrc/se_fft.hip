@@ -172,75 +172,92 @@ __device__ __forceinline__ int fdiv(int a, int d, float rd, int* rem)
     return q;
 }
 
-// One out-of-place Stockham stage of radix RAD over `nl` lines of length N
-// held in LDS (src -> dst).  Line l starts at (l / lpg) * gs + (l % lpg) * ls,
-// element e at + e * es.  Each work item is one butterfly (no register arrays
-// across butterflies); with lines_fastest the line index varies fastest
-// across threads (nl must then be a power of two), otherwise the butterfly
-// index does (unit stride in LDS either way for the layouts used here).
-template <typename R, int RAD>
-__device__ __forceinline__ void stage_pp(const C<R>* __restrict__ src, C<R>* __restrict__ dst, int N, int nl, int lpg,
-                                         int gs, int ls, int es, bool lines_fastest, const C<R>* tw, int dir, int Ns)
+// Elements (lines x length) of one in-place transform call: each work item
+// then holds at most ceil(kIpElems / RAD / SE_FFT_THREADS) butterflies.
+constexpr int kIpElems = 1536;
+
+template <int RAD>
+constexpr int ip_per_thread()
 {
+    return (kIpElems / RAD + SE_FFT_THREADS - 1) / SE_FFT_THREADS;
+}
+
+// One Stockham stage of radix RAD over `nl` lines of length N held in LDS,
+// in place: every work item reads the inputs of its butterflies (at most
+// ip_per_thread<RAD>, in registers) and transforms them, the workgroup
+// synchronises, and the results are written back over the inputs.  Line l
+// starts at (l / lpg) * gs + (l % lpg) * ls, element e at + e * es.  With
+// lines_fastest the line index varies fastest across work items, otherwise the
+// butterfly index does (unit stride in LDS either way for the layouts used).
+// One buffer per line instead of a ping-pong pair: twice the lines fit the
+// LDS, so each barrier covers twice the butterflies.
+template <typename R, int RAD>
+__device__ __forceinline__ void stage_ip(C<R>* buf, int N, int nl, int lpg, int gs, int ls, int es,
+                                         bool lines_fastest, const C<R>* tw, int dir, int Ns)
+{
+    constexpr int K = ip_per_thread<RAD>();
     const int nb = N / RAD;
     const int total = nb * nl;
     const int tstride = N / (Ns * RAD);
-    const float rnb = 1.0f / (float)nb, rns = 1.0f / (float)Ns, rlpg = 1.0f / (float)lpg;
-    const int lsh = __builtin_ctz((unsigned)nl);
-    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-        int line, j;
-        if (lines_fastest) {
-            line = idx & (nl - 1);
-            j = idx >> lsh;
-        } else {
-            line = fdiv(idx, nb, rnb, &j);
-        }
-        int lr;
-        const int lq = fdiv(line, lpg, rlpg, &lr);
-        const int base = lq * gs + lr * ls;
-        int jn;
-        const int jq = fdiv(j, Ns, rns, &jn);
-        const int ts = jn * tstride;
-        C<R> v[RAD];
-        v[0] = src[base + j * es];
+    const float rnb = 1.0f / (float)nb, rns = 1.0f / (float)Ns, rlpg = 1.0f / (float)lpg, rnl = 1.0f / (float)nl;
+    C<R> v[K][RAD];
+    int ob[K];
 #pragma unroll
-        for (int r = 1; r < RAD; r++) {
-            C<R> w = tw[r * ts];
-            if (dir < 0) w.y = -w.y;
-            v[r] = cmul(src[base + (j + r * nb) * es], w);
-        }
-        dft_small<R, RAD>(v, dir);
-        const int od = jq * Ns * RAD + jn;
+    for (int k = 0; k < K; k++) {
+        const int idx = (int)threadIdx.x + k * SE_FFT_THREADS;
+        ob[k] = -1;
+        if (idx < total) {
+            int line, j;
+            if (lines_fastest) j = fdiv(idx, nl, rnl, &line);
+            else line = fdiv(idx, nb, rnb, &j);
+            int lr;
+            const int lq = fdiv(line, lpg, rlpg, &lr);
+            const int base = lq * gs + lr * ls;
+            int jn;
+            const int jq = fdiv(j, Ns, rns, &jn);
+            const int ts = jn * tstride;
+            v[k][0] = buf[base + j * es];
 #pragma unroll
-        for (int r = 0; r < RAD; r++) dst[base + (od + r * Ns) * es] = v[r];
+            for (int r = 1; r < RAD; r++) {
+                C<R> w = tw[r * ts];
+                if (dir < 0) w.y = -w.y;
+                v[k][r] = cmul(buf[base + (j + r * nb) * es], w);
+            }
+            dft_small<R, RAD>(v[k], dir);
+            ob[k] = base + (jq * Ns * RAD + jn) * es;
+        }
     }
+    __syncthreads();
+    const int ostep = Ns * es;
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        if (ob[k] >= 0) {
+#pragma unroll
+            for (int r = 0; r < RAD; r++) buf[ob[k] + r * ostep] = v[k][r];
+        }
+    }
+    __syncthreads();
 }
 
-// Full transform, alternating between the two buffers; returns the index
-// (0 or 1) of the buffer that holds the result.  The input must be complete
-// (synchronised) on entry; the result is synchronised on return.
+// Full in-place transform of nl lines (N * nl <= kIpElems).  The input must
+// be complete (synchronised) on entry; the result is synchronised on return.
 template <typename R>
-__device__ __forceinline__ int fft_pp(C<R>* b0, C<R>* b1, int N, int nl, int lpg, int gs, int ls, int es, bool lines_fastest,
-                      const C<R>* tw, int dir, const int* rad, int nrad)
+__device__ __forceinline__ void fft_ip(C<R>* buf, int N, int nl, int lpg, int gs, int ls, int es, bool lines_fastest,
+                                       const C<R>* tw, int dir, const int* rad, int nrad)
 {
-    int Ns = 1, cur = 0;
+    int Ns = 1;
     for (int s = 0; s < nrad; s++) {
         const int r = rad[s];
-        C<R>* src = cur ? b1 : b0;
-        C<R>* dst = cur ? b0 : b1;
         switch (r) {
-            case 2: stage_pp<R, 2>(src, dst, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
-            case 3: stage_pp<R, 3>(src, dst, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
-            case 4: stage_pp<R, 4>(src, dst, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
-            case 5: stage_pp<R, 5>(src, dst, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
-            case 7: stage_pp<R, 7>(src, dst, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
-            default: stage_pp<R, 8>(src, dst, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
+            case 2: stage_ip<R, 2>(buf, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
+            case 3: stage_ip<R, 3>(buf, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
+            case 4: stage_ip<R, 4>(buf, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
+            case 5: stage_ip<R, 5>(buf, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
+            case 7: stage_ip<R, 7>(buf, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
+            default: stage_ip<R, 8>(buf, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
         }
-        __syncthreads();
         Ns *= r;
-        cur ^= 1;
     }
-    return cur;
 }
 
 // radix sequence (4 bits per stage) into an LDS array
@@ -268,7 +285,6 @@ __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_x_r2c(se_fft_args a)
     C<R>* tw = (C<R>*)smem_d;
     C<R>* twp = tw + Nh;
     C<R>* b0 = twp + Nh + 1;
-    C<R>* b1 = b0 + a.lines * Nh;
     load_tw(tw, a.tw + 2 * a.tw_xh, Nh);
     load_tw(twp, a.tw + 2 * a.tw_xp, Nh + 1);
     const int64_t rows = (int64_t)a.ncomp * a.Mg[2] * a.Mg[1];
@@ -285,7 +301,8 @@ __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_x_r2c(se_fft_args a)
         b0[l * Nh + k] = {re, im};
     }
     __syncthreads();
-    const C<R>* Z = fft_pp<R>(b0, b1, Nh, nl, nl, 0, Nh, 1, false, tw, 1, s_rad, a.nrad_xh) ? b1 : b0;
+    fft_ip<R>(b0, Nh, nl, nl, 0, Nh, 1, false, tw, 1, s_rad, a.nrad_xh);
+    const C<R>* Z = b0;
     for (int i = threadIdx.x; i < nl * (Nh + 1); i += blockDim.x) {
         int l = i / (Nh + 1), k = i - l * (Nh + 1);
         C<R> zk = Z[l * Nh + (k % Nh)];
@@ -314,7 +331,6 @@ __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_x_c2r(se_fft_args a)
     C<R>* tw = (C<R>*)smem_d;
     C<R>* twp = tw + Nh;
     C<R>* b0 = twp + Nh + 1;
-    C<R>* b1 = b0 + a.lines * Nh;
     load_tw(tw, a.tw + 2 * a.tw_xh, Nh);
     load_tw(twp, a.tw + 2 * a.tw_xp, Nh + 1);
     __syncthreads();
@@ -340,7 +356,8 @@ __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_x_c2r(se_fft_args a)
         b0[l * Nh + k] = {Ap.x - Bp.y, Ap.y + Bp.x};  // A' + i B'
     }
     __syncthreads();
-    const C<R>* Z = fft_pp<R>(b0, b1, Nh, nl, nl, 0, Nh, 1, false, tw, -1, s_rad, a.nrad_xh) ? b1 : b0;
+    fft_ip<R>(b0, Nh, nl, nl, 0, Nh, 1, false, tw, -1, s_rad, a.nrad_xh);
+    const C<R>* Z = b0;
     const int M0 = a.Mg[0];
     for (int i = threadIdx.x; i < nl * Nh; i += blockDim.x) {
         int l = i / Nh, k = i - l * Nh;
@@ -363,7 +380,6 @@ __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_y(se_fft_args a, int dir
     const int Cc = a.cols;
     C<R>* tw = (C<R>*)smem_d;
     C<R>* b0 = tw + Ny;
-    C<R>* b1 = b0 + Ny * Cc;
     load_tw(tw, a.tw + 2 * a.tw_y, Ny);
     const int nbx = (a.Hx + Cc - 1) / Cc;
     int bid = se_xcd_block(blockIdx.x, gridDim.x);  // neighbouring bundles share an XCD (L2)
@@ -383,7 +399,8 @@ __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_y(se_fft_args a, int dir
         b0[y * Cc + col] = {ok ? t.x : (R)0, ok ? t.y : (R)0};
     }
     __syncthreads();
-    const C<R>* Z = fft_pp<R>(b0, b1, Ny, Cc, Cc, 0, 1, Cc, true, tw, dir, s_rad, a.nrad_y) ? b1 : b0;
+    fft_ip<R>(b0, Ny, Cc, Cc, 0, 1, Cc, true, tw, dir, s_rad, a.nrad_y);
+    const C<R>* Z = b0;
     for (int i = threadIdx.x; i < n_out * Cc; i += blockDim.x) {
         int y = i / Cc, col = i - y * Cc;
         int kx = kx0 + col;
@@ -481,7 +498,6 @@ __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_z(se_fft_args a, int dir
     const int Cc = a.cols;
     C<R>* tw = (C<R>*)smem_d;
     C<R>* b0 = tw + Nz;
-    C<R>* b1 = b0 + Nz * Cc;
     load_tw(tw, a.tw + 2 * a.tw_z, Nz);
     const int nbx = (a.Hx + Cc - 1) / Cc;
     const int blk = se_xcd_block(blockIdx.x, gridDim.x);
@@ -503,7 +519,8 @@ __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_z(se_fft_args a, int dir
         b0[i] = {ok ? t.x : (R)0, ok ? t.y : (R)0};
     }
     __syncthreads();
-    const C<R>* Z = fft_pp<R>(b0, b1, Nz, Cc, Cc, 0, 1, Cc, true, tw, dir, s_rad, a.nrad_z) ? b1 : b0;
+    fft_ip<R>(b0, Nz, Cc, Cc, 0, 1, Cc, true, tw, dir, s_rad, a.nrad_z);
+    const C<R>* Z = b0;
     for (int i = threadIdx.x; i < n_out * Cc; i += blockDim.x) {
         int z = i / Cc, col = i - z * Cc;
         int kx = kx0 + col;
@@ -512,9 +529,8 @@ __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_z(se_fft_args a, int dir
 }
 
 // Transform along z, scaling and inverse transform for one bundle of `cols`
-// kx columns at one y, all components resident in LDS.  NC + 1 column sets:
-// each component is transformed by ping-pong with the spare set, and the
-// roles follow the result (where[c] = set holding component c).
+// kx columns at one y, all components resident in LDS (NC column sets,
+// transformed in place, several components per call).
 template <typename R, int KER, int NC>
 __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_z_scale(se_fft_args a)
 {
@@ -545,41 +561,30 @@ __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_z_scale(se_fft_args a)
         sets[i] = {ok ? t.x : (R)0, ok ? t.y : (R)0};
     }
     __syncthreads();
-    int where[NC];
-    int spare = NC;
-#pragma unroll
-    for (int c = 0; c < NC; c++) {
-        const int r = fft_pp<R>(sets + c * cs, sets + spare * cs, Nz, Cc, Cc, 0, 1, Cc, true, tw, 1, s_rad, a.nrad_z);
-        where[c] = r ? spare : c;
-        spare = r ? c : spare;
-    }
+    // as many components per transform call as fit kIpElems (lines of one
+    // component are Cc adjacent columns; components are cs apart)
+    const int gc = max(1, min(NC, kIpElems / cs));
+    for (int c0 = 0; c0 < NC; c0 += gc)
+        fft_ip<R>(sets + c0 * cs, Nz, min(gc, NC - c0) * Cc, Cc, cs, 1, Cc, true, tw, 1, s_rad, a.nrad_z);
     for (int i = threadIdx.x; i < cs; i += blockDim.x) {
         int z = i / Cc, col = i - z * Cc;
         int kx = kx0 + col;
         if (kx >= a.Hx) continue;
         C<R> F[NC], U[3];
 #pragma unroll
-        for (int c = 0; c < NC; c++) F[c] = sets[where[c] * cs + i];
+        for (int c = 0; c < NC; c++) F[c] = sets[c * cs + i];
         scale_point<R, KER, NC>(a, kx, y, z, F, U);
 #pragma unroll
-        for (int j = 0; j < 3; j++) sets[where[j] * cs + i] = U[j];
+        for (int j = 0; j < 3; j++) sets[j * cs + i] = U[j];
     }
     __syncthreads();
-#pragma unroll
-    for (int c = 0; c < 3; c++) {
-        const int r = fft_pp<R>(sets + where[c] * cs, sets + spare * cs, Nz, Cc, Cc, 0, 1, Cc, true, tw, -1, s_rad,
-                                a.nrad_z);
-        if (r) {
-            const int t = where[c];
-            where[c] = spare;
-            spare = t;
-        }
-    }
+    for (int c0 = 0; c0 < 3; c0 += gc)
+        fft_ip<R>(sets + c0 * cs, Nz, min(gc, 3 - c0) * Cc, Cc, cs, 1, Cc, true, tw, -1, s_rad, a.nrad_z);
     for (int i = threadIdx.x; i < 3 * cs; i += blockDim.x) {
         int c = i / cs, rem = i - c * cs;
         int z = rem / Cc, col = rem - z * Cc;
         int kx = kx0 + col;
-        if (kx < a.Hx && z < Mz) spec[c * cstride + z * zstride + (int64_t)y * a.Hp + kx] = sets[where[c] * cs + rem];
+        if (kx < a.Hx && z < Mz) spec[c * cstride + z * zstride + (int64_t)y * a.Hp + kx] = sets[i];
     }
 }
 
@@ -658,17 +663,17 @@ template <typename R>
 int x_lines(int Nh)
 {
     const int budget = (int)(kFftLds / sizeof(C<R>)) - (2 * Nh + 1);
-    return std::max(1, budget / (2 * Nh));
+    return std::max(1, std::min(budget / Nh, kIpElems / Nh));
 }
 
 // columns per bundle for a pass holding `sets` column sets of length N plus
-// the twiddles within the LDS budget
+// the twiddles within the LDS budget, one set per in-place transform call
 template <typename R>
 int bundle_cols(int N, int sets, int cap = 16)
 {
     const int budget = (int)(kFftLds / sizeof(C<R>)) - N;
-    int c = std::max(1, std::min(cap > 0 ? cap : 16, budget / (sets * N)));
-    while (c & (c - 1)) c &= c - 1;  // power of two (line index by shift)
+    int c = std::max(1, std::min({cap > 0 ? cap : 16, budget / (sets * N), kIpElems / N}));
+    while (c & (c - 1)) c &= c - 1;  // power of two
     return c;
 }
 
@@ -685,7 +690,7 @@ void run_x_r2c(se_fft_args a, int ncomp, hipStream_t s)
     a.ncomp = ncomp;
     a.lines = x_lines<R>(Nh);
     int64_t rows = (int64_t)ncomp * a.Mg[2] * a.Mg[1];
-    size_t lds = (size_t)(2 * Nh + 1 + 2 * a.lines * Nh) * sizeof(C<R>);
+    size_t lds = (size_t)(2 * Nh + 1 + a.lines * Nh) * sizeof(C<R>);
     allow_lds(k_fft_x_r2c<R>, lds);
     hipLaunchKernelGGL(k_fft_x_r2c<R>, dim3((unsigned)((rows + a.lines - 1) / a.lines)), dim3(SE_FFT_THREADS),
                        lds, s, a);
@@ -698,7 +703,7 @@ void run_x_c2r(se_fft_args a, int ncomp, hipStream_t s)
     a.ncomp = ncomp;
     a.lines = x_lines<R>(Nh);
     int64_t rows = (int64_t)ncomp * a.Mg[2] * a.Mg[1];
-    size_t lds = (size_t)(2 * Nh + 1 + 2 * a.lines * Nh) * sizeof(C<R>);
+    size_t lds = (size_t)(2 * Nh + 1 + a.lines * Nh) * sizeof(C<R>);
     allow_lds(k_fft_x_c2r<R>, lds);
     hipLaunchKernelGGL(k_fft_x_c2r<R>, dim3((unsigned)((rows + a.lines - 1) / a.lines)), dim3(SE_FFT_THREADS),
                        lds, s, a);
@@ -707,9 +712,9 @@ void run_x_c2r(se_fft_args a, int ncomp, hipStream_t s)
 template <typename R>
 void run_y(se_fft_args a, int ncomp, int dir, hipStream_t s)
 {
-    a.cols = bundle_cols<R>(a.N[1], 2, a.cols_cap);
+    a.cols = bundle_cols<R>(a.N[1], 1, a.cols_cap);
     int nbx = (a.Hx + a.cols - 1) / a.cols;
-    size_t lds = (size_t)(a.N[1] + 2 * a.cols * a.N[1]) * sizeof(C<R>);
+    size_t lds = (size_t)(a.N[1] + a.cols * a.N[1]) * sizeof(C<R>);
     allow_lds(k_fft_y<R>, lds);
     hipLaunchKernelGGL(k_fft_y<R>, dim3((unsigned)(nbx * ncomp * a.Mg[2])), dim3(SE_FFT_THREADS), lds, s, a, dir);
 }
@@ -717,9 +722,9 @@ void run_y(se_fft_args a, int ncomp, int dir, hipStream_t s)
 template <typename R>
 void run_z_plain(se_fft_args a, int ncomp, int dir, hipStream_t s)
 {
-    a.cols = bundle_cols<R>(a.N[2], 2, a.cols_cap);
+    a.cols = bundle_cols<R>(a.N[2], 1, a.cols_cap);
     int nbx = (a.Hx + a.cols - 1) / a.cols;
-    size_t lds = (size_t)(a.N[2] + 2 * a.cols * a.N[2]) * sizeof(C<R>);
+    size_t lds = (size_t)(a.N[2] + a.cols * a.N[2]) * sizeof(C<R>);
     allow_lds(k_fft_z<R>, lds);
     hipLaunchKernelGGL(k_fft_z<R>, dim3((unsigned)(nbx * a.N[1] * ncomp)), dim3(SE_FFT_THREADS), lds, s, a, dir);
 }
@@ -743,9 +748,12 @@ template <typename R, int KER, int NC>
 void launch_z(const se_plan* p, int slot, hipStream_t s)
 {
     se_fft_args a = make_fft_args(p, NC, slot);
-    a.cols = bundle_cols<R>(p->Nfft[2], NC + 1, p->shape_fft_cols);
+    // two columns by default: the components then share transform calls
+    // (kIpElems / (2 N) of them per call), which shortens the chain of
+    // barrier-separated stages per column more than wider rows would help
+    a.cols = bundle_cols<R>(p->Nfft[2], NC, p->shape_fft_cols > 0 ? p->shape_fft_cols : 2);
     int nbx = (p->Hx + a.cols - 1) / a.cols;
-    size_t lds = (size_t)(p->Nfft[2] + (NC + 1) * a.cols * p->Nfft[2]) * sizeof(C<R>);
+    size_t lds = (size_t)(p->Nfft[2] + NC * a.cols * p->Nfft[2]) * sizeof(C<R>);
     auto kern = k_fft_z_scale<R, KER, NC>;
     allow_lds(kern, lds);
     hipLaunchKernelGGL(kern, dim3((unsigned)(nbx * p->Nfft[1])), dim3(SE_FFT_THREADS), lds, s, a);
