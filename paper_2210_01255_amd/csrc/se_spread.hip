@@ -563,23 +563,66 @@ __global__ void __launch_bounds__(SE_RT_THREADS) k_spread_rt(se_tile_args a)
     for (int base = 0; base < total; base += SE_RT_KB) {
         (void)rt_stage_batch<R, false, NC>(a, t0, nslots, total, base, s, tid);
         const int cnt = __builtin_amdgcn_readfirstlane(s.cnt[wave]);
-        // Per point, only the pairs of z planes its support meets (a
-        // wave-uniform test): the others would add zero weights.
-        for (int i = 0; i < cnt; i++) {
-            const int p = __builtin_amdgcn_readfirstlane(s.list[wave][i]);
-            const int oz = __builtin_amdgcn_readfirstlane(s.o[p][2]);
-            const R wxy = s.w[p][wxo + lx] * s.w[p][SE_RT_TX + wyo + ly];
-            R gv[NC];
+        if constexpr (NC < 6) {
+            // two points per step so that the LDS reads of the second overlap
+            // the arithmetic of the first
+            int i = 0;
+            for (; i + 1 < cnt; i += 2) {
+                const int pa = __builtin_amdgcn_readfirstlane(s.list[wave][i]);
+                const int pb = __builtin_amdgcn_readfirstlane(s.list[wave][i + 1]);
+                const R wa = s.w[pa][wxo + lx] * s.w[pa][SE_RT_TX + wyo + ly];
+                const R wb = s.w[pb][wxo + lx] * s.w[pb][SE_RT_TX + wyo + ly];
+                R ga[NC], gb[NC], za[SE_RT_TZ], zb[SE_RT_TZ];
 #pragma unroll
-            for (int c = 0; c < NC; c++) gv[c] = wxy * s.f[p][c];
+                for (int c = 0; c < NC; c++) {
+                    ga[c] = wa * s.f[pa][c];
+                    gb[c] = wb * s.f[pb][c];
+                }
 #pragma unroll
-            for (int q = 0; q < SE_RT_TZ / 2; q++) {
-                if (oz < 2 * q + 2 && oz + a.P > 2 * q) {
+                for (int z = 0; z < SE_RT_TZ; z++) {
+                    za[z] = s.w[pa][SE_RT_TX + SE_RT_TY + z];
+                    zb[z] = s.w[pb][SE_RT_TX + SE_RT_TY + z];
+                }
 #pragma unroll
-                    for (int z = 2 * q; z < 2 * q + 2; z++) {
-                        const R wz = s.w[p][SE_RT_TX + SE_RT_TY + z];
+                for (int z = 0; z < SE_RT_TZ; z++)
 #pragma unroll
-                        for (int c = 0; c < NC; c++) acc[z][c] += gv[c] * wz;
+                    for (int c = 0; c < NC; c++) {
+                        acc[z][c] += ga[c] * za[z];
+                        acc[z][c] += gb[c] * zb[z];
+                    }
+            }
+            if (i < cnt) {
+                const int p = __builtin_amdgcn_readfirstlane(s.list[wave][i]);
+                const R wxy = s.w[p][wxo + lx] * s.w[p][SE_RT_TX + wyo + ly];
+                R gv[NC];
+#pragma unroll
+                for (int c = 0; c < NC; c++) gv[c] = wxy * s.f[p][c];
+#pragma unroll
+                for (int z = 0; z < SE_RT_TZ; z++) {
+                    const R wz = s.w[p][SE_RT_TX + SE_RT_TY + z];
+#pragma unroll
+                    for (int c = 0; c < NC; c++) acc[z][c] += gv[c] * wz;
+                }
+            }
+        } else {
+            // six components: per point, only the pairs of z planes its
+            // support meets (a wave-uniform test); the others add zero weights
+            for (int i = 0; i < cnt; i++) {
+                const int p = __builtin_amdgcn_readfirstlane(s.list[wave][i]);
+                const int oz = __builtin_amdgcn_readfirstlane(s.o[p][2]);
+                const R wxy = s.w[p][wxo + lx] * s.w[p][SE_RT_TX + wyo + ly];
+                R gv[NC];
+#pragma unroll
+                for (int c = 0; c < NC; c++) gv[c] = wxy * s.f[p][c];
+#pragma unroll
+                for (int q = 0; q < SE_RT_TZ / 2; q++) {
+                    if (oz < 2 * q + 2 && oz + a.P > 2 * q) {
+#pragma unroll
+                        for (int z = 2 * q; z < 2 * q + 2; z++) {
+                            const R wz = s.w[p][SE_RT_TX + SE_RT_TY + z];
+#pragma unroll
+                            for (int c = 0; c < NC; c++) acc[z][c] += gv[c] * wz;
+                        }
                     }
                 }
             }
