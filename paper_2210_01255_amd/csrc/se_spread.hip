@@ -688,7 +688,7 @@ __device__ __forceinline__ double rt_dpp(double v)
 constexpr int kDppRor8 = 0x128, kDppHalfMirror = 0x141, kDppXor2 = 0x4E, kDppXor1 = 0xB1;
 
 template <typename R, int NCG>
-__global__ void __launch_bounds__(SE_RT_THREADS) k_gather_rt(se_tile_args a)
+__global__ void __launch_bounds__(SE_RT_THREADS, 3) k_gather_rt(se_tile_args a)
 {
     __shared__ se_rt_lds<R, NCG> s;
     const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
