@@ -408,10 +408,10 @@ __device__ __forceinline__ void eval_queue2(const se_real_args& a, const double*
 template <int KER, int RB>
 __global__ void __launch_bounds__(256) k_real2(se_real_args a, se_real2_geom bg)
 {
-    __shared__ double tab[2 * SE_RTAB_N * kRn];
+    // the radial table (5.6 KB) is read through the L1 cache rather than
+    // staged in LDS: the four waves' staging then fits three blocks per CU
+    const double* tab = a.rtab;
     __shared__ se_real2_lds<KER, RB> lds[4];
-    for (int i = threadIdx.x; i < 2 * SE_RTAB_N * kRn; i += 256) tab[i] = a.rtab[i];
-    __syncthreads();
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t blk = (int64_t)se_xcd_block(blockIdx.x, gridDim.x) * 4 + wave;
     if (blk >= bg.nblk) return;
