@@ -176,10 +176,10 @@ __device__ __forceinline__ int fdiv(int a, int d, float rd, int* rem)
 // then holds at most ceil(kIpElems / RAD / SE_FFT_THREADS) butterflies.
 constexpr int kIpElems = 1536;
 
-template <int RAD>
+template <int RAD, int E = kIpElems>
 constexpr int ip_per_thread()
 {
-    return (kIpElems / RAD + SE_FFT_THREADS - 1) / SE_FFT_THREADS;
+    return (E / RAD + SE_FFT_THREADS - 1) / SE_FFT_THREADS;
 }
 
 // One Stockham stage of radix RAD over `nl` lines of length N held in LDS,
@@ -191,11 +191,11 @@ constexpr int ip_per_thread()
 // butterfly index does (unit stride in LDS either way for the layouts used).
 // One buffer per line instead of a ping-pong pair: twice the lines fit the
 // LDS, so each barrier covers twice the butterflies.
-template <typename R, int RAD>
+template <typename R, int RAD, int E = kIpElems>
 __device__ __forceinline__ void stage_ip(C<R>* buf, int N, int nl, int lpg, int gs, int ls, int es,
                                          bool lines_fastest, const C<R>* tw, int dir, int Ns)
 {
-    constexpr int K = ip_per_thread<RAD>();
+    constexpr int K = ip_per_thread<RAD, E>();
     const int nb = N / RAD;
     const int total = nb * nl;
     const int tstride = N / (Ns * RAD);
@@ -239,9 +239,9 @@ __device__ __forceinline__ void stage_ip(C<R>* buf, int N, int nl, int lpg, int 
     __syncthreads();
 }
 
-// Full in-place transform of nl lines (N * nl <= kIpElems).  The input must
-// be complete (synchronised) on entry; the result is synchronised on return.
-template <typename R>
+// Full in-place transform of nl lines (N * nl <= E).  The input must be
+// complete (synchronised) on entry; the result is synchronised on return.
+template <typename R, int E = kIpElems>
 __device__ __forceinline__ void fft_ip(C<R>* buf, int N, int nl, int lpg, int gs, int ls, int es, bool lines_fastest,
                                        const C<R>* tw, int dir, const int* rad, int nrad)
 {
@@ -249,12 +249,12 @@ __device__ __forceinline__ void fft_ip(C<R>* buf, int N, int nl, int lpg, int gs
     for (int s = 0; s < nrad; s++) {
         const int r = rad[s];
         switch (r) {
-            case 2: stage_ip<R, 2>(buf, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
-            case 3: stage_ip<R, 3>(buf, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
-            case 4: stage_ip<R, 4>(buf, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
-            case 5: stage_ip<R, 5>(buf, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
-            case 7: stage_ip<R, 7>(buf, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
-            default: stage_ip<R, 8>(buf, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
+            case 2: stage_ip<R, 2, E>(buf, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
+            case 3: stage_ip<R, 3, E>(buf, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
+            case 4: stage_ip<R, 4, E>(buf, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
+            case 5: stage_ip<R, 5, E>(buf, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
+            case 7: stage_ip<R, 7, E>(buf, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
+            default: stage_ip<R, 8, E>(buf, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
         }
         Ns *= r;
     }
@@ -276,7 +276,7 @@ __device__ __forceinline__ void load_tw(C<R>* dst, const double* src, int n)
 // Rows of M0 reals (zero padded to N0) as N0/2 complex values, one FFT of
 // length N0/2, then the split into the half spectrum k = 0..N0/2.
 template <typename R>
-__global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_x_r2c(se_fft_args a)
+__global__ void __launch_bounds__(SE_FFT_THREADS, 4) k_fft_x_r2c(se_fft_args a)
 {
     extern __shared__ double smem_d[];
     __shared__ int s_rad[16];
@@ -322,7 +322,7 @@ __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_x_r2c(se_fft_args a)
 
 // ------------------------------------------------------------ x: half -> real
 template <typename R>
-__global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_x_c2r(se_fft_args a)
+__global__ void __launch_bounds__(SE_FFT_THREADS, 4) k_fft_x_c2r(se_fft_args a)
 {
     extern __shared__ double smem_d[];
     __shared__ int s_rad[16];
