@@ -371,7 +371,7 @@ __global__ void __launch_bounds__(SE_FFT_THREADS, 4) k_fft_x_c2r(se_fft_args a)
 // ------------------------------------------------------------ y: complex
 // A bundle of `cols` adjacent kx columns (contiguous in a row) for one (c, z).
 template <typename R>
-__global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_y(se_fft_args a, int dir)
+__global__ void __launch_bounds__(SE_FFT_THREADS, 5) k_fft_y(se_fft_args a, int dir)
 {
     extern __shared__ double smem_d[];
     __shared__ int s_rad[16];

@@ -379,7 +379,7 @@ __global__ void __launch_bounds__(SE_TILE_THREADS) k_gather(se_tile_args a)
 #define SE_RT_TZ 8
 #define SE_RT_NW (SE_RT_TX + SE_RT_TY + SE_RT_TZ)
 
-template <typename R, int NC>
+template <typename R, int NC, bool GATHER>
 struct se_rt_lds {
     double pkb[SE_MAX_P * (SE_MAX_NU + 1)];
     int run_beg[SE_RT_MAXSLOTS];
@@ -391,8 +391,8 @@ struct se_rt_lds {
     int idx[SE_RT_KB];
     int list[4][SE_RT_KB];   // per wave: the batch's points whose support meets its columns
     int cnt[4];
-    R f[SE_RT_KB][NC];       // gridding: the batch's strengths
-    double u[SE_RT_KB][NC];  // gathering: the batch's block partial sums
+    R f[GATHER ? 1 : SE_RT_KB][NC];       // gridding: the batch's strengths
+    double u[GATHER ? SE_RT_KB : 1][NC];  // gathering: the batch's block partial sums
 };
 
 // Runs of sorted points whose anchor bins lie in the block's halo: one slot
@@ -536,9 +536,9 @@ __device__ int rt_stage_batch(const se_tile_args& a, const int* t0, int nslots, 
 }
 
 template <typename R, int NC>
-__global__ void __launch_bounds__(SE_RT_THREADS) k_spread_rt(se_tile_args a)
+__global__ void __launch_bounds__(SE_RT_THREADS, 4) k_spread_rt(se_tile_args a)
 {
-    __shared__ se_rt_lds<R, NC> s;
+    __shared__ se_rt_lds<R, NC, false> s;
     const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const se_grid_geom& g = a.g;
     int t0[3], te[3];
@@ -690,7 +690,7 @@ constexpr int kDppRor8 = 0x128, kDppHalfMirror = 0x141, kDppXor2 = 0x4E, kDppXor
 template <typename R, int NCG>
 __global__ void __launch_bounds__(SE_RT_THREADS, 3) k_gather_rt(se_tile_args a)
 {
-    __shared__ se_rt_lds<R, NCG> s;
+    __shared__ se_rt_lds<R, NCG, true> s;
     const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const se_grid_geom& g = a.g;
     int t0[3], te[3];
