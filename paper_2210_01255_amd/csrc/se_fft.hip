@@ -173,8 +173,13 @@ __device__ __forceinline__ int fdiv(int a, int d, float rd, int* rem)
 }
 
 // Elements (lines x length) of one in-place transform call: each work item
-// then holds at most ceil(kIpElems / RAD / SE_FFT_THREADS) butterflies.
+// then holds at most ceil(E / RAD / SE_FFT_THREADS) butterflies.  Passes whose
+// lines are longer than kIpElems use kernels built for kIpElemsLong, the
+// longest line a plan admits; the smaller budget keeps the common kernels at
+// fewer registers.
 constexpr int kIpElems = 1536;
+constexpr int kIpElemsLong = SE_FFT_LDS_ELEMS;
+static_assert(kIpElems <= kIpElemsLong, "element budgets");
 
 template <int RAD, int E = kIpElems>
 constexpr int ip_per_thread()
@@ -275,7 +280,7 @@ __device__ __forceinline__ void load_tw(C<R>* dst, const double* src, int n)
 // ------------------------------------------------------------ x: real -> half
 // Rows of M0 reals (zero padded to N0) as N0/2 complex values, one FFT of
 // length N0/2, then the split into the half spectrum k = 0..N0/2.
-template <typename R>
+template <typename R, int E>
 __global__ void __launch_bounds__(SE_FFT_THREADS, 4) k_fft_x_r2c(se_fft_args a)
 {
     extern __shared__ double smem_d[];
@@ -301,7 +306,7 @@ __global__ void __launch_bounds__(SE_FFT_THREADS, 4) k_fft_x_r2c(se_fft_args a)
         b0[l * Nh + k] = {re, im};
     }
     __syncthreads();
-    fft_ip<R>(b0, Nh, nl, nl, 0, Nh, 1, false, tw, 1, s_rad, a.nrad_xh);
+    fft_ip<R, E>(b0, Nh, nl, nl, 0, Nh, 1, false, tw, 1, s_rad, a.nrad_xh);
     const C<R>* Z = b0;
     for (int i = threadIdx.x; i < nl * (Nh + 1); i += blockDim.x) {
         int l = i / (Nh + 1), k = i - l * (Nh + 1);
@@ -321,7 +326,7 @@ __global__ void __launch_bounds__(SE_FFT_THREADS, 4) k_fft_x_r2c(se_fft_args a)
 }
 
 // ------------------------------------------------------------ x: half -> real
-template <typename R>
+template <typename R, int E>
 __global__ void __launch_bounds__(SE_FFT_THREADS, 4) k_fft_x_c2r(se_fft_args a)
 {
     extern __shared__ double smem_d[];
@@ -356,7 +361,7 @@ __global__ void __launch_bounds__(SE_FFT_THREADS, 4) k_fft_x_c2r(se_fft_args a)
         b0[l * Nh + k] = {Ap.x - Bp.y, Ap.y + Bp.x};  // A' + i B'
     }
     __syncthreads();
-    fft_ip<R>(b0, Nh, nl, nl, 0, Nh, 1, false, tw, -1, s_rad, a.nrad_xh);
+    fft_ip<R, E>(b0, Nh, nl, nl, 0, Nh, 1, false, tw, -1, s_rad, a.nrad_xh);
     const C<R>* Z = b0;
     const int M0 = a.Mg[0];
     for (int i = threadIdx.x; i < nl * Nh; i += blockDim.x) {
@@ -370,7 +375,7 @@ __global__ void __launch_bounds__(SE_FFT_THREADS, 4) k_fft_x_c2r(se_fft_args a)
 
 // ------------------------------------------------------------ y: complex
 // A bundle of `cols` adjacent kx columns (contiguous in a row) for one (c, z).
-template <typename R>
+template <typename R, int E>
 __global__ void __launch_bounds__(SE_FFT_THREADS, 5) k_fft_y(se_fft_args a, int dir)
 {
     extern __shared__ double smem_d[];
@@ -399,7 +404,7 @@ __global__ void __launch_bounds__(SE_FFT_THREADS, 5) k_fft_y(se_fft_args a, int 
         b0[y * Cc + col] = {ok ? t.x : (R)0, ok ? t.y : (R)0};
     }
     __syncthreads();
-    fft_ip<R>(b0, Ny, Cc, Cc, 0, 1, Cc, true, tw, dir, s_rad, a.nrad_y);
+    fft_ip<R, E>(b0, Ny, Cc, Cc, 0, 1, Cc, true, tw, dir, s_rad, a.nrad_y);
     const C<R>* Z = b0;
     for (int i = threadIdx.x; i < n_out * Cc; i += blockDim.x) {
         int y = i / Cc, col = i - y * Cc;
@@ -488,7 +493,7 @@ __device__ __forceinline__ void scale_point(const se_fft_args& a, int ix, int iy
 }
 
 // Plain complex transform along z (no scaling) for `ncomp` components.
-template <typename R>
+template <typename R, int E>
 __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_z(se_fft_args a, int dir)
 {
     extern __shared__ double smem_d[];
@@ -519,7 +524,7 @@ __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_z(se_fft_args a, int dir
         b0[i] = {ok ? t.x : (R)0, ok ? t.y : (R)0};
     }
     __syncthreads();
-    fft_ip<R>(b0, Nz, Cc, Cc, 0, 1, Cc, true, tw, dir, s_rad, a.nrad_z);
+    fft_ip<R, E>(b0, Nz, Cc, Cc, 0, 1, Cc, true, tw, dir, s_rad, a.nrad_z);
     const C<R>* Z = b0;
     for (int i = threadIdx.x; i < n_out * Cc; i += blockDim.x) {
         int z = i / Cc, col = i - z * Cc;
@@ -531,7 +536,7 @@ __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_z(se_fft_args a, int dir
 // Transform along z, scaling and inverse transform for one bundle of `cols`
 // kx columns at one y, all components resident in LDS (NC column sets,
 // transformed in place, several components per call).
-template <typename R, int KER, int NC>
+template <typename R, int KER, int NC, int E>
 __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_z_scale(se_fft_args a)
 {
     extern __shared__ double smem_d[];
@@ -563,9 +568,9 @@ __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_z_scale(se_fft_args a)
     __syncthreads();
     // as many components per transform call as fit kIpElems (lines of one
     // component are Cc adjacent columns; components are cs apart)
-    const int gc = max(1, min(NC, kIpElems / cs));
+    const int gc = max(1, min(NC, E / cs));
     for (int c0 = 0; c0 < NC; c0 += gc)
-        fft_ip<R>(sets + c0 * cs, Nz, min(gc, NC - c0) * Cc, Cc, cs, 1, Cc, true, tw, 1, s_rad, a.nrad_z);
+        fft_ip<R, E>(sets + c0 * cs, Nz, min(gc, NC - c0) * Cc, Cc, cs, 1, Cc, true, tw, 1, s_rad, a.nrad_z);
     for (int i = threadIdx.x; i < cs; i += blockDim.x) {
         int z = i / Cc, col = i - z * Cc;
         int kx = kx0 + col;
@@ -579,7 +584,7 @@ __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_z_scale(se_fft_args a)
     }
     __syncthreads();
     for (int c0 = 0; c0 < 3; c0 += gc)
-        fft_ip<R>(sets + c0 * cs, Nz, min(gc, 3 - c0) * Cc, Cc, cs, 1, Cc, true, tw, -1, s_rad, a.nrad_z);
+        fft_ip<R, E>(sets + c0 * cs, Nz, min(gc, 3 - c0) * Cc, Cc, cs, 1, Cc, true, tw, -1, s_rad, a.nrad_z);
     for (int i = threadIdx.x; i < 3 * cs; i += blockDim.x) {
         int c = i / cs, rem = i - c * cs;
         int z = rem / Cc, col = rem - z * Cc;
@@ -659,11 +664,14 @@ se_fft_args make_fft_args(const se_plan* p, int ncomp, int slot)
     return a;
 }
 
+// element budget of the kernels for lines of length N
+inline int ip_budget(int N) { return N > kIpElems ? kIpElemsLong : kIpElems; }
+
 template <typename R>
 int x_lines(int Nh)
 {
     const int budget = (int)(kFftLds / sizeof(C<R>)) - (2 * Nh + 1);
-    return std::max(1, std::min(budget / Nh, kIpElems / Nh));
+    return std::max(1, std::min(budget / Nh, ip_budget(Nh) / Nh));
 }
 
 // columns per bundle for a pass holding `sets` column sets of length N plus
@@ -672,7 +680,7 @@ template <typename R>
 int bundle_cols(int N, int sets, int cap = 16)
 {
     const int budget = (int)(kFftLds / sizeof(C<R>)) - N;
-    int c = std::max(1, std::min({cap > 0 ? cap : 16, budget / (sets * N), kIpElems / N}));
+    int c = std::max(1, std::min({cap > 0 ? cap : 16, budget / (sets * N), ip_budget(N) / N}));
     while (c & (c - 1)) c &= c - 1;  // power of two
     return c;
 }
@@ -691,9 +699,9 @@ void run_x_r2c(se_fft_args a, int ncomp, hipStream_t s)
     a.lines = x_lines<R>(Nh);
     int64_t rows = (int64_t)ncomp * a.Mg[2] * a.Mg[1];
     size_t lds = (size_t)(2 * Nh + 1 + a.lines * Nh) * sizeof(C<R>);
-    allow_lds(k_fft_x_r2c<R>, lds);
-    hipLaunchKernelGGL(k_fft_x_r2c<R>, dim3((unsigned)((rows + a.lines - 1) / a.lines)), dim3(SE_FFT_THREADS),
-                       lds, s, a);
+    auto kern = Nh > kIpElems ? k_fft_x_r2c<R, kIpElemsLong> : k_fft_x_r2c<R, kIpElems>;
+    allow_lds(kern, lds);
+    hipLaunchKernelGGL(kern, dim3((unsigned)((rows + a.lines - 1) / a.lines)), dim3(SE_FFT_THREADS), lds, s, a);
 }
 
 template <typename R>
@@ -704,9 +712,9 @@ void run_x_c2r(se_fft_args a, int ncomp, hipStream_t s)
     a.lines = x_lines<R>(Nh);
     int64_t rows = (int64_t)ncomp * a.Mg[2] * a.Mg[1];
     size_t lds = (size_t)(2 * Nh + 1 + a.lines * Nh) * sizeof(C<R>);
-    allow_lds(k_fft_x_c2r<R>, lds);
-    hipLaunchKernelGGL(k_fft_x_c2r<R>, dim3((unsigned)((rows + a.lines - 1) / a.lines)), dim3(SE_FFT_THREADS),
-                       lds, s, a);
+    auto kern = Nh > kIpElems ? k_fft_x_c2r<R, kIpElemsLong> : k_fft_x_c2r<R, kIpElems>;
+    allow_lds(kern, lds);
+    hipLaunchKernelGGL(kern, dim3((unsigned)((rows + a.lines - 1) / a.lines)), dim3(SE_FFT_THREADS), lds, s, a);
 }
 
 template <typename R>
@@ -715,8 +723,9 @@ void run_y(se_fft_args a, int ncomp, int dir, hipStream_t s)
     a.cols = bundle_cols<R>(a.N[1], 1, a.cols_cap);
     int nbx = (a.Hx + a.cols - 1) / a.cols;
     size_t lds = (size_t)(a.N[1] + a.cols * a.N[1]) * sizeof(C<R>);
-    allow_lds(k_fft_y<R>, lds);
-    hipLaunchKernelGGL(k_fft_y<R>, dim3((unsigned)(nbx * ncomp * a.Mg[2])), dim3(SE_FFT_THREADS), lds, s, a, dir);
+    auto kern = a.N[1] > kIpElems ? k_fft_y<R, kIpElemsLong> : k_fft_y<R, kIpElems>;
+    allow_lds(kern, lds);
+    hipLaunchKernelGGL(kern, dim3((unsigned)(nbx * ncomp * a.Mg[2])), dim3(SE_FFT_THREADS), lds, s, a, dir);
 }
 
 template <typename R>
@@ -725,8 +734,9 @@ void run_z_plain(se_fft_args a, int ncomp, int dir, hipStream_t s)
     a.cols = bundle_cols<R>(a.N[2], 1, a.cols_cap);
     int nbx = (a.Hx + a.cols - 1) / a.cols;
     size_t lds = (size_t)(a.N[2] + a.cols * a.N[2]) * sizeof(C<R>);
-    allow_lds(k_fft_z<R>, lds);
-    hipLaunchKernelGGL(k_fft_z<R>, dim3((unsigned)(nbx * a.N[1] * ncomp)), dim3(SE_FFT_THREADS), lds, s, a, dir);
+    auto kern = a.N[2] > kIpElems ? k_fft_z<R, kIpElemsLong> : k_fft_z<R, kIpElems>;
+    allow_lds(kern, lds);
+    hipLaunchKernelGGL(kern, dim3((unsigned)(nbx * a.N[1] * ncomp)), dim3(SE_FFT_THREADS), lds, s, a, dir);
 }
 
 template <typename R>
@@ -754,7 +764,7 @@ void launch_z(const se_plan* p, int slot, hipStream_t s)
     a.cols = bundle_cols<R>(p->Nfft[2], NC, p->shape_fft_cols > 0 ? p->shape_fft_cols : 2);
     int nbx = (p->Hx + a.cols - 1) / a.cols;
     size_t lds = (size_t)(p->Nfft[2] + NC * a.cols * p->Nfft[2]) * sizeof(C<R>);
-    auto kern = k_fft_z_scale<R, KER, NC>;
+    auto kern = p->Nfft[2] > kIpElems ? k_fft_z_scale<R, KER, NC, kIpElemsLong> : k_fft_z_scale<R, KER, NC, kIpElems>;
     allow_lds(kern, lds);
     hipLaunchKernelGGL(kern, dim3((unsigned)(nbx * p->Nfft[1])), dim3(SE_FFT_THREADS), lds, s, a);
 }
