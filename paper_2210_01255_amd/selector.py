@@ -110,13 +110,15 @@ def _timed(plan, x, str_, nu, out, reps):
     return e0.elapsed_time(e1), e1.elapsed_time(e2) / reps
 
 
-def generate(seed: int, first: int, count: int, out_path: str, max_seconds: float = 1e9, reps: int = 3):
-    """Runs for problems first .. first+count-1 of the seeded problem stream."""
+def generate(seed: int, first: int, count: int, out_path: str, max_seconds: float = 1e9, reps: int = 3, ids=None):
+    """Runs for problems first .. first+count-1 of the seeded problem stream
+    (or for the listed problem ids)."""
     import torch
     dev = torch.device("cuda:0")
     t_start = time.time()
     rows = []
-    for pid in range(first, first + count):
+    pids = list(ids) if ids is not None else list(range(first, first + count))
+    for k, pid in enumerate(pids):
         if time.time() - t_start > max_seconds:
             print("time budget reached before problem %d" % pid, flush=True)
             break
@@ -164,7 +166,7 @@ def generate(seed: int, first: int, count: int, out_path: str, max_seconds: floa
         print("problem %d N=%d D=%d k=%d aspect=%.2f tol=%.1e: best %s ms (%.0f s)" %
               (pid, N, D, kernel, aspect, tol, "%.3f" % best if best else "-", time.time() - t_start), flush=True)
         torch.cuda.empty_cache()
-        if (pid - first) % 25 == 24:
+        if k % 25 == 24:
             _save_runs(rows, out_path)
     return _save_runs(rows, out_path)
 
@@ -296,6 +298,7 @@ def main(argv=None):
     g.add_argument("--first", type=int, default=0)
     g.add_argument("--count", type=int, default=10)
     g.add_argument("--max-seconds", type=float, default=1e9)
+    g.add_argument("--ids", default=None, help="comma-separated problem ids, or @file holding them")
     g.add_argument("--out", required=True)
     t = sub.add_parser("train")
     t.add_argument("--runs", nargs="+", required=True)
@@ -310,7 +313,11 @@ def main(argv=None):
     ev.add_argument("--random", type=int, default=0, help="held-out random problems (seed 1) besides the N=1e6 set")
     a = ap.parse_args(argv)
     if a.cmd == "generate":
-        generate(a.seed, a.first, a.count, a.out, a.max_seconds)
+        ids = None
+        if a.ids:
+            txt = open(a.ids[1:]).read() if a.ids.startswith("@") else a.ids
+            ids = [int(v) for v in txt.replace("\n", ",").split(",") if v.strip()]
+        generate(a.seed, a.first, a.count, a.out, a.max_seconds, ids=ids)
         return 0
     if a.cmd == "evaluate":
         if a.weights:
