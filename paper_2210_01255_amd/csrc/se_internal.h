@@ -121,6 +121,7 @@ struct se_plan {
     double* d_str4 = nullptr;      // sorted strengths AoS [ns][4] (f or q, 0)
     double* d_nrm4 = nullptr;      // sorted normals AoS [ns][4] (stresslet)
     double* d_rtab = nullptr;      // radial-function table
+    int* d_rwork = nullptr;        // real-space work offsets: target chunks per block, scanned (nbins + 1)
     double* d_ktab = nullptr;      // D = 0: truncated kernel Ahat_{R,tr} on the half spectrum
     double* d_uF = nullptr;        // [3][nt] sorted order
     double* d_uR = nullptr;        // [3][nt]
@@ -192,6 +193,10 @@ void se_launch_fft_xy_forward(const se_plan* p, int slot, hipStream_t s);
 void se_launch_fft_z_scale(const se_plan* p, int slot, hipStream_t s);
 void se_launch_fft_inverse(const se_plan* p, int slot, hipStream_t s);
 void se_launch_gather(const se_plan* p, int slot0, int nslot, hipStream_t s);
+// Work offsets of the blocked real-space sum for the bound geometry and the
+// current launch shape (two small kernels); once per evaluation, before the
+// real-space launches.
+void se_launch_real_prep(const se_plan* p, hipStream_t s);
 void se_launch_real_space(const se_plan* p, int slot0, int nslot, hipStream_t s);
 void se_launch_reductions(const se_plan* p, int slot, hipStream_t s);
 void se_fft3d_f64(const int* Mg, const int* N, const double* h, double* grid, double* spec, const double* tw,

@@ -360,7 +360,41 @@ struct se_real2_geom {
     int TB;          // target bins per block and axis
     int nbk[3];      // blocks per axis
     int64_t nblk;
+    const int* work; // exclusive scan of the blocks' 64-target chunks (nblk + 1 entries)
 };
+
+// Block ib of TB^3 target bins: its bin range per axis.
+__device__ __forceinline__ void real2_block(const se_grid_geom& g, const se_real2_geom& bg, int64_t blk, int* b0,
+                                            int* b1)
+{
+    const int ib[3] = {(int)(blk % bg.nbk[0]), (int)((blk / bg.nbk[0]) % bg.nbk[1]),
+                       (int)(blk / ((int64_t)bg.nbk[0] * bg.nbk[1]))};
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        b0[d] = ib[d] * bg.TB;
+        b1[d] = min(b0[d] + bg.TB, g.nb[d]) - 1;
+    }
+}
+
+// Work items of the blocked sum are (block, chunk of 64 targets), so that a
+// block holding a dense cluster is spread over many wavefronts: first the
+// chunk count of every block ...
+__global__ void k_real2_chunks(se_real_args a, se_real2_geom bg, int* __restrict__ cnt)
+{
+    const int64_t blk = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (blk >= bg.nblk) return;
+    const se_grid_geom& g = a.g;
+    int b0[3], b1[3];
+    real2_block(g, bg, blk, b0, b1);
+    const int tnx = b1[0] - b0[0] + 1;
+    int nt = 0;
+    for (int bz = b0[2]; bz <= b1[2]; bz++)
+        for (int by = b0[1]; by <= b1[1]; by++) {
+            const int rowbase = (bz * g.nb[1] + by) * g.nb[0];
+            nt += a.tstart[rowbase + b0[0] + tnx] - a.tstart[rowbase + b0[0]];
+        }
+    cnt[blk] = (nt + 63) / 64;
+}
 
 __device__ __forceinline__ int wave_incl_scan(int v, int lane)
 {
@@ -370,6 +404,42 @@ __device__ __forceinline__ int wave_incl_scan(int v, int lane)
         if (lane >= off) v += t;
     }
     return v;
+}
+
+// ... then their exclusive scan in place (one workgroup, tiles of 4096
+// counts: four per thread, a wavefront scan, the wavefront totals through
+// LDS, and a carry across tiles); v[n] receives the total.
+__global__ void __launch_bounds__(1024) k_scan_excl(int* __restrict__ v, int64_t n)
+{
+    __shared__ int wsum[16];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    int carry = 0;
+    for (int64_t base = 0; base < n; base += 4096) {
+        const int64_t i0 = base + 4 * (int64_t)t;
+        int x[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) x[k] = i0 + k < n ? v[i0 + k] : 0;
+        const int s4 = x[0] + x[1] + x[2] + x[3];
+        const int incl = wave_incl_scan(s4, lane);
+        if (lane == 63) wsum[wv] = incl;
+        __syncthreads();
+        int wpre = 0, tot = 0;
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+            const int ws = wsum[k];
+            wpre += k < wv ? ws : 0;
+            tot += ws;
+        }
+        int run = carry + wpre + incl - s4;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            if (i0 + k < n) v[i0 + k] = run;
+            run += x[k];
+        }
+        carry += tot;
+        __syncthreads();
+    }
+    if (t == 0) v[n] = carry;
 }
 
 template <int KER, int RB>
@@ -405,25 +475,17 @@ __device__ __forceinline__ void eval_queue2(const se_real_args& a, const double*
     wave_sync();
 }
 
+// One work item of the blocked sum: targets 64 chunk .. 64 chunk + 63 of
+// block blk against every source within rc of the block.
 template <int KER, int RB>
-__global__ void __launch_bounds__(256) k_real2(se_real_args a, se_real2_geom bg)
+__device__ __forceinline__ void real2_item(const se_real_args& a, const se_real2_geom& bg, const double* tab,
+                                           se_real2_lds<KER, RB>& L, int lane, int64_t blk, int chunk, int& coinc)
 {
-    // the radial table (5.6 KB) is read through the L1 cache rather than
-    // staged in LDS: the four waves' staging then fits three blocks per CU
-    const double* tab = a.rtab;
-    __shared__ se_real2_lds<KER, RB> lds[4];
-    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t blk = (int64_t)se_xcd_block(blockIdx.x, gridDim.x) * 4 + wave;
-    if (blk >= bg.nblk) return;
-    se_real2_lds<KER, RB>& L = lds[wave];
     const se_grid_geom& g = a.g;
-    const int ib[3] = {(int)(blk % bg.nbk[0]), (int)((blk / bg.nbk[0]) % bg.nbk[1]),
-                       (int)(blk / ((int64_t)bg.nbk[0] * bg.nbk[1]))};
     int b0[3], b1[3], a0[3], a1[3], blo[3], bhi[3];
+    real2_block(g, bg, blk, b0, b1);
 #pragma unroll
     for (int d = 0; d < 3; d++) {
-        b0[d] = ib[d] * bg.TB;
-        b1[d] = min(b0[d] + bg.TB, g.nb[d]) - 1;
         a0[d] = b0[d] * g.B[d];
         a1[d] = min((b1[d] + 1) * g.B[d], g.Mg[d]) - 1;
         blo[d] = se_floordiv(a0[d] - a.Ra[d], g.B[d]);
@@ -505,8 +567,7 @@ __global__ void __launch_bounds__(256) k_real2(se_real_args a, se_real2_geom bg)
     wave_sync();
     const int total = L.run_pre[nslots];
     const int ntarg = L.trow_pre[ntrows];
-    int coinc = 0;
-    for (int tc = 0; tc < ntarg; tc += 64) {
+    for (int tc = 64 * chunk; tc < min(ntarg, 64 * chunk + 64); tc += 64) {
         const int ft = tc + lane;
         const bool tvalid = ft < ntarg;
         int tidx = 0;
@@ -627,6 +688,37 @@ __global__ void __launch_bounds__(256) k_real2(se_real_args a, se_real2_geom bg)
             for (int k = 0; k < 3 * RB; k++) a.u[(int64_t)k * a.nt + tidx] = L.acc[k][lane];
         }
         wave_sync();
+    }
+}
+
+// The work items, in the order of the scanned offsets, are cut into eight
+// contiguous ranges, one per XCD (workgroups are dealt to the XCDs
+// round-robin), so that neighbouring blocks share an L2; the workgroups of
+// an XCD stride through its range.  The grid is sized on the host for an
+// upper bound of the item count (blocks + targets / 64) and at least 8.
+template <int KER, int RB>
+__global__ void __launch_bounds__(256) k_real2(se_real_args a, se_real2_geom bg)
+{
+    // the radial table (5.6 KB) is read through the L1 cache rather than
+    // staged in LDS: the four waves' staging then fits three blocks per CU
+    const double* tab = a.rtab;
+    __shared__ se_real2_lds<KER, RB> lds[4];
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nwg = gridDim.x, xcd = blockIdx.x % 8, idx = blockIdx.x / 8;
+    const int nx = nwg / 8 + (xcd < nwg % 8 ? 1 : 0);
+    const int64_t items = bg.work[bg.nblk];
+    const int64_t lo = items * xcd / 8, hi = items * (xcd + 1) / 8;
+    int coinc = 0;
+    for (int64_t w = lo + (int64_t)idx * 4 + wave; w < hi; w += (int64_t)nx * 4) {
+        // item w -> (block, chunk): the last block whose offset is <= w
+        // (empty blocks share their offset with the next one)
+        int64_t blk = 0, top = bg.nblk;
+        while (top - blk > 1) {
+            const int64_t mid = (blk + top) >> 1;
+            if (bg.work[mid] <= w) blk = mid;
+            else top = mid;
+        }
+        real2_item<KER, RB>(a, bg, tab, lds[wave], lane, blk, (int)(w - bg.work[blk]), coinc);
     }
     if (__ballot(coinc) && lane == 0) atomicOr(a.flags, SE_FLAG_COINCIDENT);
 }
@@ -774,6 +866,53 @@ void se_launch_reductions(const se_plan* p, int slot, hipStream_t s)
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(SE_RED_BLOCKS), 0, s, part, red);
 }
 
+namespace {
+
+void real_cutoff_bins(const se_plan* p, int Ra[3])
+{
+    for (int d = 0; d < 3; d++) Ra[d] = (int)std::ceil(p->par.rc / p->g.h[d]) + 1;
+}
+
+// Shape of the blocked real-space sum: TB^3 target bins per block (about 48
+// targets, or the plan's launch-shape knob); false when a block's candidate
+// rows or target rows overflow the kernel's staging, which leaves the
+// per-target kernel.
+bool real2_shape(const se_plan* p, const int Ra[3], se_real2_geom* bg)
+{
+    const se_grid_geom& g = p->g;
+    const int64_t nbins = (int64_t)g.nb[0] * g.nb[1] * g.nb[2];
+    const double per_bin = (double)p->nt / (double)nbins;
+    int TB = (int)std::lround(std::cbrt(48.0 / std::max(per_bin, 1e-9)));
+    if (p->shape_real_tb > 0) TB = p->shape_real_tb;
+    TB = std::max(1, std::min(TB, 4));
+    bg->TB = TB;
+    int span[3];
+    for (int d = 0; d < 3; d++) {
+        bg->nbk[d] = (g.nb[d] + TB - 1) / TB;
+        span[d] = (TB * g.B[d] + 2 * Ra[d]) / g.B[d] + 2;
+        if (!g.periodic[d]) span[d] = std::min(span[d], g.nb[d]);
+    }
+    bg->nblk = (int64_t)bg->nbk[0] * bg->nbk[1] * bg->nbk[2];
+    bg->work = p->d_rwork;
+    const int nseg = g.periodic[0] ? (span[0] + g.nb[0] - 1) / g.nb[0] + 1 : 1;
+    return (int64_t)span[1] * span[2] * nseg <= SE_R2_SLOTS && TB * TB <= SE_R2_TROWS;
+}
+
+}  // namespace
+
+void se_launch_real_prep(const se_plan* p, hipStream_t s)
+{
+    int Ra[3];
+    real_cutoff_bins(p, Ra);
+    se_real2_geom bg;
+    if (!real2_shape(p, Ra, &bg)) return;
+    se_real_args a{};
+    a.g = p->g;
+    a.tstart = p->tas ? p->d_src_start : p->d_tgt_start;
+    hipLaunchKernelGGL(k_real2_chunks, dim3(grid1d(bg.nblk, 256)), dim3(256), 0, s, a, bg, p->d_rwork);
+    hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, s, p->d_rwork, bg.nblk);
+}
+
 void se_launch_real_space(const se_plan* p, int slot0, int nslot, hipStream_t s)
 {
     se_real_args a;
@@ -790,29 +929,13 @@ void se_launch_real_space(const se_plan* p, int slot0, int nslot, hipStream_t s)
     a.xi = p->par.xi;
     a.rc2 = p->par.rc * p->par.rc;
     a.rscale = SE_RTAB_N / se_rtab_xmax(p->par);
-    for (int d = 0; d < 3; d++) a.Ra[d] = (int)std::ceil(p->par.rc / p->g.h[d]) + 1;
+    real_cutoff_bins(p, a.Ra);
     a.tas = p->tas ? 1 : 0;
     a.u = se_slot_uR(p, slot0);
     a.flags = p->d_flags;
-    // blocked kernel: TB^3 target bins per wavefront, about 48 targets
-    const se_grid_geom& g = p->g;
-    const int64_t nbins = (int64_t)g.nb[0] * g.nb[1] * g.nb[2];
-    const double per_bin = (double)p->nt / (double)nbins;
-    int TB = (int)std::lround(std::cbrt(48.0 / std::max(per_bin, 1e-9)));
-    if (p->shape_real_tb > 0) TB = p->shape_real_tb;
-    TB = std::max(1, std::min(TB, 4));
     se_real2_geom bg;
-    bg.TB = TB;
-    int span[3];
-    for (int d = 0; d < 3; d++) {
-        bg.nbk[d] = (g.nb[d] + TB - 1) / TB;
-        span[d] = (TB * g.B[d] + 2 * a.Ra[d]) / g.B[d] + 2;
-        if (!g.periodic[d]) span[d] = std::min(span[d], g.nb[d]);
-    }
-    bg.nblk = (int64_t)bg.nbk[0] * bg.nbk[1] * bg.nbk[2];
-    const int nseg = g.periodic[0] ? (span[0] + g.nb[0] - 1) / g.nb[0] + 1 : 1;
-    if ((int64_t)span[1] * span[2] * nseg <= SE_R2_SLOTS && TB * TB <= SE_R2_TROWS) {
-        unsigned nwg = (unsigned)((bg.nblk + 3) / 4);
+    if (real2_shape(p, a.Ra, &bg)) {
+        const unsigned nwg = (unsigned)std::max<int64_t>(8, (bg.nblk + (p->nt + 63) / 64 + 3) / 4);
         if (nslot == 2 && p->kernel == SE_STOKESLET)
             hipLaunchKernelGGL((k_real2<SE_STOKESLET, 2>), dim3(nwg), dim3(256), 0, s, a, bg);
         else if (nslot == 2 && p->kernel == SE_ROTLET)
