@@ -75,6 +75,16 @@ typedef int32_t se_status;
 #define SE_POLLUTION_PAPER 0 /* (h/1.1, P+2) for D = 0, (h/1.05, P+4) for D = 1, 2, 3 */
 #define SE_POLLUTION_FINE 1  /* (h/1.1, P+2) for every D: finer grid, narrower window */
 
+/* Window function of gridding and gathering.
+ * PKB: the polynomial Kaiser-Bessel window, eqs. (KB-window), (PKB-parameters),
+ *   beta = 2.5 P, scaled by the exact Fourier transform of the KB window.
+ * TG: the truncated Gaussian of Sec. 5.4 (window comparison), eq. (TG-window),
+ *   w(r) = exp(-alpha (r/a)^2) on |r| <= a = h P / 2 with alpha = 0.91 (pi/2) P,
+ *   evaluated exactly in gridding and gathering and scaled by the Fourier
+ *   transform of the untruncated Gaussian, as the paper does. */
+#define SE_WINDOW_PKB 0
+#define SE_WINDOW_TG 1
+
 /* Problem statement (Algorithm 1 inputs plus the error tolerance). */
 typedef struct se_problem {
     int32_t struct_size;      /* sizeof(se_problem) */
@@ -98,6 +108,9 @@ typedef struct se_problem {
     int32_t n_rhs;            /* strength sets sharing one geometry (>= 1) */
     int32_t device;           /* HIP device ordinal */
     int32_t pollution;        /* SE_POLLUTION_PAPER or SE_POLLUTION_FINE */
+    int32_t window;           /* SE_WINDOW_PKB (default 0) or SE_WINDOW_TG; the learned
+                                 selector covers PKB only: TG problems take the analytic
+                                 procedure, with P from 10 U e^{-alpha(P)} = tau_abs */
 } se_problem;
 
 /* Resolved method parameters (Sec. 3 and 4). */
@@ -126,7 +139,10 @@ typedef struct se_params {
     double U;            /* Fourier-part rms estimate U(L,Q,xi), eqs. (pot-mag-est-*) */
     double est_real;     /* real-space truncation estimate at rc */
     double est_fourier;  /* Fourier truncation estimate at pi/h */
-    double est_window;   /* window estimate 10 U e^{-2.5 P} */
+    double est_window;   /* window estimate: 10 U e^{-2.5 P} (PKB), 10 U e^{-alpha} (TG) */
+    int32_t window;      /* SE_WINDOW_* (always the problem's; ignored in manual parameters) */
+    int32_t pad0;
+    double alpha;        /* TG shape 0.91 (pi/2) P (0 for PKB); manual: <= 0 means that value */
 } se_params;
 
 typedef struct se_plan se_plan;

@@ -19,6 +19,8 @@ TOL_REL, TOL_ABS = 0, 1
 PREC_AUTO, PREC_FP64, PREC_FP32 = 0, 1, 2
 SELECT_ANALYTIC, SELECT_LEARNED, SELECT_MANUAL = 0, 1, 2
 POLLUTION_PAPER, POLLUTION_FINE = 0, 1
+WINDOW_PKB, WINDOW_TG = 0, 1
+WINDOWS = {"pkb": WINDOW_PKB, "tg": WINDOW_TG}
 
 SE_OK = 0
 SE_ERR_ARG, SE_ERR_UNSUPPORTED, SE_ERR_OUT_OF_BOX, SE_ERR_NONFINITE = -1, -2, -3, -4
@@ -36,7 +38,7 @@ class se_problem(ctypes.Structure):
                 ("safety", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("selector", ctypes.c_int32), ("n_src", ctypes.c_int64), ("n_tgt", ctypes.c_int64),
                 ("targets_are_sources", ctypes.c_int32), ("n_rhs", ctypes.c_int32),
-                ("device", ctypes.c_int32), ("pollution", ctypes.c_int32)]
+                ("device", ctypes.c_int32), ("pollution", ctypes.c_int32), ("window", ctypes.c_int32)]
 
 
 class se_params(ctypes.Structure):
@@ -48,7 +50,8 @@ class se_params(ctypes.Structure):
                 ("h", ctypes.c_double * 3), ("L_ext", ctypes.c_double * 3), ("dL", ctypes.c_double * 3),
                 ("R", ctypes.c_double), ("s0", ctypes.c_double), ("s_star", ctypes.c_double),
                 ("tau_abs", ctypes.c_double), ("U", ctypes.c_double), ("est_real", ctypes.c_double),
-                ("est_fourier", ctypes.c_double), ("est_window", ctypes.c_double)]
+                ("est_fourier", ctypes.c_double), ("est_window", ctypes.c_double),
+                ("window", ctypes.c_int32), ("pad0", ctypes.c_int32), ("alpha", ctypes.c_double)]
 
 
 EXPORTS = ["se_version", "se_status_string", "se_params_select", "se_plan_create", "se_plan_destroy",
@@ -208,7 +211,7 @@ se_mlp_adam = lib.se_mlp_adam
 def make_problem(kernel="stokeslet", periodicity=3, box=(1.0, 1.0, 1.0), tol=1e-8, tol_kind=TOL_REL,
                  n_src=1, n_tgt=0, targets_are_sources=True, n_rhs=1, source_q=0.0, xi=0.0, n_rc=0.0,
                  safety=0.0, precision=PREC_FP64, selector=SELECT_ANALYTIC, device=0,
-                 pollution=0) -> se_problem:
+                 pollution=0, window=WINDOW_PKB) -> se_problem:
     p = se_problem()
     p.struct_size = ctypes.sizeof(se_problem)
     p.periodicity = int(periodicity)
@@ -229,6 +232,7 @@ def make_problem(kernel="stokeslet", periodicity=3, box=(1.0, 1.0, 1.0), tol=1e-
     p.n_rhs = int(n_rhs)
     p.device = int(device)
     p.pollution = int(pollution)
+    p.window = WINDOWS[window] if isinstance(window, str) else int(window)
     return p
 
 

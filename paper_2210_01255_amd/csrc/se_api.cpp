@@ -129,7 +129,7 @@ hipError_t aft_tables(se_plan* p)
                 else if (periodic) k = twopi * (c.ky_lo + i) / p->g.L[1];
                 else k = twopi * (i < n[d] / 2 ? i : i - n[d]) / (par.h[d] * n[d]);
                 kv.push_back(k);
-                double w = se_kb_fourier(k, a, par.beta);
+                double w = se_window_fourier(par, k, a);
                 iw.push_back(1.0 / (w * w));
             }
             nv[d] = periodic ? p->Nfft[d] : n[d];
@@ -275,6 +275,7 @@ static se_status validate_problem(const se_problem* prob)
     if (prob->precision < SE_PREC_AUTO || prob->precision > SE_PREC_FP32) return SE_ERR_ARG;
     if (prob->selector < SE_SELECT_ANALYTIC || prob->selector > SE_SELECT_MANUAL) return SE_ERR_ARG;
     if (prob->pollution != SE_POLLUTION_PAPER && prob->pollution != SE_POLLUTION_FINE) return SE_ERR_ARG;
+    if (prob->window != SE_WINDOW_PKB && prob->window != SE_WINDOW_TG) return SE_ERR_ARG;
     return SE_OK;
 }
 
@@ -453,7 +454,7 @@ se_status se_plan_create(const se_problem* prob, const se_params* manual, se_pla
         for (int i = 0; i < cnt; i++) {
             int kb = (d == 0) ? i : (i < N / 2 ? i : i - N);
             double k = 2.0 * M_PI * kb / (par.h[d] * N);
-            double w = se_kb_fourier(k, a, par.beta);
+            double w = se_window_fourier(par, k, a);
             iw.push_back(1.0 / (w * w));
         }
     }

@@ -171,6 +171,12 @@ se_status se_complete_params(const se_problem* p, double xi, double rc, double h
 se_status se_select_learned(const se_problem* p, se_params* out, std::string* msg);
 bool se_smooth_factors(int n, std::vector<int>* radices);
 void se_pkb_coefficients(int P, int nu, double beta, std::vector<double>* coef);
+// Truncated-Gaussian shape 0.91 (pi/2) P, the untruncated Gaussian's Fourier
+// transform, and the transform of the plan's window (KB or UG) at k for
+// half-support a.
+double se_tg_alpha(int P);
+double se_ug_fourier(double k, double a, double alpha);
+double se_window_fourier(const se_params& par, double k, double a);
 void se_radial_table(double xmax, std::vector<double>* tab);
 // Range of the radial table: x = xi r for r < rc (slightly widened).
 inline double se_rtab_xmax(const se_params& par) { return par.xi * par.rc * (1.0 + 1e-9) + 1e-300; }

@@ -169,6 +169,21 @@ double se_kb_fourier(double k, double a, double beta)
     return (double)val;
 }
 
+double se_tg_alpha(int P) { return 0.91 * (kPi / 2.0) * P; }
+
+// Fourier transform of the untruncated Gaussian exp(-alpha (r/a)^2), used in
+// the scaling step of the truncated-Gaussian window (Sec. 5.4):
+// sqrt(pi/alpha) a exp(-k^2 a^2 / (4 alpha)).
+double se_ug_fourier(double k, double a, double alpha)
+{
+    return std::sqrt(kPi / alpha) * a * std::exp(-k * k * a * a / (4.0 * alpha));
+}
+
+double se_window_fourier(const se_params& par, double k, double a)
+{
+    return par.window == SE_WINDOW_TG ? se_ug_fourier(k, a, par.alpha) : se_kb_fourier(k, a, par.beta);
+}
+
 // PKB window (Sec. 3.3): on each of the P subintervals [l h, (l+1) h],
 // l = -P/2 .. P/2-1, interpolate the KB window at nu+1 Chebyshev points of
 // the first kind.  coef[q*(nu+1) + c] multiplies sigma^c, with
@@ -305,6 +320,9 @@ se_status se_select_params(const se_problem* p, const se_params* manual, se_para
             return SE_ERR_ARG;
         }
         if (par.beta <= 0) par.beta = 2.5 * par.P;
+        par.window = p->window;
+        if (par.window == SE_WINDOW_TG && par.alpha <= 0) par.alpha = se_tg_alpha(par.P);
+        if (par.window != SE_WINDOW_TG) par.alpha = 0.0;
         if (par.nu_deg <= 0) par.nu_deg = std::min(par.P / 2 + 2, 10);
         if (par.nu_deg > SE_MAX_NU) par.nu_deg = SE_MAX_NU;
         for (int i = 0; i < 3; i++) {
@@ -355,8 +373,11 @@ se_status se_select_params(const se_problem* p, const se_params* manual, se_para
     // step 2: grid spacing from the Fourier truncation estimate
     double kinf = solve_kinf(kernel, b, Q, xi, tau);
     double h_est = kPi / kinf;
-    // step 3: window support from 10 U exp(-2.5 P) = tau
-    double P_est = std::log(10.0 * pot_rms(kernel, b, Q, xi) / tau) / 2.5;
+    // step 3: window support from 10 U exp(-2.5 P) = tau (PKB); the truncated
+    // Gaussian decays as exp(-alpha) = exp(-0.91 (pi/2) P) at the support edge
+    // and takes the same form of estimate with that rate
+    const double rate = p->window == SE_WINDOW_TG ? se_tg_alpha(1) : 2.5;
+    double P_est = std::log(10.0 * pot_rms(kernel, b, Q, xi) / tau) / rate;
     if (P_est < 0) P_est = 0;
     // step 4: pollution rule
     const bool fine = D == 0 || p->pollution == SE_POLLUTION_FINE;
@@ -406,6 +427,8 @@ se_status se_complete_params(const se_problem* p, double xi, double rc, double h
     par.P = P;
     par.beta = 2.5 * P;
     par.nu_deg = std::min(P / 2 + 2, 10);
+    par.window = p->window;
+    par.alpha = p->window == SE_WINDOW_TG ? se_tg_alpha(P) : 0.0;
 
     // periodic axes
     double h_common = h_t;
@@ -491,7 +514,7 @@ se_status se_complete_params(const se_problem* p, double xi, double rc, double h
     double kmin = 1e300;
     for (int i = 0; i < 3; i++) kmin = std::min(kmin, kPi / par.h[i]);
     par.est_fourier = fs_pref(kernel, b, Q, xi, kmin) * std::exp(-kmin * kmin / (4.0 * xi * xi));
-    par.est_window = 10.0 * U * std::exp(-2.5 * P);
+    par.est_window = 10.0 * U * std::exp(p->window == SE_WINDOW_TG ? -par.alpha : -2.5 * P);
     *out = par;
     return SE_OK;
 }

@@ -183,6 +183,7 @@ se_status se_select_learned(const se_problem* p, se_params* out, std::string* ms
         return st;
     };
     if (p->tol_kind != SE_TOL_REL) return fallback("absolute tolerance");
+    if (p->window != SE_WINDOW_PKB) return fallback("trained for the PKB window only");
     float x[SE_MLP_IN], y[SE_MLP_OUT];
     if (!features(p, x)) return fallback("no features");
     {

@@ -31,6 +31,7 @@ struct se_tile_args {
     const int* start;   // cell starts [nbins+1]
     const double* pkb;  // [P][nu+1]
     int P, nu;
+    double tg_c;        // truncated Gaussian: exp(-tg_c d^2), d in grid units; 0: PKB
     int ntile[3];
     void* grid;         // real grid [ncomp][Mz][My][Mx]
     const void* fs;     // sorted strengths [ncomp][n] (gridding)
@@ -132,6 +133,20 @@ __device__ __forceinline__ R pkb_weight(const double* coef, int q, R s)
     return acc;
 }
 
+// Weight of grid offset q (0 .. P-1) for a point at fractional position t in
+// its anchor cell, given s = 1 - t: the PKB polynomial of subinterval q at s,
+// or the truncated Gaussian at distance d = q - P/2 + s grid spacings
+// (|d| <= P/2 there, so the support test is implied).
+template <typename R>
+__device__ __forceinline__ R win_weight(const double* coef, double tg_c, int P, int q, R s)
+{
+    if (tg_c > 0.0) {
+        const R d = (R)(q - P / 2) + s;
+        return exp(-(R)tg_c * d * d);
+    }
+    return pkb_weight<R>(coef, q, s);
+}
+
 __device__ __forceinline__ int rl_i(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
 
 // Per-wave walk over the points whose anchors lie in the block's halo: rows
@@ -231,7 +246,7 @@ __global__ void __launch_bounds__(SE_TILE_THREADS) k_spread(se_tile_args a)
             }
             const double tj0 = se_readlane(q.t[0], j), tj1 = se_readlane(q.t[1], j), tj2 = se_readlane(q.t[2], j);
             tt = dim == 0 ? tj0 : (dim == 1 ? tj1 : tj2);
-            const R w = pkb_weight<R>(s_pkb, qq, (R)(1.0 - tt));
+            const R w = win_weight<R>(s_pkb, a.tg_c, a.P, qq, (R)(1.0 - tt));
             const int nxy = ex0 * ex1;
             const int zl = lo2 - t0[2], yl = lo1 - t0[1], xl = lo0 - t0[0];
             for (int base = 0; base < nxy; base += 64) {
@@ -319,7 +334,7 @@ __global__ void __launch_bounds__(SE_TILE_THREADS) k_gather(se_tile_args a)
             }
             const double tj0 = se_readlane(q.t[0], j), tj1 = se_readlane(q.t[1], j), tj2 = se_readlane(q.t[2], j);
             const double tt = dim == 0 ? tj0 : (dim == 1 ? tj1 : tj2);
-            const R w = pkb_weight<R>(s_pkb, qq, (R)(1.0 - tt));
+            const R w = win_weight<R>(s_pkb, a.tg_c, a.P, qq, (R)(1.0 - tt));
             const int nxy = ex0 * ex1;
             const int zl = lo2 - t0[2], yl = lo1 - t0[1], xl = lo0 - t0[0];
             R acc0 = 0, acc1 = 0, acc2 = 0;
@@ -528,7 +543,7 @@ __device__ int rt_stage_batch(const se_tile_args& a, const int* t0, int nslots, 
         const int coord = dim == 0 ? j : (dim == 1 ? j - SE_RT_TX : j - SE_RT_TX - SE_RT_TY);
         const int q = coord - s.o[p][dim];
         R w = (R)0;
-        if (q >= 0 && q < a.P && s.idx[p] >= 0) w = pkb_weight<R>(s.pkb, q, (R)(1.0 - s.t[p][dim]));
+        if (q >= 0 && q < a.P && s.idx[p] >= 0) w = win_weight<R>(s.pkb, a.tg_c, a.P, q, (R)(1.0 - s.t[p][dim]));
         s.w[p][j] = w;
     }
     __syncthreads();
@@ -809,6 +824,7 @@ se_tile_args make_args(const se_plan* p, bool gather, int slot)
     a.pkb = p->d_pkb;
     a.P = p->par.P;
     a.nu = p->par.nu_deg;
+    a.tg_c = p->par.window == SE_WINDOW_TG ? 4.0 * p->par.alpha / ((double)a.P * a.P) : 0.0;
     for (int d = 0; d < 3; d++) a.ntile[d] = p->ntile[d];
     a.grid = se_slot_grid(p, slot);
     a.fs = se_slot_fs(p, slot);

@@ -198,3 +198,29 @@ def test_fft_pass_beyond_lds_is_refused_at_plan_creation():
     h = ctypes.c_void_p()
     st = se.lib.se_plan_create(ctypes.byref(prob), ctypes.byref(par), ctypes.byref(h))
     assert st == se.SE_ERR_UNSUPPORTED
+
+
+def test_truncated_gaussian_window_parameters(se):
+    """Truncated-Gaussian window (Sec. 5.4, eq. TG-window): shape alpha =
+    0.91 (pi/2) P, the same grid as the PKB window, a wider support whose
+    estimate 10 U e^{-alpha} meets tau_abs, and the analytic procedure when
+    the learned selector is asked for (it was trained on PKB runs)."""
+    for D in (3, 2, 1, 0):
+        for tol in (1e-4, 1e-6, 1e-8, 1e-10):
+            kw = dict(kernel="stokeslet", periodicity=D, tol=tol, n_src=100_000, source_q=1.0, safety=10)
+            a = se.select_params(**kw)
+            b = se.select_params(window="tg", **kw)
+            assert a["window"] == se.WINDOW_PKB and a["alpha"] == 0.0
+            assert b["window"] == se.WINDOW_TG
+            assert b["alpha"] == pytest.approx(0.91 * math.pi / 2 * b["P"], rel=1e-15)
+            assert b["xi"] == a["xi"] and b["rc"] == a["rc"]
+            # same grid on periodic axes; free axes pad by the (wider) support
+            assert b["M"][:D] == a["M"][:D]
+            assert all(b["M"][i] >= a["M"][i] for i in range(D, 3))
+            assert a["P"] <= b["P"] <= 32 and b["P"] % 2 == 0
+            assert b["est_window"] == pytest.approx(10 * b["U"] * math.exp(-b["alpha"]), rel=1e-12)
+            assert b["est_window"] <= b["tau_abs"] * (1 + 1e-12)
+            c = se.select_params(window="tg", selector=se.SELECT_LEARNED, **kw)
+            assert c == b
+    with pytest.raises(se.SEError):
+        se.select_params(kernel="stokeslet", periodicity=3, tol=1e-8, n_src=10, window=7)
