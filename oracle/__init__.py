@@ -17,6 +17,11 @@ What it computes (Bagge & Tornberg, Sec. 2):
     singular modes k^P = 0 in the closed forms of Appendices A.2 and B.2
     (``reduced_oracle.c``), reported as 'k0'.
 
+The harmonic kernel 1/|r| (Sec. 2) is carried per component: f[n][3] holds
+three independent charge sets and u[m][3] their potentials, with the
+classical Ewald split of Sec. 2.1 and, for D = 2 and 1, the classical zero
+modes in the gauges -2 pi |z| and -2 log(rho).
+
 The oracle chooses its own splitting parameter xi_o and truncations from a
 cost balance and a fixed damping margin (erfc(xi rc) and exp(-k^2/4xi^2)
 both ~ e^{-36}); nothing is taken from the fast method's parameter selector.
@@ -35,7 +40,7 @@ _BUILD = os.path.join(_HERE, "_build")
 _SO = os.path.join(_BUILD, "libewald_oracle.so")
 _SRCS = ["ewald_oracle.c", "reduced_oracle.c"]
 
-KERNELS = {"stokeslet": 0, "rotlet": 1, "stresslet": 2}
+KERNELS = {"stokeslet": 0, "rotlet": 1, "stresslet": 2, "harmonic": 3}
 
 
 def build(force: bool = True) -> str:
@@ -206,6 +211,11 @@ def ewald(D, kernel, box, x, f=None, q=None, nu=None, targets=None, self_src=Non
     u0 = np.zeros((nt, 3))
     if D == 3 and kernel == "stresslet":
         L.oracle_k0_stresslet_3p(_d(box), ns, _d(x), _d(a), _d(b), nt, _d(xt), _d(u0))
+    elif D == 3 and kernel == "harmonic":
+        # uniform neutralising background of each charge set: the k -> 0
+        # limit of (4 pi/k^2)(gammaE - 1) Q/V = -pi Q / (V xi^2)
+        V = float(box[0]) * float(box[1]) * float(box[2])
+        u0[:] = -math.pi / (V * float(xi) ** 2) * np.sum(a, axis=0)[None, :]
     elif D in (1, 2):
         L.oracle_zero_mode(D, kid, _d(box), float(xi), ns, _d(x), _d(a), _d(b) if b is not None else None,
                            nt, _d(xt), _d(u0))

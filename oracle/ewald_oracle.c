@@ -9,6 +9,12 @@
  * with arbitrary periodicity"):
  *
  *   free-space kernels S, Omega, T ........ Sec. 2, eq. (stokes-kernels)
+ *   harmonic kernel H = 1/|r| ............. Sec. 2, applied per component
+ *                                            (three independent charge sets);
+ *                                            Sec. 2.1 split with the classical
+ *                                            screening, eq. (ewald-screening):
+ *                                            real part erfc(xi r)/r, Fourier
+ *                                            part (4 pi/k^2) gammaE
  *   real-space kernels S^R, Omega^R, T^R ... Sec. 2.1, eqs. (stokeslet-real),
  *                                            (rotlet-real), (stresslet-real)
  *   Fourier kernels (D = 3) ................ Sec. 2.1, eqs. (stokeslet-fourier),
@@ -39,6 +45,7 @@
 #define OR_STOKESLET 0
 #define OR_ROTLET 1
 #define OR_STRESSLET 2
+#define OR_HARMONIC 3
 
 static const double OR_PI = 3.14159265358979323846264338327950288;
 
@@ -75,6 +82,8 @@ void oracle_free_kernel(int kernel, const double *r, const double *f,
             for (int l = 0; l < 3; l++)
                 for (int m = 0; m < 3; m++)
                     acc += levi(j, l, m) * r[m] / (rn * r2) * f[l];
+        } else if (kernel == OR_HARMONIC) {
+            acc = f[j] / rn;
         } else {
             for (int l = 0; l < 3; l++)
                 for (int m = 0; m < 3; m++)
@@ -107,6 +116,8 @@ void oracle_real_kernel(int kernel, double xi, const double *r, const double *f,
             for (int l = 0; l < 3; l++)
                 for (int m = 0; m < 3; m++)
                     acc += levi(j, l, m) * (r[m] / r2) * c1 * f[l];
+        } else if (kernel == OR_HARMONIC) {
+            acc = ec / rn * f[j];
         } else {
             double c1 = 3.0 * ec / rn + (3.0 + 2.0 * xi * xi * r2) * 2.0 * xi * gauss / sqpi;
             double c2 = 4.0 * xi * xi * xi * gauss / sqpi;
@@ -202,6 +213,8 @@ static void fourier_kernel_apply(int kernel, double xi, const double *k,
                     double complex G = -levi(j, l, m) * I * k[m] * (4.0 * OR_PI / k2) * gE;
                     acc += G * S[l];
                 }
+        } else if (kernel == OR_HARMONIC) {
+            acc = (4.0 * OR_PI / k2) * gE * S[j];
         } else {
             for (int l = 0; l < 3; l++)
                 for (int m = 0; m < 3; m++) {
@@ -385,16 +398,18 @@ void oracle_k0_stresslet_3p(const double *L, long ns, const double *xs, const do
 
 /* ------------------------------------------------------------------------ */
 /* Self term, eq. (self-term): -G^F(0; xi) . f(x_m); for the stokeslet this  */
-/* is -4 xi/sqrt(pi) f (eq. 3p-stokeslet-self-term), zero for Omega and T.   */
+/* is -4 xi/sqrt(pi) f (eq. 3p-stokeslet-self-term), zero for Omega and T;   */
+/* for the harmonic H^F(0) = lim (1 - erfc(xi r))/r = 2 xi/sqrt(pi).         */
 /* ------------------------------------------------------------------------ */
 void oracle_self_part(int kernel, double xi, long nt, const long *self_src,
                       const double *f, double *u)
 {
-    if (kernel != OR_STOKESLET || !self_src) return;
+    if ((kernel != OR_STOKESLET && kernel != OR_HARMONIC) || !self_src) return;
+    double c = kernel == OR_STOKESLET ? -4.0 * xi / sqrt(OR_PI) : -2.0 * xi / sqrt(OR_PI);
     for (long m = 0; m < nt; m++) {
         long n = self_src[m];
         if (n < 0) continue;
-        for (int j = 0; j < 3; j++) u[3 * m + j] += -4.0 * xi / sqrt(OR_PI) * f[3 * n + j];
+        for (int j = 0; j < 3; j++) u[3 * m + j] += c * f[3 * n + j];
     }
 }
 

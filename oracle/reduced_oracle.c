@@ -13,6 +13,12 @@
  *     stresslet eq. (1p-stresslet-Q0), with their rho -> 0 limits
  *     eqs. (1p-stokeslet-Q0-limit), (1p-stresslet-Q0-limit) and a zero rotlet.
  *
+ *
+ *   harmonic (per component; the classical Ewald zero modes, gauge -2 pi |z|
+ *   for D = 2 and -2 log(rho) for D = 1, i.e. the xi -> infinity limits):
+ *     D = 2:  -2 pi (r3 erf(xi r3) + e^{-xi^2 r3^2}/(sqrt(pi) xi))
+ *     D = 1:  -(E1(xi^2 rho^2) + log(rho^2)), at rho = 0: euler + log(xi^2)
+ *
  * The nonsingular modes (k^P != 0) are evaluated by the caller through the
  * trapezoidal rule of the defining integrals (see oracle/reduced.py).
  */
@@ -22,6 +28,7 @@
 #define OR_STOKESLET 0
 #define OR_ROTLET 1
 #define OR_STRESSLET 2
+#define OR_HARMONIC 3
 
 static const double OR_PI = 3.14159265358979323846264338327950288;
 static const double OR_EULER = 0.57721566490153286060651209008240243;
@@ -76,7 +83,10 @@ static double phi2_of(double V)
 static void zero_mode_2p(int kernel, double xi, double r3, const double *f, const double *nu, double *out)
 {
     double e = exp(-xi * xi * r3 * r3);
-    if (kernel == OR_ROTLET) {
+    if (kernel == OR_HARMONIC) {
+        double c = -2.0 * OR_PI * (r3 * erf(xi * r3) + e / (sqrt(OR_PI) * xi));
+        for (int j = 0; j < 3; j++) out[j] += c * f[j];
+    } else if (kernel == OR_ROTLET) {
         double c = 2.0 * OR_PI * erf(xi * r3);
         out[0] += c * f[1];
         out[1] += -c * f[0];
@@ -99,7 +109,10 @@ static void zero_mode_1p(int kernel, double xi, double r2, double r3, const doub
     double rho2 = r2 * r2 + r3 * r3;
     double rho = sqrt(rho2);
     double V = xi * xi * rho2;
-    if (kernel == OR_ROTLET) {
+    if (kernel == OR_HARMONIC) {
+        double c = rho == 0.0 ? OR_EULER + log(xi * xi) : -(oracle_e1(V) + log(rho2));
+        for (int j = 0; j < 3; j++) out[j] += c * f[j];
+    } else if (kernel == OR_ROTLET) {
         if (rho == 0.0) return;
         double c = 2.0 * phi1_of(V) / rho;
         double t2 = r2 / rho, t3 = r3 / rho;
