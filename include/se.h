@@ -58,6 +58,17 @@ typedef int32_t se_status;
 #define SE_STOKESLET 0
 #define SE_ROTLET 1
 #define SE_STRESSLET 2
+/* Harmonic (Laplace) kernel H(r) = 1/|r| of Sec. 2, through the same
+ * pipeline with the classical Ewald screening of Sec. 2.1, eq.
+ * (ewald-screening), and the harmonic modified kernels of Sec. 3.1 (the ones
+ * the rotlet is built from).  Applied
+ * per component: the strengths f[n][3] are three independent scalar charge
+ * sets and u[m][3] their three potentials, u_c(x_m) = sum_n q_{n,c} / |r|
+ * summed over the periodic images.  Gauges: D = 3 drops the k = 0 mode (a
+ * neutralising background); D = 2 uses -2 pi |z| for the zero mode
+ * (no constant); D = 1 uses -2 log(rho) (l_H = 1); D = 0 is the free-space
+ * sum.  For neutral charge sets (sum_n q_{n,c} = 0) the gauge drops out. */
+#define SE_HARMONIC 3
 
 #define SE_TOL_REL 0 /* rms-relative tolerance, mapped through the Fourier-part rms estimate U */
 #define SE_TOL_ABS 1 /* absolute rms tolerance tau_rms (Sec. 4) */
@@ -78,7 +89,7 @@ typedef int32_t se_status;
 /* Window function of gridding and gathering.
  * PKB: the polynomial Kaiser-Bessel window, eqs. (KB-window), (PKB-parameters),
  *   beta = 2.5 P, scaled by the exact Fourier transform of the KB window.
- * TG: the truncated Gaussian of Sec. 5.4 (window comparison), eq. (TG-window),
+ * TG: the truncated Gaussian of Sec. 5.3 (window comparison), eq. (TG-window),
  *   w(r) = exp(-alpha (r/a)^2) on |r| <= a = h P / 2 with alpha = 0.91 (pi/2) P,
  *   evaluated exactly in gridding and gathering and scaled by the Fourier
  *   transform of the untruncated Gaussian, as the paper does. */
@@ -89,7 +100,7 @@ typedef int32_t se_status;
 typedef struct se_problem {
     int32_t struct_size;      /* sizeof(se_problem) */
     int32_t periodicity;      /* D in {0,1,2,3}: the first D axes are periodic */
-    int32_t kernel;           /* SE_STOKESLET, SE_ROTLET or SE_STRESSLET */
+    int32_t kernel;           /* SE_STOKESLET, SE_ROTLET, SE_STRESSLET or SE_HARMONIC */
     int32_t tol_kind;         /* SE_TOL_REL or SE_TOL_ABS */
     double box[3];            /* primary cell [0,L1) x [0,L2) x [0,L3), all > 0 */
     double tol;               /* rms tolerance (> 0) */

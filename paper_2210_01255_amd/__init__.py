@@ -13,8 +13,8 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libse_mi355x.so")
 
-STOKESLET, ROTLET, STRESSLET = 0, 1, 2
-KERNELS = {"stokeslet": STOKESLET, "rotlet": ROTLET, "stresslet": STRESSLET}
+STOKESLET, ROTLET, STRESSLET, HARMONIC = 0, 1, 2, 3
+KERNELS = {"stokeslet": STOKESLET, "rotlet": ROTLET, "stresslet": STRESSLET, "harmonic": HARMONIC}
 TOL_REL, TOL_ABS = 0, 1
 PREC_AUTO, PREC_FP64, PREC_FP32 = 0, 1, 2
 SELECT_ANALYTIC, SELECT_LEARNED, SELECT_MANUAL = 0, 1, 2

@@ -264,7 +264,7 @@ static se_status validate_problem(const se_problem* prob)
 {
     if (prob->struct_size != (int32_t)sizeof(se_problem)) return SE_ERR_ARG;
     if (prob->periodicity < 0 || prob->periodicity > 3) return SE_ERR_ARG;
-    if (prob->kernel < SE_STOKESLET || prob->kernel > SE_STRESSLET) return SE_ERR_ARG;
+    if (prob->kernel < SE_STOKESLET || prob->kernel > SE_HARMONIC) return SE_ERR_ARG;
     if (prob->tol_kind != SE_TOL_REL && prob->tol_kind != SE_TOL_ABS) return SE_ERR_ARG;
     if (!(prob->tol > 0) || !std::isfinite(prob->tol)) return SE_ERR_ARG;
     for (int i = 0; i < 3; i++)

@@ -101,7 +101,7 @@ inline unsigned blocks(int64_t n) { return (unsigned)((n + 255) / 256); }
 se_status se_d0_precompute(se_plan* p)
 {
     const se_params& par = p->par;
-    const int biharmonic = p->kernel != SE_ROTLET;
+    const int biharmonic = p->kernel == SE_STOKESLET || p->kernel == SE_STRESSLET;
     int n0[3], m[3], n2[3];
     double h[3];
     for (int d = 0; d < 3; d++) {

@@ -430,7 +430,7 @@ __device__ __forceinline__ double green_scalar(const se_fft_args& a, int ix, int
 {
     if (a.D == 0) return a.ktab[((int64_t)iz * a.N[1] + iy) * a.Hx + ix];
     if (k2 == 0.0) return 0.0;
-    return KER == SE_ROTLET ? 4.0 * M_PI / k2 : -8.0 * M_PI / (k2 * k2);
+    return se_harmonic_based(KER) ? 4.0 * M_PI / k2 : -8.0 * M_PI / (k2 * k2);
 }
 
 // u = Khat(k) F with the scalar factor c = Ahat gammahat W already formed.
@@ -444,6 +444,9 @@ __device__ __forceinline__ void apply_green(double cd, const double* k, double k
         C<R> kf = {kr[0] * F[0].x + kr[1] * F[1].x + kr[2] * F[2].x, kr[0] * F[0].y + kr[1] * F[1].y + kr[2] * F[2].y};
 #pragma unroll
         for (int j = 0; j < 3; j++) U[j] = {c * (kr[j] * kf.x - kk * F[j].x), c * (kr[j] * kf.y - kk * F[j].y)};
+    } else if constexpr (KER == SE_HARMONIC) {
+#pragma unroll
+        for (int j = 0; j < 3; j++) U[j] = {c * F[j].x, c * F[j].y};
     } else if constexpr (KER == SE_ROTLET) {
         C<R> w[3];  // F x k
         w[0] = {F[1].x * kr[2] - F[2].x * kr[1], F[1].y * kr[2] - F[2].y * kr[1]};
@@ -480,7 +483,7 @@ __device__ __forceinline__ void scale_point(const se_fft_args& a, int ix, int iy
     const bool moved = (a.D == 2 && ix <= a.skip_kx && kb[1] <= a.skip_ky && -kb[1] <= a.skip_ky) ||
                        (a.D == 1 && ix <= a.skip_kx);
     const double G = moved ? 0.0 : green_scalar<KER>(a, ix, iy, iz, k2);
-    if (G == 0.0 || (KER != SE_STOKESLET && nyq)) {
+    if (G == 0.0 || (se_odd_kernel(KER) && nyq)) {
         U[0] = U[1] = U[2] = {(R)0, (R)0};
         return;
     }
@@ -488,7 +491,7 @@ __device__ __forceinline__ void scale_point(const se_fft_args& a, int ix, int iy
     const double gE = exp(-e);
     const double iw = a.invw2[a.iw_off[0] + ix] * a.invw2[a.iw_off[1] + iy] * a.invw2[a.iw_off[2] + iz];
     const double W = a.scale * iw;
-    const double screen = KER == SE_ROTLET ? gE : gE * (1.0 + e);
+    const double screen = se_harmonic_based(KER) ? gE : gE * (1.0 + e);
     apply_green<R, KER>(G * screen * W, k, k2, F, U);
 }
 
@@ -783,6 +786,7 @@ void launch_z_dispatch(const se_plan* p, int slot, hipStream_t s)
 {
     if (p->kernel == SE_STOKESLET) launch_z<R, SE_STOKESLET, 3>(p, slot, s);
     else if (p->kernel == SE_ROTLET) launch_z<R, SE_ROTLET, 3>(p, slot, s);
+    else if (p->kernel == SE_HARMONIC) launch_z<R, SE_HARMONIC, 3>(p, slot, s);
     else launch_z<R, SE_STRESSLET, 6>(p, slot, s);
 }
 
@@ -899,20 +903,27 @@ __global__ void k_cls_scale(se_cls_args a)
     const bool nyq = (2 * iz == a.nz) || (a.D == 1 && 2 * iy == a.ny);
     const double e = k2 / (4.0 * a.xi * a.xi);
     const double gE = exp(-e);
-    const double screen = KER == SE_ROTLET ? gE : gE * (1.0 + e);
+    const double screen = se_harmonic_based(KER) ? gE : gE * (1.0 + e);
     const double W = a.scale * a.iw[ix] * a.iw[a.nkx + iy] * a.iw[a.nkx + a.ny + iz];
     U[0] = U[1] = U[2] = {(R)0, (R)0};
     const bool kp0 = (k[0] == 0.0) && (a.D == 1 || k[1] == 0.0);
-    if (KER != SE_STOKESLET && nyq) {
+    if (se_odd_kernel(KER) && nyq) {
         // odd kernels: no Hermitian partner on Nyquist indices
     } else if (!a.zero) {
         if (!kp0) {
-            const double G = KER == SE_ROTLET ? 4.0 * M_PI / k2 : -8.0 * M_PI / (k2 * k2);
+            const double G = se_harmonic_based(KER) ? 4.0 * M_PI / k2 : -8.0 * M_PI / (k2 * k2);
             apply_green<R, KER>(G * screen * W, k, k2, F, U);
         }
     } else if (a.D == 2) {
         const double kz = k[2], Rk = a.R * kz;
-        if constexpr (KER == SE_STOKESLET) {
+        if constexpr (KER == SE_HARMONIC) {
+            // Hhat_R^{2P} per component, limit -2 pi R^2
+            const double H = kz == 0.0 ? -2.0 * M_PI * a.R * a.R
+                                       : 4.0 * M_PI / (kz * kz) * (1.0 - cos(Rk) - Rk * sin(Rk));
+            const R c = (R)(H * screen * W);
+#pragma unroll
+            for (int j = 0; j < 3; j++) U[j] = {c * F[j].x, c * F[j].y};
+        } else if constexpr (KER == SE_STOKESLET) {
             // Hhat_R^{2P} D^S, limit -2 pi R^2
             const double H = kz == 0.0 ? -2.0 * M_PI * a.R * a.R
                                        : 4.0 * M_PI / (kz * kz) * (1.0 - cos(Rk) - Rk * sin(Rk));
@@ -937,7 +948,7 @@ __global__ void k_cls_scale(se_cls_args a)
     } else {
         const double H = a.mk[2 * (iz * (int64_t)a.ny + iy)];
         const double B = a.mk[2 * (iz * (int64_t)a.ny + iy) + 1];
-        if constexpr (KER == SE_ROTLET) {
+        if constexpr (KER == SE_ROTLET || KER == SE_HARMONIC) {
             apply_green<R, KER>(H * screen * W, k, k2, F, U);
         } else if constexpr (KER == SE_STOKESLET) {
             apply_green<R, KER>(B * screen * W, k, k2, F, U);
@@ -1021,6 +1032,7 @@ void cls_transform_dispatch(const se_plan* p, int slot, hipStream_t s)
 {
     if (p->kernel == SE_STOKESLET) cls_transform<R, SE_STOKESLET, 3>(p, slot, s);
     else if (p->kernel == SE_ROTLET) cls_transform<R, SE_ROTLET, 3>(p, slot, s);
+    else if (p->kernel == SE_HARMONIC) cls_transform<R, SE_HARMONIC, 3>(p, slot, s);
     else cls_transform<R, SE_STRESSLET, 6>(p, slot, s);
 }
 

@@ -19,6 +19,11 @@
 #define SE_FLAG_COINCIDENT 4
 
 // Largest supported window support and polynomial degree.
+// Kernels whose scalar building block is the harmonic (rotlet, harmonic)
+// rather than the biharmonic, and kernels odd in k (no real Nyquist mode).
+constexpr bool se_harmonic_based(int kernel) { return kernel == SE_ROTLET || kernel == SE_HARMONIC; }
+constexpr bool se_odd_kernel(int kernel) { return kernel == SE_ROTLET || kernel == SE_STRESSLET; }
+
 #define SE_MAX_P 32
 #define SE_MAX_NU 10
 

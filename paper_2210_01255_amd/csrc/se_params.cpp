@@ -17,7 +17,7 @@ const double kNrcUniform[2][4] = {{2500.0, 950.0, 450.0, 400.0}, {6000.0, 1600.0
 // Box-padding factor lambda, Table 2 (estimates-lambda).
 double lambda_factor(int kernel, int D)
 {
-    if (D == 0) return kernel == SE_STOKESLET ? 2.2 : (kernel == SE_STRESSLET ? 2.4 : 1.5);
+    if (D == 0) return kernel == SE_STOKESLET ? 2.2 : (kernel == SE_STRESSLET ? 2.4 : 1.5);  // H: as Omega
     return 2.4;
 }
 
@@ -36,6 +36,13 @@ double pot_rms(int kernel, const Box& b, double Q, double xi)
         return 1.8 * sq * fu / b.Lc;
     }
     if (kernel == SE_STRESSLET) return 7.2 * sq * std::sqrt(t) / (b.Lc * b.Lc);
+    if (kernel == SE_HARMONIC) {
+        // harmonic: U^2 = (8Q/V) int_{k0}^inf e^{-k^2/(2 xi^2)} / k^2 dk over the
+        // Fourier part of uncorrelated charges, k0 = 2 pi / Lc
+        const double k0 = 2.0 * kPi / b.Lc, s = 1.0 / (std::sqrt(2.0) * xi);
+        const double I = std::exp(-k0 * k0 * s * s) / k0 - std::sqrt(kPi) * s * std::erfc(k0 * s);
+        return std::sqrt(8.0 * Q / b.V * std::max(I, 0.0));
+    }
     return 2.4 * sq * std::sqrt(t) * std::exp(-11.60 / (t * t)) / (b.Lc * b.Lc);
 }
 
@@ -45,6 +52,8 @@ double rs_pref(int kernel, const Box& b, double Q, double xi, double rc)
 {
     if (kernel == SE_STOKESLET) return std::sqrt(4.0 * Q * rc / b.V);
     if (kernel == SE_STRESSLET) return std::sqrt(112.0 * Q * std::pow(xi, 4) * rc * rc * rc / (9.0 * b.V));
+    // harmonic: (4 pi Q/V) int_rc^inf erfc(xi r)^2 dr with erfc(x) ~ e^{-x^2}/(x sqrt(pi))
+    if (kernel == SE_HARMONIC) return std::sqrt(Q / (b.V * rc * rc * rc)) / (xi * xi);
     return std::sqrt(8.0 * Q / (3.0 * b.V * rc));
 }
 
@@ -54,6 +63,8 @@ double fs_pref(int kernel, const Box& b, double Q, double xi, double k)
 {
     if (kernel == SE_STOKESLET) return 4.0 / (kPi * b.Lc) * std::sqrt(Q / 3.0);
     if (kernel == SE_STRESSLET) return 4.0 * k / (3.0 * kPi * b.Lc) * std::sqrt(7.0 * Q / 2.0);
+    // harmonic: (8Q/V) int_k^inf e^{-k^2/(2 xi^2)} / k^2 dk ~ (8Q/V) xi^2 e^{-k^2/(2 xi^2)} / k^3
+    if (kernel == SE_HARMONIC) return std::sqrt(8.0 * Q / b.V) * xi / std::pow(k, 1.5);
     return std::sqrt(8.0 * xi * xi * Q / (3.0 * kPi * b.V * k));
 }
 
@@ -172,7 +183,7 @@ double se_kb_fourier(double k, double a, double beta)
 double se_tg_alpha(int P) { return 0.91 * (kPi / 2.0) * P; }
 
 // Fourier transform of the untruncated Gaussian exp(-alpha (r/a)^2), used in
-// the scaling step of the truncated-Gaussian window (Sec. 5.4):
+// the scaling step of the truncated-Gaussian window (Sec. 5.3):
 // sqrt(pi/alpha) a exp(-k^2 a^2 / (4 alpha)).
 double se_ug_fourier(double k, double a, double alpha)
 {
@@ -455,7 +466,7 @@ se_status se_complete_params(const se_problem* p, double xi, double rc, double h
     // step 6: extended grid in the free directions
     if (D < 3) {
         double lam = lambda_factor(kernel, D);
-        double theta = (kernel == SE_ROTLET) ? 0.0 : 8.0;
+        double theta = (kernel == SE_ROTLET || kernel == SE_HARMONIC) ? 0.0 : 8.0;
         for (int i = D; i < 3; i++) {
             double target = p->box[i] / h_common + P + (lam - 1.0) * std::max((double)P, theta);
             // FFT lengths along free axes are s*M' (D=1,2) or 2M' (D=0); keep M' smooth

@@ -45,6 +45,7 @@ __device__ __forceinline__ double horner_tab(const double* c, double sg)
 // (2x/sqrt(pi)) e^{-x^2} and E(x) = e^{-x^2} (tabulated, see se_radial_table):
 //   S:     (G/r)(f + r (r.f)/r^2) - (4 xi/sqrt(pi)) E f
 //   Omega: (G/r^3) (f x r)
+//   H:     (erfc(x)/r) f, per component
 //   T:     -2 r (r.q)(r.nu)/r^4 * (3G + (4x^3/sqrt(pi)) E)/r
 //          + (4 xi^3/sqrt(pi)) E (q (r.nu) + nu (r.q) + r (q.nu))
 struct se_radial {
@@ -75,6 +76,11 @@ __device__ __forceinline__ void real_apply(const se_radial& q, double xi, const 
         const double rf = (r[0] * f[0] + r[1] * f[1] + r[2] * f[2]) * inv * inv;
 #pragma unroll
         for (int j = 0; j < 3; j++) u[j] += c1 * (f[j] + r[j] * rf) - c2 * f[j];
+    } else if constexpr (KER == SE_HARMONIC) {
+        // erfc(x)/r = (G - (2x/sqrt(pi)) E)/r per component
+        const double c1 = (q.G - (2.0 / kSqrtPi) * q.x * q.E) * inv;
+#pragma unroll
+        for (int j = 0; j < 3; j++) u[j] += c1 * f[j];
     } else if constexpr (KER == SE_ROTLET) {
         const double c1 = q.G * inv * inv * inv;
         u[0] += c1 * (f[1] * r[2] - f[2] * r[1]);
@@ -940,6 +946,8 @@ void se_launch_real_space(const se_plan* p, int slot0, int nslot, hipStream_t s)
             hipLaunchKernelGGL((k_real2<SE_STOKESLET, 2>), dim3(nwg), dim3(256), 0, s, a, bg);
         else if (nslot == 2 && p->kernel == SE_ROTLET)
             hipLaunchKernelGGL((k_real2<SE_ROTLET, 2>), dim3(nwg), dim3(256), 0, s, a, bg);
+        else if (nslot == 2 && p->kernel == SE_HARMONIC)
+            hipLaunchKernelGGL((k_real2<SE_HARMONIC, 2>), dim3(nwg), dim3(256), 0, s, a, bg);
         else {
             for (int k = 0; k < nslot; k++) {
                 se_real_args b = a;
@@ -949,6 +957,8 @@ void se_launch_real_space(const se_plan* p, int slot0, int nslot, hipStream_t s)
                     hipLaunchKernelGGL((k_real2<SE_STOKESLET, 1>), dim3(nwg), dim3(256), 0, s, b, bg);
                 else if (p->kernel == SE_ROTLET)
                     hipLaunchKernelGGL((k_real2<SE_ROTLET, 1>), dim3(nwg), dim3(256), 0, s, b, bg);
+                else if (p->kernel == SE_HARMONIC)
+                    hipLaunchKernelGGL((k_real2<SE_HARMONIC, 1>), dim3(nwg), dim3(256), 0, s, b, bg);
                 else
                     hipLaunchKernelGGL((k_real2<SE_STRESSLET, 1>), dim3(nwg), dim3(256), 0, s, b, bg);
             }
@@ -962,6 +972,7 @@ void se_launch_real_space(const se_plan* p, int slot0, int nslot, hipStream_t s)
         b.u = se_slot_uR(p, slot0 + k);
         if (p->kernel == SE_STOKESLET) hipLaunchKernelGGL(k_real<SE_STOKESLET>, dim3(nb), dim3(256), 0, s, b);
         else if (p->kernel == SE_ROTLET) hipLaunchKernelGGL(k_real<SE_ROTLET>, dim3(nb), dim3(256), 0, s, b);
+        else if (p->kernel == SE_HARMONIC) hipLaunchKernelGGL(k_real<SE_HARMONIC>, dim3(nb), dim3(256), 0, s, b);
         else hipLaunchKernelGGL(k_real<SE_STRESSLET>, dim3(nb), dim3(256), 0, s, b);
     }
 }
@@ -976,13 +987,28 @@ void se_launch_finalize(const se_plan* p, int slot, double* u, double* u_real, d
     a.f64 = se_slot_fs64(p, slot);
     a.xt = p->tas ? p->d_src : p->d_tgt;
     a.red = se_slot_red(p, slot);
-    a.self_c = (p->kernel == SE_STOKESLET && p->tas) ? -4.0 * p->par.xi / kSqrtPi : 0.0;
+    // self terms (targets are sources): -4 xi/sqrt(pi) f (stokeslet), and
+    // -2 xi/sqrt(pi) q for the harmonic (the limit of H - H^R at r = 0)
+    a.self_c = 0.0;
+    if (p->tas && p->kernel == SE_STOKESLET) a.self_c = -4.0 * p->par.xi / kSqrtPi;
+    if (p->tas && p->kernel == SE_HARMONIC) a.self_c = -2.0 * p->par.xi / kSqrtPi;
     a.k0_c = (p->kernel == SE_STRESSLET && p->D == 3) ? -8.0 * M_PI / (p->g.L[0] * p->g.L[1] * p->g.L[2]) : 0.0;
     // D = 0 stokeslet: the optimal biharmonic b_B = -1/(2R) adds 4 b_B sum f
     // (eq. 0p-stokeslet-extra-contribution); remove it so u decays at infinity.
     for (int j = 0; j < 3; j++) a.gauge[j] = 0.0;
     if (p->D == 0 && p->kernel == SE_STOKESLET)
         for (int j = 0; j < 3; j++) a.gauge[j] = 2.0 / p->par.R;
+    if (p->D == 3 && p->kernel == SE_HARMONIC) {
+        // uniform neutralising background per charge set (the k -> 0 limit of
+        // (4 pi/k^2)(gammaE - 1) / V): -pi / (V xi^2) sum q
+        for (int j = 0; j < 3; j++)
+            a.gauge[j] = -M_PI / (p->g.L[0] * p->g.L[1] * p->g.L[2] * p->par.xi * p->par.xi);
+    }
+    if (p->D == 1 && p->kernel == SE_HARMONIC) {
+        // Hhat_R^{1P} is the transform of -2 log(rho/R) on rho < R (l_H = R);
+        // return to l_H = 1: subtract (2 log R / L1) sum q per component
+        for (int j = 0; j < 3; j++) a.gauge[j] = -2.0 * std::log(p->par.R) / p->g.L[0];
+    }
     if (p->D == 1 && p->kernel == SE_STOKESLET) {
         // eq. (1p-stokeslet-extra-contribution) for l_H = R, l_B = R sqrt(e),
         // removed so that the result is in the gauge l_B = 1, l_H = 1/e

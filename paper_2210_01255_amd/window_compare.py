@@ -1,4 +1,4 @@
-"""Window comparison of Sec. 5.4 (PKB against the truncated Gaussian): time of
+"""Window comparison of Sec. 5.3 (PKB against the truncated Gaussian): time of
 gridding plus gathering against the rms-relative error of the Fourier-space
 part, triply periodic, uniform sources.
 

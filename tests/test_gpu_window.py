@@ -1,4 +1,4 @@
-"""Truncated-Gaussian window (Sec. 5.4, eq. TG-window) through the whole
+"""Truncated-Gaussian window (Sec. 5.3, eq. TG-window) through the whole
 path: gridding and gathering with exp(-alpha (r/a)^2) evaluated exactly, the
 scaling step with the untruncated Gaussian's transform, against the FP64
 oracle at the requested rms-relative tolerance (safety factor 10 as in the

@@ -46,7 +46,7 @@ def test_table4_xi_from_table3_nrc(se):
         assert abs(p["xi"] - float(xi)) < 5e-5, (kernel, D, p["xi"], xi)
 
 
-@pytest.mark.parametrize("kernel", ["stokeslet", "rotlet", "stresslet"])
+@pytest.mark.parametrize("kernel", ["stokeslet", "rotlet", "stresslet", "harmonic"])
 @pytest.mark.parametrize("D", [0, 1, 2, 3])
 def test_parameter_rules(se, kernel, D):
     p = se.select_params(kernel=kernel, periodicity=D, tol=1e-8, tol_kind=se.TOL_ABS, n_src=100000,
@@ -201,7 +201,7 @@ def test_fft_pass_beyond_lds_is_refused_at_plan_creation():
 
 
 def test_truncated_gaussian_window_parameters(se):
-    """Truncated-Gaussian window (Sec. 5.4, eq. TG-window): shape alpha =
+    """Truncated-Gaussian window (Sec. 5.3, eq. TG-window): shape alpha =
     0.91 (pi/2) P, the same grid as the PKB window, a wider support whose
     estimate 10 U e^{-alpha} meets tau_abs, and the analytic procedure when
     the learned selector is asked for (it was trained on PKB runs)."""
