@@ -485,8 +485,10 @@ __device__ __forceinline__ bool rt_meets(const int* o, int P, int wxo, int wyo)
 
 // One batch: locate candidates base .. base + KB - 1, anchor them, list them
 // per wave (the points whose support meets the wave's 8 x 8 x 8 columns) and
-// stage the block-restricted 1-D weights.  Returns the batch size.
-template <typename R, bool GATHER, int NC, typename L>
+// stage the block-restricted 1-D weights (PKB, or the truncated Gaussian
+// when TG: a template parameter, so that the PKB kernels carry no second
+// weight path).  Returns the batch size.
+template <typename R, bool GATHER, int NC, bool TG, typename L>
 __device__ int rt_stage_batch(const se_tile_args& a, const int* t0, int nslots, int total, int base, L& s, int tid)
 {
     const se_grid_geom& g = a.g;
@@ -543,14 +545,22 @@ __device__ int rt_stage_batch(const se_tile_args& a, const int* t0, int nslots, 
         const int coord = dim == 0 ? j : (dim == 1 ? j - SE_RT_TX : j - SE_RT_TX - SE_RT_TY);
         const int q = coord - s.o[p][dim];
         R w = (R)0;
-        if (q >= 0 && q < a.P && s.idx[p] >= 0) w = win_weight<R>(s.pkb, a.tg_c, a.P, q, (R)(1.0 - s.t[p][dim]));
+        if (q >= 0 && q < a.P && s.idx[p] >= 0) {
+            const R sl = (R)(1.0 - s.t[p][dim]);
+            if constexpr (TG) {
+                const R d = (R)(q - a.P / 2) + sl;
+                w = exp(-(R)a.tg_c * d * d);
+            } else {
+                w = pkb_weight<R>(s.pkb, q, sl);
+            }
+        }
         s.w[p][j] = w;
     }
     __syncthreads();
     return nb;
 }
 
-template <typename R, int NC>
+template <typename R, int NC, bool TG>
 __global__ void __launch_bounds__(SE_RT_THREADS, 4) k_spread_rt(se_tile_args a)
 {
     __shared__ se_rt_lds<R, NC, false> s;
@@ -576,7 +586,7 @@ __global__ void __launch_bounds__(SE_RT_THREADS, 4) k_spread_rt(se_tile_args a)
 #pragma unroll
         for (int c = 0; c < NC; c++) acc[z][c] = (R)0;
     for (int base = 0; base < total; base += SE_RT_KB) {
-        (void)rt_stage_batch<R, false, NC>(a, t0, nslots, total, base, s, tid);
+        (void)rt_stage_batch<R, false, NC, TG>(a, t0, nslots, total, base, s, tid);
         const int cnt = __builtin_amdgcn_readfirstlane(s.cnt[wave]);
         if constexpr (NC < 6) {
             // two points per step so that the LDS reads of the second overlap
@@ -702,7 +712,7 @@ __device__ __forceinline__ double rt_dpp(double v)
 }
 constexpr int kDppRor8 = 0x128, kDppHalfMirror = 0x141, kDppXor2 = 0x4E, kDppXor1 = 0xB1;
 
-template <typename R, int NCG>
+template <typename R, int NCG, bool TG>
 __global__ void __launch_bounds__(SE_RT_THREADS, 3) k_gather_rt(se_tile_args a)
 {
     __shared__ se_rt_lds<R, NCG, true> s;
@@ -741,7 +751,7 @@ __global__ void __launch_bounds__(SE_RT_THREADS, 3) k_gather_rt(se_tile_args a)
     const int64_t n = a.n;
     constexpr int GP = 24 / NCG;  // points per reduce-scatter group
     for (int base = 0; base < total; base += SE_RT_KB) {
-        const int nb = rt_stage_batch<R, true, NCG>(a, t0, nslots, total, base, s, tid);
+        const int nb = rt_stage_batch<R, true, NCG, TG>(a, t0, nslots, total, base, s, tid);
         // Groups of GP points: per-lane partial sums v[NCG j + c] (24 values),
         // then one reduce-scatter over the wave: halving steps across lane
         // bits 5, 4, 3 leave lane group k (bits 5..3) with values 3k .. 3k+2,
@@ -886,7 +896,8 @@ void launch_spread_rt(const se_plan* p, int slot, hipStream_t s)
 {
     se_tile_args a = make_args(p, false, slot);
     unsigned nb = (unsigned)(p->ntile[0] * p->ntile[1] * p->ntile[2]);
-    hipLaunchKernelGGL((k_spread_rt<R, NC>), dim3(nb), dim3(SE_RT_THREADS), 0, s, a);
+    if (a.tg_c > 0.0) hipLaunchKernelGGL((k_spread_rt<R, NC, true>), dim3(nb), dim3(SE_RT_THREADS), 0, s, a);
+    else hipLaunchKernelGGL((k_spread_rt<R, NC, false>), dim3(nb), dim3(SE_RT_THREADS), 0, s, a);
 }
 
 template <typename R, int NCG>
@@ -894,7 +905,8 @@ void launch_gather_rt(const se_plan* p, int slot, hipStream_t s)
 {
     se_tile_args a = make_args(p, true, slot);
     unsigned nb = (unsigned)(p->ntile[0] * p->ntile[1] * p->ntile[2]);
-    hipLaunchKernelGGL((k_gather_rt<R, NCG>), dim3(nb), dim3(SE_RT_THREADS), 0, s, a);
+    if (a.tg_c > 0.0) hipLaunchKernelGGL((k_gather_rt<R, NCG, true>), dim3(nb), dim3(SE_RT_THREADS), 0, s, a);
+    else hipLaunchKernelGGL((k_gather_rt<R, NCG, false>), dim3(nb), dim3(SE_RT_THREADS), 0, s, a);
 }
 
 // slot0 .. slot0 + nslot - 1: right-hand sides of the current chunk (two
