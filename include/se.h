@@ -335,6 +335,31 @@ se_status se_mlp_forward(const float* theta, const float* X, int64_t n, float* Y
 se_status se_mlp_adam(float* theta, float* m, float* v, const float* grad, int64_t n, int32_t t, float lr, float beta1,
                       float beta2, float eps, void* stream);
 
+/* Direct Ewald reference on the GPU (no grid, no window), for checking the
+ * fast method on large systems on every target.
+ *   periodicity 3: the classical Ewald sum of Sec. 2.2, eqs.
+ *     (3p-ewald-decomp-self), (real-space-potential-3p),
+ *     (fourier-space-potential-3p), (k0-stresslet-3p), (self-term): the
+ *     real-space part over all pairs at the minimum image with
+ *     rc = min(L)/2 and the exact kernels (erfc, exp), the Fourier part as
+ *     the explicit lattice sum over 0 < |k| <= 13 xi; the harmonic adds its
+ *     neutralising background -pi Q_c/(V xi^2);
+ *   periodicity 0: the free-space sum over all pairs.
+ * Both truncations sit near e^{-42}.  xi <= 0 picks 13 / min(L); a caller xi
+ * below that is rejected (SE_ERR_ARG: the real-space tail would exceed the
+ * cut-off).  Cost O(N_t N_s) pairs plus O((N_s + N_t) N_k) phases.
+ * kernel: SE_STOKESLET, SE_ROTLET, SE_STRESSLET or SE_HARMONIC; strengths
+ * [n_src][3] (f, q, or three charge sets), normals_xyz [n_src][3] for the
+ * stresslet (else null); tgt_xyz null: targets are the sources (n_tgt
+ * ignored, the pair m = n omitted).  All point arrays are caller-owned
+ * device FP64 row-major; u_out [n_tgt][3] device.  Allocates and frees
+ * temporary device memory and synchronises the stream before returning.
+ * Errors: SE_ERR_ARG, SE_ERR_COINCIDENT (a distinct pair at r = 0, skipped
+ * in the result), SE_ERR_NOMEM, SE_ERR_HIP. */
+se_status se_ewald_reference(int32_t kernel, int32_t periodicity, const double box[3], double xi, int64_t n_src,
+                             const double* src_xyz, const double* strengths, const double* normals_xyz,
+                             int64_t n_tgt, const double* tgt_xyz, double* u_out, int32_t device, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

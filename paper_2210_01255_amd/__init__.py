@@ -60,7 +60,7 @@ EXPORTS = ["se_version", "se_status_string", "se_params_select", "se_plan_create
            "se_debug_cell_list", "se_plan_set_shape", "se_plan_get_shape", "se_batch_create", "se_batch_destroy",
            "se_batch_plan", "se_batch_set_geometry", "se_batch_execute", "se_batch_tune", "se_selector_features",
            "se_selector_train", "se_selector_save", "se_selector_load", "se_selector_ready", "se_selector_get",
-           "se_selector_predict", "se_mlp_loss_grad", "se_mlp_forward", "se_mlp_adam"]
+           "se_selector_predict", "se_mlp_loss_grad", "se_mlp_forward", "se_mlp_adam", "se_ewald_reference"]
 
 PHASES = ["geometry", "strengths", "spread", "fft_fwd_xy", "fft_z_scale", "fft_inv_yx", "gather", "real_space",
           "epilogue"]
@@ -164,6 +164,9 @@ def _load():
     L.se_mlp_loss_grad.argtypes = [vp, vp, vp, ctypes.c_int64, vp, vp, vp]
     L.se_mlp_forward.restype = i32
     L.se_mlp_forward.argtypes = [vp, vp, ctypes.c_int64, vp, vp]
+    L.se_ewald_reference.restype = i32
+    L.se_ewald_reference.argtypes = [i32, i32, P(ctypes.c_double), ctypes.c_double, ctypes.c_int64, vp, vp, vp,
+                                     ctypes.c_int64, vp, vp, i32, vp]
     L.se_mlp_adam.restype = i32
     L.se_mlp_adam.argtypes = [vp, vp, vp, vp, ctypes.c_int64, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                               ctypes.c_float, vp]
@@ -206,6 +209,7 @@ se_selector_predict = lib.se_selector_predict
 se_mlp_loss_grad = lib.se_mlp_loss_grad
 se_mlp_forward = lib.se_mlp_forward
 se_mlp_adam = lib.se_mlp_adam
+se_ewald_reference = lib.se_ewald_reference
 
 
 def make_problem(kernel="stokeslet", periodicity=3, box=(1.0, 1.0, 1.0), tol=1e-8, tol_kind=TOL_REL,
@@ -244,6 +248,27 @@ def params_to_dict(par: se_params) -> dict:
             v = list(v)
         out[name] = v
     return out
+
+
+def ewald_reference(kernel, periodicity, box, x, strengths, normals=None, targets=None, xi=0.0, stream=None):
+    """Direct Ewald sum on the GPU (se_ewald_reference): D = 3 or 0, device
+    FP64 tensors [n][3]; returns u [n_tgt][3] on the same device."""
+    import torch
+    kid = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+    Plan._check(x, (x.shape[0], 3), "src")
+    Plan._check(strengths, (x.shape[0], 3), "strengths")
+    Plan._check(normals, (x.shape[0], 3), "normals")
+    nt = x.shape[0] if targets is None else targets.shape[0]
+    if targets is not None:
+        Plan._check(targets, (nt, 3), "targets")
+    u = torch.empty((nt, 3), dtype=torch.float64, device=x.device)
+    b = (ctypes.c_double * 3)(*[float(v) for v in box])
+    st = lib.se_ewald_reference(int(kid), int(periodicity), b, ctypes.c_double(float(xi)), ctypes.c_int64(x.shape[0]),
+                                _ptr(x), _ptr(strengths), _ptr(normals), ctypes.c_int64(nt), _ptr(targets), _ptr(u),
+                                int(x.device.index or 0), _stream(stream))
+    if st != SE_OK:
+        raise SEError(st, "se_ewald_reference")
+    return u
 
 
 def select_params(**kw) -> dict:

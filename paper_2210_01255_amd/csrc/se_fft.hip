@@ -1040,6 +1040,152 @@ void cls_transform_dispatch(const se_plan* p, int slot, hipStream_t s)
 
 // D = 1: the class planes are copied out after the x transform (before y);
 // D = 2: the class columns after the x and y transforms.
+namespace {
+
+// ------------------------------------------------ direct k-space reference
+// Triply periodic Fourier part as the explicit lattice sum (Sec. 2.2, eq.
+// fourier-space-potential-3p) over the half space of k with 0 < |k| <= kmax:
+//   S(k) = sum_n F_n e^{-i k.x_n},  U(k) = (2/V) Ghat^F(k) S(k),
+//   u(x) += Re sum_k U(k) e^{i k.x}
+// (the -k half is the complex conjugate).  F_n is f_n, or the symmetric
+// part of q_n nu_n^T (6 components) for the stresslet; Ghat^F is the same
+// scalar-times-operator form as the grid scaling, without the window.
+struct se_dref_k_args {
+    int nk;
+    const double* kv;  // [nk][3]
+    int64_t ns;
+    const double* xs;  // [ns][3]
+    const double* f;   // [ns][3]
+    const double* nu;  // [ns][3] (stresslet)
+    double xi, scale;  // scale = 2 / V
+    double* U;         // [nk][3] complex (6 doubles per k)
+    int64_t nt;
+    const double* xt;  // [nt][3]
+    double* u;         // [nt][3], accumulated
+};
+
+template <int KER, int NC>
+__global__ void __launch_bounds__(256) k_dref_sk(se_dref_k_args a)
+{
+    __shared__ double red[NC * 2][256];
+    const int ik = blockIdx.x, t = threadIdx.x;
+    const double k[3] = {a.kv[3 * ik], a.kv[3 * ik + 1], a.kv[3 * ik + 2]};
+    double sr[NC], si[NC];
+#pragma unroll
+    for (int c = 0; c < NC; c++) sr[c] = si[c] = 0.0;
+    for (int64_t n = t; n < a.ns; n += 256) {
+        const double th = -(k[0] * a.xs[3 * n] + k[1] * a.xs[3 * n + 1] + k[2] * a.xs[3 * n + 2]);
+        double sn, cs;
+        sincos(th, &sn, &cs);
+        double F[NC];
+        if constexpr (NC == 3) {
+#pragma unroll
+            for (int c = 0; c < 3; c++) F[c] = a.f[3 * n + c];
+        } else {
+            const double q[3] = {a.f[3 * n], a.f[3 * n + 1], a.f[3 * n + 2]};
+            const double v[3] = {a.nu[3 * n], a.nu[3 * n + 1], a.nu[3 * n + 2]};
+            F[0] = q[0] * v[0];
+            F[1] = q[1] * v[1];
+            F[2] = q[2] * v[2];
+            F[3] = 0.5 * (q[0] * v[1] + q[1] * v[0]);
+            F[4] = 0.5 * (q[0] * v[2] + q[2] * v[0]);
+            F[5] = 0.5 * (q[1] * v[2] + q[2] * v[1]);
+        }
+#pragma unroll
+        for (int c = 0; c < NC; c++) {
+            sr[c] += F[c] * cs;
+            si[c] += F[c] * sn;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < NC; c++) {
+        red[2 * c][t] = sr[c];
+        red[2 * c + 1][t] = si[c];
+    }
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (t < off)
+#pragma unroll
+            for (int c = 0; c < 2 * NC; c++) red[c][t] += red[c][t + off];
+        __syncthreads();
+    }
+    if (t == 0) {
+        C<double> F[NC], U[3];
+#pragma unroll
+        for (int c = 0; c < NC; c++) F[c] = {red[2 * c][0], red[2 * c + 1][0]};
+        const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+        const double e = k2 / (4.0 * a.xi * a.xi);
+        const double gE = exp(-e);
+        const double screen = se_harmonic_based(KER) ? gE : gE * (1.0 + e);
+        const double G = se_harmonic_based(KER) ? 4.0 * M_PI / k2 : -8.0 * M_PI / (k2 * k2);
+        apply_green<double, KER>(G * screen * a.scale, k, k2, F, U);
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            a.U[6 * ik + 2 * j] = U[j].x;
+            a.U[6 * ik + 2 * j + 1] = U[j].y;
+        }
+    }
+}
+
+// one thread per target; the k list passes through LDS in tiles
+__global__ void __launch_bounds__(256) k_dref_keval(se_dref_k_args a)
+{
+    __shared__ double sk[256][3];
+    __shared__ double su[256][6];
+    const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double x[3] = {0.0, 0.0, 0.0};
+    if (m < a.nt)
+        for (int d = 0; d < 3; d++) x[d] = a.xt[3 * m + d];
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int base = 0; base < a.nk; base += 256) {
+        const int i = base + threadIdx.x;
+        if (i < a.nk) {
+            for (int d = 0; d < 3; d++) sk[threadIdx.x][d] = a.kv[3 * i + d];
+            for (int d = 0; d < 6; d++) su[threadIdx.x][d] = a.U[6 * i + d];
+        }
+        __syncthreads();
+        const int cnt = min(256, a.nk - base);
+        for (int j = 0; j < cnt; j++) {
+            const double th = sk[j][0] * x[0] + sk[j][1] * x[1] + sk[j][2] * x[2];
+            double sn, cs;
+            sincos(th, &sn, &cs);
+#pragma unroll
+            for (int c = 0; c < 3; c++) acc[c] += su[j][2 * c] * cs - su[j][2 * c + 1] * sn;
+        }
+        __syncthreads();
+    }
+    if (m < a.nt)
+        for (int c = 0; c < 3; c++) a.u[3 * m + c] += acc[c];
+}
+
+}  // namespace
+
+void se_launch_dref_kspace(int kernel, int nk, const double* kv, double xi, double volume, int64_t ns,
+                           const double* xs, const double* f, const double* nu, double* U, int64_t nt,
+                           const double* xt, double* u, hipStream_t s)
+{
+    se_dref_k_args a;
+    a.nk = nk;
+    a.kv = kv;
+    a.ns = ns;
+    a.xs = xs;
+    a.f = f;
+    a.nu = nu;
+    a.xi = xi;
+    a.scale = 2.0 / volume;
+    a.U = U;
+    a.nt = nt;
+    a.xt = xt;
+    a.u = u;
+    if (nk > 0) {
+        if (kernel == SE_STOKESLET) hipLaunchKernelGGL((k_dref_sk<SE_STOKESLET, 3>), dim3(nk), dim3(256), 0, s, a);
+        else if (kernel == SE_ROTLET) hipLaunchKernelGGL((k_dref_sk<SE_ROTLET, 3>), dim3(nk), dim3(256), 0, s, a);
+        else if (kernel == SE_HARMONIC) hipLaunchKernelGGL((k_dref_sk<SE_HARMONIC, 3>), dim3(nk), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_dref_sk<SE_STRESSLET, 6>), dim3(nk), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_dref_keval, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, a);
+    }
+}
+
 void se_launch_fft_xy_forward(const se_plan* p, int slot, hipStream_t s)
 {
     if (p->fp32) launch_fwd<float>(p, slot, s);

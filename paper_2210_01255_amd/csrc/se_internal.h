@@ -208,6 +208,18 @@ void se_launch_gather(const se_plan* p, int slot0, int nslot, hipStream_t s);
 // current launch shape (two small kernels); once per evaluation, before the
 // real-space launches.
 void se_launch_real_prep(const se_plan* p, hipStream_t s);
+// Direct Ewald reference (se_reference.cpp): all-pairs real space (or the
+// free-space sum for D = 0), the explicit k-space lattice sum, and the terms
+// outside both (self, stresslet k = 0, harmonic background).
+void se_launch_dref_real(int kernel, int D, const double* L, double xi, double rc, int64_t ns, const double* xs,
+                         const double* f, const double* nu, int64_t nt, const double* xt, int tas, double* u,
+                         int* flags, hipStream_t s);
+void se_launch_dref_kspace(int kernel, int nk, const double* kv, double xi, double volume, int64_t ns,
+                           const double* xs, const double* f, const double* nu, double* U, int64_t nt,
+                           const double* xt, double* u, hipStream_t s);
+void se_launch_dref_terms(int kernel, int D, const double* L, double xi, int64_t ns, const double* xs,
+                          const double* f, const double* nu, int64_t nt, const double* xt, int tas, double* sums,
+                          double* u, hipStream_t s);
 void se_launch_real_space(const se_plan* p, int slot0, int nslot, hipStream_t s);
 void se_launch_reductions(const se_plan* p, int slot, hipStream_t s);
 void se_fft3d_f64(const int* Mg, const int* N, const double* h, double* grid, double* spec, const double* tw,

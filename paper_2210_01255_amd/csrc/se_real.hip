@@ -850,6 +850,164 @@ inline unsigned grid1d(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs)
 
 }  // namespace
 
+namespace {
+
+// ------------------------------------------------- direct real-space reference
+// All pairs, one thread per target, sources through LDS in tiles of 256.
+// D = 3: the minimum image within rc <= min L / 2 (at most one image of a
+// pair is that close) with the exact real-space kernels, eqs.
+// (stokeslet-real), (rotlet-real), (stresslet-real), erfc(xi r)/r for the
+// harmonic; D = 0: the free-space kernels (the same forms at xi = 0).
+// The pair m = n is skipped when targets are sources; coincident distinct
+// pairs are skipped and flagged.
+struct se_dref_r_args {
+    int D;
+    double L[3];
+    double xi, rc2;
+    int64_t ns, nt;
+    const double* xs;
+    const double* f;
+    const double* nu;
+    const double* xt;
+    int tas;
+    double* u;
+    int* flags;
+};
+
+template <int KER>
+__global__ void __launch_bounds__(256) k_dref_real(se_dref_r_args a)
+{
+    constexpr int NN = KER == SE_STRESSLET ? 256 : 1;
+    __shared__ double sx[256][3], sf[256][3], sn[NN][3];
+    const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double x[3] = {0.0, 0.0, 0.0};
+    if (m < a.nt)
+        for (int d = 0; d < 3; d++) x[d] = a.xt[3 * m + d];
+    double acc[3] = {0.0, 0.0, 0.0};
+    int coinc = 0;
+    for (int64_t base = 0; base < a.ns; base += 256) {
+        const int64_t n = base + threadIdx.x;
+        if (n < a.ns)
+            for (int d = 0; d < 3; d++) {
+                sx[threadIdx.x][d] = a.xs[3 * n + d];
+                sf[threadIdx.x][d] = a.f[3 * n + d];
+                if constexpr (KER == SE_STRESSLET) sn[threadIdx.x][d] = a.nu[3 * n + d];
+            }
+        __syncthreads();
+        const int cnt = (int)min((int64_t)256, a.ns - base);
+        if (m < a.nt) {
+            for (int j = 0; j < cnt; j++) {
+                if (a.tas && base + j == m) continue;
+                double r[3];
+#pragma unroll
+                for (int d = 0; d < 3; d++) {
+                    r[d] = x[d] - sx[j][d];
+                    if (d < a.D) r[d] -= a.L[d] * rint(r[d] / a.L[d]);
+                }
+                const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+                if (a.D == 3 && r2 >= a.rc2) continue;
+                if (r2 == 0.0) {
+                    coinc = 1;
+                    continue;
+                }
+                se_radial q;
+                q.inv = 1.0 / sqrt(r2);
+                q.x = a.xi * r2 * q.inv;
+                q.E = exp(-q.x * q.x);
+                q.G = erfc(q.x) + (2.0 / kSqrtPi) * q.x * q.E;
+                const double* nn = nullptr;
+                if constexpr (KER == SE_STRESSLET) nn = sn[j];
+                real_apply<KER>(q, a.xi, r, sf[j], nn, acc);
+            }
+        }
+        __syncthreads();
+    }
+    if (m < a.nt)
+        for (int d = 0; d < 3; d++) a.u[3 * m + d] = acc[d];
+    if (coinc) atomicOr(a.flags, SE_FLAG_COINCIDENT);
+}
+
+// Source sums for the terms outside the lattice sums: sum f (3), sum q.nu,
+// sum x_n (q.nu) (3); one workgroup, fixed order (deterministic).
+__global__ void __launch_bounds__(1024) k_dref_sums(int64_t ns, const double* xs, const double* f, const double* nu,
+                                                    int stresslet, double* out)
+{
+    __shared__ double red[7][1024];
+    double v[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int64_t n = threadIdx.x; n < ns; n += 1024) {
+        for (int d = 0; d < 3; d++) v[d] += f[3 * n + d];
+        if (stresslet) {
+            const double qn = f[3 * n] * nu[3 * n] + f[3 * n + 1] * nu[3 * n + 1] + f[3 * n + 2] * nu[3 * n + 2];
+            v[3] += qn;
+            for (int d = 0; d < 3; d++) v[4 + d] += xs[3 * n + d] * qn;
+        }
+    }
+    for (int c = 0; c < 7; c++) red[c][threadIdx.x] = v[c];
+    __syncthreads();
+    for (int off = 512; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off)
+            for (int c = 0; c < 7; c++) red[c][threadIdx.x] += red[c][threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x < 7) out[threadIdx.x] = red[threadIdx.x][0];
+}
+
+// u += self term (targets are sources), the D = 3 stresslet k = 0 term
+// (eq. k0-stresslet-3p) and the harmonic's neutralising background.
+__global__ void k_dref_terms(int64_t nt, const double* xt, const double* f, int tas, double self_c, double k0_c,
+                             double bg_c, const double* sums, double* u)
+{
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= nt) return;
+    for (int j = 0; j < 3; j++) {
+        double v = bg_c * sums[j];
+        if (tas) v += self_c * f[3 * m + j];
+        if (k0_c != 0.0) v += k0_c * (xt[3 * m + j] * sums[3] - sums[4 + j]);
+        u[3 * m + j] += v;
+    }
+}
+
+}  // namespace
+
+void se_launch_dref_real(int kernel, int D, const double* L, double xi, double rc, int64_t ns, const double* xs,
+                         const double* f, const double* nu, int64_t nt, const double* xt, int tas, double* u,
+                         int* flags, hipStream_t s)
+{
+    se_dref_r_args a;
+    a.D = D;
+    for (int d = 0; d < 3; d++) a.L[d] = L[d];
+    a.xi = D == 0 ? 0.0 : xi;
+    a.rc2 = rc * rc;
+    a.ns = ns;
+    a.nt = nt;
+    a.xs = xs;
+    a.f = f;
+    a.nu = nu;
+    a.xt = xt;
+    a.tas = tas;
+    a.u = u;
+    a.flags = flags;
+    const dim3 g((unsigned)((nt + 255) / 256));
+    if (kernel == SE_STOKESLET) hipLaunchKernelGGL(k_dref_real<SE_STOKESLET>, g, dim3(256), 0, s, a);
+    else if (kernel == SE_ROTLET) hipLaunchKernelGGL(k_dref_real<SE_ROTLET>, g, dim3(256), 0, s, a);
+    else if (kernel == SE_HARMONIC) hipLaunchKernelGGL(k_dref_real<SE_HARMONIC>, g, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_dref_real<SE_STRESSLET>, g, dim3(256), 0, s, a);
+}
+
+void se_launch_dref_terms(int kernel, int D, const double* L, double xi, int64_t ns, const double* xs,
+                          const double* f, const double* nu, int64_t nt, const double* xt, int tas, double* sums,
+                          double* u, hipStream_t s)
+{
+    if (D != 3) return;
+    const double V = L[0] * L[1] * L[2];
+    const double self_c = kernel == SE_STOKESLET ? -4.0 * xi / kSqrtPi : (kernel == SE_HARMONIC ? -2.0 * xi / kSqrtPi : 0.0);
+    const double k0_c = kernel == SE_STRESSLET ? -8.0 * M_PI / V : 0.0;
+    const double bg_c = kernel == SE_HARMONIC ? -M_PI / (V * xi * xi) : 0.0;
+    hipLaunchKernelGGL(k_dref_sums, dim3(1), dim3(1024), 0, s, ns, xs, f, nu, kernel == SE_STRESSLET ? 1 : 0, sums);
+    hipLaunchKernelGGL(k_dref_terms, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, nt, tas ? xs : xt, f, tas,
+                       self_c, k0_c, bg_c, sums, u);
+}
+
 void se_launch_strengths(const se_plan* p, const double* f, int slot, hipStream_t s)
 {
     double* f64 = se_slot_fs64(p, slot);
