@@ -40,7 +40,8 @@ void free_all(se_plan* p)
     void* ptrs[] = {p->d_flags, p->d_src, p->d_nrm, p->d_src_perm, p->d_src_start, p->d_tgt, p->d_tgt_perm,
                     p->d_tgt_start, p->d_keys_a, p->d_keys_b, p->d_vals_a, p->d_sort_tmp, p->d_fs, p->d_fs64,
                     p->d_red, p->d_grid, p->d_spec, p->d_uF, p->d_uR, p->d_pkb, p->d_invw2, p->d_tw,
-                    p->d_pos4, p->d_tpos4, p->d_str4, p->d_nrm4, p->d_rtab, p->d_ktab, p->d_rwork};
+                    p->d_pos4, p->d_tpos4, p->d_str4, p->d_nrm4, p->d_rtab, p->d_ktab, p->d_rwork,
+                    p->d_rtx_s, p->d_rtx_t};
     for (void* q : ptrs)
         if (q) hipFree(q);
     for (se_aft_class& c : p->cls) {
@@ -396,6 +397,11 @@ se_status se_plan_create(const se_problem* prob, const se_params* manual, se_pla
     p->d_src_perm = A.get<int>(p->ns);
     p->d_src_start = A.get<int>(p->nbins + 1);
     p->d_rwork = A.get<int>(p->nbins + 1);
+    {
+        const int64_t ntiles = (int64_t)p->ntile[0] * p->ntile[1] * p->ntile[2];
+        p->d_rtx_s = A.get<int>(ntiles + 1);
+        if (!p->tas) p->d_rtx_t = A.get<int>(ntiles + 1);
+    }
     if (!p->tas) {
         p->d_tgt = A.get<double>(3 * p->nt);
         p->d_tgt_perm = A.get<int>(p->nt);
@@ -629,6 +635,7 @@ se_status se_run_plan(se_plan* p, const double* strengths, double* u, double* ur
         }
         {
             PhaseScope ps(p, 2, s);
+            if (r0 == 0) se_launch_tile_prep(p, s);
             se_launch_spread(p, 0, nr, s);
         }
         {

@@ -127,6 +127,8 @@ struct se_plan {
     double* d_nrm4 = nullptr;      // sorted normals AoS [ns][4] (stresslet)
     double* d_rtab = nullptr;      // radial-function table
     int* d_rwork = nullptr;        // real-space work offsets: target chunks per block, scanned (nbins + 1)
+    int* d_rtx_s = nullptr;        // gridding: items beyond each tile's first, scanned (ntiles + 1)
+    int* d_rtx_t = nullptr;        // gathering at separate targets: the same (ntiles + 1)
     double* d_ktab = nullptr;      // D = 0: truncated kernel Ahat_{R,tr} on the half spectrum
     double* d_uF = nullptr;        // [3][nt] sorted order
     double* d_uR = nullptr;        // [3][nt]
@@ -208,6 +210,11 @@ void se_launch_gather(const se_plan* p, int slot0, int nslot, hipStream_t s);
 // current launch shape (two small kernels); once per evaluation, before the
 // real-space launches.
 void se_launch_real_prep(const se_plan* p, hipStream_t s);
+// Work items of the register-tiled gridding and gathering for the bound
+// geometry (crowded tiles get items beyond their first); once per evaluation.
+void se_launch_tile_prep(const se_plan* p, hipStream_t s);
+// Exclusive scan of n ints in place by one workgroup; v[n] receives the total.
+void se_launch_scan_excl(int* v, int64_t n, hipStream_t s);
 // Direct Ewald reference (se_reference.cpp): all-pairs real space (or the
 // free-space sum for D = 0), the explicit k-space lattice sum, and the terms
 // outside both (self, stresslet k = 0, harmonic background).

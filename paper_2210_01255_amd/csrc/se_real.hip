@@ -1064,6 +1064,11 @@ bool real2_shape(const se_plan* p, const int Ra[3], se_real2_geom* bg)
 
 }  // namespace
 
+void se_launch_scan_excl(int* v, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, s, v, n);
+}
+
 void se_launch_real_prep(const se_plan* p, hipStream_t s)
 {
     int Ra[3];

@@ -32,6 +32,8 @@ struct se_tile_args {
     const double* pkb;  // [P][nu+1]
     int P, nu;
     double tg_c;        // truncated Gaussian: exp(-tg_c d^2), d in grid units; 0: PKB
+    int chunk;          // register-tiled kernels: candidates per work item (a multiple of the batch)
+    const int* xoff;    // exclusive scan over tiles of the items beyond each tile's first [ntiles + 1]
     int ntile[3];
     void* grid;         // real grid [ncomp][Mz][My][Mx]
     const void* fs;     // sorted strengths [ncomp][n] (gridding)
@@ -105,10 +107,9 @@ __device__ __forceinline__ int wrap_bin(const se_grid_geom& g, const int* ub, in
     return (wb[2] * g.nb[1] + wb[1]) * g.nb[0] + wb[0];
 }
 
-__device__ __forceinline__ void tile_origin(const int* ntile, int TX, int TY, int TZ, const se_grid_geom& g,
-                                            int* t0, int* te)
+__device__ __forceinline__ void tile_origin_at(int bid, const int* ntile, int TX, int TY, int TZ,
+                                               const se_grid_geom& g, int* t0, int* te)
 {
-    int bid = se_xcd_block(blockIdx.x, gridDim.x);
     int tx = bid % ntile[0];
     int ty = (bid / ntile[0]) % ntile[1];
     int tz = bid / (ntile[0] * ntile[1]);
@@ -118,6 +119,12 @@ __device__ __forceinline__ void tile_origin(const int* ntile, int TX, int TY, in
     te[0] = min(TX, g.Mg[0] - t0[0]);
     te[1] = min(TY, g.Mg[1] - t0[1]);
     te[2] = min(TZ, g.Mg[2] - t0[2]);
+}
+
+__device__ __forceinline__ void tile_origin(const int* ntile, int TX, int TY, int TZ, const se_grid_geom& g,
+                                            int* t0, int* te)
+{
+    tile_origin_at(se_xcd_block(blockIdx.x, gridDim.x), ntile, TX, TY, TZ, g, t0, te);
 }
 
 // Unrolled Horner with SE_MAX_NU + 1 coefficients (zero padded beyond nu,
@@ -560,21 +567,24 @@ __device__ int rt_stage_batch(const se_tile_args& a, const int* t0, int nslots, 
     return nb;
 }
 
-template <typename R, int NC, bool TG>
-__global__ void __launch_bounds__(SE_RT_THREADS, 4) k_spread_rt(se_tile_args a)
+// Gridding of one tile from its candidates c_lo .. c_hi - 1 (a work item).
+// The first item of a tile stores its sums; further items of a crowded tile
+// (EXTRA, launched after the first items) add theirs atomically.
+template <typename R, int NC, bool TG, bool EXTRA>
+__device__ __forceinline__ void spread_rt_tile(const se_tile_args& a, se_rt_lds<R, NC, false>& s, int tile, int c_lo,
+                                               int c_hi)
 {
-    __shared__ se_rt_lds<R, NC, false> s;
     const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const se_grid_geom& g = a.g;
     int t0[3], te[3];
-    tile_origin(a.ntile, SE_RT_TX, SE_RT_TY, SE_RT_TZ, g, t0, te);
+    tile_origin_at(tile, a.ntile, SE_RT_TX, SE_RT_TY, SE_RT_TZ, g, t0, te);
     for (int i = tid; i < SE_MAX_P * (SE_MAX_NU + 1); i += SE_RT_THREADS) {
         int q = i / (SE_MAX_NU + 1), k = i - q * (SE_MAX_NU + 1);
         s.pkb[i] = (q < a.P && k <= a.nu) ? a.pkb[q * (a.nu + 1) + k] : 0.0;
     }
     int b0[3], nbr[3];
     halo_bins(g, t0, te, a.P, b0, nbr);
-    const int total = rt_build_runs(a, t0, te, s, tid);
+    const int total = min(rt_build_runs(a, t0, te, s, tid), c_hi);
     int nseg = 1;
     if (g.periodic[0]) nseg = se_floordiv(b0[0] + nbr[0] - 1, g.nb[0]) - se_floordiv(b0[0], g.nb[0]) + 1;
     const int nslots = nbr[0] > 0 ? nbr[1] * nbr[2] * nseg : 0;
@@ -585,7 +595,7 @@ __global__ void __launch_bounds__(SE_RT_THREADS, 4) k_spread_rt(se_tile_args a)
     for (int z = 0; z < SE_RT_TZ; z++)
 #pragma unroll
         for (int c = 0; c < NC; c++) acc[z][c] = (R)0;
-    for (int base = 0; base < total; base += SE_RT_KB) {
+    for (int base = c_lo; base < total; base += SE_RT_KB) {
         (void)rt_stage_batch<R, false, NC, TG>(a, t0, nslots, total, base, s, tid);
         const int cnt = __builtin_amdgcn_readfirstlane(s.cnt[wave]);
         if constexpr (NC < 6) {
@@ -665,9 +675,50 @@ __global__ void __launch_bounds__(SE_RT_THREADS, 4) k_spread_rt(se_tile_args a)
             if (z < te[2]) {
                 const int64_t o = (int64_t)(t0[2] + z) * plane + col;
 #pragma unroll
-                for (int c = 0; c < NC; c++) grid[c * vol + o] = acc[z][c];
+                for (int c = 0; c < NC; c++) {
+                    if constexpr (EXTRA) {
+                        if (acc[z][c] != (R)0) atomicAdd(&grid[c * vol + o], acc[z][c]);
+                    } else {
+                        grid[c * vol + o] = acc[z][c];
+                    }
+                }
             }
         }
+    }
+}
+
+// The item -> tile map of the further items: the last tile whose offset is
+// <= e (tiles without further items share their offset with the next).
+__device__ __forceinline__ int rt_extra_tile(const int* xoff, int ntiles, int e)
+{
+    int lo = 0, hi = ntiles;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (xoff[mid] <= e) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// first item of every tile (XCD-aware tile order)
+template <typename R, int NC, bool TG>
+__global__ void __launch_bounds__(SE_RT_THREADS, 4) k_spread_rt(se_tile_args a)
+{
+    __shared__ se_rt_lds<R, NC, false> s;
+    spread_rt_tile<R, NC, TG, false>(a, s, se_xcd_block(blockIdx.x, gridDim.x), 0, a.chunk);
+}
+
+// further items of crowded tiles; the workgroups stride through them
+template <typename R, int NC, bool TG>
+__global__ void __launch_bounds__(SE_RT_THREADS, 4) k_spread_rt_extra(se_tile_args a, int ntiles)
+{
+    __shared__ se_rt_lds<R, NC, false> s;
+    const int items = a.xoff[ntiles];
+    for (int e = blockIdx.x; e < items; e += gridDim.x) {
+        const int tile = rt_extra_tile(a.xoff, ntiles, e);
+        const int c0 = (1 + e - a.xoff[tile]) * a.chunk;
+        spread_rt_tile<R, NC, TG, true>(a, s, tile, c0, c0 + a.chunk);
+        __syncthreads();
     }
 }
 
@@ -712,14 +763,16 @@ __device__ __forceinline__ double rt_dpp(double v)
 }
 constexpr int kDppRor8 = 0x128, kDppHalfMirror = 0x141, kDppXor2 = 0x4E, kDppXor1 = 0xB1;
 
+// Gathering of one tile to its candidates c_lo .. c_hi - 1 (a work item);
+// every item adds to the targets atomically.
 template <typename R, int NCG, bool TG>
-__global__ void __launch_bounds__(SE_RT_THREADS, 3) k_gather_rt(se_tile_args a)
+__device__ __forceinline__ void gather_rt_tile(const se_tile_args& a, se_rt_lds<R, NCG, true>& s, int tile, int c_lo,
+                                               int c_hi)
 {
-    __shared__ se_rt_lds<R, NCG, true> s;
     const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const se_grid_geom& g = a.g;
     int t0[3], te[3];
-    tile_origin(a.ntile, SE_RT_TX, SE_RT_TY, SE_RT_TZ, g, t0, te);
+    tile_origin_at(tile, a.ntile, SE_RT_TX, SE_RT_TY, SE_RT_TZ, g, t0, te);
     for (int i = tid; i < SE_MAX_P * (SE_MAX_NU + 1); i += SE_RT_THREADS) {
         int q = i / (SE_MAX_NU + 1), k = i - q * (SE_MAX_NU + 1);
         s.pkb[i] = (q < a.P && k <= a.nu) ? a.pkb[q * (a.nu + 1) + k] : 0.0;
@@ -744,13 +797,13 @@ __global__ void __launch_bounds__(SE_RT_THREADS, 3) k_gather_rt(se_tile_args a)
     }
     int b0[3], nbr[3];
     halo_bins(g, t0, te, a.P, b0, nbr);
-    const int total = rt_build_runs(a, t0, te, s, tid);
+    const int total = min(rt_build_runs(a, t0, te, s, tid), c_hi);
     int nseg = 1;
     if (g.periodic[0]) nseg = se_floordiv(b0[0] + nbr[0] - 1, g.nb[0]) - se_floordiv(b0[0], g.nb[0]) + 1;
     const int nslots = nbr[0] > 0 ? nbr[1] * nbr[2] * nseg : 0;
     const int64_t n = a.n;
     constexpr int GP = 24 / NCG;  // points per reduce-scatter group
-    for (int base = 0; base < total; base += SE_RT_KB) {
+    for (int base = c_lo; base < total; base += SE_RT_KB) {
         const int nb = rt_stage_batch<R, true, NCG, TG>(a, t0, nslots, total, base, s, tid);
         // Groups of GP points: per-lane partial sums v[NCG j + c] (24 values),
         // then one reduce-scatter over the wave: halving steps across lane
@@ -818,11 +871,72 @@ __global__ void __launch_bounds__(SE_RT_THREADS, 3) k_gather_rt(se_tile_args a)
     }
 }
 
+template <typename R, int NCG, bool TG>
+__global__ void __launch_bounds__(SE_RT_THREADS, 3) k_gather_rt(se_tile_args a)
+{
+    __shared__ se_rt_lds<R, NCG, true> s;
+    gather_rt_tile<R, NCG, TG>(a, s, se_xcd_block(blockIdx.x, gridDim.x), 0, a.chunk);
+}
+
+template <typename R, int NCG, bool TG>
+__global__ void __launch_bounds__(SE_RT_THREADS, 3) k_gather_rt_extra(se_tile_args a, int ntiles)
+{
+    __shared__ se_rt_lds<R, NCG, true> s;
+    const int items = a.xoff[ntiles];
+    for (int e = blockIdx.x; e < items; e += gridDim.x) {
+        const int tile = rt_extra_tile(a.xoff, ntiles, e);
+        const int c0 = (1 + e - a.xoff[tile]) * a.chunk;
+        gather_rt_tile<R, NCG, TG>(a, s, tile, c0, c0 + a.chunk);
+        __syncthreads();
+    }
+}
+
+// Candidates of every tile (the same runs as rt_build_runs, one thread per
+// tile) -> the number of items beyond the tile's first.
+__global__ void k_rt_count(se_tile_args a, int ntiles, int* __restrict__ cnt)
+{
+    const int tile = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tile >= ntiles) return;
+    const se_grid_geom& g = a.g;
+    int t0[3], te[3], b0[3], nbr[3];
+    tile_origin_at(tile, a.ntile, SE_RT_TX, SE_RT_TY, SE_RT_TZ, g, t0, te);
+    halo_bins(g, t0, te, a.P, b0, nbr);
+    int kx0 = 0, kx1 = 0;
+    if (g.periodic[0]) {
+        kx0 = se_floordiv(b0[0], g.nb[0]);
+        kx1 = se_floordiv(b0[0] + nbr[0] - 1, g.nb[0]);
+    }
+    const int nseg = nbr[0] > 0 ? kx1 - kx0 + 1 : 0;
+    const int nslots = nbr[1] * nbr[2] * nseg;
+    int total = 0;
+    for (int slot = 0; slot < nslots; slot++) {
+        const int row = slot / nseg, k = kx0 + slot % nseg;
+        const int uy = b0[1] + row % nbr[1], uz = b0[2] + row / nbr[1];
+        const int wy = g.periodic[1] ? uy - se_floordiv(uy, g.nb[1]) * g.nb[1] : uy;
+        const int wz = g.periodic[2] ? uz - se_floordiv(uz, g.nb[2]) * g.nb[2] : uz;
+        int lo = b0[0], hi = b0[0] + nbr[0] - 1;
+        if (g.periodic[0]) {
+            lo = max(lo, k * g.nb[0]);
+            hi = min(hi, (k + 1) * g.nb[0] - 1);
+        }
+        const int wx0 = lo - k * g.nb[0];
+        const int rowbase = (wz * g.nb[1] + wy) * g.nb[0];
+        total += a.start[rowbase + wx0 + (hi - lo + 1)] - a.start[rowbase + wx0];
+    }
+    cnt[tile] = total > a.chunk ? (total - 1) / a.chunk : 0;
+}
+
 template <typename K>
 void set_lds(K kern, size_t bytes)
 {
     if (bytes > 65536) (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
+
+// Candidates per work item of the register-tiled kernels (16 batches): a
+// tile of uniform points at the usual densities has a few hundred, so it
+// stays one item; a tile over a dense cluster is split.
+constexpr int kRtChunk = 16 * SE_RT_KB;
+constexpr unsigned kRtExtraBlocks = 1024;
 
 se_tile_args make_args(const se_plan* p, bool gather, int slot)
 {
@@ -835,6 +949,8 @@ se_tile_args make_args(const se_plan* p, bool gather, int slot)
     a.P = p->par.P;
     a.nu = p->par.nu_deg;
     a.tg_c = p->par.window == SE_WINDOW_TG ? 4.0 * p->par.alpha / ((double)a.P * a.P) : 0.0;
+    a.chunk = kRtChunk;
+    a.xoff = gather && !p->tas ? p->d_rtx_t : p->d_rtx_s;
     for (int d = 0; d < 3; d++) a.ntile[d] = p->ntile[d];
     a.grid = se_slot_grid(p, slot);
     a.fs = se_slot_fs(p, slot);
@@ -896,8 +1012,15 @@ void launch_spread_rt(const se_plan* p, int slot, hipStream_t s)
 {
     se_tile_args a = make_args(p, false, slot);
     unsigned nb = (unsigned)(p->ntile[0] * p->ntile[1] * p->ntile[2]);
-    if (a.tg_c > 0.0) hipLaunchKernelGGL((k_spread_rt<R, NC, true>), dim3(nb), dim3(SE_RT_THREADS), 0, s, a);
-    else hipLaunchKernelGGL((k_spread_rt<R, NC, false>), dim3(nb), dim3(SE_RT_THREADS), 0, s, a);
+    if (a.tg_c > 0.0) {
+        hipLaunchKernelGGL((k_spread_rt<R, NC, true>), dim3(nb), dim3(SE_RT_THREADS), 0, s, a);
+        hipLaunchKernelGGL((k_spread_rt_extra<R, NC, true>), dim3(kRtExtraBlocks), dim3(SE_RT_THREADS), 0, s, a,
+                           (int)nb);
+    } else {
+        hipLaunchKernelGGL((k_spread_rt<R, NC, false>), dim3(nb), dim3(SE_RT_THREADS), 0, s, a);
+        hipLaunchKernelGGL((k_spread_rt_extra<R, NC, false>), dim3(kRtExtraBlocks), dim3(SE_RT_THREADS), 0, s, a,
+                           (int)nb);
+    }
 }
 
 template <typename R, int NCG>
@@ -905,8 +1028,27 @@ void launch_gather_rt(const se_plan* p, int slot, hipStream_t s)
 {
     se_tile_args a = make_args(p, true, slot);
     unsigned nb = (unsigned)(p->ntile[0] * p->ntile[1] * p->ntile[2]);
-    if (a.tg_c > 0.0) hipLaunchKernelGGL((k_gather_rt<R, NCG, true>), dim3(nb), dim3(SE_RT_THREADS), 0, s, a);
-    else hipLaunchKernelGGL((k_gather_rt<R, NCG, false>), dim3(nb), dim3(SE_RT_THREADS), 0, s, a);
+    if (a.tg_c > 0.0) {
+        hipLaunchKernelGGL((k_gather_rt<R, NCG, true>), dim3(nb), dim3(SE_RT_THREADS), 0, s, a);
+        hipLaunchKernelGGL((k_gather_rt_extra<R, NCG, true>), dim3(kRtExtraBlocks), dim3(SE_RT_THREADS), 0, s, a,
+                           (int)nb);
+    } else {
+        hipLaunchKernelGGL((k_gather_rt<R, NCG, false>), dim3(nb), dim3(SE_RT_THREADS), 0, s, a);
+        hipLaunchKernelGGL((k_gather_rt_extra<R, NCG, false>), dim3(kRtExtraBlocks), dim3(SE_RT_THREADS), 0, s, a,
+                           (int)nb);
+    }
+}
+
+void se_launch_tile_prep(const se_plan* p, hipStream_t s)
+{
+    if (!se_rt_fits(p)) return;
+    const int ntiles = p->ntile[0] * p->ntile[1] * p->ntile[2];
+    for (int which = 0; which < (p->tas ? 1 : 2); which++) {
+        se_tile_args a = make_args(p, which == 1, 0);
+        int* cnt = which == 1 ? p->d_rtx_t : p->d_rtx_s;
+        hipLaunchKernelGGL(k_rt_count, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0, s, a, ntiles, cnt);
+        se_launch_scan_excl(cnt, ntiles, s);
+    }
 }
 
 // slot0 .. slot0 + nslot - 1: right-hand sides of the current chunk (two
