@@ -337,6 +337,14 @@ se_status se_mlp_adam(float* theta, float* m, float* v, const float* grad, int64
 
 /* Direct Ewald reference on the GPU (no grid, no window), for checking the
  * fast method on large systems on every target.
+ *   periodicity 2, 1: the decomposition of Sec. 2.3 with the same real
+ *     space (images along the periodic axes, rc = min periodic side / 2),
+ *     the modes k^P != 0 of eqs. (2p-fourier-space) / (1p-fourier-space) by
+ *     the trapezoidal rule in the free wavenumbers (a lattice sum over the
+ *     cell whose free sides are extended by 7 times the longest periodic
+ *     side), the modes k^P = 0 in the closed forms of Appendices A.2 and B.2
+ *     (the D = 1 stokeslet in the gauge l_B = 1, the harmonic with l_H = 1),
+ *     and the self term; sources and targets must lie in the box;
  *   periodicity 3: the classical Ewald sum of Sec. 2.2, eqs.
  *     (3p-ewald-decomp-self), (real-space-potential-3p),
  *     (fourier-space-potential-3p), (k0-stresslet-3p), (self-term): the
@@ -345,7 +353,7 @@ se_status se_mlp_adam(float* theta, float* m, float* v, const float* grad, int64
  *     the explicit lattice sum over 0 < |k| <= 13 xi; the harmonic adds its
  *     neutralising background -pi Q_c/(V xi^2);
  *   periodicity 0: the free-space sum over all pairs.
- * Both truncations sit near e^{-42}.  xi <= 0 picks 13 / min(L); a caller xi
+ * Both truncations sit near e^{-42}.  xi <= 0 picks 13 / (least periodic side); a caller xi
  * below that is rejected (SE_ERR_ARG: the real-space tail would exceed the
  * cut-off).  Cost O(N_t N_s) pairs plus O((N_s + N_t) N_k) phases.
  * kernel: SE_STOKESLET, SE_ROTLET, SE_STRESSLET or SE_HARMONIC; strengths

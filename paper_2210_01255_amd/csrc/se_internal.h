@@ -224,6 +224,8 @@ void se_launch_dref_real(int kernel, int D, const double* L, double xi, double r
 void se_launch_dref_kspace(int kernel, int nk, const double* kv, double xi, double volume, int64_t ns,
                            const double* xs, const double* f, const double* nu, double* U, int64_t nt,
                            const double* xt, double* u, hipStream_t s);
+void se_launch_dref_zero(int kernel, int D, const double* L, double xi, int64_t ns, const double* xs,
+                         const double* f, const double* nu, int64_t nt, const double* xt, double* u, hipStream_t s);
 void se_launch_dref_terms(int kernel, int D, const double* L, double xi, int64_t ns, const double* xs,
                           const double* f, const double* nu, int64_t nt, const double* xt, int tas, double* sums,
                           double* u, hipStream_t s);

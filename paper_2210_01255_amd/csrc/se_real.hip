@@ -905,7 +905,7 @@ __global__ void __launch_bounds__(256) k_dref_real(se_dref_r_args a)
                     if (d < a.D) r[d] -= a.L[d] * rint(r[d] / a.L[d]);
                 }
                 const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-                if (a.D == 3 && r2 >= a.rc2) continue;
+                if (a.D > 0 && r2 >= a.rc2) continue;
                 if (r2 == 0.0) {
                     coinc = 1;
                     continue;
@@ -925,6 +925,154 @@ __global__ void __launch_bounds__(256) k_dref_real(se_dref_r_args a)
     if (m < a.nt)
         for (int d = 0; d < 3; d++) a.u[3 * m + d] = acc[d];
     if (coinc) atomicOr(a.flags, SE_FLAG_COINCIDENT);
+}
+
+// Zero modes k^P = 0 of the Fourier part for D = 2 and D = 1, in the closed
+// forms of Appendix A.2 (eqs. 2p-rotlet-Q0, 2p-stokeslet-Q0,
+// 2p-stresslet-Q0 and the harmonic's Q^{H,2P,(0)}) and Appendix B.2 (eqs.
+// 1p-rotlet-Q0, 1p-stokeslet-Q0 with its limit, 1p-stresslet-Q0, and
+// Q^{H,1P,(0)} with l_H = 1), over all pairs including m = n.
+// E1 by its power series (x <= 1) and its continued fraction evaluated
+// with the modified Lentz method (x > 1).
+__device__ double dref_e1(double x)
+{
+    const double euler = 0.57721566490153286061;
+    if (x <= 1.0) {
+        double term = 1.0, sum = 0.0;
+        for (int k = 1; k < 80; k++) {
+            term *= -x / k;
+            sum += term / k;
+            if (fabs(term) < 1e-18 * k * fabs(sum)) break;
+        }
+        return -euler - log(x) - sum;
+    }
+    double b = x + 1.0, c = 1e300, d = 1.0 / b, h = d;
+    for (int i = 1; i < 300; i++) {
+        const double an = -(double)i * i;
+        b += 2.0;
+        d = 1.0 / (an * d + b);
+        c = b + an / c;
+        const double del = c * d;
+        h *= del;
+        if (fabs(del - 1.0) < 1e-16) break;
+    }
+    return h * exp(-x);
+}
+
+template <int KER>
+__device__ __forceinline__ void dref_zero_2p(double xi, double r3, const double* f, const double* nu, double* u)
+{
+    const double e = exp(-xi * xi * r3 * r3), ef = erf(xi * r3);
+    if constexpr (KER == SE_HARMONIC) {
+        const double c = -2.0 * M_PI * (r3 * ef + e / (kSqrtPi * xi));
+        for (int j = 0; j < 3; j++) u[j] += c * f[j];
+    } else if constexpr (KER == SE_STOKESLET) {
+        const double c = -2.0 * M_PI * (2.0 * r3 * ef + e / (kSqrtPi * xi));
+        u[0] += c * f[0];
+        u[1] += c * f[1];
+    } else if constexpr (KER == SE_ROTLET) {
+        const double c = 2.0 * M_PI * ef;
+        u[0] += c * f[1];
+        u[1] -= c * f[0];
+    } else {
+        const double c = -4.0 * M_PI * (ef + xi * r3 * e / kSqrtPi);
+        u[0] += c * (f[0] * nu[2] + f[2] * nu[0]);
+        u[1] += c * (f[1] * nu[2] + f[2] * nu[1]);
+        u[2] += c * (f[0] * nu[0] + f[1] * nu[1] + f[2] * nu[2]);
+    }
+}
+
+template <int KER>
+__device__ __forceinline__ void dref_zero_1p(double xi, double r2, double r3, const double* f, const double* nu,
+                                             double* u)
+{
+    const double euler = 0.57721566490153286061;
+    const double rho2 = r2 * r2 + r3 * r3, V = xi * xi * rho2;
+    if (rho2 == 0.0) {
+        if constexpr (KER == SE_HARMONIC) {
+            const double c = euler + log(xi * xi);
+            for (int j = 0; j < 3; j++) u[j] += c * f[j];
+        } else if constexpr (KER == SE_STOKESLET) {
+            const double c = euler + log(xi * xi) - 1.0;
+            u[0] += 2.0 * c * f[0];
+            u[1] += c * f[1];
+            u[2] += c * f[2];
+        }
+        return;  // rotlet and stresslet: zero
+    }
+    const double rho = sqrt(rho2), t2 = r2 / rho, t3 = r3 / rho;
+    const double p1 = -expm1(-V);
+    if constexpr (KER == SE_HARMONIC) {
+        const double c = -(dref_e1(V) + log(rho2));
+        for (int j = 0; j < 3; j++) u[j] += c * f[j];
+    } else if constexpr (KER == SE_ROTLET) {
+        const double c = 2.0 * p1 / rho;
+        u[0] += c * (t3 * f[1] - t2 * f[2]);
+        u[1] -= c * t3 * f[0];
+        u[2] += c * t2 * f[0];
+    } else if constexpr (KER == SE_STOKESLET) {
+        const double p0 = dref_e1(V) + log(rho2) + 1.0;
+        u[0] -= 2.0 * (p0 + p1) * f[0];
+        u[1] -= (p0 + 2.0 * t3 * t3 * p1) * f[1] - 2.0 * t2 * t3 * p1 * f[2];
+        u[2] -= -2.0 * t2 * t3 * p1 * f[1] + (p0 + 2.0 * t2 * t2 * p1) * f[2];
+    } else {
+        double p2;
+        if (V < 0.05) {  // 1 - (1 + V) e^{-V} = sum_{n>=2} (-1)^n (n-1) V^n / n!
+            double pw = V * V, fact = 2.0;
+            p2 = 0.0;
+            for (int n = 2; n < 24; n++) {
+                p2 += ((n & 1) ? -1.0 : 1.0) * (n - 1) * pw / fact;
+                pw *= V;
+                fact *= n + 1;
+            }
+        } else {
+            p2 = p1 - V * exp(-V);
+        }
+        const double R = -4.0 / rho;
+        const double q112 = R * t2 * (2.0 * p1 - p2), q113 = R * t3 * (2.0 * p1 - p2);
+        const double q222 = R * t2 * (3.0 * p1 - (t2 * t2 + 3.0 * t3 * t3) * p2);
+        const double q223 = R * t3 * (p1 - (t3 * t3 - t2 * t2) * p2);
+        const double q233 = R * t2 * (p1 - (t2 * t2 - t3 * t3) * p2);
+        const double q333 = R * t3 * (3.0 * p1 - (3.0 * t2 * t2 + t3 * t3) * p2);
+        const double* q = f;
+        u[0] += q112 * (q[0] * nu[1] + q[1] * nu[0]) + q113 * (q[0] * nu[2] + q[2] * nu[0]);
+        u[1] += q112 * q[0] * nu[0] + q222 * q[1] * nu[1] + q223 * (q[1] * nu[2] + q[2] * nu[1]) + q233 * q[2] * nu[2];
+        u[2] += q113 * q[0] * nu[0] + q223 * q[1] * nu[1] + q233 * (q[1] * nu[2] + q[2] * nu[1]) + q333 * q[2] * nu[2];
+    }
+}
+
+template <int KER>
+__global__ void __launch_bounds__(256) k_dref_zero(se_dref_r_args a, double inv_area)
+{
+    constexpr int NN = KER == SE_STRESSLET ? 256 : 1;
+    __shared__ double sx[256][3], sf[256][3], sn[NN][3];
+    const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double x[3] = {0.0, 0.0, 0.0};
+    if (m < a.nt)
+        for (int d = 0; d < 3; d++) x[d] = a.xt[3 * m + d];
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int64_t base = 0; base < a.ns; base += 256) {
+        const int64_t n = base + threadIdx.x;
+        if (n < a.ns)
+            for (int d = 0; d < 3; d++) {
+                sx[threadIdx.x][d] = a.xs[3 * n + d];
+                sf[threadIdx.x][d] = a.f[3 * n + d];
+                if constexpr (KER == SE_STRESSLET) sn[threadIdx.x][d] = a.nu[3 * n + d];
+            }
+        __syncthreads();
+        const int cnt = (int)min((int64_t)256, a.ns - base);
+        if (m < a.nt) {
+            for (int j = 0; j < cnt; j++) {
+                const double* nn = nullptr;
+                if constexpr (KER == SE_STRESSLET) nn = sn[j];
+                if (a.D == 2) dref_zero_2p<KER>(a.xi, x[2] - sx[j][2], sf[j], nn, acc);
+                else dref_zero_1p<KER>(a.xi, x[1] - sx[j][1], x[2] - sx[j][2], sf[j], nn, acc);
+            }
+        }
+        __syncthreads();
+    }
+    if (m < a.nt)
+        for (int d = 0; d < 3; d++) a.u[3 * m + d] += acc[d] * inv_area;
 }
 
 // Source sums for the terms outside the lattice sums: sum f (3), sum q.nu,
@@ -994,15 +1142,37 @@ void se_launch_dref_real(int kernel, int D, const double* L, double xi, double r
     else hipLaunchKernelGGL(k_dref_real<SE_STRESSLET>, g, dim3(256), 0, s, a);
 }
 
+void se_launch_dref_zero(int kernel, int D, const double* L, double xi, int64_t ns, const double* xs,
+                         const double* f, const double* nu, int64_t nt, const double* xt, double* u, hipStream_t s)
+{
+    if (D != 1 && D != 2) return;
+    se_dref_r_args a{};
+    a.D = D;
+    a.xi = xi;
+    a.ns = ns;
+    a.nt = nt;
+    a.xs = xs;
+    a.f = f;
+    a.nu = nu;
+    a.xt = xt;
+    a.u = u;
+    const double inv_area = D == 2 ? 1.0 / (L[0] * L[1]) : 1.0 / L[0];
+    const dim3 g((unsigned)((nt + 255) / 256));
+    if (kernel == SE_STOKESLET) hipLaunchKernelGGL(k_dref_zero<SE_STOKESLET>, g, dim3(256), 0, s, a, inv_area);
+    else if (kernel == SE_ROTLET) hipLaunchKernelGGL(k_dref_zero<SE_ROTLET>, g, dim3(256), 0, s, a, inv_area);
+    else if (kernel == SE_HARMONIC) hipLaunchKernelGGL(k_dref_zero<SE_HARMONIC>, g, dim3(256), 0, s, a, inv_area);
+    else hipLaunchKernelGGL(k_dref_zero<SE_STRESSLET>, g, dim3(256), 0, s, a, inv_area);
+}
+
 void se_launch_dref_terms(int kernel, int D, const double* L, double xi, int64_t ns, const double* xs,
                           const double* f, const double* nu, int64_t nt, const double* xt, int tas, double* sums,
                           double* u, hipStream_t s)
 {
-    if (D != 3) return;
+    if (D == 0) return;
     const double V = L[0] * L[1] * L[2];
     const double self_c = kernel == SE_STOKESLET ? -4.0 * xi / kSqrtPi : (kernel == SE_HARMONIC ? -2.0 * xi / kSqrtPi : 0.0);
-    const double k0_c = kernel == SE_STRESSLET ? -8.0 * M_PI / V : 0.0;
-    const double bg_c = kernel == SE_HARMONIC ? -M_PI / (V * xi * xi) : 0.0;
+    const double k0_c = kernel == SE_STRESSLET && D == 3 ? -8.0 * M_PI / V : 0.0;
+    const double bg_c = kernel == SE_HARMONIC && D == 3 ? -M_PI / (V * xi * xi) : 0.0;
     hipLaunchKernelGGL(k_dref_sums, dim3(1), dim3(1024), 0, s, ns, xs, f, nu, kernel == SE_STRESSLET ? 1 : 0, sums);
     hipLaunchKernelGGL(k_dref_terms, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, nt, tas ? xs : xt, f, tas,
                        self_c, k0_c, bg_c, sums, u);

@@ -34,10 +34,13 @@ def _gpu_ref(se, torch, kernel, D, s, targets=None):
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
-@pytest.mark.parametrize("D,box", [(3, (1.0, 1.0, 1.0)), (3, (1.3, 0.8, 1.9)), (0, (1.0, 1.0, 1.0))])
+@pytest.mark.parametrize("D,box", [(3, (1.0, 1.0, 1.0)), (3, (1.3, 0.8, 1.9)), (0, (1.0, 1.0, 1.0)),
+                                   (2, (1.0, 1.0, 1.0)), (2, (1.2, 0.9, 1.1)), (1, (1.0, 1.0, 1.0)),
+                                   (1, (1.3, 0.9, 1.1))])
 def test_reference_matches_oracle(env, kernel, D, box):
     se, oracle, torch = env
-    s = W.system(8100 + D, 800, box=box, kernel=kernel, zero_mean=(kernel == "stokeslet"))
+    n = 800 if D in (0, 3) else 400
+    s = W.system(8100 + D, n, box=box, kernel=kernel, zero_mean=(kernel == "stokeslet"), periodicity=D)
     print("case reference %s D=%d box=%s" % (kernel, D, box), flush=True)
     u = _gpu_ref(se, torch, kernel, D, s)
     err = oracle.rms_rel_error(u, _ref(env, kernel, s, D=D))
@@ -53,7 +56,7 @@ def test_reference_rejects_bad_arguments(env):
     s = W.system(8300, 50)
     x, f = _dev(torch, s["x"]), _dev(torch, s["f"])
     with pytest.raises(se.SEError):
-        se.ewald_reference("stokeslet", 2, (1, 1, 1), x, f)       # D = 2 not offered
+        se.ewald_reference("stokeslet", 4, (1, 1, 1), x, f)       # no such periodicity
     with pytest.raises(se.SEError):
         se.ewald_reference("stokeslet", 3, (1, 1, 1), x, f, xi=3.0)  # real-space tail beyond L/2
     with pytest.raises(se.SEError):
@@ -73,6 +76,28 @@ def test_fast_method_on_all_targets_n1e5(env, kernel, tol):
     ref = _gpu_ref(se, torch, kernel, 3, s)
     err = oracle.rms_rel_error(u.cpu().numpy(), ref)
     print("case %s N=1e5 tol=%g: all-target rms-rel err %.3g" % (kernel, tol, err), flush=True)
+    assert err <= tol
+
+
+@pytest.mark.parametrize("D,kernel,tol,prec", [(2, "stokeslet", 1e-8, "fp64"), (2, "stresslet", 1e-6, "fp32"),
+                                               (1, "rotlet", 1e-8, "fp64"), (1, "stresslet", 1e-6, "fp64")])
+def test_fast_method_on_all_targets_reduced(env, D, kernel, tol, prec):
+    """Doubly and singly periodic systems of N = 2e4 (the doubly periodic
+    workload's size) on every target."""
+    se, oracle, torch = env
+    n = 20_000
+    s = W.system(8500 + D, n, kernel=kernel, periodicity=D)
+    plan = se.Plan(kernel=kernel, periodicity=D, tol=tol, n_src=n, source_q=_q_of(kernel, s), safety=10.0,
+                   precision=se.PREC_FP64 if prec == "fp64" else se.PREC_FP32)
+    plan.set_geometry(_dev(torch, s["x"]), _dev(torch, s.get("nu")))
+    u = plan.execute(_dev(torch, s["q"] if kernel == "stresslet" else s["f"]))
+    plan.sync()
+    t0 = time.perf_counter()
+    ref = _gpu_ref(se, torch, kernel, D, s)
+    t1 = time.perf_counter()
+    err = oracle.rms_rel_error(u.cpu().numpy(), ref)
+    print("case %s D=%d N=2e4 tol=%g %s: all-target rms-rel err %.3g (reference %.2f s)" %
+          (kernel, D, tol, prec, err, t1 - t0), flush=True)
     assert err <= tol
 
 
