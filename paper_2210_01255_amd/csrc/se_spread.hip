@@ -16,6 +16,7 @@
 // point is visited once, so supports wider than the grid are handled too);
 // free axes are clipped.
 #include <algorithm>
+#include <cmath>
 
 #include "se_device.h"
 
@@ -932,11 +933,30 @@ void set_lds(K kern, size_t bytes)
     if (bytes > 65536) (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-// Candidates per work item of the register-tiled kernels (16 batches): a
-// tile of uniform points at the usual densities has a few hundred, so it
-// stays one item; a tile over a dense cluster is split.
+// Candidates per work item of the register-tiled kernels: at least 16
+// batches.  When the grid has tiles enough to fill the chip several times
+// over, a tile is split only well above the mean candidate count of a
+// uniform system (three times it), so that only tiles over dense clusters
+// split; on grids with few tiles the 16-batch items also add parallelism.
 constexpr int kRtChunk = 16 * SE_RT_KB;
 constexpr unsigned kRtExtraBlocks = 1024;
+constexpr int64_t kRtManyTiles = 8192;
+
+int rt_chunk(const se_plan* p, int64_t npts)
+{
+    const int64_t ntiles = (int64_t)p->ntile[0] * p->ntile[1] * p->ntile[2];
+    if (ntiles < kRtManyTiles) return kRtChunk;
+    const se_grid_geom& g = p->g;
+    const int T[3] = {SE_RT_TX, SE_RT_TY, SE_RT_TZ};
+    double frac = 1.0;  // halo bins of a tile / all bins, per axis
+    for (int d = 0; d < 3; d++) {
+        const int nbr = std::min((T[d] + p->par.P - 2) / g.B[d] + 2, g.nb[d]);
+        frac *= (double)nbr / g.nb[d];
+    }
+    const double mean = frac * (double)npts;
+    const int64_t c = ((int64_t)std::ceil(3.0 * mean / SE_RT_KB)) * SE_RT_KB;
+    return (int)std::max<int64_t>(kRtChunk, std::min<int64_t>(c, 1 << 20));
+}
 
 se_tile_args make_args(const se_plan* p, bool gather, int slot)
 {
@@ -949,7 +969,7 @@ se_tile_args make_args(const se_plan* p, bool gather, int slot)
     a.P = p->par.P;
     a.nu = p->par.nu_deg;
     a.tg_c = p->par.window == SE_WINDOW_TG ? 4.0 * p->par.alpha / ((double)a.P * a.P) : 0.0;
-    a.chunk = kRtChunk;
+    a.chunk = rt_chunk(p, a.n);
     a.xoff = gather && !p->tas ? p->d_rtx_t : p->d_rtx_s;
     for (int d = 0; d < 3; d++) a.ntile[d] = p->ntile[d];
     a.grid = se_slot_grid(p, slot);
