@@ -368,6 +368,32 @@ se_status se_ewald_reference(int32_t kernel, int32_t periodicity, const double b
                              const double* src_xyz, const double* strengths, const double* normals_xyz,
                              int64_t n_tgt, const double* tgt_xyz, double* u_out, int32_t device, void* stream);
 
+/* Boundary-integral driver: restarted GMRES over the plan's periodic
+ * stresslet sum, the use the method is built for (Sec. 6), on the nodes x_n
+ * of closed surfaces with quadrature weights w_n and unit outward normals
+ * nu_n (the plan's sources and normals).  The double layer is regularised
+ * with the stresslet identity (Sec. 2.4, eq. stresslet-identity), whose
+ * value on the surface is 4 pi q0:
+ *   (D q)_m = sum_{n != m} w_n T^{DP}(x_m - x_n) (q_n - q_m) nu_n + 4 pi q_m,
+ * and the solver returns q with alpha q + D q = g for each of the plan's
+ * n_rhs right-hand sides, in lock step (one evaluation covers all sets).
+ * With outward normals the double layer of a constant density is 8 pi q0
+ * inside and 0 outside, so alpha = +4 pi and -4 pi give its interior and
+ * exterior limits.
+ * plan: SE_STRESSLET, targets are sources, geometry bound.  weights [n]
+ * device; g [n_rhs][n][3] device; q [n_rhs][n][3] device, the initial guess
+ * on entry and the solution on return.  GMRES(restart) with classical
+ * Gram-Schmidt applied twice; a cycle ends when every system's residual
+ * estimate is <= tol |g| or after max_iter operator applications in total;
+ * each cycle starts from the true residual.  iters (host, may be null)
+ * receives the applications used, resid (host, n_rhs, may be null) the last
+ * relative residuals (true residuals once converged).  Allocates and frees
+ * its Krylov basis ((restart + 4) n_rhs 3 n doubles) and synchronises the
+ * stream.  Errors: SE_ERR_ARG, SE_ERR_STATE (no geometry), SE_ERR_NOMEM,
+ * SE_ERR_HIP and those of se_execute. */
+se_status se_bie_solve(se_plan* plan, double alpha, const double* weights, const double* g, double* q,
+                       int32_t restart, int32_t max_iter, double tol, int32_t* iters, double* resid, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -60,7 +60,7 @@ EXPORTS = ["se_version", "se_status_string", "se_params_select", "se_plan_create
            "se_debug_cell_list", "se_plan_set_shape", "se_plan_get_shape", "se_batch_create", "se_batch_destroy",
            "se_batch_plan", "se_batch_set_geometry", "se_batch_execute", "se_batch_tune", "se_selector_features",
            "se_selector_train", "se_selector_save", "se_selector_load", "se_selector_ready", "se_selector_get",
-           "se_selector_predict", "se_mlp_loss_grad", "se_mlp_forward", "se_mlp_adam", "se_ewald_reference"]
+           "se_selector_predict", "se_mlp_loss_grad", "se_mlp_forward", "se_mlp_adam", "se_ewald_reference", "se_bie_solve"]
 
 PHASES = ["geometry", "strengths", "spread", "fft_fwd_xy", "fft_z_scale", "fft_inv_yx", "gather", "real_space",
           "epilogue"]
@@ -167,6 +167,9 @@ def _load():
     L.se_ewald_reference.restype = i32
     L.se_ewald_reference.argtypes = [i32, i32, P(ctypes.c_double), ctypes.c_double, ctypes.c_int64, vp, vp, vp,
                                      ctypes.c_int64, vp, vp, i32, vp]
+    L.se_bie_solve.restype = i32
+    L.se_bie_solve.argtypes = [vp, ctypes.c_double, vp, vp, vp, i32, i32, ctypes.c_double, P(i32),
+                               P(ctypes.c_double), vp]
     L.se_mlp_adam.restype = i32
     L.se_mlp_adam.argtypes = [vp, vp, vp, vp, ctypes.c_int64, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                               ctypes.c_float, vp]
@@ -210,6 +213,7 @@ se_mlp_loss_grad = lib.se_mlp_loss_grad
 se_mlp_forward = lib.se_mlp_forward
 se_mlp_adam = lib.se_mlp_adam
 se_ewald_reference = lib.se_ewald_reference
+se_bie_solve = lib.se_bie_solve
 
 
 def make_problem(kernel="stokeslet", periodicity=3, box=(1.0, 1.0, 1.0), tol=1e-8, tol_kind=TOL_REL,
@@ -248,6 +252,24 @@ def params_to_dict(par: se_params) -> dict:
             v = list(v)
         out[name] = v
     return out
+
+
+def bie_solve(plan, alpha, weights, g, q0=None, restart=30, max_iter=300, tol=1e-10, stream=None):
+    """GMRES for alpha q + D q = g (se_bie_solve) on a stresslet plan whose
+    geometry (surface nodes and normals) is bound; g [n_rhs][n][3] (or
+    [n][3]) device FP64.  Returns (q, iterations, relative residuals)."""
+    import torch
+    shp = (plan.n_rhs, plan.n_src, 3) if plan.n_rhs > 1 else (plan.n_src, 3)
+    Plan._check(g, shp, "g")
+    Plan._check(weights, (plan.n_src,), "weights")
+    q = torch.zeros_like(g) if q0 is None else q0.clone()
+    it = ctypes.c_int32(0)
+    res = (ctypes.c_double * plan.n_rhs)()
+    st = lib.se_bie_solve(plan.handle, ctypes.c_double(float(alpha)), _ptr(weights), _ptr(g), _ptr(q), int(restart),
+                          int(max_iter), ctypes.c_double(float(tol)), ctypes.byref(it), res, _stream(stream))
+    if st != SE_OK:
+        raise SEError(st, "se_bie_solve")
+    return q, int(it.value), list(res)
 
 
 def ewald_reference(kernel, periodicity, box, x, strengths, normals=None, targets=None, xi=0.0, stream=None):
