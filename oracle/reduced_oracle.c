@@ -14,8 +14,9 @@
  *     eqs. (1p-stokeslet-Q0-limit), (1p-stresslet-Q0-limit) and a zero rotlet.
  *
  *
- *   harmonic (per component; the classical Ewald zero modes, gauge -2 pi |z|
- *   for D = 2 and -2 log(rho) for D = 1, i.e. the xi -> infinity limits):
+ *   harmonic (per component): Q^{H,2P,(0)} of Appendix A.2 and Q^{H,1P,(0)}
+ *   of Appendix B.2 with l_H = 1 (gauges -2 pi |z| and -2 log(rho), their
+ *   xi -> infinity limits):
  *     D = 2:  -2 pi (r3 erf(xi r3) + e^{-xi^2 r3^2}/(sqrt(pi) xi))
  *     D = 1:  -(E1(xi^2 rho^2) + log(rho^2)), at rho = 0: euler + log(xi^2)
  *

@@ -92,3 +92,28 @@ def test_elongated_clustered_16_rhs_fp32(env, D, kernel):
         print("D=%d %s rhs %d sampled err fp64 %.3g fp32 %.3g" % (D, kernel, r, e64, e32), flush=True)
         assert e64 <= 1e-8
         assert e32 <= tol
+
+
+@pytest.mark.parametrize("D,kernel", [(1, "rotlet"), (0, "stresslet")])
+def test_elongated_clustered_all_targets(env, D, kernel):
+    """The same elongated clustered workload (N = 1e5, 16 rhs, FP32 at 1e-6
+    and FP64 at 1e-9) against the GPU direct reference on every target, for
+    the first and the last strength set."""
+    import torch
+    se, oracle, _ = env
+    n, nrhs, tol = 100000, 16, 1e-6
+    s = W.system(2700 + 10 * D + len(kernel), n, box=(4.0, 1.0, 1.0), kernel=kernel, layout="mixed",
+                 periodicity=D, n_rhs=nrhs)
+    u32 = _plan_run(env, kernel, s, D, tol, se.PREC_FP32, nrhs)
+    u64 = _plan_run(env, kernel, s, D, 1e-9, se.PREC_FP64, nrhs)
+    dev = torch.device("cuda:0")
+    x = torch.tensor(s["x"], device=dev)
+    nu = torch.tensor(s["nu"], device=dev) if kernel == "stresslet" else None
+    for r in (0, nrhs - 1):
+        a = torch.tensor(np.ascontiguousarray((s["q"] if kernel == "stresslet" else s["f"])[r]), device=dev)
+        ref = se.ewald_reference(kernel, D, (4.0, 1.0, 1.0), x, a, normals=nu).cpu().numpy()
+        e64 = oracle.rms_rel_error(u64[r], ref)
+        e32 = oracle.rms_rel_error(u32[r], ref)
+        print("D=%d %s rhs %d all-target err fp64 %.3g fp32 %.3g" % (D, kernel, r, e64, e32), flush=True)
+        assert e64 <= 1e-8
+        assert e32 <= tol
