@@ -49,6 +49,8 @@ def parse():
                     help="plain form: error-pollution rule, 0 (h/1.05, P+4) as the paper applies it for D = 3, "
                          "or 1 (h/1.1, P+2)")
     ap.add_argument("--cpu-sample", type=int, default=2000, help="targets in the oracle sample (0: skip)")
+    ap.add_argument("--tune", type=int, default=0, help="run the batch autotuner before timing (1; at the default "
+                    "workload it keeps the automatic shapes) or use the automatic launch shapes (0)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="after the run, one plain device copy of this size (HBM counter calibration)")
     return ap.parse_args()
@@ -181,6 +183,12 @@ def main():
         batch.set_geometry([x], stream=side)
         batch.execute([fb], [ub], stream=side)
 
+    # the batch's autotuner (real-space blocking, FFT column bundles), part
+    # of setting the batch up like plan creation, outside the timed region
+    with torch.cuda.stream(side):
+        batch.set_geometry([x], stream=side)
+        tuned = batch.tune([fb], [ub], stream=side)[0] if args.tune else (0, 0)
+    side.synchronize()
     with torch.cuda.stream(side):
         for _ in range(max(1, args.warmup)):
             batched_step()
@@ -277,6 +285,8 @@ def main():
                                "f~N(0,1)^3 zero mean, tol 1e-8 rms-rel, FP64; learned parameters, %d strength "
                                "sets on the shared geometry, one replayed HIP graph per step" % nrhs,
                    "form": "learned+batched", "n_rhs": nrhs, "learned": pdesc(par),
+                   "launch_shape": {"real_tb": int(tuned[0]), "fft_cols": int(tuned[1]),
+                                    "autotuned": bool(args.tune)},
                    "plain": dict(pdesc(plain_par), safety=args.safety, n_rc=args.nrc or 400.0,
                                  pollution_rule=["h/1.05,P+4", "h/1.1,P+2"][args.pollution])},
         "plain": {"value": round(plain_value, 1), "ms_per_step": round(plain_ms, 4),
