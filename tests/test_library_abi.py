@@ -224,3 +224,23 @@ def test_truncated_gaussian_window_parameters(se):
             assert c == b
     with pytest.raises(se.SEError):
         se.select_params(kernel="stokeslet", periodicity=3, tol=1e-8, n_src=10, window=7)
+
+
+def test_reference_and_bie_reject_bad_arguments_without_a_device(se):
+    """Argument checks of se_ewald_reference and se_bie_solve happen before
+    any device call."""
+    import ctypes
+    box = (ctypes.c_double * 3)(1.0, 1.0, 1.0)
+    p = ctypes.c_void_p(8)  # never dereferenced: every call below fails its checks first
+    ref = se.lib.se_ewald_reference
+    assert ref(0, 4, box, 0.0, 10, p, p, None, 0, None, p, 0, None) == se.SE_ERR_ARG   # periodicity
+    assert ref(7, 3, box, 0.0, 10, p, p, None, 0, None, p, 0, None) == se.SE_ERR_ARG   # kernel
+    assert ref(2, 3, box, 0.0, 10, p, p, None, 0, None, p, 0, None) == se.SE_ERR_ARG   # stresslet without normals
+    assert ref(0, 3, box, 0.0, 0, p, p, None, 0, None, p, 0, None) == se.SE_ERR_ARG    # no sources
+    assert ref(0, 3, box, 3.0, 10, p, p, None, 0, None, p, 0, None) == se.SE_ERR_ARG   # xi too small for rc = L/2
+    bad = (ctypes.c_double * 3)(1.0, -1.0, 1.0)
+    assert ref(0, 3, bad, 0.0, 10, p, p, None, 0, None, p, 0, None) == se.SE_ERR_ARG
+    bie = se.lib.se_bie_solve
+    assert bie(None, 0.0, p, p, p, 30, 100, 1e-8, None, None, None) == se.SE_ERR_ARG
+    assert bie(p, 0.0, p, p, p, 0, 100, 1e-8, None, None, None) == se.SE_ERR_ARG        # restart
+    assert bie(p, 0.0, p, p, p, 30, 100, -1.0, None, None, None) == se.SE_ERR_ARG       # tolerance
