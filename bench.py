@@ -7,7 +7,9 @@ parameters, one strength set per step) and learned+batched (learned
 parameters, 16 strength sets on the shared geometry, the evaluation replayed
 as one HIP graph); `value` is the latter's targets/s.  Inputs are resident in
 HBM before the timed regions start.
-Prints ONE JSON line (see the design doc for the roofline and baseline recipes).
+Prints ONE JSON line, with the roofline of the dominant kernel (algorithmic
+work per launch over its live duration, against the MI355X peak) and the FP64
+oracle timed on a bounded sample of targets as the CPU baseline.
 """
 from __future__ import annotations
 
@@ -134,9 +136,8 @@ def _roofline_one(phase, ms_per_launch, par, n_src, n_tgt, ncomp, fp64, box_vol=
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (--gpus %d requested); "
-              "the multi-GPU design is described in DESIGN.md, nothing is launched." % args.gpus,
-              file=sys.stderr)
+        print("bench.py: the benchmark runs on one GPU only (--gpus %d requested); nothing is launched."
+              % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_2210_01255_amd as se
