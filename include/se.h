@@ -46,7 +46,7 @@ typedef int32_t se_status;
 
 #define SE_OK 0
 #define SE_ERR_ARG (-1)             /* invalid argument (null pointer, bad size, bad enum) */
-#define SE_ERR_UNSUPPORTED (-2)     /* valid request outside what this build implements */
+#define SE_ERR_UNSUPPORTED (-2)     /* valid request outside what this library implements */
 #define SE_ERR_OUT_OF_BOX (-3)      /* a position lies outside [0, L_i) (device-detected) */
 #define SE_ERR_NONFINITE (-4)       /* a position or strength is NaN/Inf (device-detected) */
 #define SE_ERR_COINCIDENT (-5)      /* two distinct points coincide (device-detected) */

@@ -349,7 +349,7 @@ se_status se_select_params(const se_problem* p, const se_params* manual, se_para
             }
         }
         if (D < 3) {
-            *msg = "manual parameters are only supported for D = 3 in this build";
+            *msg = "manual parameters are only supported for D = 3 by this library";
             return SE_ERR_UNSUPPORTED;
         }
         par.U = pot_rms(kernel, b, Q, par.xi);
