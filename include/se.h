@@ -266,6 +266,14 @@ se_status se_batch_execute(se_batch* batch, const double* const* strengths, doub
  * rounding. */
 se_status se_batch_tune(se_batch* batch, const double* const* strengths, double* const* u_out, void* stream);
 
+/* Opt-in wrapping of periodic coordinates: with on = 1, se_set_geometry
+ * reduces the coordinates along the periodic axes modulo L_i into [0, L_i)
+ * (the primary cell, in which eq. k0-stresslet-3p is stated) before binning;
+ * with 0 (the default) a point outside the box raises SE_ERR_OUT_OF_BOX at
+ * the next se_sync_status.  Free-axis coordinates must lie in [0, L_i) either
+ * way.  Takes effect at the next se_set_geometry.  Errors: SE_ERR_ARG. */
+se_status se_plan_set_wrap(se_plan* plan, int32_t on);
+
 /* Launch-shape knobs of one plan (0 = automatic): real-space target bins per
  * block axis (1..4) and the cap on FFT column bundles (1..16, power of 2). */
 se_status se_plan_set_shape(se_plan* plan, int32_t real_tb, int32_t fft_cols);

@@ -57,7 +57,7 @@ class se_params(ctypes.Structure):
 EXPORTS = ["se_version", "se_status_string", "se_params_select", "se_plan_create", "se_plan_destroy",
            "se_plan_get_params", "se_plan_workspace_bytes", "se_plan_last_message", "se_set_geometry",
            "se_execute", "se_execute_split", "se_sync_status", "se_plan_set_timing", "se_plan_phase_times",
-           "se_debug_cell_list", "se_plan_set_shape", "se_plan_get_shape", "se_batch_create", "se_batch_destroy",
+           "se_debug_cell_list", "se_plan_set_wrap", "se_plan_set_shape", "se_plan_get_shape", "se_batch_create", "se_batch_destroy",
            "se_batch_plan", "se_batch_set_geometry", "se_batch_execute", "se_batch_tune", "se_selector_features",
            "se_selector_train", "se_selector_save", "se_selector_load", "se_selector_ready", "se_selector_get",
            "se_selector_predict", "se_mlp_loss_grad", "se_mlp_forward", "se_mlp_adam", "se_ewald_reference", "se_bie_solve"]
@@ -170,6 +170,8 @@ def _load():
     L.se_bie_solve.restype = i32
     L.se_bie_solve.argtypes = [vp, ctypes.c_double, vp, vp, vp, i32, i32, ctypes.c_double, P(i32),
                                P(ctypes.c_double), vp]
+    L.se_plan_set_wrap.restype = i32
+    L.se_plan_set_wrap.argtypes = [vp, i32]
     L.se_mlp_adam.restype = i32
     L.se_mlp_adam.argtypes = [vp, vp, vp, vp, ctypes.c_int64, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                               ctypes.c_float, vp]
@@ -352,6 +354,12 @@ class Plan:
             if getattr(self, "_owned", True):
                 lib.se_plan_destroy(self.handle)
             self.handle = None
+
+    def set_wrap(self, on=True):
+        """Reduce periodic coordinates modulo L_i when binding (se_plan_set_wrap)."""
+        st = lib.se_plan_set_wrap(self.handle, 1 if on else 0)
+        if st != SE_OK:
+            raise SEError(st, "se_plan_set_wrap")
 
     def set_shape(self, real_tb=0, fft_cols=0):
         st = lib.se_plan_set_shape(self.handle, int(real_tb), int(fft_cols))

@@ -574,7 +574,7 @@ se_status se_plan_phase_times(const se_plan* plan, double* ms, int32_t* counts, 
 static se_status bind_points(se_plan* p, const double* xyz, int64_t n, int* perm, int* start, double* sorted,
                              double* sorted4, hipStream_t s)
 {
-    se_launch_bin_keys(p->g, xyz, n, p->d_keys_a, p->d_vals_a, p->d_flags, s);
+    se_launch_bin_keys(p->g, xyz, n, p->d_keys_a, p->d_vals_a, p->d_flags, p->wrap, s);
     se_status st = se_sort_pairs_raw(p->d_sort_tmp, p->sort_tmp_bytes, p->d_keys_a, p->d_keys_b, p->d_vals_a, perm,
                                      n, key_bits(p->nbins), s);
     if (st != SE_OK) {
@@ -582,7 +582,7 @@ static se_status bind_points(se_plan* p, const double* xyz, int64_t n, int* perm
         return st;
     }
     se_launch_cell_starts(p->d_keys_b, n, p->nbins, start, s);
-    se_launch_gather_sorted(xyz, perm, n, p->g, sorted, sorted4, 1, s);
+    se_launch_gather_sorted(xyz, perm, n, p->g, sorted, sorted4, 1, p->wrap, s);
     return check_hip(p, hipGetLastError(), "bind_points");
 }
 
@@ -601,7 +601,7 @@ se_status se_set_geometry(se_plan* plan, const double* src_xyz, const double* nr
         st = bind_points(plan, src_xyz, plan->ns, plan->d_src_perm, plan->d_src_start, plan->d_src, plan->d_pos4, s);
         if (st != SE_OK) return st;
         if (plan->kernel == SE_STRESSLET)
-            se_launch_gather_sorted(nrm_xyz, plan->d_src_perm, plan->ns, plan->g, plan->d_nrm, plan->d_nrm4, 0, s);
+            se_launch_gather_sorted(nrm_xyz, plan->d_src_perm, plan->ns, plan->g, plan->d_nrm, plan->d_nrm4, 0, 0, s);
         if (!plan->tas) {
             st = bind_points(plan, tgt_xyz, plan->nt, plan->d_tgt_perm, plan->d_tgt_start, plan->d_tgt, plan->d_tpos4,
                              s);
@@ -682,6 +682,13 @@ se_status se_execute_split(se_plan* plan, const double* strengths, double* u_rea
 {
     if (!u_real || !u_fourier) return SE_ERR_ARG;
     return se_run_plan(plan, strengths, nullptr, u_real, u_fourier, (hipStream_t)stream);
+}
+
+se_status se_plan_set_wrap(se_plan* plan, int32_t on)
+{
+    if (!plan || (on != 0 && on != 1)) return SE_ERR_ARG;
+    plan->wrap = on;
+    return SE_OK;
 }
 
 se_status se_plan_set_shape(se_plan* plan, int32_t real_tb, int32_t fft_cols)

@@ -20,10 +20,19 @@ __global__ void k_fill_double(double* p, double v, int64_t n)
     for (; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
 }
 
+// Periodic coordinate reduced into [0, L) (the opt-in wrap); the same
+// arithmetic in binning and in the sorted copies keeps the two consistent.
+__device__ __forceinline__ double wrap_coord(double x, double L)
+{
+    double y = x - L * floor(x / L);
+    return (y >= L || y < 0.0) ? 0.0 : y;
+}
+
 // One key per point: the bin of its grid anchor.  Invalid points (non-finite
-// or outside [0, L_i)) raise a flag and are binned as if at the origin.
+// or outside [0, L_i)) raise a flag and are binned as if at the origin.  With
+// wrap, periodic coordinates are first reduced modulo L_i.
 __global__ void k_bin_keys(se_grid_geom g, const double* __restrict__ xyz, int64_t n,
-                           int* __restrict__ keys, int* __restrict__ idx, int* flags)
+                           int* __restrict__ keys, int* __restrict__ idx, int* flags, int wrap)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -31,6 +40,7 @@ __global__ void k_bin_keys(se_grid_geom g, const double* __restrict__ xyz, int64
     int bad = 0;
     for (int d = 0; d < 3; d++) {
         x[d] = xyz[3 * i + d];
+        if (wrap && g.periodic[d] && isfinite(x[d])) x[d] = wrap_coord(x[d], g.L[d]);
         if (!isfinite(x[d])) bad |= SE_FLAG_NONFINITE;
         else if (!(x[d] >= 0.0 && x[d] < g.L[d])) bad |= SE_FLAG_OUT_OF_BOX;
     }
@@ -47,7 +57,7 @@ __global__ void k_bin_keys(se_grid_geom g, const double* __restrict__ xyz, int64
 // out[d*n + s] = xyz[perm[s]][d]; invalid points are replaced by the origin.
 __global__ void k_gather_sorted(const double* __restrict__ xyz, const int* __restrict__ perm,
                                 int64_t n, se_grid_geom g, double* __restrict__ out, double* __restrict__ out4,
-                                int sanitize)
+                                int sanitize, int wrap)
 {
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
@@ -56,6 +66,7 @@ __global__ void k_gather_sorted(const double* __restrict__ xyz, const int* __res
     bool bad = false;
     for (int d = 0; d < 3; d++) {
         x[d] = xyz[3 * o + d];
+        if (wrap && g.periodic[d] && isfinite(x[d])) x[d] = wrap_coord(x[d], g.L[d]);
         if (sanitize && (!isfinite(x[d]) || !(x[d] >= 0.0 && x[d] < g.L[d]))) bad = true;
         if (!sanitize && !isfinite(x[d])) x[d] = 0.0;
     }
@@ -106,18 +117,18 @@ void se_launch_fill_double(double* p, double v, int64_t n, hipStream_t s)
 }
 
 void se_launch_bin_keys(const se_grid_geom& g, const double* xyz, int64_t n, int* keys, int* idx,
-                        int* flags, hipStream_t s)
+                        int* flags, int wrap, hipStream_t s)
 {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_bin_keys, dim3(grid1d(n, 256)), dim3(256), 0, s, g, xyz, n, keys, idx, flags);
+    hipLaunchKernelGGL(k_bin_keys, dim3(grid1d(n, 256)), dim3(256), 0, s, g, xyz, n, keys, idx, flags, wrap);
 }
 
 void se_launch_gather_sorted(const double* xyz, const int* perm, int64_t n, const se_grid_geom& g,
-                             double* out_soa, double* out_aos4, int sanitize, hipStream_t s)
+                             double* out_soa, double* out_aos4, int sanitize, int wrap, hipStream_t s)
 {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_gather_sorted, dim3(grid1d(n, 256)), dim3(256), 0, s, xyz, perm, n, g,
-                       out_soa, out_aos4, sanitize);
+                       out_soa, out_aos4, sanitize, wrap);
 }
 
 void se_launch_cell_starts(const int* sorted_keys, int64_t n, int64_t nbins, int* start, hipStream_t s)

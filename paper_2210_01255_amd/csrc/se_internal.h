@@ -89,6 +89,7 @@ struct se_plan {
     int nrhs = 1;
     int rb = 1;      // right-hand sides per chunk (buffers hold rb slots)
     int shape_real_tb = 0;   // launch-shape knobs (0: automatic), see se_plan_set_shape
+    int wrap = 0;            // reduce periodic coordinates modulo L_i when binding (se_plan_set_wrap)
     int shape_fft_cols = 0;
     bool fp32 = false;
     int device = 0;
@@ -194,9 +195,9 @@ void se_launch_fill_int(int* p, int v, int64_t n, hipStream_t s);
 void se_launch_fill_double(double* p, double v, int64_t n, hipStream_t s);
 void se_launch_fill_bytes_zero(void* p, size_t bytes, hipStream_t s);
 void se_launch_bin_keys(const se_grid_geom& g, const double* xyz, int64_t n, int* keys, int* idx,
-                        int* flags, hipStream_t s);
+                        int* flags, int wrap, hipStream_t s);
 void se_launch_gather_sorted(const double* xyz, const int* perm, int64_t n, const se_grid_geom& g,
-                             double* out_soa, double* out_aos4, int sanitize, hipStream_t s);
+                             double* out_soa, double* out_aos4, int sanitize, int wrap, hipStream_t s);
 void se_launch_cell_starts(const int* sorted_keys, int64_t n, int64_t nbins, int* start,
                            hipStream_t s);
 se_status se_sort_pairs(se_plan* p, int64_t n, hipStream_t s);
