@@ -97,6 +97,24 @@ def roofline_for(phase, ms_per_launch, par, n_src, n_tgt, ncomp, fp64, box_vol=1
     return r
 
 
+def hbm_bytes(phase, par, n_src, n_tgt, ncomp, fp64, slots=1):
+    """Algorithmic HBM bytes of one launch of a phase: every input read once
+    and every output written once (a launch covers `slots` right-hand sides,
+    `ncomp` components each)."""
+    rs = 8 if fp64 else 4
+    M = par["M"]
+    grid = M[0] * M[1] * M[2] * rs
+    nc = ncomp * slots
+    if phase == "spread":   # positions, strengths -> grid
+        return n_src * (24 + 8 * nc) + nc * grid
+    if phase == "gather":   # grid, positions -> FP64 accumulators
+        return nc * grid + n_tgt * (24 + 8 * nc)
+    if phase == "real_space":  # positions and strengths of sources and targets -> u
+        return n_src * (24 + 8 * nc) + n_tgt * (24 + 8 * nc)
+    r = _roofline_one(phase, 1.0, par, n_src, n_tgt, ncomp, fp64)
+    return r["work_per_launch"] * slots if r is not None and r["unit"] == "GB/s" else None
+
+
 def _roofline_one(phase, ms_per_launch, par, n_src, n_tgt, ncomp, fp64, box_vol=1.0):
     P = par["P"]
     M = par["M"]
@@ -131,6 +149,18 @@ def _roofline_one(phase, ms_per_launch, par, n_src, n_tgt, ncomp, fp64, box_vol=
         return None
     return {"bound": "hbm", "achieved": byt / sec / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "work_per_launch": byt}
+
+
+def cpu_model():
+    """The host CPU's model name (lscpu's "Model name" field)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def main():
@@ -225,11 +255,21 @@ def main():
                 "unit": rl["unit"], "frac": round(rl["achieved"] / rl["peak"], 5),
                 "traffic": measured_traffic(dom), "ms_per_launch": round(per_launch[dom], 4),
                 "work_per_launch": rl["work_per_launch"]}
+    # every phase against its binding roofline and against HBM: the
+    # algorithmic bytes, and the counter-measured bytes where they were taken
+    # on the current kernel source, over the live launch duration
     phase_frac = {}
     for k, v in per_launch.items():
         r = roofline_for(k, v, par, n, n, 3, True, slots=slots) if v > 0 else None
         if r is not None:
-            phase_frac[k] = {"bound": r["bound"], "frac": round(r["achieved"] / r["peak"], 5)}
+            e = {"bound": r["bound"], "frac": round(r["achieved"] / r["peak"], 5)}
+            b = hbm_bytes(k, par, n, n, 3, True, slots=slots)
+            if b:
+                e["hbm_frac"] = round(b / (v * 1e-3) / 1e9 / PEAK_HBM_GBS, 5)
+            t = measured_traffic(k)
+            if t:
+                e["hbm_frac_measured"] = round(t / (v * 1e-3) / 1e9 / PEAK_HBM_GBS, 5)
+            phase_frac[k] = e
 
     if args.copy_calib_mib > 0:
         nel = args.copy_calib_mib * (1 << 20) // 8
@@ -259,7 +299,7 @@ def main():
         if omp:
             cores = min(cores, int(omp))
         cpu = {"value": round(args.cpu_sample / (c1 - c0), 4), "unit": "targets/s", "cores": cores,
-               "kind": "oracle",
+               "kind": "oracle", "nproc": os.cpu_count(), "cpu_model": cpu_model(),
                "sample": "%d of %d targets (all %d sources), FP64 classical Ewald, xi_o=%.3f, %.1f s"
                          % (args.cpu_sample, n, n, ref["xi"], c1 - c0)}
         err_plain = oracle.rms_rel_error(u0.cpu().numpy()[idx], ref.total)

@@ -288,10 +288,10 @@ se_status se_plan_get_shape(const se_plan* plan, int32_t* real_tb, int32_t* fft_
  * log10 of the rms-relative tolerance.  Outputs: ln(xi Lc), ln(Lc/h), P and
  * ln(xi rc), with Lc = (L1 L2 L3)^(1/3) and h the grid spacing.  The
  * proposed xi is kept; the steps of Sec. 4.6 (fine pollution rule) at that
- * xi, over safety factors 0.2 .. 50, give a family of parameter sets, and the
+ * xi, over safety factors 1 .. 50, give a family of parameter sets, and the
  * member nearest to the proposed (rc, h, P) is used.  It is
- * rejected if an estimate exceeds ten times the tolerance (the estimates are
- * within a factor 10 of the measured error); then, and when no weights are
+ * rejected if the real-space, Fourier or window estimate, or their rms
+ * combination, exceeds the tolerance; then, and when no weights are
  * loaded, selection falls back to SE_SELECT_ANALYTIC (se_plan_last_message
  * says which was used).  Weights are process-wide: the latest of
  * se_selector_train / se_selector_load, else the file named by the environment
@@ -336,7 +336,10 @@ se_status se_selector_predict(const float* X, float* Y, int64_t n, void* stream)
  * loss = sum_i |mlp(theta, x_i) - y_i|^2 / (n SE_MLP_OUT) and grad = d loss / d
  * theta (n >= 1; grad SE_MLP_NPARAM floats, loss one float); forward gives
  * mlp(theta, x_i); adam applies one Adam step with bias corrections at step
- * t >= 1 to n parameters. */
+ * t >= 1 to n parameters.  forward and adam are stream-ordered and allocate
+ * nothing; loss_grad allocates a temporary buffer of per-block partial sums
+ * and synchronises the stream before returning (training itself uses a
+ * buffer kept for the whole run). */
 se_status se_mlp_loss_grad(const float* theta, const float* X, const float* Y, int64_t n, float* grad, float* loss,
                            void* stream);
 se_status se_mlp_forward(const float* theta, const float* X, int64_t n, float* Y, void* stream);

@@ -315,27 +315,37 @@ se_status se_plan_create(const se_problem* prob, const se_params* manual, se_pla
     p->tas = prob->targets_are_sources != 0;
     p->nt = p->tas ? prob->n_src : prob->n_tgt;
 
-    // precision: the FP32 grid path is for tolerances >= 1e-6
-    if (prob->precision == SE_PREC_FP32) {
-        double rel = prob->tol;
-        if (prob->tol_kind == SE_TOL_REL && rel < 1e-6) {
-            delete p;
-            return SE_ERR_TOL_UNREACHABLE;
-        }
-        p->fp32 = true;
-    } else if (prob->precision == SE_PREC_AUTO) {
-        p->fp32 = (prob->tol_kind == SE_TOL_REL && prob->tol >= 1e-6);
-    }
     std::string msg;
     se_status st = prob->selector == SE_SELECT_LEARNED ? se_select_learned(prob, &p->par, &msg)
                                                        : se_select_params(prob, manual, &p->par, &msg);
-    if (st == SE_OK && prob->selector == SE_SELECT_LEARNED && !fft_sizes_ok(p->par.n_fft, p->ncomp, p->fp32)) {
-        st = se_select_params(prob, nullptr, &p->par, &msg);
-        msg = "learned selector: grid beyond the FFT limits; analytic parameters";
-    }
     if (st != SE_OK) {
         delete p;
         return st;
+    }
+    // precision: the FP32 grid path is for rms-relative tolerances >= 1e-6.
+    // An absolute tolerance is taken relative to the Fourier-part rms
+    // estimate U of the selected parameters, the scale the relative form is
+    // mapped through; without an estimate it counts as unreachable in FP32.
+    {
+        const double rel = prob->tol_kind == SE_TOL_REL ? prob->tol
+                           : (p->par.U > 0.0 ? prob->tol / p->par.U : 0.0);
+        if (prob->precision == SE_PREC_FP32) {
+            if (!(rel >= 1e-6)) {
+                delete p;
+                return SE_ERR_TOL_UNREACHABLE;
+            }
+            p->fp32 = true;
+        } else if (prob->precision == SE_PREC_AUTO) {
+            p->fp32 = rel >= 1e-6;
+        }
+    }
+    if (prob->selector == SE_SELECT_LEARNED && !fft_sizes_ok(p->par.n_fft, p->ncomp, p->fp32)) {
+        st = se_select_params(prob, nullptr, &p->par, &msg);
+        msg = "learned selector: grid beyond the FFT limits; analytic parameters";
+        if (st != SE_OK) {
+            delete p;
+            return st;
+        }
     }
     p->msg = msg;
     const se_params& par = p->par;

@@ -125,17 +125,25 @@ se_status se_d0_precompute(se_plan* p)
     if (!ok) {
         st = SE_ERR_NOMEM;
     } else {
+        if (hipMemcpy(tw0, twh.data(), twh.size() * 8, hipMemcpyHostToDevice) != hipSuccess) st = SE_ERR_HIP;
+    }
+    if (st == SE_OK) {
         hipStream_t s = 0;
-        hipMemcpy(tw0, twh.data(), twh.size() * 8, hipMemcpyHostToDevice);
         double vol0 = h[0] * n0[0] * h[1] * n0[1] * h[2] * n0[2];
         hipLaunchKernelGGL(k_d0_fill, dim3(blocks(nh0)), dim3(256), 0, s, (double2*)spec0, n0[0], n0[1], n0[2], h[0],
                            h[1], h[2], par.R, biharmonic, 1.0 / vol0);
         se_fft3d_f64(n0, n0, h, grid0, spec0, tw0, off0, 1, -1, s);
-        hipLaunchKernelGGL(k_d0_truncate, dim3(blocks(nr2)), dim3(256), 0, s, grid0, n0[0], n0[1], n0[2], grid2, m[0],
-                           m[1], m[2], biharmonic);
-        se_fft3d_f64(n2, n2, h, grid2, spec2, p->d_tw, p->tw_off, 1, 1, s);
-        hipLaunchKernelGGL(k_d0_extract, dim3(blocks(nh2)), dim3(256), 0, s, (const double2*)spec2, p->d_ktab, nh2,
-                           h[0] * h[1] * h[2]);
+        if (hipGetLastError() != hipSuccess) st = SE_ERR_HIP;
+        if (st == SE_OK) {
+            hipLaunchKernelGGL(k_d0_truncate, dim3(blocks(nr2)), dim3(256), 0, s, grid0, n0[0], n0[1], n0[2], grid2,
+                               m[0], m[1], m[2], biharmonic);
+            se_fft3d_f64(n2, n2, h, grid2, spec2, p->d_tw, p->tw_off, 1, 1, s);
+            if (hipGetLastError() != hipSuccess) st = SE_ERR_HIP;
+        }
+        if (st == SE_OK)
+            hipLaunchKernelGGL(k_d0_extract, dim3(blocks(nh2)), dim3(256), 0, s, (const double2*)spec2, p->d_ktab,
+                               nh2, h[0] * h[1] * h[2]);
+        // the queued work must finish before the buffers are freed, whatever failed
         if (hipDeviceSynchronize() != hipSuccess || hipGetLastError() != hipSuccess) st = SE_ERR_HIP;
     }
     if (spec0) hipFree(spec0);

@@ -173,8 +173,8 @@ bool features(const se_problem* p, float* x)
 
 // Learned path of parameter selection.  The network proposes (xi, h, P, rc)
 // for the problem; xi is kept, the other three pick one safety factor for the
-// steps of Sec. 4.6, and the result is rejected if one of the real-space,
-// Fourier and window estimates of Sec. 4 exceeds ten times the tolerance.
+// steps of Sec. 4.6, and the result is rejected if the real-space, Fourier
+// and window estimates of Sec. 4, each or combined, exceed the tolerance.
 se_status se_select_learned(const se_problem* p, se_params* out, std::string* msg)
 {
     auto fallback = [&](const char* why) {
@@ -225,7 +225,7 @@ se_status se_select_learned(const se_problem* p, se_params* out, std::string* ms
     std::string m2;
     double best = 1e300;
     for (int k = 0; k <= 64; k++) {
-        q.safety = 0.2 * std::pow(250.0, k / 64.0);  // 0.2 .. 50
+        q.safety = std::pow(50.0, k / 64.0);  // 1 .. 50: every member aims at or below tol
         se_params a;
         if (se_select_params(&q, nullptr, &a, &m2) != SE_OK) continue;
         double ha = 1e300;
@@ -239,11 +239,14 @@ se_status se_select_learned(const se_problem* p, se_params* out, std::string* ms
         }
     }
     if (!(best < 1e300)) return fallback("analytic completion failed");
-    // the estimates are within a factor 10 of the measured error (Sec. 4):
-    // a parameter set they put above 10 tol cannot meet tol
-    const double lim = 10.0 * p->tol * par.U;
-    if (par.est_real > lim || par.est_fourier > lim || par.est_window > lim)
-        return fallback("estimates above ten times the tolerance");
+    // the real-space, Fourier and window parts are independent errors of
+    // the result (Sec. 4): a set whose estimates, each or combined in rms,
+    // exceed the tolerance is not used
+    const double lim = p->tol * par.U;
+    const double comb = std::sqrt(par.est_real * par.est_real + par.est_fourier * par.est_fourier +
+                                  par.est_window * par.est_window);
+    if (par.est_real > lim || par.est_fourier > lim || par.est_window > lim || comb > lim)
+        return fallback("estimates above the tolerance");
     *out = par;
     *msg = "learned parameters";
     return SE_OK;

@@ -148,9 +148,9 @@ def test_batch_graph_replays_match_eager_and_oracle(env):
 def test_batch_of_64_uneven_systems_with_tuning(env):
     """64 systems, N log-uniform in [1e3, 5e4], D uniform in {3,2,1,0}, box
     aspect in [1,4], tol 1e-6: autotuned shapes, graph replay; every member
-    against the replayed eager pass, and against the oracle on 24 sampled
-    targets (singly periodic members up to N = 1e4 only: the oracle's
-    trapezoidal k-sums over the virtual cell take seconds per 1e4 sources)."""
+    against the replayed eager pass, and on every target at the requested
+    tolerance against the GPU direct Ewald reference (itself checked against
+    the oracle to 1e-12 in test_gpu_reference.py)."""
     se, oracle, torch = env
     tol = 1e-6
     systems = _systems(64, 64, 1e3, 5e4)
@@ -192,18 +192,17 @@ def test_batch_of_64_uneven_systems_with_tuning(env):
     st.synchronize()
     print("64 systems: graph replay %.3f ms, one after another %.3f ms" %
           (ev[0].elapsed_time(ev[1]) / 5, ev[1].elapsed_time(ev[2]) / 5), flush=True)
-    g = W.rng(6400)
+    worst = 0.0
     for i, (s, o, u0) in enumerate(zip(systems, outs, before)):
         u = o.cpu().numpy()
         assert oracle.rms_rel_error(u, u0) <= 1e-12, i
-        if s["D"] == 1 and len(s["x"]) > 10000:
-            continue
-        idx = np.sort(g.choice(len(s["x"]), size=24, replace=False)).astype(np.int64)
-        # sampled error: normalised by the rms of the full result (eq. rel-rms-error)
-        ref = _oracle_ref(env, s, "stokeslet", idx)
-        err = np.sqrt(np.mean(np.sum((u[idx] - ref) ** 2, axis=1))) / np.sqrt(np.mean(np.sum(u ** 2, axis=1)))
-        print("sys %d D=%d N=%d sampled err %.3g" % (i, s["D"], len(s["x"]), err), flush=True)
-        assert err <= 3 * tol
+        ref = se.ewald_reference("stokeslet", s["D"], tuple(s["box"]), x[i], f[i]).cpu().numpy()
+        err = oracle.rms_rel_error(u, ref)
+        worst = max(worst, err)
+        print("sys %d D=%d N=%d box=%s all-target err %.3g" % (i, s["D"], len(s["x"]),
+                                                               np.round(s["box"], 3).tolist(), err), flush=True)
+        assert err <= tol, (i, err)
+    print("64 systems: worst all-target err %.3g (tol %g)" % (worst, tol), flush=True)
     b.close()
 
 

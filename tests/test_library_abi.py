@@ -244,3 +244,29 @@ def test_reference_and_bie_reject_bad_arguments_without_a_device(se):
     assert bie(None, 0.0, p, p, p, 30, 100, 1e-8, None, None, None) == se.SE_ERR_ARG
     assert bie(p, 0.0, p, p, p, 0, 100, 1e-8, None, None, None) == se.SE_ERR_ARG        # restart
     assert bie(p, 0.0, p, p, p, 30, 100, -1.0, None, None, None) == se.SE_ERR_ARG       # tolerance
+
+
+def test_fp32_rejects_tolerances_below_its_floor_in_either_form(se):
+    """The FP32 grid path is for rms-relative tolerances >= 1e-6.  An absolute
+    tolerance counts relative to the Fourier-part rms estimate U of the
+    selected parameters, so a tight absolute tolerance is refused as well
+    (SE_ERR_TOL_UNREACHABLE, before any device call), and a loose one is not."""
+    import ctypes
+    U = se.select_params(kernel="stokeslet", periodicity=3, tol=1e-9, tol_kind=se.TOL_ABS, n_src=1000,
+                         source_q=3000.0)["U"]
+    assert U > 0
+    for tol, kind in ((1e-8, se.TOL_REL), (1e-8 * U, se.TOL_ABS), (1e-9, se.TOL_ABS)):
+        prob = se.make_problem(kernel="stokeslet", periodicity=3, tol=tol, tol_kind=kind, n_src=1000,
+                               source_q=3000.0, precision=se.PREC_FP32)
+        h = ctypes.c_void_p()
+        st = se.lib.se_plan_create(ctypes.byref(prob), None, ctypes.byref(h))
+        assert st == se.SE_ERR_TOL_UNREACHABLE, (tol, kind, st)
+    # 1e-4 relative in absolute form passes the precision check; plan creation
+    # then needs a device, so here it can only fail later, at the device calls
+    prob = se.make_problem(kernel="stokeslet", periodicity=3, tol=1e-4 * U, tol_kind=se.TOL_ABS, n_src=1000,
+                           source_q=3000.0, precision=se.PREC_FP32)
+    h = ctypes.c_void_p()
+    st = se.lib.se_plan_create(ctypes.byref(prob), None, ctypes.byref(h))
+    assert st != se.SE_ERR_TOL_UNREACHABLE
+    if st == se.SE_OK:
+        se.lib.se_plan_destroy(h)
