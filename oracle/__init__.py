@@ -73,6 +73,8 @@ def lib():
         L.oracle_real_part.restype = l
         L.oracle_fourier_part_3p.argtypes = [i, dp, d, d, l, dp, dp, dp, l, dp, dp]
         L.oracle_fourier_part_3p.restype = l
+        L.oracle_fourier_part_3p_box.argtypes = [i, dp, d, dp, l, dp, dp, dp, l, dp, dp]
+        L.oracle_fourier_part_3p_box.restype = l
         L.oracle_k0_stresslet_3p.argtypes = [dp, l, dp, dp, dp, l, dp, dp]
         L.oracle_k0_stresslet_3p.restype = None
         L.oracle_self_part.argtypes = [i, d, l, lp, dp, dp]

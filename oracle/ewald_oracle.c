@@ -230,9 +230,10 @@ static void fourier_kernel_apply(int kernel, double xi, const double *k,
 }
 
 /* Enumerate k-bar in a half space with 0 < |k| <= kmax; k = 2 pi kbar_i / L_i. */
-static long list_halfspace_k(const double *L, double kmax, int D, int *Kb, int **out)
+static long list_halfspace_k(const double *L, double kmax, const double *kbox, int D, int *Kb, int **out)
 {
-    for (int i = 0; i < 3; i++) Kb[i] = (int)floor(kmax * L[i] / (2.0 * OR_PI));
+    /* kbox == NULL: the sphere |k| <= kmax; else the box |k_i| <= kbox[i] */
+    for (int i = 0; i < 3; i++) Kb[i] = (int)floor((kbox ? kbox[i] : kmax) * L[i] / (2.0 * OR_PI));
     long cap = (long)(2 * Kb[0] + 1) * (2 * Kb[1] + 1) * (Kb[2] + 1);
     int *lst = (int *)malloc(sizeof(int) * 3 * (size_t)cap);
     long cnt = 0;
@@ -247,7 +248,7 @@ static long list_halfspace_k(const double *L, double kmax, int D, int *Kb, int *
                 double kk[3] = {2.0 * OR_PI * k1 / L[0], 2.0 * OR_PI * k2 / L[1],
                                 2.0 * OR_PI * k3 / L[2]};
                 double kn2 = kk[0] * kk[0] + kk[1] * kk[1] + kk[2] * kk[2];
-                if (kn2 > kmax * kmax) continue;
+                if (!kbox && kn2 > kmax * kmax) continue;
                 lst[3 * cnt + 0] = k1;
                 lst[3 * cnt + 1] = k2;
                 lst[3 * cnt + 2] = k3;
@@ -279,13 +280,13 @@ static void phase_table(double x, double L, int K, double complex *E)
 /* 2 pi / P_v, of the integrals over the free wavenumbers in eqs.            */
 /* (2p-fourier-space) / (1p-fourier-space) for the nonsingular modes.        */
 /* ------------------------------------------------------------------------ */
-static long fourier_sum(int D, int kernel, const double *L, double xi, double kmax,
+static long fourier_sum(int D, int kernel, const double *L, double xi, double kmax, const double *kbox,
                         long ns, const double *xs, const double *f, const double *nu,
                         long nt, const double *xt, double *u)
 {
     int Kb[3];
     int *kl = NULL;
-    long nk = list_halfspace_k(L, kmax, D, Kb, &kl);
+    long nk = list_halfspace_k(L, kmax, kbox, D, Kb, &kl);
     int ncs = (kernel == OR_STRESSLET) ? 9 : 3;
     double complex *S = (double complex *)calloc((size_t)nk * ncs, sizeof(double complex));
     double V = L[0] * L[1] * L[2];
@@ -365,7 +366,18 @@ long oracle_fourier_part_3p(int kernel, const double *L, double xi, double kmax,
                             long ns, const double *xs, const double *f, const double *nu,
                             long nt, const double *xt, double *u)
 {
-    return fourier_sum(3, kernel, L, xi, kmax, ns, xs, f, nu, nt, xt, u);
+    return fourier_sum(3, kernel, L, xi, kmax, NULL, ns, xs, f, nu, nt, xt, u);
+}
+
+/* The same lattice sum over the box |k_i| <= kbox[i] instead of a sphere:
+ * the modes a grid of spacing h_i = pi/kbox[i] holds, the truncation the SE
+ * method makes (Appendix C notes that it truncates a cube of side 2 k_inf
+ * where its estimates assume a sphere). */
+long oracle_fourier_part_3p_box(int kernel, const double *L, double xi, const double *kbox,
+                                long ns, const double *xs, const double *f, const double *nu,
+                                long nt, const double *xt, double *u)
+{
+    return fourier_sum(3, kernel, L, xi, 0.0, kbox, ns, xs, f, nu, nt, xt, u);
 }
 
 /* Nonsingular modes k^P != 0 for D = 2, 1; Lv = (L_1, L_2, P_v) or
@@ -374,7 +386,7 @@ long oracle_reduced_fourier_part(int D, int kernel, const double *Lv, double xi,
                                  long ns, const double *xs, const double *f, const double *nu,
                                  long nt, const double *xt, double *u)
 {
-    return fourier_sum(D, kernel, Lv, xi, kmax, ns, xs, f, nu, nt, xt, u);
+    return fourier_sum(D, kernel, Lv, xi, kmax, NULL, ns, xs, f, nu, nt, xt, u);
 }
 
 /* ------------------------------------------------------------------------ */
