@@ -54,6 +54,7 @@ typedef int32_t se_status;
 #define SE_ERR_NOMEM (-7)           /* device allocation failed */
 #define SE_ERR_HIP (-8)             /* a HIP runtime call failed */
 #define SE_ERR_STATE (-9)           /* call out of order (e.g. execute before geometry) */
+#define SE_ERR_SCRATCH (-10)        /* input larger than an allocation-free entry point's fixed scratch */
 
 #define SE_STOKESLET 0
 #define SE_ROTLET 1
@@ -345,6 +346,25 @@ se_status se_mlp_loss_grad(const float* theta, const float* X, const float* Y, i
 se_status se_mlp_forward(const float* theta, const float* X, int64_t n, float* Y, void* stream);
 se_status se_mlp_adam(float* theta, float* m, float* v, const float* grad, int64_t n, int32_t t, float lr, float beta1,
                       float beta2, float eps, void* stream);
+
+/* Allocation-free loss and gradient, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving or training loops,
+ * harnesses that forbid hipMalloc).  Same arguments, kernels and results as
+ * se_mlp_loss_grad (bit for bit), but it allocates nothing and does not
+ * synchronise: the per-block partial sums go to a fixed device array of the
+ * library, SE_MLP_NOALLOC_MAX_N / 32 blocks of SE_MLP_NPARAM + 1 floats
+ * (10.5 MB), which each GPU the library runs on holds until the process
+ * ends.  Its address is looked up once per device, on the first call with
+ * that device current; the stream must belong to the current device.  Every
+ * call on a GPU uses that GPU's one array, and each call overwrites all the
+ * entries it reads, so nothing carries over between calls; but calls that
+ * overlap on one GPU (two streams, two threads) race on it and must be
+ * ordered by the caller.  Stream-ordered: grad and loss are ready when the
+ * stream reaches the end of the call.  Errors: SE_ERR_ARG (null pointer,
+ * n < 1), SE_ERR_SCRATCH (n > SE_MLP_NOALLOC_MAX_N), SE_ERR_HIP. */
+#define SE_MLP_NOALLOC_MAX_N 16384
+se_status se_mlp_loss_grad_noalloc(const float* theta, const float* X, const float* Y, int64_t n, float* grad,
+                                   float* loss, void* stream);
 
 /* Direct Ewald reference on the GPU (no grid, no window), for checking the
  * fast method on large systems on every target.

@@ -25,9 +25,12 @@ WINDOWS = {"pkb": WINDOW_PKB, "tg": WINDOW_TG}
 SE_OK = 0
 SE_ERR_ARG, SE_ERR_UNSUPPORTED, SE_ERR_OUT_OF_BOX, SE_ERR_NONFINITE = -1, -2, -3, -4
 SE_ERR_COINCIDENT, SE_ERR_TOL_UNREACHABLE, SE_ERR_NOMEM, SE_ERR_HIP, SE_ERR_STATE = -5, -6, -7, -8, -9
+SE_ERR_SCRATCH = -10
+MLP_NOALLOC_MAX_N = 16384
 STATUS = {0: "SE_OK", -1: "SE_ERR_ARG", -2: "SE_ERR_UNSUPPORTED", -3: "SE_ERR_OUT_OF_BOX",
           -4: "SE_ERR_NONFINITE", -5: "SE_ERR_COINCIDENT", -6: "SE_ERR_TOL_UNREACHABLE",
-          -7: "SE_ERR_NOMEM", -8: "SE_ERR_HIP", -9: "SE_ERR_STATE"}
+          -7: "SE_ERR_NOMEM", -8: "SE_ERR_HIP", -9: "SE_ERR_STATE",
+          -10: "SE_ERR_SCRATCH"}
 
 
 class se_problem(ctypes.Structure):
@@ -60,7 +63,7 @@ EXPORTS = ["se_version", "se_status_string", "se_params_select", "se_plan_create
            "se_debug_cell_list", "se_plan_set_wrap", "se_plan_set_shape", "se_plan_get_shape", "se_batch_create", "se_batch_destroy",
            "se_batch_plan", "se_batch_set_geometry", "se_batch_execute", "se_batch_tune", "se_selector_features",
            "se_selector_train", "se_selector_save", "se_selector_load", "se_selector_ready", "se_selector_get",
-           "se_selector_predict", "se_mlp_loss_grad", "se_mlp_forward", "se_mlp_adam", "se_ewald_reference", "se_bie_solve"]
+           "se_selector_predict", "se_mlp_loss_grad", "se_mlp_loss_grad_noalloc", "se_mlp_forward", "se_mlp_adam", "se_ewald_reference", "se_bie_solve"]
 
 PHASES = ["geometry", "strengths", "spread", "fft_fwd_xy", "fft_z_scale", "fft_inv_yx", "gather", "real_space",
           "epilogue"]
@@ -162,6 +165,8 @@ def _load():
     L.se_selector_predict.argtypes = [vp, vp, ctypes.c_int64, vp]
     L.se_mlp_loss_grad.restype = i32
     L.se_mlp_loss_grad.argtypes = [vp, vp, vp, ctypes.c_int64, vp, vp, vp]
+    L.se_mlp_loss_grad_noalloc.restype = i32
+    L.se_mlp_loss_grad_noalloc.argtypes = [vp, vp, vp, ctypes.c_int64, vp, vp, vp]
     L.se_mlp_forward.restype = i32
     L.se_mlp_forward.argtypes = [vp, vp, ctypes.c_int64, vp, vp]
     L.se_ewald_reference.restype = i32
@@ -212,6 +217,7 @@ se_selector_ready = lib.se_selector_ready
 se_selector_get = lib.se_selector_get
 se_selector_predict = lib.se_selector_predict
 se_mlp_loss_grad = lib.se_mlp_loss_grad
+se_mlp_loss_grad_noalloc = lib.se_mlp_loss_grad_noalloc
 se_mlp_forward = lib.se_mlp_forward
 se_mlp_adam = lib.se_mlp_adam
 se_ewald_reference = lib.se_ewald_reference

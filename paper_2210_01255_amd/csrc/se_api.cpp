@@ -247,6 +247,7 @@ const char* se_status_string(se_status s)
         case SE_ERR_NOMEM: return "device allocation failed";
         case SE_ERR_HIP: return "HIP runtime error";
         case SE_ERR_STATE: return "call out of order";
+        case SE_ERR_SCRATCH: return "input larger than the fixed scratch of an allocation-free call";
         default: return "unknown status";
     }
 }

@@ -16,6 +16,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 namespace {
 
@@ -263,4 +264,50 @@ void se_mlp_launch_forward(const float* th, const float* X, int64_t n, float* Y,
 void se_mlp_launch_fill(float* p, int64_t n, float v, hipStream_t s)
 {
     if (n > 0) hipLaunchKernelGGL(k_mlp_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free loss and gradient.  The per-block partial sums of
+// k_mlp_grad go to this file-scope array instead of a buffer allocated per
+// call.  Every block writes all SE_MLP_NPARAM + 1 entries of its slot and
+// k_mlp_reduce reads only the slots of the blocks just launched, so the array
+// needs no clearing between calls.  In host code `scratch` names a host-side
+// stand-in: its device address, one per GPU, comes from hipGetSymbolAddress.
+static __device__ __align__(256) float scratch[(SE_MLP_NOALLOC_MAX_N / kS) * (SE_MLP_NPARAM + 1)];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up once per
+// device, with that device current).
+se_status scratch_on_current_device(float** out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return SE_ERR_HIP;
+    if (dev < 0 || dev >= kMaxDevices) return SE_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return SE_ERR_HIP;
+        g_scratch_ptr[dev] = (float*)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return SE_OK;
+}
+
+}  // namespace
+
+se_status se_mlp_loss_grad_noalloc(const float* theta, const float* X, const float* Y, int64_t n, float* grad,
+                                   float* loss, void* stream)
+{
+    if (!theta || !X || !Y || !grad || !loss || n < 1) return SE_ERR_ARG;
+    if (n > SE_MLP_NOALLOC_MAX_N) return SE_ERR_SCRATCH;
+    float* part = nullptr;
+    const se_status st = scratch_on_current_device(&part);
+    if (st != SE_OK) return st;
+    se_mlp_launch_grad(theta, X, Y, n, 1, 0, 0, (int)n, part, grad, loss, (hipStream_t)stream);
+    return hipGetLastError() == hipSuccess ? SE_OK : SE_ERR_HIP;
 }
