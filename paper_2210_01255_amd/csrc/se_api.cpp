@@ -8,10 +8,7 @@
 
 #include "se_internal.h"
 
-// defined in se_geom.hip / se_spread.hip
-se_status se_sort_pairs_raw(void* tmp, size_t tmp_bytes, const int* keys_in, int* keys_out, const int* vals_in,
-                            int* vals_out, int64_t n, int end_bit, hipStream_t s);
-size_t se_sort_tmp_bytes(int64_t n, int end_bit);
+// defined in se_spread.hip
 void se_tile_shape(int ncomp, bool fp32, int* tile);
 
 namespace {

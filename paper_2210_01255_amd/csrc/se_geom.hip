@@ -1,8 +1,17 @@
 // se_geom.hip -- cell list: validation, grid anchors, bin keys, stable sort,
 // sorted gathers and cell starts (Sec. 4.1.2 cell list; Sec. 3.3 window anchors).
+//
+// The sort is a least-significant-digit radix sort of (bin key, point index)
+// pairs with 8-bit digits, written for this library: per pass a count kernel
+// (digit histogram of each block of 4096 keys), an exclusive scan of the
+// histograms in digit-major order (one workgroup), and a scatter kernel that
+// ranks each key among the equal digits before it in its block (wavefront
+// ballots over the digit bits, then per-wave counts in LDS).  Every position
+// follows from the keys alone, so the permutation is the stable one and does
+// not depend on scheduling; no pass clears memory, so binding can be recorded
+// into a HIP graph.
+#include <algorithm>
 #include <cstring>
-
-#include <rocprim/device/device_radix_sort.hpp>
 
 #include "se_device.h"
 
@@ -137,22 +146,131 @@ void se_launch_cell_starts(const int* sorted_keys, int64_t n, int64_t nbins, int
                        nbins, start);
 }
 
-// Stable LSD radix sort of (key, index) pairs: keys in d_keys_a, indices in
-// d_vals_a; sorted keys land in d_keys_b and the permutation in the caller's
-// perm buffer (passed through d_vals_a -> perm by the caller).
-se_status se_sort_pairs_raw(void* tmp, size_t tmp_bytes, const int* keys_in, int* keys_out,
-                            const int* vals_in, int* vals_out, int64_t n, int end_bit, hipStream_t s)
+// ---------------------------------------------------------------------------
+// Radix sort of (key, value) pairs.
+namespace {
+
+constexpr int kRsThreads = 256;
+constexpr int kRsItems = 16;                     // keys per thread
+constexpr int kRsBlock = kRsThreads * kRsItems;  // keys per block
+constexpr int kRsBits = 8;
+constexpr int kRsDigits = 1 << kRsBits;
+
+__device__ __forceinline__ int rs_digit(int key, int shift, int mask) { return (key >> shift) & mask; }
+
+// hist[d * nblocks + b] = number of keys of block b whose digit is d.
+__global__ void __launch_bounds__(kRsThreads) k_rs_count(const int* __restrict__ keys, int64_t n, int shift, int mask,
+                                                       int nblocks, int* __restrict__ hist)
 {
-    size_t need = tmp_bytes;
-    hipError_t e = rocprim::radix_sort_pairs(tmp, need, keys_in, keys_out, vals_in, vals_out,
-                                             (size_t)n, 0, end_bit, s);
-    return e == hipSuccess ? SE_OK : SE_ERR_HIP;
+    __shared__ int cnt[kRsDigits];
+    const int t = threadIdx.x;
+    cnt[t] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kRsBlock;
+#pragma unroll 4
+    for (int k = 0; k < kRsItems; k++) {
+        const int64_t i = base + (int64_t)k * kRsThreads + t;
+        if (i < n) atomicAdd(&cnt[rs_digit(keys[i], shift, mask)], 1);
+    }
+    __syncthreads();
+    hist[(int64_t)t * nblocks + blockIdx.x] = cnt[t];
+}
+
+// Keys of block b in their input order k * 256 + t (k = 0 .. 15): each wave
+// takes 64 consecutive keys, finds the lanes holding its digit with one
+// ballot per digit bit, and ranks itself among the lower lanes; the wave
+// counts per digit are combined in wave order and carried over k, so that a
+// key's position is off[d] + (equal digits before it in the block).
+__global__ void __launch_bounds__(kRsThreads) k_rs_scatter(const int* __restrict__ keys_in,
+                                                         const int* __restrict__ vals_in, int64_t n, int shift,
+                                                         int mask, int nbits, int nblocks,
+                                                         const int* __restrict__ off, int* __restrict__ keys_out,
+                                                         int* __restrict__ vals_out)
+{
+    constexpr int W = kRsThreads / 64;
+    __shared__ int run[kRsDigits];        // position of the next key of each digit
+    __shared__ int wcnt[W][kRsDigits];    // keys of each digit per wave in this step
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    run[t] = off[(int64_t)t * nblocks + blockIdx.x];
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int64_t base = (int64_t)blockIdx.x * kRsBlock;
+    for (int k = 0; k < kRsItems; k++) {
+#pragma unroll
+        for (int w = 0; w < W; w++) wcnt[w][t] = 0;
+        __syncthreads();
+        const int64_t i = base + (int64_t)k * kRsThreads + t;
+        const bool valid = i < n;
+        const int key = valid ? keys_in[i] : 0;
+        const int val = valid ? vals_in[i] : 0;
+        const int d = rs_digit(key, shift, mask);
+        uint64_t peers = __ballot(valid);
+        if (!valid) peers = 0;
+        for (int b = 0; b < nbits; b++) {
+            const uint64_t on = __ballot((d >> b) & 1);
+            peers &= ((d >> b) & 1) ? on : ~on;
+        }
+        const int rank = __builtin_popcountll(peers & below);
+        // the lowest lane of each group records the group's size
+        if (valid && rank == 0) wcnt[wv][d] = __builtin_popcountll(peers);
+        __syncthreads();
+        int pre = 0;
+        for (int w = 0; w < wv; w++) pre += wcnt[w][d];
+        const int pos = run[d] + pre + rank;
+        if (valid) {
+            keys_out[pos] = key;
+            vals_out[pos] = val;
+        }
+        __syncthreads();
+        int tot = 0;
+#pragma unroll
+        for (int w = 0; w < W; w++) tot += wcnt[w][t];
+        run[t] += tot;
+        // run[] is read again only after the next step's first barrier
+    }
+}
+
+inline int rs_nblocks(int64_t n) { return (int)((n + kRsBlock - 1) / kRsBlock); }
+
+}  // namespace
+
+// Stable sort of (key, value) pairs by keys in [0, 2^end_bit): sorted keys to
+// keys_out and the values in the same order to vals_out (the inputs are not
+// written).  tmp holds a second pair of arrays and the digit histograms
+// (se_sort_tmp_bytes).
+se_status se_sort_pairs_raw(void* tmp, size_t tmp_bytes, const int* keys_in, int* keys_out, const int* vals_in,
+                            int* vals_out, int64_t n, int end_bit, hipStream_t s)
+{
+    if (n <= 0) return SE_OK;
+    if (n > ((int64_t)1 << 31) - 1 || end_bit < 1 || end_bit > 31 || tmp_bytes < se_sort_tmp_bytes(n, end_bit))
+        return SE_ERR_ARG;
+    const int nb = rs_nblocks(n);
+    int* kt = (int*)tmp;
+    int* vt = kt + n;
+    int* hist = vt + n;
+    const int npass = (end_bit + kRsBits - 1) / kRsBits;
+    const int* ki = keys_in;
+    const int* vi = vals_in;
+    for (int pass = 0; pass < npass; pass++) {
+        // the last pass writes the caller's arrays; earlier ones alternate so
+        // that it does
+        const bool to_out = ((npass - 1 - pass) % 2) == 0;
+        int* ko = to_out ? keys_out : kt;
+        int* vo = to_out ? vals_out : vt;
+        const int shift = pass * kRsBits;
+        const int nbits = std::min(kRsBits, end_bit - shift);
+        const int mask = (1 << nbits) - 1;
+        hipLaunchKernelGGL(k_rs_count, dim3(nb), dim3(kRsThreads), 0, s, ki, n, shift, mask, nb, hist);
+        se_launch_scan_excl(hist, (int64_t)kRsDigits * nb, s);
+        hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(kRsThreads), 0, s, ki, vi, n, shift, mask, nbits, nb, hist,
+                           ko, vo);
+        ki = ko;
+        vi = vo;
+    }
+    return hipGetLastError() == hipSuccess ? SE_OK : SE_ERR_HIP;
 }
 
 size_t se_sort_tmp_bytes(int64_t n, int end_bit)
 {
-    size_t need = 0;
-    (void)rocprim::radix_sort_pairs((void*)nullptr, need, (const int*)nullptr, (int*)nullptr,
-                              (const int*)nullptr, (int*)nullptr, (size_t)n, 0, end_bit, (hipStream_t)0);
-    return need;
+    (void)end_bit;
+    return sizeof(int) * ((size_t)2 * (size_t)std::max<int64_t>(n, 1) + (size_t)kRsDigits * rs_nblocks(std::max<int64_t>(n, 1)) + 1);
 }

@@ -200,7 +200,10 @@ void se_launch_gather_sorted(const double* xyz, const int* perm, int64_t n, cons
                              double* out_soa, double* out_aos4, int sanitize, int wrap, hipStream_t s);
 void se_launch_cell_starts(const int* sorted_keys, int64_t n, int64_t nbins, int* start,
                            hipStream_t s);
-se_status se_sort_pairs(se_plan* p, int64_t n, hipStream_t s);
+// Stable radix sort of (key, value) pairs, keys in [0, 2^end_bit) (se_geom.hip).
+se_status se_sort_pairs_raw(void* tmp, size_t tmp_bytes, const int* keys_in, int* keys_out, const int* vals_in,
+                            int* vals_out, int64_t n, int end_bit, hipStream_t s);
+size_t se_sort_tmp_bytes(int64_t n, int end_bit);
 void se_launch_strengths(const se_plan* p, const double* f, int slot, hipStream_t s);
 void se_launch_spread(const se_plan* p, int slot0, int nslot, hipStream_t s);
 void se_launch_fft_xy_forward(const se_plan* p, int slot, hipStream_t s);
