@@ -4,8 +4,8 @@ One step = one pass of the whole hot path over the batch: se_set_geometry (cell
 list) + the evaluation (gridding, FFT, scaling, IFFT, gathering, real-space
 sum, self term).  Two forms run on the same inputs: plain (analytic
 parameters, one strength set per step) and learned+batched (learned
-parameters, 16 strength sets on the shared geometry, the evaluation replayed
-as one HIP graph); `value` is the latter's targets/s.  Inputs are resident in
+parameters, 16 strength sets on the shared geometry, binding and evaluation
+replayed as HIP graphs); `value` is the latter's targets/s.  Inputs are resident in
 HBM before the timed regions start.
 Prints ONE JSON line, with the roofline of the dominant kernel (algorithmic
 work per launch over its live duration, against the MI355X peak) and the FP64
@@ -202,7 +202,7 @@ def main():
     plain_par = plan.params
 
     # ---- learned + batched: learned parameters, nrhs sets on the shared
-    # geometry, the evaluation replayed as one HIP graph on a side stream
+    # geometry, binding and evaluation each replayed as a HIP graph on a side stream
     batch = se.Batch([dict(selector=se.SELECT_LEARNED, n_rhs=nrhs, **common)])
     bplan = batch.plans[0]
     fb = f if nrhs > 1 else f0
@@ -324,7 +324,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "triply periodic stokeslet, unit cube, N=1e6 uniform sources = targets, "
                                "f~N(0,1)^3 zero mean, tol 1e-8 rms-rel, FP64; learned parameters, %d strength "
-                               "sets on the shared geometry, one replayed HIP graph per step" % nrhs,
+                               "sets on the shared geometry; binding and evaluation replayed as HIP graphs" % nrhs,
                    "form": "learned+batched", "n_rhs": nrhs, "learned": pdesc(par),
                    "launch_shape": {"real_tb": int(tuned[0]), "fft_cols": int(tuned[1]),
                                     "autotuned": bool(args.tune)},

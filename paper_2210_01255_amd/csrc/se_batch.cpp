@@ -24,6 +24,11 @@ struct se_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<uintptr_t> key;  // stream, pointers and launch shapes the graph holds
+    // geometry binding (bin keys, sort, cell starts, sorted copies), recorded
+    // the same way and keyed by the stream and the position pointers
+    hipGraph_t ggraph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    std::vector<uintptr_t> gkey;
     hipStream_t lane[kLanes] = {};
     hipEvent_t fork = nullptr, join[kLanes] = {};
 };
@@ -37,6 +42,15 @@ void drop_graph(se_batch* b)
     b->exec = nullptr;
     b->graph = nullptr;
     b->key.clear();
+}
+
+void drop_geometry_graph(se_batch* b)
+{
+    if (b->gexec) hipGraphExecDestroy(b->gexec);
+    if (b->ggraph) hipGraphDestroy(b->ggraph);
+    b->gexec = nullptr;
+    b->ggraph = nullptr;
+    b->gkey.clear();
 }
 
 se_status run_eager(se_batch* b, const double* const* f, double* const* u, hipStream_t s)
@@ -59,10 +73,13 @@ bool make_lanes(se_batch* b)
     return true;
 }
 
-// Records every member's launches into a graph: fork from s onto the lanes,
-// system i on lane i mod kLanes, join back on s (timing events off: they
-// would need host synchronisation inside the capture).
-se_status record(se_batch* b, const double* const* f, double* const* u, hipStream_t s)
+// Records every member's launches (work(i, stream) for system i) into a
+// graph: fork from s onto the lanes, system i on lane i mod kLanes, join back
+// on s (timing events off: they would need host synchronisation inside the
+// capture).  Every cross-stream dependency goes through s, the stream that
+// began the capture.
+template <typename Work>
+se_status record(se_batch* b, hipStream_t s, Work&& work, hipGraph_t* graph, hipGraphExec_t* exec)
 {
     if (!make_lanes(b)) return SE_ERR_HIP;
     std::vector<bool> timing(b->plans.size());
@@ -79,8 +96,7 @@ se_status record(se_batch* b, const double* const* f, double* const* u, hipStrea
         hipError_t e = hipEventRecord(b->fork, s);
         for (int l = 0; l < lanes && e == hipSuccess; l++) e = hipStreamWaitEvent(b->lane[l], b->fork, 0);
         if (e != hipSuccess) st = SE_ERR_HIP;
-        for (size_t i = 0; i < b->plans.size() && st == SE_OK; i++)
-            st = se_run_plan(b->plans[i], f[i], u[i], nullptr, nullptr, b->lane[i % lanes]);
+        for (size_t i = 0; i < b->plans.size() && st == SE_OK; i++) st = work(i, b->lane[i % lanes]);
         for (int l = 0; l < lanes; l++) {
             hipError_t e1 = hipEventRecord(b->join[l], b->lane[l]);
             if (e1 == hipSuccess) e1 = hipStreamWaitEvent(s, b->join[l], 0);
@@ -90,8 +106,8 @@ se_status record(se_batch* b, const double* const* f, double* const* u, hipStrea
         if (st == SE_OK && (e != hipSuccess || !g)) st = SE_ERR_HIP;
     }
     for (size_t i = 0; i < b->plans.size(); i++) b->plans[i]->timing = timing[i];
-    if (st == SE_OK && hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) {
-        b->exec = nullptr;
+    if (st == SE_OK && hipGraphInstantiate(exec, g, nullptr, nullptr, 0) != hipSuccess) {
+        *exec = nullptr;
         st = SE_ERR_HIP;
     }
     if (st != SE_OK) {
@@ -99,7 +115,7 @@ se_status record(se_batch* b, const double* const* f, double* const* u, hipStrea
         (void)hipGetLastError();
         return st;
     }
-    b->graph = g;
+    *graph = g;
     return SE_OK;
 }
 
@@ -147,6 +163,7 @@ se_status se_batch_destroy(se_batch* b)
     hipSetDevice(b->device);
     hipDeviceSynchronize();
     drop_graph(b);
+    drop_geometry_graph(b);
     if (b->fork) hipEventDestroy(b->fork);
     for (int l = 0; l < kLanes; l++) {
         if (b->lane[l]) hipStreamDestroy(b->lane[l]);
@@ -168,13 +185,33 @@ se_status se_batch_set_geometry(se_batch* b, const double* const* src, const dou
                                 const double* const* tgt, void* stream)
 {
     if (!b || !src) return SE_ERR_ARG;
+    for (size_t i = 0; i < b->plans.size(); i++)
+        if (!src[i]) return SE_ERR_ARG;
     if (hipSetDevice(b->device) != hipSuccess) return SE_ERR_HIP;
-    // binding rewrites the plans' own cell lists and sorted copies in place:
-    // a recorded graph stays valid
+    hipStream_t s = (hipStream_t)stream;
+    auto bind = [&](size_t i, hipStream_t st) {
+        return se_set_geometry(b->plans[i], src[i], nrm ? nrm[i] : nullptr, tgt ? tgt[i] : nullptr, st);
+    };
+    // binding rewrites the plans' own cell lists and sorted copies in place,
+    // so the evaluation graph stays valid across it; the binding itself is
+    // replayed from its own graph while the stream and pointers are unchanged
+    std::vector<uintptr_t> key;
+    key.push_back((uintptr_t)stream);
     for (size_t i = 0; i < b->plans.size(); i++) {
-        se_status st = se_set_geometry(b->plans[i], src[i], nrm ? nrm[i] : nullptr, tgt ? tgt[i] : nullptr, stream);
+        key.push_back((uintptr_t)src[i]);
+        key.push_back((uintptr_t)(nrm ? nrm[i] : nullptr));
+        key.push_back((uintptr_t)(tgt ? tgt[i] : nullptr));
+    }
+    bool bound = true;
+    for (se_plan* p : b->plans) bound = bound && p->have_geometry;
+    if (s && b->gexec && bound && key == b->gkey) return hipGraphLaunch(b->gexec, s) == hipSuccess ? SE_OK : SE_ERR_HIP;
+    drop_geometry_graph(b);
+    for (size_t i = 0; i < b->plans.size(); i++) {
+        se_status st = bind(i, s);
         if (st != SE_OK) return st;
     }
+    // the eager pass above is the result of this call; the graph serves the next ones
+    if (s && record(b, s, bind, &b->ggraph, &b->gexec) == SE_OK) b->gkey = key;
     return SE_OK;
 }
 
@@ -203,7 +240,8 @@ se_status se_batch_execute(se_batch* b, const double* const* f, double* const* u
     se_status st = run_eager(b, f, u, s);
     if (st != SE_OK) return st;
     // the eager pass above is the result of this call; the graph serves the next ones
-    if (record(b, f, u, s) == SE_OK) b->key = key;
+    auto run = [&](size_t i, hipStream_t st) { return se_run_plan(b->plans[i], f[i], u[i], nullptr, nullptr, st); };
+    if (record(b, s, run, &b->graph, &b->exec) == SE_OK) b->key = key;
     return SE_OK;
 }
 
