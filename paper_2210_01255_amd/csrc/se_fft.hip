@@ -155,20 +155,25 @@ __device__ __forceinline__ void dft_small(C<R>* v, int dir)
     }
 }
 
-// q = a / d, r = a % d for 0 <= a < 2^20, 1 <= d < 2^12, through a float
-// reciprocal (one correction step covers its rounding).
-__device__ __forceinline__ int fdiv(int a, int d, float rd, int* rem)
+// Division by a divisor d that is the same for the whole workgroup:
+// q = floor(a m / 2^32) with m = floor((2^32 - 1)/d) + 1 (m = 0 stands for
+// d = 1).  m - 2^32/d lies in (0, 1], so the quotient is exact while
+// a < 2^32/d; the line kernels divide indices below 2^12 by divisors below
+// 2^12.  The remainder uses 24-bit products (operands below 2^16).
+struct se_udiv {
+    int d;
+    uint32_t m;
+};
+
+__device__ __forceinline__ se_udiv make_udiv(int d)
 {
-    int q = (int)((float)a * rd);
-    int r = a - q * d;
-    if (r < 0) {
-        q--;
-        r += d;
-    } else if (r >= d) {
-        q++;
-        r -= d;
-    }
-    *rem = r;
+    return {d, d > 1 ? 0xFFFFFFFFu / (uint32_t)d + 1u : 0u};
+}
+
+__device__ __forceinline__ int udiv(int a, se_udiv u, int* rem)
+{
+    const int q = u.m ? (int)__umulhi((uint32_t)a, u.m) : a;
+    *rem = a - __mul24(q, u.d);
     return q;
 }
 
@@ -196,15 +201,17 @@ constexpr int ip_per_thread()
 // butterfly index does (unit stride in LDS either way for the layouts used).
 // One buffer per line instead of a ping-pong pair: twice the lines fit the
 // LDS, so each barrier covers twice the butterflies.
-template <typename R, int RAD, int E = kIpElems>
-__device__ __forceinline__ void stage_ip(C<R>* buf, int N, int nl, int lpg, int gs, int ls, int es,
-                                         bool lines_fastest, const C<R>* tw, int dir, int Ns)
+template <typename R, int RAD, int DIR, int E = kIpElems>
+__device__ __forceinline__ void stage_ip(C<R>* buf, int off, int N, int nl, int gs, int ls, int es, bool lines_fastest,
+                                         const C<R>* tw, int Ns, se_udiv dnl, se_udiv dlpg)
 {
     constexpr int K = ip_per_thread<RAD, E>();
     const int nb = N / RAD;
     const int total = nb * nl;
     const int tstride = N / (Ns * RAD);
-    const float rnb = 1.0f / (float)nb, rns = 1.0f / (float)Ns, rlpg = 1.0f / (float)lpg, rnl = 1.0f / (float)nl;
+    const se_udiv dnb = make_udiv(nb), dns = make_udiv(Ns);
+    const int istep = nb * es;  // between the inputs of one butterfly
+    const int ostep = Ns * es;  // between its outputs
     C<R> v[K][RAD];
     int ob[K];
 #pragma unroll
@@ -213,27 +220,27 @@ __device__ __forceinline__ void stage_ip(C<R>* buf, int N, int nl, int lpg, int 
         ob[k] = -1;
         if (idx < total) {
             int line, j;
-            if (lines_fastest) j = fdiv(idx, nl, rnl, &line);
-            else line = fdiv(idx, nb, rnb, &j);
+            if (lines_fastest) j = udiv(idx, dnl, &line);
+            else line = udiv(idx, dnb, &j);
             int lr;
-            const int lq = fdiv(line, lpg, rlpg, &lr);
-            const int base = lq * gs + lr * ls;
+            const int lq = udiv(line, dlpg, &lr);
+            const int base = off + __mul24(lq, gs) + __mul24(lr, ls);
             int jn;
-            const int jq = fdiv(j, Ns, rns, &jn);
-            const int ts = jn * tstride;
-            v[k][0] = buf[base + j * es];
+            const int jq = udiv(j, dns, &jn);
+            const int ts = __mul24(jn, tstride);
+            const int i0 = base + __mul24(j, es);
+            v[k][0] = buf[i0];
 #pragma unroll
             for (int r = 1; r < RAD; r++) {
                 C<R> w = tw[r * ts];
-                if (dir < 0) w.y = -w.y;
-                v[k][r] = cmul(buf[base + (j + r * nb) * es], w);
+                if (DIR < 0) w.y = -w.y;
+                v[k][r] = cmul(buf[i0 + r * istep], w);
             }
-            dft_small<R, RAD>(v[k], dir);
-            ob[k] = base + (jq * Ns * RAD + jn) * es;
+            dft_small<R, RAD>(v[k], DIR);
+            ob[k] = base + __mul24(__mul24(jq, Ns) * RAD + jn, es);
         }
     }
     __syncthreads();
-    const int ostep = Ns * es;
 #pragma unroll
     for (int k = 0; k < K; k++) {
         if (ob[k] >= 0) {
@@ -244,22 +251,25 @@ __device__ __forceinline__ void stage_ip(C<R>* buf, int N, int nl, int lpg, int 
     __syncthreads();
 }
 
-// Full in-place transform of nl lines (N * nl <= E).  The input must be
-// complete (synchronised) on entry; the result is synchronised on return.
-template <typename R, int E = kIpElems>
-__device__ __forceinline__ void fft_ip(C<R>* buf, int N, int nl, int lpg, int gs, int ls, int es, bool lines_fastest,
-                                       const C<R>* tw, int dir, const int* rad, int nrad)
+// Full in-place transform of nl lines (N * nl <= E) in direction DIR (+1:
+// e^{-2 pi i n k/N}).  Line l starts at off + (l / lpg) * gs + (l % lpg) *
+// ls, element e at + e * es.  The input must be complete (synchronised) on
+// entry; the result is synchronised on return.
+template <typename R, int DIR, int E = kIpElems>
+__device__ __forceinline__ void fft_ip(C<R>* buf, int off, int N, int nl, int lpg, int gs, int ls, int es,
+                                       bool lines_fastest, const C<R>* tw, const int* rad, int nrad)
 {
+    const se_udiv dnl = make_udiv(nl), dlpg = make_udiv(lpg);
     int Ns = 1;
     for (int s = 0; s < nrad; s++) {
         const int r = rad[s];
         switch (r) {
-            case 2: stage_ip<R, 2, E>(buf, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
-            case 3: stage_ip<R, 3, E>(buf, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
-            case 4: stage_ip<R, 4, E>(buf, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
-            case 5: stage_ip<R, 5, E>(buf, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
-            case 7: stage_ip<R, 7, E>(buf, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
-            default: stage_ip<R, 8, E>(buf, N, nl, lpg, gs, ls, es, lines_fastest, tw, dir, Ns); break;
+            case 2: stage_ip<R, 2, DIR, E>(buf, off, N, nl, gs, ls, es, lines_fastest, tw, Ns, dnl, dlpg); break;
+            case 3: stage_ip<R, 3, DIR, E>(buf, off, N, nl, gs, ls, es, lines_fastest, tw, Ns, dnl, dlpg); break;
+            case 4: stage_ip<R, 4, DIR, E>(buf, off, N, nl, gs, ls, es, lines_fastest, tw, Ns, dnl, dlpg); break;
+            case 5: stage_ip<R, 5, DIR, E>(buf, off, N, nl, gs, ls, es, lines_fastest, tw, Ns, dnl, dlpg); break;
+            case 7: stage_ip<R, 7, DIR, E>(buf, off, N, nl, gs, ls, es, lines_fastest, tw, Ns, dnl, dlpg); break;
+            default: stage_ip<R, 8, DIR, E>(buf, off, N, nl, gs, ls, es, lines_fastest, tw, Ns, dnl, dlpg); break;
         }
         Ns *= r;
     }
@@ -306,7 +316,7 @@ __global__ void __launch_bounds__(SE_FFT_THREADS, 4) k_fft_x_r2c(se_fft_args a)
         b0[l * Nh + k] = {re, im};
     }
     __syncthreads();
-    fft_ip<R, E>(b0, Nh, nl, nl, 0, Nh, 1, false, tw, 1, s_rad, a.nrad_xh);
+    fft_ip<R, 1, E>(b0, 0, Nh, nl, nl, 0, Nh, 1, false, tw, s_rad, a.nrad_xh);
     const C<R>* Z = b0;
     for (int i = threadIdx.x; i < nl * (Nh + 1); i += blockDim.x) {
         int l = i / (Nh + 1), k = i - l * (Nh + 1);
@@ -361,7 +371,7 @@ __global__ void __launch_bounds__(SE_FFT_THREADS, 4) k_fft_x_c2r(se_fft_args a)
         b0[l * Nh + k] = {Ap.x - Bp.y, Ap.y + Bp.x};  // A' + i B'
     }
     __syncthreads();
-    fft_ip<R, E>(b0, Nh, nl, nl, 0, Nh, 1, false, tw, -1, s_rad, a.nrad_xh);
+    fft_ip<R, -1, E>(b0, 0, Nh, nl, nl, 0, Nh, 1, false, tw, s_rad, a.nrad_xh);
     const C<R>* Z = b0;
     const int M0 = a.Mg[0];
     for (int i = threadIdx.x; i < nl * Nh; i += blockDim.x) {
@@ -375,9 +385,10 @@ __global__ void __launch_bounds__(SE_FFT_THREADS, 4) k_fft_x_c2r(se_fft_args a)
 
 // ------------------------------------------------------------ y: complex
 // A bundle of `cols` adjacent kx columns (contiguous in a row) for one (c, z).
-template <typename R, int E>
-__global__ void __launch_bounds__(SE_FFT_THREADS, 5) k_fft_y(se_fft_args a, int dir)
+template <typename R, int E, int DIR>
+__global__ void __launch_bounds__(SE_FFT_THREADS, 5) k_fft_y(se_fft_args a)
 {
+    constexpr int dir = DIR;
     extern __shared__ double smem_d[];
     __shared__ int s_rad[16];
     load_rad(s_rad, a.rad_y, a.nrad_y);
@@ -404,7 +415,7 @@ __global__ void __launch_bounds__(SE_FFT_THREADS, 5) k_fft_y(se_fft_args a, int 
         b0[y * Cc + col] = {ok ? t.x : (R)0, ok ? t.y : (R)0};
     }
     __syncthreads();
-    fft_ip<R, E>(b0, Ny, Cc, Cc, 0, 1, Cc, true, tw, dir, s_rad, a.nrad_y);
+    fft_ip<R, DIR, E>(b0, 0, Ny, Cc, Cc, 0, 1, Cc, true, tw, s_rad, a.nrad_y);
     const C<R>* Z = b0;
     for (int i = threadIdx.x; i < n_out * Cc; i += blockDim.x) {
         int y = i / Cc, col = i - y * Cc;
@@ -496,9 +507,10 @@ __device__ __forceinline__ void scale_point(const se_fft_args& a, int ix, int iy
 }
 
 // Plain complex transform along z (no scaling) for `ncomp` components.
-template <typename R, int E>
-__global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_z(se_fft_args a, int dir)
+template <typename R, int E, int DIR>
+__global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_z(se_fft_args a)
 {
+    constexpr int dir = DIR;
     extern __shared__ double smem_d[];
     __shared__ int s_rad[16];
     load_rad(s_rad, a.rad_z, a.nrad_z);
@@ -527,7 +539,7 @@ __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_z(se_fft_args a, int dir
         b0[i] = {ok ? t.x : (R)0, ok ? t.y : (R)0};
     }
     __syncthreads();
-    fft_ip<R, E>(b0, Nz, Cc, Cc, 0, 1, Cc, true, tw, dir, s_rad, a.nrad_z);
+    fft_ip<R, DIR, E>(b0, 0, Nz, Cc, Cc, 0, 1, Cc, true, tw, s_rad, a.nrad_z);
     const C<R>* Z = b0;
     for (int i = threadIdx.x; i < n_out * Cc; i += blockDim.x) {
         int z = i / Cc, col = i - z * Cc;
@@ -573,7 +585,7 @@ __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_z_scale(se_fft_args a)
     // component are Cc adjacent columns; components are cs apart)
     const int gc = max(1, min(NC, E / cs));
     for (int c0 = 0; c0 < NC; c0 += gc)
-        fft_ip<R, E>(sets + c0 * cs, Nz, min(gc, NC - c0) * Cc, Cc, cs, 1, Cc, true, tw, 1, s_rad, a.nrad_z);
+        fft_ip<R, 1, E>(sets, c0 * cs, Nz, min(gc, NC - c0) * Cc, Cc, cs, 1, Cc, true, tw, s_rad, a.nrad_z);
     for (int i = threadIdx.x; i < cs; i += blockDim.x) {
         int z = i / Cc, col = i - z * Cc;
         int kx = kx0 + col;
@@ -587,7 +599,7 @@ __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_z_scale(se_fft_args a)
     }
     __syncthreads();
     for (int c0 = 0; c0 < 3; c0 += gc)
-        fft_ip<R, E>(sets + c0 * cs, Nz, min(gc, 3 - c0) * Cc, Cc, cs, 1, Cc, true, tw, -1, s_rad, a.nrad_z);
+        fft_ip<R, -1, E>(sets, c0 * cs, Nz, min(gc, 3 - c0) * Cc, Cc, cs, 1, Cc, true, tw, s_rad, a.nrad_z);
     for (int i = threadIdx.x; i < 3 * cs; i += blockDim.x) {
         int c = i / cs, rem = i - c * cs;
         int z = rem / Cc, col = rem - z * Cc;
@@ -726,9 +738,10 @@ void run_y(se_fft_args a, int ncomp, int dir, hipStream_t s)
     a.cols = bundle_cols<R>(a.N[1], 1, a.cols_cap);
     int nbx = (a.Hx + a.cols - 1) / a.cols;
     size_t lds = (size_t)(a.N[1] + a.cols * a.N[1]) * sizeof(C<R>);
-    auto kern = a.N[1] > kIpElems ? k_fft_y<R, kIpElemsLong> : k_fft_y<R, kIpElems>;
+    auto kern = dir > 0 ? (a.N[1] > kIpElems ? k_fft_y<R, kIpElemsLong, 1> : k_fft_y<R, kIpElems, 1>)
+                        : (a.N[1] > kIpElems ? k_fft_y<R, kIpElemsLong, -1> : k_fft_y<R, kIpElems, -1>);
     allow_lds(kern, lds);
-    hipLaunchKernelGGL(kern, dim3((unsigned)(nbx * ncomp * a.Mg[2])), dim3(SE_FFT_THREADS), lds, s, a, dir);
+    hipLaunchKernelGGL(kern, dim3((unsigned)(nbx * ncomp * a.Mg[2])), dim3(SE_FFT_THREADS), lds, s, a);
 }
 
 template <typename R>
@@ -737,9 +750,10 @@ void run_z_plain(se_fft_args a, int ncomp, int dir, hipStream_t s)
     a.cols = bundle_cols<R>(a.N[2], 1, a.cols_cap);
     int nbx = (a.Hx + a.cols - 1) / a.cols;
     size_t lds = (size_t)(a.N[2] + a.cols * a.N[2]) * sizeof(C<R>);
-    auto kern = a.N[2] > kIpElems ? k_fft_z<R, kIpElemsLong> : k_fft_z<R, kIpElems>;
+    auto kern = dir > 0 ? (a.N[2] > kIpElems ? k_fft_z<R, kIpElemsLong, 1> : k_fft_z<R, kIpElems, 1>)
+                        : (a.N[2] > kIpElems ? k_fft_z<R, kIpElemsLong, -1> : k_fft_z<R, kIpElems, -1>);
     allow_lds(kern, lds);
-    hipLaunchKernelGGL(kern, dim3((unsigned)(nbx * a.N[1] * ncomp)), dim3(SE_FFT_THREADS), lds, s, a, dir);
+    hipLaunchKernelGGL(kern, dim3((unsigned)(nbx * a.N[1] * ncomp)), dim3(SE_FFT_THREADS), lds, s, a);
 }
 
 template <typename R>
