@@ -40,6 +40,7 @@ struct se_fft_args {
     int D;
     double kfac[3];  // 2 pi / (h_i N_i)
     double xi;
+    double inv4xi2;  // 1 / (4 xi^2)
     double scale;    // h1 h2 h3 / (N1 N2 N3)
     const double* invw2;  // 1/what0^2: [Hx | N1 | N2] per axis
     int iw_off[3];
@@ -308,8 +309,13 @@ __global__ void __launch_bounds__(SE_FFT_THREADS, 4) k_fft_x_r2c(se_fft_args a)
     const R* grid = (const R*)a.grid;
     C<R>* spec = (C<R>*)a.spec;
     const int M0 = a.Mg[0];
+    const se_udiv dNh = make_udiv(Nh), dNh1 = make_udiv(Nh + 1), dMy = make_udiv(a.Mg[1]);
+    // (c z, y) of the block's first row; rows l < nl follow it
+    const int64_t cz0 = row0 / a.Mg[1];
+    const int y0 = (int)(row0 - cz0 * a.Mg[1]);
     for (int i = threadIdx.x; i < nl * Nh; i += blockDim.x) {
-        int l = i / Nh, k = i - l * Nh;
+        int k;
+        const int l = udiv(i, dNh, &k);
         const R* row = grid + (row0 + l) * M0;
         R re = (2 * k < M0) ? row[2 * k] : (R)0;
         R im = (2 * k + 1 < M0) ? row[2 * k + 1] : (R)0;
@@ -319,18 +325,18 @@ __global__ void __launch_bounds__(SE_FFT_THREADS, 4) k_fft_x_r2c(se_fft_args a)
     fft_ip<R, 1, E>(b0, 0, Nh, nl, nl, 0, Nh, 1, false, tw, s_rad, a.nrad_xh);
     const C<R>* Z = b0;
     for (int i = threadIdx.x; i < nl * (Nh + 1); i += blockDim.x) {
-        int l = i / (Nh + 1), k = i - l * (Nh + 1);
-        C<R> zk = Z[l * Nh + (k % Nh)];
-        C<R> zn = Z[l * Nh + ((Nh - k) % Nh)];
+        int k;
+        const int l = udiv(i, dNh1, &k);
+        C<R> zk = Z[l * Nh + (k == Nh ? 0 : k)];
+        C<R> zn = Z[l * Nh + (k == 0 ? 0 : Nh - k)];
         zn.y = -zn.y;  // conj(Z_{N-k})
         C<R> A = {(zk.x + zn.x) * (R)0.5, (zk.y + zn.y) * (R)0.5};
         C<R> Bm = {(zk.x - zn.x) * (R)0.5, (zk.y - zn.y) * (R)0.5};
         // X_k = A_k - i e^{-2 pi i k/N0} (Z_k - conj Z_{N-k})/2
         C<R> t = cmul(Bm, twp[k]);
         C<R> X = {A.x + t.y, A.y - t.x};
-        int64_t row = row0 + l;
-        int64_t cz = row / a.Mg[1];
-        int y = (int)(row - cz * a.Mg[1]);
+        int y;
+        const int64_t cz = cz0 + udiv(y0 + l, dMy, &y);
         spec[(cz * a.N[1] + y) * a.Hp + k] = X;
     }
 }
@@ -354,11 +360,13 @@ __global__ void __launch_bounds__(SE_FFT_THREADS, 4) k_fft_x_c2r(se_fft_args a)
     const int nl = (int)min((int64_t)a.lines, rows - row0);
     R* grid = (R*)a.grid;
     const C<R>* spec = (const C<R>*)a.spec;
+    const se_udiv dNh = make_udiv(Nh), dMy = make_udiv(a.Mg[1]);
+    const int64_t cz0 = row0 / a.Mg[1];
+    const int y0 = (int)(row0 - cz0 * a.Mg[1]);
     for (int i = threadIdx.x; i < nl * Nh; i += blockDim.x) {
-        int l = i / Nh, k = i - l * Nh;
-        int64_t row = row0 + l;
-        int64_t cz = row / a.Mg[1];
-        int y = (int)(row - cz * a.Mg[1]);
+        int k, y;
+        const int l = udiv(i, dNh, &k);
+        const int64_t cz = cz0 + udiv(y0 + l, dMy, &y);
         const C<R>* X = spec + (cz * a.N[1] + y) * a.Hp;
         C<R> xk = X[k];
         C<R> xn = X[Nh - k];
@@ -375,7 +383,8 @@ __global__ void __launch_bounds__(SE_FFT_THREADS, 4) k_fft_x_c2r(se_fft_args a)
     const C<R>* Z = b0;
     const int M0 = a.Mg[0];
     for (int i = threadIdx.x; i < nl * Nh; i += blockDim.x) {
-        int l = i / Nh, k = i - l * Nh;
+        int k;
+        const int l = udiv(i, dNh, &k);
         R* row = grid + (row0 + l) * M0;
         C<R> z = Z[l * Nh + k];
         if (2 * k < M0) row[2 * k] = z.x;
@@ -406,8 +415,10 @@ __global__ void __launch_bounds__(SE_FFT_THREADS, 5) k_fft_y(se_fft_args a)
     C<R>* base = spec + cz * (int64_t)Ny * a.Hp;
     const int n_in = dir > 0 ? a.Mg[1] : Ny;
     const int n_out = dir > 0 ? Ny : a.Mg[1];
+    const se_udiv dC = make_udiv(Cc);
     for (int i = threadIdx.x; i < Ny * Cc; i += blockDim.x) {
-        int y = i / Cc, col = i - y * Cc;
+        int col;
+        const int y = udiv(i, dC, &col);
         int kx = kx0 + col;
         // unconditional load from a valid address (kx0 < Hx), then select
         const bool ok = kx < a.Hx && y < n_in;
@@ -418,7 +429,8 @@ __global__ void __launch_bounds__(SE_FFT_THREADS, 5) k_fft_y(se_fft_args a)
     fft_ip<R, DIR, E>(b0, 0, Ny, Cc, Cc, 0, 1, Cc, true, tw, s_rad, a.nrad_y);
     const C<R>* Z = b0;
     for (int i = threadIdx.x; i < n_out * Cc; i += blockDim.x) {
-        int y = i / Cc, col = i - y * Cc;
+        int col;
+        const int y = udiv(i, dC, &col);
         int kx = kx0 + col;
         if (kx < a.Hx) base[(int64_t)y * a.Hp + kx] = Z[y * Cc + col];
     }
@@ -441,7 +453,8 @@ __device__ __forceinline__ double green_scalar(const se_fft_args& a, int ix, int
 {
     if (a.D == 0) return a.ktab[((int64_t)iz * a.N[1] + iy) * a.Hx + ix];
     if (k2 == 0.0) return 0.0;
-    return se_harmonic_based(KER) ? 4.0 * M_PI / k2 : -8.0 * M_PI / (k2 * k2);
+    const double r = 1.0 / k2;
+    return se_harmonic_based(KER) ? 4.0 * M_PI * r : -8.0 * M_PI * r * r;
 }
 
 // u = Khat(k) F with the scalar factor c = Ahat gammahat W already formed.
@@ -498,7 +511,7 @@ __device__ __forceinline__ void scale_point(const se_fft_args& a, int ix, int iy
         U[0] = U[1] = U[2] = {(R)0, (R)0};
         return;
     }
-    const double e = k2 / (4.0 * a.xi * a.xi);
+    const double e = k2 * a.inv4xi2;
     const double gE = exp(-e);
     const double iw = a.invw2[a.iw_off[0] + ix] * a.invw2[a.iw_off[1] + iy] * a.invw2[a.iw_off[2] + iz];
     const double W = a.scale * iw;
@@ -531,8 +544,10 @@ __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_z(se_fft_args a)
     C<R>* spec = (C<R>*)a.spec + (int64_t)c * Mz * zstride;
     const int n_in = dir > 0 ? Mz : Nz;
     const int n_out = dir > 0 ? Nz : Mz;
+    const se_udiv dC = make_udiv(Cc);
     for (int i = threadIdx.x; i < Nz * Cc; i += blockDim.x) {
-        int z = i / Cc, col = i - z * Cc;
+        int col;
+        const int z = udiv(i, dC, &col);
         int kx = kx0 + col;
         const bool ok = kx < a.Hx && z < n_in && z < Mz;
         const C<R> t = spec[ok ? z * zstride + (int64_t)y * a.Hp + kx : (int64_t)y * a.Hp + kx0];
@@ -542,7 +557,8 @@ __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_z(se_fft_args a)
     fft_ip<R, DIR, E>(b0, 0, Nz, Cc, Cc, 0, 1, Cc, true, tw, s_rad, a.nrad_z);
     const C<R>* Z = b0;
     for (int i = threadIdx.x; i < n_out * Cc; i += blockDim.x) {
-        int z = i / Cc, col = i - z * Cc;
+        int col;
+        const int z = udiv(i, dC, &col);
         int kx = kx0 + col;
         if (kx < a.Hx && z < Mz) spec[z * zstride + (int64_t)y * a.Hp + kx] = Z[i];
     }
@@ -572,9 +588,11 @@ __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_z_scale(se_fft_args a)
     const int64_t cstride = (int64_t)Mz * a.N[1] * a.Hp;
     const int64_t zstride = (int64_t)a.N[1] * a.Hp;
     C<R>* spec = (C<R>*)a.spec;
+    const se_udiv dcs = make_udiv(cs), dC = make_udiv(Cc);
     for (int i = threadIdx.x; i < NC * cs; i += blockDim.x) {
-        int c = i / cs, rem = i - c * cs;
-        int z = rem / Cc, col = rem - z * Cc;
+        int rem, col;
+        const int c = udiv(i, dcs, &rem);
+        const int z = udiv(rem, dC, &col);
         int kx = kx0 + col;
         const bool ok = kx < a.Hx && z < Mz;
         const C<R> t = spec[c * cstride + (ok ? z * zstride + (int64_t)y * a.Hp + kx : (int64_t)y * a.Hp + kx0)];
@@ -587,7 +605,8 @@ __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_z_scale(se_fft_args a)
     for (int c0 = 0; c0 < NC; c0 += gc)
         fft_ip<R, 1, E>(sets, c0 * cs, Nz, min(gc, NC - c0) * Cc, Cc, cs, 1, Cc, true, tw, s_rad, a.nrad_z);
     for (int i = threadIdx.x; i < cs; i += blockDim.x) {
-        int z = i / Cc, col = i - z * Cc;
+        int col;
+        const int z = udiv(i, dC, &col);
         int kx = kx0 + col;
         if (kx >= a.Hx) continue;
         C<R> F[NC], U[3];
@@ -601,8 +620,9 @@ __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_z_scale(se_fft_args a)
     for (int c0 = 0; c0 < 3; c0 += gc)
         fft_ip<R, -1, E>(sets, c0 * cs, Nz, min(gc, 3 - c0) * Cc, Cc, cs, 1, Cc, true, tw, s_rad, a.nrad_z);
     for (int i = threadIdx.x; i < 3 * cs; i += blockDim.x) {
-        int c = i / cs, rem = i - c * cs;
-        int z = rem / Cc, col = rem - z * Cc;
+        int rem, col;
+        const int c = udiv(i, dcs, &rem);
+        const int z = udiv(rem, dC, &col);
         int kx = kx0 + col;
         if (kx < a.Hx && z < Mz) spec[c * cstride + z * zstride + (int64_t)y * a.Hp + kx] = sets[i];
     }
@@ -663,6 +683,7 @@ se_fft_args make_fft_args(const se_plan* p, int ncomp, int slot)
     a.kernel = p->kernel;
     a.D = p->D;
     a.xi = p->par.xi;
+    a.inv4xi2 = 1.0 / (4.0 * p->par.xi * p->par.xi);
     a.invw2 = p->d_invw2;
     a.iw_off[0] = 0;
     a.iw_off[1] = p->Hx;
