@@ -2,10 +2,14 @@
 // periodicity, evaluated on one stream and replayed as one HIP graph.
 //
 // Each member is an ordinary plan (its own parameters from the Sec. 4.6
-// procedure, its own grid and cell list); the batch adds the launch-level
-// plumbing: a graph that holds every member's full evaluation (strengths
-// through finalisation, Secs. 3.2-3.3 and 4), and a per-member autotuner over
-// the launch shapes that leave the arithmetic unchanged.
+// procedure, its own grid and cell list).  A batch of several members runs
+// phase by phase: one launch per phase covers the work items of all members
+// (the tiles of gridding and gathering, the line bundles of every FFT pass,
+// the blocks of the real-space sum), reading each member's argument record
+// from a device array; only the member-specific steps (strengths, the
+// upsampled-class steps of D = 1, 2, the epilogue) are launched per member.
+// The batch records this schedule into a graph, and autotunes each member's
+// launch shapes (which leave the arithmetic unchanged).
 #include "se_internal.h"
 
 #include <hip/hip_runtime.h>
@@ -18,8 +22,32 @@
 // graph holds them as parallel branches and small systems share the chip.
 constexpr int kLanes = 4;
 
+// One step of the phase-major schedule: a merged launch over jobs of one
+// family and variant, or a step of one member.
+struct se_step {
+    int kind = 0;  // 0: merged launch, else a member step (below)
+    int family = 0, variant = 0, n = 0, blocks = 0;
+    size_t lds = 0, args_off = 0, boff_off = 0;
+    int plan = 0, r0 = 0, nr = 0, slot = 0, which = 0;
+};
+enum {
+    kStepMerged = 0,
+    kStepStrengths,  // strengths, reductions and the cleared Fourier accumulators of a chunk
+    kStepPrep,       // per-geometry counts and scans of the tiles and the real-space blocks
+    kStepSpread,     // gridding of a member without a merged form
+    kStepGather,
+    kStepReal,
+    kStepCls,        // an upsampled-class step of the adaptive FFT
+    kStepFinalize,
+};
+
 struct se_batch {
     std::vector<se_plan*> plans;
+    // phase-major schedule (batches of two or more members) and its device
+    // argument records, rebuilt when a member's launch shapes change
+    std::vector<se_step> steps;
+    std::vector<uintptr_t> skey;
+    char* d_jobs = nullptr;
     int device = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -51,6 +79,188 @@ void drop_geometry_graph(se_batch* b)
     b->gexec = nullptr;
     b->ggraph = nullptr;
     b->gkey.clear();
+}
+
+// Shapes that the schedule depends on (the merged records hold the plans'
+// launch shapes).
+std::vector<uintptr_t> schedule_key(const se_batch* b)
+{
+    std::vector<uintptr_t> k;
+    for (const se_plan* p : b->plans) {
+        k.push_back((uintptr_t)p->shape_real_tb);
+        k.push_back((uintptr_t)p->shape_fft_cols);
+    }
+    return k;
+}
+
+// Groups jobs by family and variant into merged steps (at most `cap` jobs
+// each), appending their records (one struct each, packed as the kernels
+// index them) and workgroup prefixes to the host image.
+void emit_merged(std::vector<se_job>& jobs, int cap, std::vector<se_step>* steps, std::vector<char>* img)
+{
+    auto align = [&](size_t a) { img->resize((img->size() + a - 1) / a * a); };
+    std::vector<bool> done(jobs.size(), false);
+    for (size_t i = 0; i < jobs.size(); i++) {
+        if (done[i]) continue;
+        std::vector<size_t> grp;
+        for (size_t k = i; k < jobs.size(); k++)
+            if (!done[k] && jobs[k].family == jobs[i].family && jobs[k].variant == jobs[i].variant) {
+                grp.push_back(k);
+                done[k] = true;
+            }
+        for (size_t g0 = 0; g0 < grp.size(); g0 += cap) {
+            const size_t g1 = std::min(grp.size(), g0 + cap);
+            se_step st;
+            st.kind = kStepMerged;
+            st.family = jobs[i].family;
+            st.variant = jobs[i].variant;
+            st.n = (int)(g1 - g0);
+            align(256);
+            st.args_off = img->size();
+            for (size_t k = g0; k < g1; k++) {
+                const se_job& j = jobs[grp[k]];
+                img->insert(img->end(), j.args.begin(), j.args.end());
+                st.lds = std::max(st.lds, j.lds);
+            }
+            align(256);
+            st.boff_off = img->size();
+            int acc = 0;
+            for (size_t k = g0; k <= g1; k++) {
+                const int v = acc;
+                img->insert(img->end(), (const char*)&v, (const char*)&v + sizeof(int));
+                if (k < g1) acc += jobs[grp[k]].blocks;
+            }
+            st.blocks = acc;
+            steps->push_back(st);
+        }
+    }
+    jobs.clear();
+}
+
+// The phase-major schedule of a batch: per chunk of right-hand sides the
+// member steps and merged launches in pipeline order.
+se_status build_schedule(se_batch* b)
+{
+    std::vector<se_step> steps;
+    std::vector<char> img;
+    std::vector<se_job> jobs;
+    int nchunk = 0;
+    for (const se_plan* p : b->plans) nchunk = std::max(nchunk, (p->nrhs + p->rb - 1) / p->rb);
+    auto member = [&](int kind, int i, int r0, int nr, int slot = 0, int which = 0) {
+        se_step st;
+        st.kind = kind;
+        st.plan = i;
+        st.r0 = r0;
+        st.nr = nr;
+        st.slot = slot;
+        st.which = which;
+        steps.push_back(st);
+    };
+    const int np = (int)b->plans.size();
+    for (int c = 0; c < nchunk; c++) {
+        std::vector<int> r0(np), nr(np, 0);
+        for (int i = 0; i < np; i++) {
+            const se_plan* p = b->plans[i];
+            r0[i] = c * p->rb;
+            nr[i] = r0[i] < p->nrhs ? std::min(p->rb, p->nrhs - r0[i]) : 0;
+        }
+        for (int i = 0; i < np; i++)
+            if (nr[i]) {
+                member(kStepStrengths, i, r0[i], nr[i]);
+                if (c == 0) member(kStepPrep, i, 0, nr[i]);
+            }
+        // gridding
+        for (int i = 0; i < np; i++)
+            if (nr[i] && !se_tile_jobs(b->plans[i], false, nr[i], &jobs)) member(kStepSpread, i, r0[i], nr[i]);
+        emit_merged(jobs, SE_JOB_MAX, &steps, &img);
+        // forward transforms: x, class step 0, y, class step 1
+        const int fam_fwd[2] = {SE_JOB_FFT_X_R2C, SE_JOB_FFT_Y_FWD};
+        for (int pass = 0; pass < 2; pass++) {
+            for (int i = 0; i < np; i++)
+                for (int k = 0; k < nr[i]; k++) se_fft_jobs(b->plans[i], fam_fwd[pass], k, &jobs);
+            emit_merged(jobs, SE_JOB_MAX, &steps, &img);
+            for (int i = 0; i < np; i++)
+                for (int k = 0; k < nr[i]; k++)
+                    if (b->plans[i]->D == 1 || b->plans[i]->D == 2) member(kStepCls, i, r0[i], nr[i], k, pass);
+        }
+        // z transform, scaling and inverse z; class step 2
+        for (int i = 0; i < np; i++)
+            for (int k = 0; k < nr[i]; k++) se_fft_jobs(b->plans[i], SE_JOB_FFT_Z_SCALE, k, &jobs);
+        emit_merged(jobs, SE_JOB_MAX, &steps, &img);
+        for (int i = 0; i < np; i++)
+            for (int k = 0; k < nr[i]; k++)
+                if (b->plans[i]->D == 1 || b->plans[i]->D == 2) member(kStepCls, i, r0[i], nr[i], k, 2);
+        // inverse y, class step 3, inverse x
+        for (int i = 0; i < np; i++)
+            for (int k = 0; k < nr[i]; k++) se_fft_jobs(b->plans[i], SE_JOB_FFT_Y_INV, k, &jobs);
+        emit_merged(jobs, SE_JOB_MAX, &steps, &img);
+        for (int i = 0; i < np; i++)
+            for (int k = 0; k < nr[i]; k++)
+                if (b->plans[i]->D == 1) member(kStepCls, i, r0[i], nr[i], k, 3);
+        for (int i = 0; i < np; i++)
+            for (int k = 0; k < nr[i]; k++) se_fft_jobs(b->plans[i], SE_JOB_FFT_X_C2R, k, &jobs);
+        emit_merged(jobs, SE_JOB_MAX, &steps, &img);
+        // gathering
+        for (int i = 0; i < np; i++)
+            if (nr[i] && !se_tile_jobs(b->plans[i], true, nr[i], &jobs)) member(kStepGather, i, r0[i], nr[i]);
+        emit_merged(jobs, SE_JOB_MAX, &steps, &img);
+        // real-space sums
+        for (int i = 0; i < np; i++)
+            if (nr[i] && !se_real_jobs(b->plans[i], nr[i], &jobs)) member(kStepReal, i, r0[i], nr[i]);
+        emit_merged(jobs, se_real_job_max(), &steps, &img);
+        for (int i = 0; i < np; i++)
+            if (nr[i]) member(kStepFinalize, i, r0[i], nr[i]);
+    }
+    if (b->d_jobs) hipFree(b->d_jobs);
+    b->d_jobs = nullptr;
+    if (!img.empty()) {
+        if (hipMalloc(&b->d_jobs, img.size()) != hipSuccess) return SE_ERR_NOMEM;
+        if (hipMemcpy(b->d_jobs, img.data(), img.size(), hipMemcpyHostToDevice) != hipSuccess) return SE_ERR_HIP;
+    }
+    b->steps = std::move(steps);
+    b->skey = schedule_key(b);
+    return SE_OK;
+}
+
+// One evaluation of every member through the schedule, on stream s.
+se_status run_schedule(se_batch* b, const double* const* f, double* const* u, hipStream_t s)
+{
+    for (const se_step& st : b->steps) {
+        se_plan* p = b->plans[st.plan];
+        switch (st.kind) {
+            case kStepMerged: {
+                const void* args = b->d_jobs + st.args_off;
+                const int* boff = (const int*)(b->d_jobs + st.boff_off);
+                if (st.family == SE_JOB_SPREAD || st.family == SE_JOB_GATHER)
+                    se_tile_launch_multi(st.family, st.variant, args, boff, st.n, st.blocks, s);
+                else if (st.family == SE_JOB_REAL)
+                    se_real_launch_multi(st.variant, args, st.n, st.blocks, s);
+                else
+                    se_fft_launch_multi(st.family, st.variant, args, boff, st.n, st.blocks, st.lds, s);
+                break;
+            }
+            case kStepStrengths:
+                for (int k = 0; k < st.nr; k++) {
+                    se_launch_strengths(p, f[st.plan] + (size_t)(st.r0 + k) * p->ns * 3, k, s);
+                    se_launch_reductions(p, k, s);
+                }
+                se_launch_fill_double(p->d_uF, 0.0, (int64_t)st.nr * 3 * p->nt, s);
+                break;
+            case kStepPrep:
+                se_launch_tile_prep(p, s);
+                se_launch_real_prep(p, s);
+                break;
+            case kStepSpread: se_launch_spread(p, 0, st.nr, s); break;
+            case kStepGather: se_launch_gather(p, 0, st.nr, s); break;
+            case kStepReal: se_launch_real_space(p, 0, st.nr, s); break;
+            case kStepCls: se_launch_fft_cls(p, st.slot, st.which, s); break;
+            case kStepFinalize:
+                for (int k = 0; k < st.nr; k++)
+                    se_launch_finalize(p, k, u[st.plan] + (size_t)(st.r0 + k) * p->nt * 3, nullptr, nullptr, s);
+                break;
+        }
+    }
+    return hipGetLastError() == hipSuccess ? SE_OK : SE_ERR_HIP;
 }
 
 se_status run_eager(se_batch* b, const double* const* f, double* const* u, hipStream_t s)
@@ -119,6 +329,28 @@ se_status record(se_batch* b, hipStream_t s, Work&& work, hipGraph_t* graph, hip
     return SE_OK;
 }
 
+// Records the schedule on s alone (its only stream) into a graph.
+se_status record_schedule(se_batch* b, const double* const* f, double* const* u, hipStream_t s)
+{
+    se_status st = SE_OK;
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) != hipSuccess) return SE_ERR_HIP;
+    st = run_schedule(b, f, u, s);
+    const hipError_t e = hipStreamEndCapture(s, &g);
+    if (st == SE_OK && (e != hipSuccess || !g)) st = SE_ERR_HIP;
+    if (st == SE_OK && hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+        b->exec = nullptr;
+        st = SE_ERR_HIP;
+    }
+    if (st != SE_OK) {
+        if (g) hipGraphDestroy(g);
+        (void)hipGetLastError();
+        return st;
+    }
+    b->graph = g;
+    return SE_OK;
+}
+
 bool check_args(const se_batch* b, const double* const* f, double* const* u)
 {
     if (!b || !f || !u) return false;
@@ -164,6 +396,7 @@ se_status se_batch_destroy(se_batch* b)
     hipDeviceSynchronize();
     drop_graph(b);
     drop_geometry_graph(b);
+    if (b->d_jobs) hipFree(b->d_jobs);
     if (b->fork) hipEventDestroy(b->fork);
     for (int l = 0; l < kLanes; l++) {
         if (b->lane[l]) hipStreamDestroy(b->lane[l]);
@@ -222,7 +455,14 @@ se_status se_batch_execute(se_batch* b, const double* const* f, double* const* u
         if (!p->have_geometry) return SE_ERR_STATE;
     if (hipSetDevice(b->device) != hipSuccess) return SE_ERR_HIP;
     hipStream_t s = (hipStream_t)stream;
-    if (!s) return run_eager(b, f, u, s);
+    // several members: the phase-major schedule (merged launches)
+    const bool merged = b->plans.size() >= 2;
+    if (merged && (b->steps.empty() || b->skey != schedule_key(b))) {
+        drop_graph(b);
+        se_status st = build_schedule(b);
+        if (st != SE_OK) return st;
+    }
+    if (!s) return merged ? run_schedule(b, f, u, s) : run_eager(b, f, u, s);
 
     std::vector<uintptr_t> key;
     key.reserve(4 * b->plans.size() + 1);
@@ -237,11 +477,15 @@ se_status se_batch_execute(se_batch* b, const double* const* f, double* const* u
     if (b->exec && key == b->key) return hipGraphLaunch(b->exec, s) == hipSuccess ? SE_OK : SE_ERR_HIP;
 
     drop_graph(b);
-    se_status st = run_eager(b, f, u, s);
+    se_status st = merged ? run_schedule(b, f, u, s) : run_eager(b, f, u, s);
     if (st != SE_OK) return st;
     // the eager pass above is the result of this call; the graph serves the next ones
-    auto run = [&](size_t i, hipStream_t st) { return se_run_plan(b->plans[i], f[i], u[i], nullptr, nullptr, st); };
-    if (record(b, s, run, &b->graph, &b->exec) == SE_OK) b->key = key;
+    if (merged) {
+        if (record_schedule(b, f, u, s) == SE_OK) b->key = key;
+    } else {
+        auto run = [&](size_t i, hipStream_t st) { return se_run_plan(b->plans[i], f[i], u[i], nullptr, nullptr, st); };
+        if (record(b, s, run, &b->graph, &b->exec) == SE_OK) b->key = key;
+    }
     return SE_OK;
 }
 

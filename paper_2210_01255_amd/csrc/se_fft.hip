@@ -292,7 +292,7 @@ __device__ __forceinline__ void load_tw(C<R>* dst, const double* src, int n)
 // Rows of M0 reals (zero padded to N0) as N0/2 complex values, one FFT of
 // length N0/2, then the split into the half spectrum k = 0..N0/2.
 template <typename R, int E>
-__global__ void __launch_bounds__(SE_FFT_THREADS, 4) k_fft_x_r2c(se_fft_args a)
+__device__ __forceinline__ void fft_x_r2c_body(const se_fft_args& a, int blk)
 {
     extern __shared__ double smem_d[];
     __shared__ int s_rad[16];
@@ -304,7 +304,7 @@ __global__ void __launch_bounds__(SE_FFT_THREADS, 4) k_fft_x_r2c(se_fft_args a)
     load_tw(tw, a.tw + 2 * a.tw_xh, Nh);
     load_tw(twp, a.tw + 2 * a.tw_xp, Nh + 1);
     const int64_t rows = (int64_t)a.ncomp * a.Mg[2] * a.Mg[1];
-    const int64_t row0 = (int64_t)se_xcd_block(blockIdx.x, gridDim.x) * a.lines;
+    const int64_t row0 = (int64_t)blk * a.lines;
     const int nl = (int)min((int64_t)a.lines, rows - row0);
     const R* grid = (const R*)a.grid;
     C<R>* spec = (C<R>*)a.spec;
@@ -343,7 +343,7 @@ __global__ void __launch_bounds__(SE_FFT_THREADS, 4) k_fft_x_r2c(se_fft_args a)
 
 // ------------------------------------------------------------ x: half -> real
 template <typename R, int E>
-__global__ void __launch_bounds__(SE_FFT_THREADS, 4) k_fft_x_c2r(se_fft_args a)
+__device__ __forceinline__ void fft_x_c2r_body(const se_fft_args& a, int blk)
 {
     extern __shared__ double smem_d[];
     __shared__ int s_rad[16];
@@ -356,7 +356,7 @@ __global__ void __launch_bounds__(SE_FFT_THREADS, 4) k_fft_x_c2r(se_fft_args a)
     load_tw(twp, a.tw + 2 * a.tw_xp, Nh + 1);
     __syncthreads();
     const int64_t rows = (int64_t)a.ncomp * a.Mg[2] * a.Mg[1];
-    const int64_t row0 = (int64_t)se_xcd_block(blockIdx.x, gridDim.x) * a.lines;
+    const int64_t row0 = (int64_t)blk * a.lines;
     const int nl = (int)min((int64_t)a.lines, rows - row0);
     R* grid = (R*)a.grid;
     const C<R>* spec = (const C<R>*)a.spec;
@@ -395,7 +395,7 @@ __global__ void __launch_bounds__(SE_FFT_THREADS, 4) k_fft_x_c2r(se_fft_args a)
 // ------------------------------------------------------------ y: complex
 // A bundle of `cols` adjacent kx columns (contiguous in a row) for one (c, z).
 template <typename R, int E, int DIR>
-__global__ void __launch_bounds__(SE_FFT_THREADS, 5) k_fft_y(se_fft_args a)
+__device__ __forceinline__ void fft_y_body(const se_fft_args& a, int bid)
 {
     constexpr int dir = DIR;
     extern __shared__ double smem_d[];
@@ -407,7 +407,6 @@ __global__ void __launch_bounds__(SE_FFT_THREADS, 5) k_fft_y(se_fft_args a)
     C<R>* b0 = tw + Ny;
     load_tw(tw, a.tw + 2 * a.tw_y, Ny);
     const int nbx = (a.Hx + Cc - 1) / Cc;
-    int bid = se_xcd_block(blockIdx.x, gridDim.x);  // neighbouring bundles share an XCD (L2)
     int bx = bid % nbx;
     int64_t cz = bid / nbx;  // c * Mz + z
     const int kx0 = bx * Cc;
@@ -568,7 +567,7 @@ __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_z(se_fft_args a)
 // kx columns at one y, all components resident in LDS (NC column sets,
 // transformed in place, several components per call).
 template <typename R, int KER, int NC, int E>
-__global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_z_scale(se_fft_args a)
+__device__ __forceinline__ void fft_z_scale_body(const se_fft_args& a, int blk)
 {
     extern __shared__ double smem_d[];
     __shared__ int s_rad[16];
@@ -580,7 +579,6 @@ __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_z_scale(se_fft_args a)
     C<R>* sets = tw + Nz;
     load_tw(tw, a.tw + 2 * a.tw_z, Nz);
     const int nbx = (a.Hx + Cc - 1) / Cc;
-    const int blk = se_xcd_block(blockIdx.x, gridDim.x);
     const int bx = blk % nbx;
     const int y = blk / nbx;
     const int kx0 = bx * Cc;
@@ -626,6 +624,69 @@ __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_z_scale(se_fft_args a)
         int kx = kx0 + col;
         if (kx < a.Hx && z < Mz) spec[c * cstride + z * zstride + (int64_t)y * a.Hp + kx] = sets[i];
     }
+}
+
+// Kernels over one plan's pass (neighbouring blocks share an XCD and its
+// L2) and merged kernels over the jobs of many plans: job j's record is
+// av[j] and its blocks are boff[j] .. boff[j+1] - 1 of the launch.
+__device__ __forceinline__ int fft_job_of(const int* __restrict__ boff, int n, int g)
+{
+    int lo = 0, hi = n;  // largest j with boff[j] <= g
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (boff[mid] <= g) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+template <typename R, int E>
+__global__ void __launch_bounds__(SE_FFT_THREADS, 4) k_fft_x_r2c(se_fft_args a)
+{
+    fft_x_r2c_body<R, E>(a, se_xcd_block(blockIdx.x, gridDim.x));
+}
+template <typename R, int E>
+__global__ void __launch_bounds__(SE_FFT_THREADS, 4) k_fft_x_r2c_multi(const se_fft_args* __restrict__ av,
+                                                                     const int* __restrict__ boff, int n)
+{
+    const int g = se_xcd_block(blockIdx.x, gridDim.x), j = fft_job_of(boff, n, g);
+    fft_x_r2c_body<R, E>(av[j], g - boff[j]);
+}
+template <typename R, int E>
+__global__ void __launch_bounds__(SE_FFT_THREADS, 4) k_fft_x_c2r(se_fft_args a)
+{
+    fft_x_c2r_body<R, E>(a, se_xcd_block(blockIdx.x, gridDim.x));
+}
+template <typename R, int E>
+__global__ void __launch_bounds__(SE_FFT_THREADS, 4) k_fft_x_c2r_multi(const se_fft_args* __restrict__ av,
+                                                                     const int* __restrict__ boff, int n)
+{
+    const int g = se_xcd_block(blockIdx.x, gridDim.x), j = fft_job_of(boff, n, g);
+    fft_x_c2r_body<R, E>(av[j], g - boff[j]);
+}
+template <typename R, int E, int DIR>
+__global__ void __launch_bounds__(SE_FFT_THREADS, 5) k_fft_y(se_fft_args a)
+{
+    fft_y_body<R, E, DIR>(a, se_xcd_block(blockIdx.x, gridDim.x));
+}
+template <typename R, int E, int DIR>
+__global__ void __launch_bounds__(SE_FFT_THREADS, 5) k_fft_y_multi(const se_fft_args* __restrict__ av,
+                                                                 const int* __restrict__ boff, int n)
+{
+    const int g = se_xcd_block(blockIdx.x, gridDim.x), j = fft_job_of(boff, n, g);
+    fft_y_body<R, E, DIR>(av[j], g - boff[j]);
+}
+template <typename R, int KER, int NC, int E>
+__global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_z_scale(se_fft_args a)
+{
+    fft_z_scale_body<R, KER, NC, E>(a, se_xcd_block(blockIdx.x, gridDim.x));
+}
+template <typename R, int KER, int NC, int E>
+__global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_z_scale_multi(const se_fft_args* __restrict__ av,
+                                                                    const int* __restrict__ boff, int n)
+{
+    const int g = se_xcd_block(blockIdx.x, gridDim.x), j = fft_job_of(boff, n, g);
+    fft_z_scale_body<R, KER, NC, E>(av[j], g - boff[j]);
 }
 
 // LDS budgets (bytes) of the line kernels: two workgroups per CU.
@@ -1276,5 +1337,123 @@ void se_fft3d_f64(const int* Mg, const int* N, const double* h, double* grid, do
         run_z_plain<double>(a, ncomp, -1, s);
         run_y<double>(a, ncomp, -1, s);
         run_x_c2r<double>(a, ncomp, s);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Jobs of merged batches: the records, workgroups and LDS that the
+// single-plan launchers above choose.  Variant: bit 0 FP32, bit 1 the
+// long-line kernels; the fused z pass adds the kernel type (bits 2-4) and 6
+// components (bit 5).
+namespace {
+
+template <typename R>
+void fft_job(const se_plan* p, int family, int slot, std::vector<se_job>* out)
+{
+    se_job j;
+    j.family = family;
+    se_fft_args a;
+    int Nline = 0;
+    if (family == SE_JOB_FFT_X_R2C || family == SE_JOB_FFT_X_C2R) {
+        const int nc = family == SE_JOB_FFT_X_R2C ? p->ncomp : 3;
+        a = make_fft_args(p, nc, slot);
+        const int Nh = a.N[0] / 2;
+        a.ncomp = nc;
+        a.lines = x_lines<R>(Nh);
+        const int64_t rows = (int64_t)nc * a.Mg[2] * a.Mg[1];
+        j.blocks = (int)((rows + a.lines - 1) / a.lines);
+        j.lds = (size_t)(2 * Nh + 1 + a.lines * Nh) * sizeof(C<R>);
+        Nline = Nh;
+    } else if (family == SE_JOB_FFT_Y_FWD || family == SE_JOB_FFT_Y_INV) {
+        const int nc = family == SE_JOB_FFT_Y_FWD ? p->ncomp : 3;
+        a = make_fft_args(p, nc, slot);
+        a.cols = bundle_cols<R>(a.N[1], 1, a.cols_cap);
+        const int nbx = (a.Hx + a.cols - 1) / a.cols;
+        j.blocks = nbx * nc * a.Mg[2];
+        j.lds = (size_t)(a.N[1] + a.cols * a.N[1]) * sizeof(C<R>);
+        Nline = a.N[1];
+    } else {
+        const int NC = p->kernel == SE_STRESSLET ? 6 : 3;
+        a = make_fft_args(p, NC, slot);
+        a.cols = bundle_cols<R>(p->Nfft[2], NC, p->shape_fft_cols > 0 ? p->shape_fft_cols : 2);
+        const int nbx = (p->Hx + a.cols - 1) / a.cols;
+        j.blocks = nbx * p->Nfft[1];
+        j.lds = (size_t)(p->Nfft[2] + NC * a.cols * p->Nfft[2]) * sizeof(C<R>);
+        Nline = p->Nfft[2];
+        j.variant = (p->kernel << 2) | (NC == 6 ? 32 : 0);
+    }
+    j.variant |= (p->fp32 ? 1 : 0) | (Nline > kIpElems ? 2 : 0);
+    j.args.resize(sizeof(se_fft_args));
+    std::memcpy(j.args.data(), &a, sizeof(a));
+    out->push_back(std::move(j));
+}
+
+template <typename K>
+void multi_launch(K kern, const void* args, const int* boff, int n, int blocks, size_t lds, hipStream_t s)
+{
+    allow_lds(kern, lds);
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(SE_FFT_THREADS), lds, s, (const se_fft_args*)args, boff, n);
+}
+
+template <typename R, int E>
+void fft_multi_e(int family, int variant, const void* args, const int* boff, int n, int blocks, size_t lds,
+                 hipStream_t s)
+{
+    switch (family) {
+        case SE_JOB_FFT_X_R2C: multi_launch(k_fft_x_r2c_multi<R, E>, args, boff, n, blocks, lds, s); break;
+        case SE_JOB_FFT_X_C2R: multi_launch(k_fft_x_c2r_multi<R, E>, args, boff, n, blocks, lds, s); break;
+        case SE_JOB_FFT_Y_FWD: multi_launch(k_fft_y_multi<R, E, 1>, args, boff, n, blocks, lds, s); break;
+        case SE_JOB_FFT_Y_INV: multi_launch(k_fft_y_multi<R, E, -1>, args, boff, n, blocks, lds, s); break;
+        default: {
+            const int ker = (variant >> 2) & 7;
+            if (ker == SE_STOKESLET)
+                multi_launch(k_fft_z_scale_multi<R, SE_STOKESLET, 3, E>, args, boff, n, blocks, lds, s);
+            else if (ker == SE_ROTLET)
+                multi_launch(k_fft_z_scale_multi<R, SE_ROTLET, 3, E>, args, boff, n, blocks, lds, s);
+            else if (ker == SE_HARMONIC)
+                multi_launch(k_fft_z_scale_multi<R, SE_HARMONIC, 3, E>, args, boff, n, blocks, lds, s);
+            else
+                multi_launch(k_fft_z_scale_multi<R, SE_STRESSLET, 6, E>, args, boff, n, blocks, lds, s);
+        }
+    }
+}
+
+}  // namespace
+
+bool se_fft_jobs(const se_plan* p, int family, int slot, std::vector<se_job>* out)
+{
+    if (p->fp32) fft_job<float>(p, family, slot, out);
+    else fft_job<double>(p, family, slot, out);
+    return true;
+}
+
+void se_fft_launch_multi(int family, int variant, const void* args, const int* boff, int n, int blocks, size_t lds,
+                         hipStream_t s)
+{
+    if (n <= 0 || blocks <= 0) return;
+    const bool fp32 = variant & 1, lng = variant & 2;
+    if (fp32) {
+        if (lng) fft_multi_e<float, kIpElemsLong>(family, variant, args, boff, n, blocks, lds, s);
+        else fft_multi_e<float, kIpElems>(family, variant, args, boff, n, blocks, lds, s);
+    } else {
+        if (lng) fft_multi_e<double, kIpElemsLong>(family, variant, args, boff, n, blocks, lds, s);
+        else fft_multi_e<double, kIpElems>(family, variant, args, boff, n, blocks, lds, s);
+    }
+}
+
+void se_launch_fft_cls(const se_plan* p, int slot, int which, hipStream_t s)
+{
+    if (p->fp32) {
+        if (which == 0 && p->D == 1) cls_gather<float>(p, slot, s);
+        if (which == 1 && p->D == 2) cls_gather<float>(p, slot, s);
+        if (which == 2 && (p->D == 1 || p->D == 2)) cls_transform_dispatch<float>(p, slot, s);
+        if (which == 2 && p->D == 2) cls_scatter<float>(p, slot, s);
+        if (which == 3 && p->D == 1) cls_scatter<float>(p, slot, s);
+    } else {
+        if (which == 0 && p->D == 1) cls_gather<double>(p, slot, s);
+        if (which == 1 && p->D == 2) cls_gather<double>(p, slot, s);
+        if (which == 2 && (p->D == 1 || p->D == 2)) cls_transform_dispatch<double>(p, slot, s);
+        if (which == 2 && p->D == 2) cls_scatter<double>(p, slot, s);
+        if (which == 3 && p->D == 1) cls_scatter<double>(p, slot, s);
     }
 }

@@ -242,6 +242,47 @@ se_status se_d0_precompute(se_plan* p);
 bool se_fft_fits(const int* N, int ncomp, bool fp32);
 void se_launch_finalize(const se_plan* p, int slot, double* u, double* u_real, double* u_fourier, hipStream_t s);
 
+// Merged launches for batches of systems: one launch of a phase covers the
+// work items of many plans.  A job is one plan's share of a phase (one
+// right-hand-side slot, or the pair of them that a kernel takes together):
+// its kernel family and variant (the template arguments), the workgroups of
+// its first-item launch, its dynamic LDS and its argument record.
+enum {
+    SE_JOB_SPREAD = 0,
+    SE_JOB_GATHER = 1,
+    SE_JOB_FFT_X_R2C = 2,
+    SE_JOB_FFT_Y_FWD = 3,
+    SE_JOB_FFT_Z_SCALE = 4,
+    SE_JOB_FFT_Y_INV = 5,
+    SE_JOB_FFT_X_C2R = 6,
+    SE_JOB_REAL = 7,
+};
+constexpr int SE_JOB_MAX = 1024;  // jobs per merged launch
+struct se_job {
+    int family = 0;
+    int variant = 0;
+    int blocks = 0;
+    size_t lds = 0;
+    std::vector<char> args;
+};
+// Jobs of one plan for one phase (se_spread.hip, se_fft.hip, se_real.hip);
+// false when the plan's phase has no merged form (then it runs alone).
+bool se_tile_jobs(const se_plan* p, bool gather, int nslot, std::vector<se_job>* out);
+bool se_fft_jobs(const se_plan* p, int family, int slot, std::vector<se_job>* out);
+bool se_real_jobs(const se_plan* p, int nslot, std::vector<se_job>* out);
+// One merged launch over n jobs of one family and variant: args is the
+// device array of their records, boff[0..n] the prefix of their workgroups.
+void se_tile_launch_multi(int family, int variant, const void* args, const int* boff, int n, int blocks,
+                          hipStream_t s);
+void se_fft_launch_multi(int family, int variant, const void* args, const int* boff, int n, int blocks, size_t lds,
+                         hipStream_t s);
+void se_real_launch_multi(int variant, const void* args, int n, int blocks, hipStream_t s);
+int se_real_job_max();  // jobs per merged real-space launch
+// The upsampled-class steps of the adaptive FFT (D = 1, 2) of one slot, in
+// pipeline order: which = 0 after the x pass, 1 after the y pass, 2 after the
+// z pass (class transforms and scaling), 3 after the inverse y pass.
+void se_launch_fft_cls(const se_plan* p, int slot, int which, hipStream_t s);
+
 // One evaluation of all right-hand sides of a plan on stream s (kernel
 // launches only, so it can be recorded into a graph when timing is off).
 extern "C" __attribute__((visibility("hidden"))) se_status se_run_plan(se_plan* p, const double* strengths, double* u,

@@ -3,6 +3,7 @@
 // self term (eq. 3p-stokeslet-self-term), the non-periodic stresslet term
 // (eq. k0-stresslet-3p) and scatters back to the caller's order.
 #include <algorithm>
+#include <cstring>
 #include <cmath>
 
 #include "se_device.h"
@@ -829,6 +830,55 @@ struct se_fin_args {
     double* u_four;
 };
 
+// Merged real-space sums of many plans (batches of systems): job j is
+// (args, block geometry) of one plan and slot; its items follow the
+// device-side scan of its blocks, and all jobs' items are split over the
+// XCDs as in k_real2.
+struct se_real_job {
+    se_real_args a;
+    se_real2_geom bg;
+};
+constexpr int kRealJobMax = 256;
+
+template <int KER, int RB>
+__global__ void __launch_bounds__(256) k_real2_multi(const se_real_job* __restrict__ jv, int n)
+{
+    __shared__ se_real2_lds<KER, RB> lds[4];
+    __shared__ int pre[kRealJobMax + 1];
+    for (int j = threadIdx.x; j < n; j += blockDim.x) pre[j + 1] = jv[j].bg.work[jv[j].bg.nblk];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        pre[0] = 0;
+        for (int j = 0; j < n; j++) pre[j + 1] += pre[j];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nwg = gridDim.x, xcd = blockIdx.x % 8, idx = blockIdx.x / 8;
+    const int nx = nwg / 8 + (xcd < nwg % 8 ? 1 : 0);
+    const int64_t items = pre[n];
+    const int64_t lo = items * xcd / 8, hi = items * (xcd + 1) / 8;
+    for (int64_t w = lo + (int64_t)idx * 4 + wave; w < hi; w += (int64_t)nx * 4) {
+        int j = 0, top = n;  // the last job whose offset is <= w
+        while (top - j > 1) {
+            const int mid = (j + top) >> 1;
+            if (pre[mid] <= w) j = mid;
+            else top = mid;
+        }
+        const se_real_args& a = jv[j].a;
+        const se_real2_geom& bg = jv[j].bg;
+        const int64_t lw = w - pre[j];
+        int64_t blk = 0, tb = bg.nblk;
+        while (tb - blk > 1) {
+            const int64_t mid = (blk + tb) >> 1;
+            if (bg.work[mid] <= lw) blk = mid;
+            else tb = mid;
+        }
+        int coinc = 0;
+        real2_item<KER, RB>(a, bg, a.rtab, lds[wave], lane, blk, (int)(lw - bg.work[blk]), coinc);
+        if (__ballot(coinc) && lane == 0) atomicOr(a.flags, SE_FLAG_COINCIDENT);
+    }
+}
+
 __global__ void k_finalize(se_fin_args a)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1353,4 +1403,67 @@ void se_launch_finalize(const se_plan* p, int slot, double* u, double* u_real, d
     a.u_real = u_real;
     a.u_four = u_fourier;
     hipLaunchKernelGGL(k_finalize, dim3(grid1d(p->nt, 256)), dim3(256), 0, s, a);
+}
+
+// ---------------------------------------------------------------------------
+// Jobs of merged batches: the blocked real-space sum of one plan (one job per
+// pair of slots that a kernel takes together, else per slot), as
+// se_launch_real_space launches it.  Variant: kernel type | RB << 3.
+bool se_real_jobs(const se_plan* p, int nslot, std::vector<se_job>* out)
+{
+    se_real_job J;
+    se_real_args& a = J.a;
+    a.g = p->g;
+    a.xt = (const double4*)(p->tas ? p->d_pos4 : p->d_tpos4);
+    a.nt = p->nt;
+    a.xs = (const double4*)p->d_pos4;
+    a.ns = p->ns;
+    a.nrm = (const double4*)p->d_nrm4;
+    a.rtab = p->d_rtab;
+    a.start = p->d_src_start;
+    a.tstart = p->tas ? p->d_src_start : p->d_tgt_start;
+    a.xi = p->par.xi;
+    a.rc2 = p->par.rc * p->par.rc;
+    a.rscale = SE_RTAB_N / se_rtab_xmax(p->par);
+    real_cutoff_bins(p, a.Ra);
+    a.tas = p->tas ? 1 : 0;
+    a.flags = p->d_flags;
+    if (!real2_shape(p, a.Ra, &J.bg)) return false;
+    const int blocks = (int)std::max<int64_t>(1, (J.bg.nblk + (p->nt + 63) / 64 + 3) / 4);
+    auto add = [&](int slot, int rb) {
+        se_job j;
+        j.family = SE_JOB_REAL;
+        j.variant = p->kernel | (rb << 3);
+        j.blocks = blocks;
+        a.f = (const double4*)se_slot_str4(p, slot);
+        a.u = se_slot_uR(p, slot);
+        j.args.resize(sizeof(se_real_job));
+        std::memcpy(j.args.data(), &J, sizeof(J));
+        out->push_back(std::move(j));
+    };
+    if (nslot == 2 && p->kernel != SE_STRESSLET) add(0, 2);
+    else
+        for (int k = 0; k < nslot; k++) add(k, 1);
+    return true;
+}
+
+int se_real_job_max() { return kRealJobMax; }
+
+void se_real_launch_multi(int variant, const void* args, int n, int blocks, hipStream_t s)
+{
+    if (n <= 0 || n > kRealJobMax) return;
+    const unsigned nwg = (unsigned)std::max(8, blocks);
+    const se_real_job* jv = (const se_real_job*)args;
+    const int ker = variant & 7, rb = variant >> 3;
+    if (rb == 2) {
+        if (ker == SE_STOKESLET) hipLaunchKernelGGL((k_real2_multi<SE_STOKESLET, 2>), dim3(nwg), dim3(256), 0, s, jv, n);
+        else if (ker == SE_ROTLET) hipLaunchKernelGGL((k_real2_multi<SE_ROTLET, 2>), dim3(nwg), dim3(256), 0, s, jv, n);
+        else hipLaunchKernelGGL((k_real2_multi<SE_HARMONIC, 2>), dim3(nwg), dim3(256), 0, s, jv, n);
+    } else {
+        if (ker == SE_STOKESLET) hipLaunchKernelGGL((k_real2_multi<SE_STOKESLET, 1>), dim3(nwg), dim3(256), 0, s, jv, n);
+        else if (ker == SE_ROTLET) hipLaunchKernelGGL((k_real2_multi<SE_ROTLET, 1>), dim3(nwg), dim3(256), 0, s, jv, n);
+        else if (ker == SE_HARMONIC)
+            hipLaunchKernelGGL((k_real2_multi<SE_HARMONIC, 1>), dim3(nwg), dim3(256), 0, s, jv, n);
+        else hipLaunchKernelGGL((k_real2_multi<SE_STRESSLET, 1>), dim3(nwg), dim3(256), 0, s, jv, n);
+    }
 }

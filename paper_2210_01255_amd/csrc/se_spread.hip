@@ -17,6 +17,7 @@
 // free axes are clipped.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 
 #include "se_device.h"
 
@@ -892,6 +893,98 @@ __global__ void __launch_bounds__(SE_RT_THREADS, 3) k_gather_rt_extra(se_tile_ar
     }
 }
 
+// ---------------------------------------------------------------------------
+// Merged launches over the tiles of many plans (batches of systems): job j's
+// argument record is av[j]; its first items are the workgroups boff[j] ..
+// boff[j+1] - 1 (XCD-aware order over the whole launch), and its further
+// items follow the device-side counts of every job.
+#define SE_MULTI_MAX SE_JOB_MAX
+
+__device__ __forceinline__ int job_of(const int* __restrict__ boff, int n, int g)
+{
+    int lo = 0, hi = n;  // largest j with boff[j] <= g
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (boff[mid] <= g) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// pre[j] = further items of jobs 0 .. j-1 (each job's count is the total of
+// its exclusive scan over tiles)
+__device__ __forceinline__ void extra_prefix(const se_tile_args* __restrict__ av, int n, int* pre)
+{
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        const se_tile_args& a = av[j];
+        pre[j + 1] = a.xoff[a.ntile[0] * a.ntile[1] * a.ntile[2]];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        pre[0] = 0;
+        for (int j = 0; j < n; j++) pre[j + 1] += pre[j];
+    }
+    __syncthreads();
+}
+
+template <typename R, int NC, bool TG>
+__global__ void __launch_bounds__(SE_RT_THREADS, 4) k_spread_rt_multi(const se_tile_args* __restrict__ av,
+                                                                    const int* __restrict__ boff, int n)
+{
+    __shared__ se_rt_lds<R, NC, false> s;
+    const int g = se_xcd_block(blockIdx.x, gridDim.x);
+    const int j = job_of(boff, n, g);
+    spread_rt_tile<R, NC, TG, false>(av[j], s, g - boff[j], 0, av[j].chunk);
+}
+
+template <typename R, int NC, bool TG>
+__global__ void __launch_bounds__(SE_RT_THREADS, 4) k_spread_rt_extra_multi(const se_tile_args* __restrict__ av, int n)
+{
+    __shared__ se_rt_lds<R, NC, false> s;
+    __shared__ int pre[SE_MULTI_MAX + 1];
+    extra_prefix(av, n, pre);
+    const int items = pre[n];
+    for (int e = blockIdx.x; e < items; e += gridDim.x) {
+        const int j = job_of(pre, n, e);
+        const se_tile_args& a = av[j];
+        const int ntiles = a.ntile[0] * a.ntile[1] * a.ntile[2];
+        const int le = e - pre[j];
+        const int tile = rt_extra_tile(a.xoff, ntiles, le);
+        const int c0 = (1 + le - a.xoff[tile]) * a.chunk;
+        spread_rt_tile<R, NC, TG, true>(a, s, tile, c0, c0 + a.chunk);
+        __syncthreads();
+    }
+}
+
+template <typename R, int NCG, bool TG>
+__global__ void __launch_bounds__(SE_RT_THREADS, 3) k_gather_rt_multi(const se_tile_args* __restrict__ av,
+                                                                    const int* __restrict__ boff, int n)
+{
+    __shared__ se_rt_lds<R, NCG, true> s;
+    const int g = se_xcd_block(blockIdx.x, gridDim.x);
+    const int j = job_of(boff, n, g);
+    gather_rt_tile<R, NCG, TG>(av[j], s, g - boff[j], 0, av[j].chunk);
+}
+
+template <typename R, int NCG, bool TG>
+__global__ void __launch_bounds__(SE_RT_THREADS, 3) k_gather_rt_extra_multi(const se_tile_args* __restrict__ av, int n)
+{
+    __shared__ se_rt_lds<R, NCG, true> s;
+    __shared__ int pre[SE_MULTI_MAX + 1];
+    extra_prefix(av, n, pre);
+    const int items = pre[n];
+    for (int e = blockIdx.x; e < items; e += gridDim.x) {
+        const int j = job_of(pre, n, e);
+        const se_tile_args& a = av[j];
+        const int ntiles = a.ntile[0] * a.ntile[1] * a.ntile[2];
+        const int le = e - pre[j];
+        const int tile = rt_extra_tile(a.xoff, ntiles, le);
+        const int c0 = (1 + le - a.xoff[tile]) * a.chunk;
+        gather_rt_tile<R, NCG, TG>(a, s, tile, c0, c0 + a.chunk);
+        __syncthreads();
+    }
+}
+
 // Candidates of every tile (the same runs as rt_build_runs, one thread per
 // tile) -> the number of items beyond the tile's first.
 __global__ void k_rt_count(se_tile_args a, int ntiles, int* __restrict__ cnt)
@@ -1120,5 +1213,78 @@ void se_launch_gather(const se_plan* p, int slot0, int nslot, hipStream_t s)
     for (int k = 0; k < nslot; k++) {
         if (p->fp32) launch_gather<float, 16, 16, 8>(p, slot0 + k, s);
         else launch_gather<double, 16, 16, 8>(p, slot0 + k, s);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Jobs of merged batches.  Variant: bit 0 FP32 grid, bit 1 truncated
+// Gaussian, bits 2.. the components per pass (3 or 6), as the single-plan
+// launches above choose them.
+namespace {
+
+void add_tile_job(const se_plan* p, bool gather, int slot, int nc, std::vector<se_job>* out)
+{
+    se_job j;
+    j.family = gather ? SE_JOB_GATHER : SE_JOB_SPREAD;
+    const se_tile_args a = make_args(p, gather, slot);
+    j.variant = (p->fp32 ? 1 : 0) | (a.tg_c > 0.0 ? 2 : 0) | (nc << 2);
+    j.blocks = p->ntile[0] * p->ntile[1] * p->ntile[2];
+    j.args.resize(sizeof(se_tile_args));
+    std::memcpy(j.args.data(), &a, sizeof(a));
+    out->push_back(std::move(j));
+}
+
+template <typename R, int NC, bool TG>
+void tile_multi(bool gather, const void* args, const int* boff, int n, int blocks, hipStream_t s)
+{
+    const se_tile_args* av = (const se_tile_args*)args;
+    if (gather) {
+        hipLaunchKernelGGL((k_gather_rt_multi<R, NC, TG>), dim3(blocks), dim3(SE_RT_THREADS), 0, s, av, boff, n);
+        hipLaunchKernelGGL((k_gather_rt_extra_multi<R, NC, TG>), dim3(kRtExtraBlocks), dim3(SE_RT_THREADS), 0, s, av,
+                           n);
+    } else {
+        hipLaunchKernelGGL((k_spread_rt_multi<R, NC, TG>), dim3(blocks), dim3(SE_RT_THREADS), 0, s, av, boff, n);
+        hipLaunchKernelGGL((k_spread_rt_extra_multi<R, NC, TG>), dim3(kRtExtraBlocks), dim3(SE_RT_THREADS), 0, s, av,
+                           n);
+    }
+}
+
+template <typename R, bool TG>
+void tile_multi_nc(bool gather, int nc, const void* args, const int* boff, int n, int blocks, hipStream_t s)
+{
+    if (nc == 6) tile_multi<R, 6, TG>(gather, args, boff, n, blocks, s);
+    else tile_multi<R, 3, TG>(gather, args, boff, n, blocks, s);
+}
+
+}  // namespace
+
+bool se_tile_jobs(const se_plan* p, bool gather, int nslot, std::vector<se_job>* out)
+{
+    if (!se_rt_fits(p)) return false;
+    if (gather) {
+        if (nslot == 2) add_tile_job(p, true, 0, 6, out);
+        else
+            for (int k = 0; k < nslot; k++) add_tile_job(p, true, k, 3, out);
+    } else {
+        if (p->ncomp == 3 && nslot == 2) add_tile_job(p, false, 0, 6, out);
+        else
+            for (int k = 0; k < nslot; k++) add_tile_job(p, false, k, p->ncomp, out);
+    }
+    return true;
+}
+
+void se_tile_launch_multi(int family, int variant, const void* args, const int* boff, int n, int blocks,
+                          hipStream_t s)
+{
+    if (n <= 0 || n > SE_MULTI_MAX) return;
+    const bool gather = family == SE_JOB_GATHER;
+    const bool fp32 = variant & 1, tg = variant & 2;
+    const int nc = variant >> 2;
+    if (fp32) {
+        if (tg) tile_multi_nc<float, true>(gather, nc, args, boff, n, blocks, s);
+        else tile_multi_nc<float, false>(gather, nc, args, boff, n, blocks, s);
+    } else {
+        if (tg) tile_multi_nc<double, true>(gather, nc, args, boff, n, blocks, s);
+        else tile_multi_nc<double, false>(gather, nc, args, boff, n, blocks, s);
     }
 }

@@ -206,6 +206,78 @@ def test_batch_of_64_uneven_systems_with_tuning(env):
     b.close()
 
 
+def test_batch_merged_launches_cover_every_variant(env):
+    """A batch whose merged phase launches mix every job variant: the four
+    kernels, D = 3, 2, 1, 0, one to three right-hand sides (pairs and a
+    single slot in one chunk), FP32 grids, the truncated-Gaussian window and
+    separate targets.  Each member, eager and on graph replays, against a
+    single plan of the same problem (1e-12 relative for FP64 grids; FP32
+    grids within 1e-5, where the order of the atomic additions shows)."""
+    se, oracle, torch = env
+    specs = [
+        dict(kernel="stokeslet", D=3, n=900, rhs=3),
+        dict(kernel="rotlet", D=2, n=700, rhs=2),
+        dict(kernel="stresslet", D=1, n=600, rhs=2),
+        dict(kernel="stokeslet", D=0, n=500, rhs=1, fp32=True),
+        dict(kernel="harmonic", D=3, n=400, rhs=2, window="tg"),
+        dict(kernel="stokeslet", D=3, n=800, rhs=2, nt=300),
+        dict(kernel="rotlet", D=1, n=650, rhs=3, fp32=True, window="tg"),
+        dict(kernel="stresslet", D=0, n=450, rhs=1),
+        dict(kernel="stokeslet", D=2, n=1200, rhs=2, fp32=True),
+    ]
+    probs, xs, nus, tgs, fs = [], [], [], [], []
+    g = W.rng(77)
+    for i, c in enumerate(specs):
+        box = tuple(W.aspect_box(g))
+        s = W.system(7700 + i, c["n"], box=box, kernel=c["kernel"], zero_mean=(c["D"] == 3), n_rhs=c["rhs"])
+        key = "q" if c["kernel"] == "stresslet" else "f"
+        fr = s[key] if c["rhs"] > 1 else s[key][0]
+        nt = c.get("nt", 0)
+        tol = 1e-5 if c.get("fp32") else 1e-8
+        probs.append(dict(kernel=c["kernel"], periodicity=c["D"], box=box, tol=tol, n_src=c["n"], n_tgt=nt,
+                          targets_are_sources=nt == 0, n_rhs=c["rhs"], source_q=float(np.sum(fr ** 2)) / c["rhs"],
+                          precision=se.PREC_FP32 if c.get("fp32") else se.PREC_FP64,
+                          window=c.get("window", "pkb")))
+        xs.append(torch.tensor(s["x"], device="cuda:0"))
+        nus.append(torch.tensor(s["nu"], device="cuda:0") if "nu" in s else None)
+        tgs.append(torch.tensor(g.random((nt, 3)) * np.asarray(box)[None, :], device="cuda:0") if nt else None)
+        fs.append(torch.tensor(fr, device="cuda:0"))
+    b = se.Batch(probs)
+    print("merged batch:", [(c["kernel"], c["D"], c["rhs"], p.params["M"], p.params["P"])
+                            for c, p in zip(specs, b.plans)], flush=True)
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(st):
+        b.set_geometry(xs, nus, tgs, stream=st)
+        outs = b.execute(fs, stream=st)  # eager pass (records the graph)
+    st.synchronize()
+    eager = [o.cpu().numpy() for o in outs]
+    singles = []
+    for c, pr, x, nu, tg, f in zip(specs, probs, xs, nus, tgs, fs):
+        single = se.Plan(**pr)
+        single.set_geometry(x, nu, tg)
+        u = single.execute(f)
+        single.sync()
+        singles.append(u.cpu().numpy())
+    for rep in range(3):
+        for o in outs:
+            o.fill_(float("nan"))
+        st.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(st):
+            b.execute(fs, outs, stream=st)  # graph replay
+        st.synchronize()
+        for i, (c, o, u0, us) in enumerate(zip(specs, outs, eager, singles)):
+            u = o.cpu().numpy()
+            bar = 1e-5 if c.get("fp32") else 1e-12
+            assert np.all(np.isfinite(u)), (rep, i)
+            e1, e2 = oracle.rms_rel_error(u, u0), oracle.rms_rel_error(u, us)
+            if rep == 0:
+                print("member %d %s D=%d rhs=%d: replay vs eager %.2e, vs single plan %.2e" %
+                      (i, c["kernel"], c["D"], c["rhs"], e1, e2), flush=True)
+            assert e1 <= bar and e2 <= bar, (rep, i, e1, e2)
+    b.close()
+
+
 def test_batch_rejects_bad_arguments(env):
     se, _, torch = env
     with pytest.raises(se.SEError):
