@@ -281,8 +281,8 @@ def bie_solve(plan, alpha, weights, g, q0=None, restart=30, max_iter=300, tol=1e
 
 
 def ewald_reference(kernel, periodicity, box, x, strengths, normals=None, targets=None, xi=0.0, stream=None):
-    """Direct Ewald sum on the GPU (se_ewald_reference): D = 3 or 0, device
-    FP64 tensors [n][3]; returns u [n_tgt][3] on the same device."""
+    """Direct Ewald sum on the GPU (se_ewald_reference): D = 3, 2, 1 or 0,
+    device FP64 tensors [n][3]; returns u [n_tgt][3] on the same device."""
     import torch
     kid = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
     Plan._check(x, (x.shape[0], 3), "src")
