@@ -457,16 +457,32 @@ __device__ __forceinline__ double green_scalar(const se_fft_args& a, int ix, int
 }
 
 // u = Khat(k) F with the scalar factor c = Ahat gammahat W already formed.
+// nyq: bit d set when component d of k sits on a Nyquist index (+-pi/h alias
+// to one grid mode).  The stokeslet's k k^T then takes the mean over both
+// aliases, which keeps k_d k_l only when both or neither of d, l are Nyquist
+// components; this makes the scaled spectrum Hermitian, so that the real
+// inverse transform equals the real part of the complex one (a half
+// spectrum that is not Hermitian on its kx = 0 and Nyquist planes would
+// otherwise leak through the real x transform with the 1/what^2 gain).
 template <typename R, int KER>
-__device__ __forceinline__ void apply_green(double cd, const double* k, double k2, const C<R>* F, C<R>* U)
+__device__ __forceinline__ void apply_green(double cd, const double* k, double k2, const C<R>* F, C<R>* U,
+                                            int nyq = 0)
 {
     const R kr[3] = {(R)k[0], (R)k[1], (R)k[2]};
     const R kk = (R)k2;
     const R c = (R)cd;
     if constexpr (KER == SE_STOKESLET) {
-        C<R> kf = {kr[0] * F[0].x + kr[1] * F[1].x + kr[2] * F[2].x, kr[0] * F[0].y + kr[1] * F[1].y + kr[2] * F[2].y};
+        C<R> kf = {(R)0, (R)0}, kn = {(R)0, (R)0};  // k.F over the regular / the Nyquist components
 #pragma unroll
-        for (int j = 0; j < 3; j++) U[j] = {c * (kr[j] * kf.x - kk * F[j].x), c * (kr[j] * kf.y - kk * F[j].y)};
+        for (int l = 0; l < 3; l++) {
+            if ((nyq >> l) & 1) kn = {kn.x + kr[l] * F[l].x, kn.y + kr[l] * F[l].y};
+            else kf = {kf.x + kr[l] * F[l].x, kf.y + kr[l] * F[l].y};
+        }
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            const C<R> p = ((nyq >> j) & 1) ? kn : kf;
+            U[j] = {c * (kr[j] * p.x - kk * F[j].x), c * (kr[j] * p.y - kk * F[j].y)};
+        }
     } else if constexpr (KER == SE_HARMONIC) {
 #pragma unroll
         for (int j = 0; j < 3; j++) U[j] = {c * F[j].x, c * F[j].y};
@@ -501,7 +517,8 @@ __device__ __forceinline__ void scale_point(const se_fft_args& a, int ix, int iy
     const int kb[3] = {ix, iy < a.N[1] / 2 ? iy : iy - a.N[1], iz < a.N[2] / 2 ? iz : iz - a.N[2]};
     const double k[3] = {a.kfac[0] * kb[0], a.kfac[1] * kb[1], a.kfac[2] * kb[2]};
     const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
-    const bool nyq = (2 * ix == a.N[0]) || (2 * iy == a.N[1]) || (2 * iz == a.N[2]);
+    const int nyqb = (2 * ix == a.N[0] ? 1 : 0) | (2 * iy == a.N[1] ? 2 : 0) | (2 * iz == a.N[2] ? 4 : 0);
+    const bool nyq = nyqb != 0;
     // D = 2: columns |kx|, |ky| <= k*; D = 1: planes kx <= k* (upsampled classes)
     const bool moved = (a.D == 2 && ix <= a.skip_kx && kb[1] <= a.skip_ky && -kb[1] <= a.skip_ky) ||
                        (a.D == 1 && ix <= a.skip_kx);
@@ -515,7 +532,7 @@ __device__ __forceinline__ void scale_point(const se_fft_args& a, int ix, int iy
     const double iw = a.invw2[a.iw_off[0] + ix] * a.invw2[a.iw_off[1] + iy] * a.invw2[a.iw_off[2] + iz];
     const double W = a.scale * iw;
     const double screen = se_harmonic_based(KER) ? gE : gE * (1.0 + e);
-    apply_green<R, KER>(G * screen * W, k, k2, F, U);
+    apply_green<R, KER>(G * screen * W, k, k2, F, U, nyqb);
 }
 
 // Plain complex transform along z (no scaling) for `ncomp` components.
