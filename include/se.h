@@ -170,7 +170,12 @@ const char* se_status_string(se_status s);
 se_status se_params_select(const se_problem* prob, se_params* out);
 
 /* Select parameters (Sec. 4.6, or `manual` when selector = SE_SELECT_MANUAL,
- * where `manual` must then be non-null) and allocate all device workspace on
+ * where `manual` must then be non-null: xi, rc, an even P <= 32 and, for
+ * D = 3, the grid M[0..2]; for D = 2, 1 the periodic grid sizes M[0..D-1],
+ * and for D = 0 the target spacing h[0], from which the free-direction
+ * parameters (extended grid, truncation radius, upsampling; Sec. 4.6 steps
+ * 6-7) are completed as the procedure completes its own; beta, nu_deg and
+ * alpha <= 0 take the procedure's values) and allocate all device workspace on
  * prob->device.  On success *out owns the plan.  Errors: SE_ERR_ARG,
  * SE_ERR_UNSUPPORTED, SE_ERR_TOL_UNREACHABLE, SE_ERR_NOMEM, SE_ERR_HIP. */
 se_status se_plan_create(const se_problem* prob, const se_params* manual, se_plan** out);

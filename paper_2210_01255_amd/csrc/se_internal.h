@@ -172,8 +172,16 @@ inline double* se_slot_uR(const se_plan* p, int slot) { return p->d_uR + (size_t
 // ---- planner (se_params.cpp)
 se_status se_select_params(const se_problem* p, const se_params* manual, se_params* out,
                            std::string* msg);
+// M_periodic: the periodic axes' grid sizes to use instead of rounding
+// box / h_t (manual parameters).
 se_status se_complete_params(const se_problem* p, double xi, double rc, double h_t, int P, se_params* out,
-                             std::string* msg);
+                             std::string* msg, const int* M_periodic = nullptr);
+// Steps 1-5 of the analytic procedure (before grid rounding and completion).
+struct se_targets {
+    double xi, rc, h_t;
+    int P;
+};
+void se_analytic_targets(const se_problem* p, se_targets* out);
 // Learned selection (MLP proposal, then completion and the estimate check);
 // falls back to se_select_params and says so in msg.
 se_status se_select_learned(const se_problem* p, se_params* out, std::string* msg);

@@ -336,28 +336,59 @@ se_status se_select_params(const se_problem* p, const se_params* manual, se_para
         if (par.window != SE_WINDOW_TG) par.alpha = 0.0;
         if (par.nu_deg <= 0) par.nu_deg = std::min(par.P / 2 + 2, 10);
         if (par.nu_deg > SE_MAX_NU) par.nu_deg = SE_MAX_NU;
+        if (D < 3) {
+            // free directions: steps 5-7 from (xi, rc, P) and the periodic
+            // grid M[0..D-1] (D = 0: the target spacing h[0]), as the
+            // analytic procedure completes its own
+            bool have_m = D > 0;
+            for (int i = 0; i < D; i++) have_m = have_m && par.M[i] >= 2 && !(par.M[i] & 1);
+            if (!have_m && !(par.h[0] > 0)) {
+                *msg = "manual parameters for D < 3: need even periodic grid sizes M[0..D-1] (D = 0: h[0] > 0)";
+                return SE_ERR_ARG;
+            }
+            const double ht = have_m ? p->box[0] / par.M[0] : par.h[0];
+            int mp[3] = {par.M[0], par.M[1], par.M[2]};
+            const int nu = par.nu_deg;
+            const double alpha = par.alpha, beta = par.beta;
+            se_status st = se_complete_params(p, par.xi, par.rc, ht, par.P, out, msg, have_m ? mp : nullptr);
+            if (st != SE_OK) return st;
+            out->nu_deg = nu;
+            out->beta = beta;
+            out->alpha = alpha;
+            return SE_OK;
+        }
         for (int i = 0; i < 3; i++) {
             if (par.M[i] < 2 || (par.M[i] & 1)) {
                 *msg = "manual parameters: grid sizes must be even and >= 2";
                 return SE_ERR_ARG;
             }
-            if (i < D) {
-                par.h[i] = p->box[i] / par.M[i];
-                par.L_ext[i] = p->box[i];
-                par.dL[i] = 0;
-                par.n_fft[i] = par.M[i];
-            }
-        }
-        if (D < 3) {
-            *msg = "manual parameters are only supported for D = 3 by this library";
-            return SE_ERR_UNSUPPORTED;
+            par.h[i] = p->box[i] / par.M[i];
+            par.L_ext[i] = p->box[i];
+            par.dL[i] = 0;
+            par.n_fft[i] = par.M[i];
         }
         par.U = pot_rms(kernel, b, Q, par.xi);
         par.tau_abs = p->tol_kind == SE_TOL_ABS ? p->tol / safety : p->tol * par.U / safety;
         *out = par;
         return SE_OK;
     }
+    se_targets t;
+    se_analytic_targets(p, &t);
+    return se_complete_params(p, t.xi, t.rc, t.h_t, t.P, out, msg);
+}
 
+// Steps 1-5 of Sec. 4.6: xi (given, or from N_rc with the real-space
+// estimate, Sec. 5.2), rc, the target grid spacing and the window support
+// after the pollution rule.
+void se_analytic_targets(const se_problem* p, se_targets* out)
+{
+    const int D = p->periodicity, kernel = p->kernel;
+    Box b;
+    b.V = p->box[0] * p->box[1] * p->box[2];
+    b.Lc = std::cbrt(b.V);
+    const double N = (double)p->n_src;
+    const double Q = p->source_q > 0 ? p->source_q : 3.0 * N;
+    const double safety = p->safety > 0 ? p->safety : 1.0;
     // ---- xi and tau_abs
     double xi = p->xi;
     auto tau_of = [&](double x) {
@@ -397,7 +428,10 @@ se_status se_select_params(const se_problem* p, const se_params* manual, se_para
     // step 5: even window support
     int P = 2 * (int)std::ceil(P_t / 2.0 - 1e-12);
     if (P < 4) P = 4;
-    return se_complete_params(p, xi, rc, h_t, P, out, msg);
+    out->xi = xi;
+    out->rc = rc;
+    out->h_t = h_t;
+    out->P = P;
 }
 
 // Steps 5-7 of Sec. 4.6 from (xi, rc, target spacing h_t, window support P):
@@ -407,7 +441,7 @@ se_status se_select_params(const se_problem* p, const se_params* manual, se_para
 // (upsampling-factor-sstar), (estimate-kbarstar), and the three truncation
 // estimates at the final parameters.
 se_status se_complete_params(const se_problem* p, double xi, double rc, double h_t, int P, se_params* out,
-                             std::string* msg)
+                             std::string* msg, const int* M_periodic)
 {
     const int D = p->periodicity, kernel = p->kernel;
     Box b;
@@ -444,7 +478,7 @@ se_status se_complete_params(const se_problem* p, double xi, double rc, double h
     // periodic axes
     double h_common = h_t;
     for (int i = 0; i < D; i++) {
-        int M = round_grid(p->box[i] / h_t, fM, i == 0);
+        int M = M_periodic ? M_periodic[i] : round_grid(p->box[i] / h_t, fM, i == 0);
         par.M[i] = M;
         par.h[i] = p->box[i] / M;
         par.L_ext[i] = p->box[i];
