@@ -212,12 +212,12 @@ se_status se_select_learned(const se_problem* p, se_params* out, std::string* ms
     const double rc = std::exp((double)y[3]) / xi;
     if (!(xi > 0) || !(h > 0) || !(rc > 0)) return fallback("proposal out of range");
     // The analytic steps of Sec. 4.6 (fine pollution rule) at the proposed xi
-    // form a one-parameter family in the safety factor; the member nearest to
-    // the proposed (rc, h, P), each difference weighted by the typical error
-    // of that output on held-out problems, is the parameter set.  So the
-    // real-space, Fourier and window parts always come from one consistent
-    // accuracy target, and a proposal that is itself such a member maps back
-    // to it.
+    // form a family in the safety factor, each member with its window support
+    // P or P - 2 (the training runs measure both); the member nearest to the
+    // proposed (rc, h, P), each difference weighted by the typical error of
+    // that output on held-out problems, is the parameter set.  So the
+    // real-space and Fourier parts always come from one consistent accuracy
+    // target, and a proposal that is itself such a member maps back to it.
     se_problem q = *p;
     q.xi = xi;
     q.pollution = SE_POLLUTION_FINE;
@@ -226,16 +226,21 @@ se_status se_select_learned(const se_problem* p, se_params* out, std::string* ms
     double best = 1e300;
     for (int k = 0; k <= 64; k++) {
         q.safety = std::pow(50.0, k / 64.0);  // 1 .. 50: every member aims at or below tol
-        se_params a;
-        if (se_select_params(&q, nullptr, &a, &m2) != SE_OK) continue;
-        double ha = 1e300;
-        for (int d = 0; d < 3; d++)
-            if (d < p->periodicity || p->periodicity == 0) ha = std::min(ha, a.h[d]);
-        const double dr = std::log(a.rc / rc) / 0.04, dh = std::log(ha / h) / 0.12, dp = (a.P - Pp) / 0.7;
-        const double dist = dr * dr + dh * dh + dp * dp;
-        if (dist < best) {
-            best = dist;
-            par = a;
+        se_targets t;
+        se_analytic_targets(&q, &t);
+        for (int dP = 0; dP <= 2; dP += 2) {
+            if (t.P - dP < 4) continue;
+            se_params a;
+            if (se_complete_params(&q, t.xi, t.rc, t.h_t, t.P - dP, &a, &m2) != SE_OK) continue;
+            double ha = 1e300;
+            for (int d = 0; d < 3; d++)
+                if (d < p->periodicity || p->periodicity == 0) ha = std::min(ha, a.h[d]);
+            const double dr = std::log(a.rc / rc) / 0.04, dh = std::log(ha / h) / 0.12, dp = (a.P - Pp) / 0.7;
+            const double dist = dr * dr + dh * dh + dp * dp;
+            if (dist < best) {
+                best = dist;
+                par = a;
+            }
         }
     }
     if (!(best < 1e300)) return fallback("analytic completion failed");

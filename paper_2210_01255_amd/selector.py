@@ -5,12 +5,15 @@ problem's features (log10 N, box elongation, periodicity, kernel, log10 of
 the rms-relative tolerance) to (xi, h, P, rc).  Its training records are
 runs of the method itself:
 
-* ``generate``: for each sampled problem, a reference computed with the same
-  method at a much tighter tolerance, then candidate parameter sets from the
-  analytic procedure of Sec. 4.6 with varied n_rc (Sec. 5.2), safety factor
-  and error-pollution rule; each run records its parameters, the measured time
-  of se_set_geometry + se_execute and the measured rms-relative error against
-  the reference.
+* ``generate``: for each sampled problem, a reference (the direct Ewald sum,
+  se_ewald_reference, for D = 3 and 0; the same method at a much tighter
+  tolerance for D = 2 and 1, where the direct sum's Fourier integrals are too
+  slow at large N), then candidate parameter sets from the analytic procedure
+  of Sec. 4.6 with varied n_rc (Sec. 5.2) and safety factor, each also run
+  with its window support lowered by 2 (the free-direction parameters then
+  completed as the procedure does); each run records its parameters, the
+  measured time of se_set_geometry + se_execute and the measured rms-relative
+  error against the reference.
 * ``labels``: per problem, the fastest run whose measured error is within
   ``margin`` times the tolerance.
 * ``train``: se_selector_train on the labels, then se_selector_save.
@@ -30,18 +33,18 @@ import time
 
 import numpy as np
 
-from . import (KERNELS, MLP_IN, MLP_OUT, POLLUTION_FINE, POLLUTION_PAPER, PREC_FP64, SE_OK, SEError, Plan, lib,
-               make_problem, se_train_cfg)
+from . import (KERNELS, MLP_IN, MLP_OUT, POLLUTION_FINE, POLLUTION_PAPER, PREC_FP64, SE_OK, SELECT_MANUAL, SEError,
+               Plan, ewald_reference, lib, make_problem, se_params, se_train_cfg)
 
 # Expected sources within rc for the uniform system, Table 3 (rows: stokeslet
 # and rotlet, stresslet; columns D = 0..3): the candidates scale these.
 NRC_TABLE = {0: (2500.0, 950.0, 450.0, 400.0), 1: (2500.0, 950.0, 450.0, 400.0), 2: (6000.0, 1600.0, 800.0, 800.0)}
-NRC_SCALE = (0.1, 0.15, 0.25, 0.4, 0.65)
+NRC_SCALE = (0.06, 0.1, 0.15, 0.25, 0.4)
 SAFETY_PERIODIC = (0.3, 1.0, 3.0, 10.0)
 SAFETY_FREE = (0.3, 1.2, 5.0, 20.0)
 
 FIELDS = ("problem", "N", "D", "kernel", "aspect", "box0", "box1", "box2", "tol", "n_rc", "safety", "pollution",
-          "xi", "rc", "h", "P", "M0", "M1", "M2", "create_ms", "geom_ms", "exec_ms", "err", "ok")
+          "xi", "rc", "h", "P", "M0", "M1", "M2", "create_ms", "geom_ms", "exec_ms", "err", "ok", "dP", "ref")
 
 
 def features(N, D, kernel, box, tol) -> np.ndarray:
@@ -95,6 +98,20 @@ def candidates(D, kernel):
     return [(s * base, c, POLLUTION_FINE) for s in NRC_SCALE for c in safeties]
 
 
+def lowered_window(par, D):
+    """Manual parameters of an analytic set with the window support lowered
+    by 2: the same xi, rc and periodic grid (D = 0: the spacing), from which
+    the free directions are completed."""
+    m = se_params()
+    m.struct_size = ctypes.sizeof(se_params)
+    m.xi, m.rc, m.P = par["xi"], par["rc"], par["P"] - 2
+    for i in range(D):
+        m.M[i] = par["M"][i]
+    if D == 0:
+        m.h[0] = min(par["h"]) * (1.0 + 1e-12)
+    return m
+
+
 def _timed(plan, x, str_, nu, out, reps):
     import torch
     e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
@@ -129,13 +146,19 @@ def generate(seed: int, first: int, count: int, out_path: str, max_seconds: floa
         sd = torch.tensor(s, device=dev)
         nud = torch.tensor(nu, device=dev) if nu is not None else None
         common = dict(kernel=kernel, periodicity=D, box=tuple(box), n_src=N, source_q=Q, precision=PREC_FP64)
-        tol_ref = max(min(tol * 1e-3, 1e-11), 1e-13)
         try:
-            ref_plan = Plan(tol=tol_ref, safety=10.0, **common)
-            ref_plan.set_geometry(xd, nud)
-            ref = ref_plan.execute(sd)
-            ref_plan.sync()
-            del ref_plan
+            if D in (3, 0):
+                ref = ewald_reference(kernel, D, tuple(box), xd, sd, nud)
+                torch.cuda.synchronize()
+                ref_kind = 1
+            else:
+                tol_ref = max(min(tol * 1e-3, 1e-11), 1e-13)
+                ref_plan = Plan(tol=tol_ref, safety=10.0, **common)
+                ref_plan.set_geometry(xd, nud)
+                ref = ref_plan.execute(sd)
+                ref_plan.sync()
+                del ref_plan
+                ref_kind = 0
         except SEError as e:
             print("problem %d N=%d D=%d k=%d tol=%.1e: no reference (%s)" % (pid, N, D, kernel, tol, e), flush=True)
             continue
@@ -143,12 +166,12 @@ def generate(seed: int, first: int, count: int, out_path: str, max_seconds: floa
         out = torch.empty_like(ref)
         aspect = float(box.max() / box.min())
         best = None
-        for (nrc, safety, pol) in candidates(D, kernel):
-            row = dict(problem=pid, N=N, D=D, kernel=kernel, aspect=aspect, box0=box[0], box1=box[1], box2=box[2],
-                       tol=tol, n_rc=nrc, safety=safety, pollution=pol)
+
+        def run(row, make):
+            nonlocal best
             try:
                 t0 = time.time()
-                plan = Plan(tol=tol, n_rc=nrc, safety=safety, pollution=pol, **common)
+                plan = make()
                 cms = 1e3 * (time.time() - t0)
                 gms, ems = _timed(plan, xd, sd, nud, out, reps)
                 plan.sync()
@@ -160,9 +183,22 @@ def generate(seed: int, first: int, count: int, out_path: str, max_seconds: floa
                 del plan
                 if err <= tol and (best is None or gms + ems < best):
                     best = gms + ems
+                return par
             except SEError:
                 row.update(xi=0, rc=0, h=0, P=0, M0=0, M1=0, M2=0, create_ms=0, geom_ms=0, exec_ms=0, err=np.inf, ok=0)
+                return None
+
+        for (nrc, safety, pol) in candidates(D, kernel):
+            base = dict(problem=pid, N=N, D=D, kernel=kernel, aspect=aspect, box0=box[0], box1=box[1], box2=box[2],
+                        tol=tol, n_rc=nrc, safety=safety, pollution=pol, ref=ref_kind)
+            row = dict(base, dP=0)
+            par = run(row, lambda: Plan(tol=tol, n_rc=nrc, safety=safety, pollution=pol, **common))
             rows.append(row)
+            if par is not None and par["P"] - 2 >= 4:
+                row = dict(base, dP=2)
+                m = lowered_window(par, D)
+                rows.append(row)
+                run(row, lambda: Plan(m, tol=tol, safety=safety, selector=SELECT_MANUAL, **common))
         print("problem %d N=%d D=%d k=%d aspect=%.2f tol=%.1e: best %s ms (%.0f s)" %
               (pid, N, D, kernel, aspect, tol, "%.3f" % best if best else "-", time.time() - t_start), flush=True)
         torch.cuda.empty_cache()
@@ -231,7 +267,7 @@ def load_runs(paths):
             for k in FIELDS}
 
 
-def labels(runs, margin=0.5):
+def labels(runs, margin=0.3):
     """(X, Y, problem ids): per problem the fastest run with err <= margin*tol."""
     X, Y, ids = [], [], []
     prob = runs["problem"].astype(np.int64)
@@ -307,7 +343,7 @@ def main(argv=None):
     t.add_argument("--epochs", type=int, default=150)
     t.add_argument("--batch", type=int, default=64)
     t.add_argument("--lr", type=float, default=1e-3)
-    t.add_argument("--margin", type=float, default=0.5)
+    t.add_argument("--margin", type=float, default=0.3)
     t.add_argument("--seed", type=int, default=1)
     ev = sub.add_parser("evaluate")
     ev.add_argument("--weights", default=None)
