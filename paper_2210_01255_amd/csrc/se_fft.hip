@@ -184,6 +184,10 @@ __device__ __forceinline__ int udiv(int a, se_udiv u, int* rem)
 // longest line a plan admits; the smaller budget keeps the common kernels at
 // fewer registers.
 constexpr int kIpElems = 1536;
+// elements between the column sets of the fused z pass beyond their size:
+// with sets a multiple of 8 elements (128 bytes) apart, the lanes that read
+// the same element of two components hit the same LDS banks
+constexpr int kZSetPad = 4;
 constexpr int kIpElemsLong = SE_FFT_LDS_ELEMS;
 static_assert(kIpElems <= kIpElemsLong, "element budgets");
 
@@ -591,7 +595,8 @@ __device__ __forceinline__ void fft_z_scale_body(const se_fft_args& a, int blk)
     load_rad(s_rad, a.rad_z, a.nrad_z);
     const int Nz = a.N[2];
     const int Cc = a.cols;
-    const int cs = Nz * Cc;  // LDS column-set size
+    const int cs = Nz * Cc;          // LDS column-set size
+    const int csp = cs + kZSetPad;   // column-set stride (bank offset between components)
     C<R>* tw = (C<R>*)smem_d;
     C<R>* sets = tw + Nz;
     load_tw(tw, a.tw + 2 * a.tw_z, Nz);
@@ -611,14 +616,14 @@ __device__ __forceinline__ void fft_z_scale_body(const se_fft_args& a, int blk)
         int kx = kx0 + col;
         const bool ok = kx < a.Hx && z < Mz;
         const C<R> t = spec[c * cstride + (ok ? z * zstride + (int64_t)y * a.Hp + kx : (int64_t)y * a.Hp + kx0)];
-        sets[i] = {ok ? t.x : (R)0, ok ? t.y : (R)0};
+        sets[c * csp + rem] = {ok ? t.x : (R)0, ok ? t.y : (R)0};
     }
     __syncthreads();
     // as many components per transform call as fit kIpElems (lines of one
     // component are Cc adjacent columns; components are cs apart)
     const int gc = max(1, min(NC, E / cs));
     for (int c0 = 0; c0 < NC; c0 += gc)
-        fft_ip<R, 1, E>(sets, c0 * cs, Nz, min(gc, NC - c0) * Cc, Cc, cs, 1, Cc, true, tw, s_rad, a.nrad_z);
+        fft_ip<R, 1, E>(sets, c0 * csp, Nz, min(gc, NC - c0) * Cc, Cc, csp, 1, Cc, true, tw, s_rad, a.nrad_z);
     for (int i = threadIdx.x; i < cs; i += blockDim.x) {
         int col;
         const int z = udiv(i, dC, &col);
@@ -626,20 +631,20 @@ __device__ __forceinline__ void fft_z_scale_body(const se_fft_args& a, int blk)
         if (kx >= a.Hx) continue;
         C<R> F[NC], U[3];
 #pragma unroll
-        for (int c = 0; c < NC; c++) F[c] = sets[c * cs + i];
+        for (int c = 0; c < NC; c++) F[c] = sets[c * csp + i];
         scale_point<R, KER, NC>(a, kx, y, z, F, U);
 #pragma unroll
-        for (int j = 0; j < 3; j++) sets[j * cs + i] = U[j];
+        for (int j = 0; j < 3; j++) sets[j * csp + i] = U[j];
     }
     __syncthreads();
     for (int c0 = 0; c0 < 3; c0 += gc)
-        fft_ip<R, -1, E>(sets, c0 * cs, Nz, min(gc, 3 - c0) * Cc, Cc, cs, 1, Cc, true, tw, s_rad, a.nrad_z);
+        fft_ip<R, -1, E>(sets, c0 * csp, Nz, min(gc, 3 - c0) * Cc, Cc, csp, 1, Cc, true, tw, s_rad, a.nrad_z);
     for (int i = threadIdx.x; i < 3 * cs; i += blockDim.x) {
         int rem, col;
         const int c = udiv(i, dcs, &rem);
         const int z = udiv(rem, dC, &col);
         int kx = kx0 + col;
-        if (kx < a.Hx && z < Mz) spec[c * cstride + z * zstride + (int64_t)y * a.Hp + kx] = sets[i];
+        if (kx < a.Hx && z < Mz) spec[c * cstride + z * zstride + (int64_t)y * a.Hp + kx] = sets[c * csp + rem];
     }
 }
 
@@ -791,9 +796,9 @@ int x_lines(int Nh)
 // columns per bundle for a pass holding `sets` column sets of length N plus
 // the twiddles within the LDS budget, one set per in-place transform call
 template <typename R>
-int bundle_cols(int N, int sets, int cap = 16)
+int bundle_cols(int N, int sets, int cap = 16, int pad = 0)
 {
-    const int budget = (int)(kFftLds / sizeof(C<R>)) - N;
+    const int budget = (int)(kFftLds / sizeof(C<R>)) - N - sets * pad;
     int c = std::max(1, std::min({cap > 0 ? cap : 16, budget / (sets * N), ip_budget(N) / N}));
     while (c & (c - 1)) c &= c - 1;  // power of two
     return c;
@@ -877,9 +882,9 @@ void launch_z(const se_plan* p, int slot, hipStream_t s)
     // two columns by default: the components then share transform calls
     // (kIpElems / (2 N) of them per call), which shortens the chain of
     // barrier-separated stages per column more than wider rows would help
-    a.cols = bundle_cols<R>(p->Nfft[2], NC, p->shape_fft_cols > 0 ? p->shape_fft_cols : 2);
+    a.cols = bundle_cols<R>(p->Nfft[2], NC, p->shape_fft_cols > 0 ? p->shape_fft_cols : 2, kZSetPad);
     int nbx = (p->Hx + a.cols - 1) / a.cols;
-    size_t lds = (size_t)(p->Nfft[2] + NC * a.cols * p->Nfft[2]) * sizeof(C<R>);
+    size_t lds = (size_t)(p->Nfft[2] + NC * (a.cols * p->Nfft[2] + kZSetPad)) * sizeof(C<R>);
     auto kern = p->Nfft[2] > kIpElems ? k_fft_z_scale<R, KER, NC, kIpElemsLong> : k_fft_z_scale<R, KER, NC, kIpElems>;
     allow_lds(kern, lds);
     hipLaunchKernelGGL(kern, dim3((unsigned)(nbx * p->Nfft[1])), dim3(SE_FFT_THREADS), lds, s, a);
@@ -1335,7 +1340,8 @@ bool se_fft_fits(const int* N, int ncomp, bool fp32)
     const size_t lim = 160 * 1024 - kFftLdsStatic;
     const size_t nh = (size_t)N[0] / 2;
     return (2 * nh + 1 + 2 * nh) * cb <= lim && (size_t)N[1] * 3 * cb <= lim && (size_t)N[2] * 3 * cb <= lim &&
-           (size_t)N[2] * (1 + (ncomp + 1)) * cb <= lim;
+           (size_t)N[2] * (1 + (ncomp + 1)) * cb <= lim &&
+           ((size_t)N[2] * (1 + ncomp) + (size_t)kZSetPad * ncomp) * cb <= lim;
 }
 
 // FP64 3-D transform of ncomp components on an arbitrary grid:
@@ -1392,10 +1398,10 @@ void fft_job(const se_plan* p, int family, int slot, std::vector<se_job>* out)
     } else {
         const int NC = p->kernel == SE_STRESSLET ? 6 : 3;
         a = make_fft_args(p, NC, slot);
-        a.cols = bundle_cols<R>(p->Nfft[2], NC, p->shape_fft_cols > 0 ? p->shape_fft_cols : 2);
+        a.cols = bundle_cols<R>(p->Nfft[2], NC, p->shape_fft_cols > 0 ? p->shape_fft_cols : 2, kZSetPad);
         const int nbx = (p->Hx + a.cols - 1) / a.cols;
         j.blocks = nbx * p->Nfft[1];
-        j.lds = (size_t)(p->Nfft[2] + NC * a.cols * p->Nfft[2]) * sizeof(C<R>);
+        j.lds = (size_t)(p->Nfft[2] + NC * (a.cols * p->Nfft[2] + kZSetPad)) * sizeof(C<R>);
         Nline = p->Nfft[2];
         j.variant = (p->kernel << 2) | (NC == 6 ? 32 : 0);
     }
