@@ -41,11 +41,17 @@ def _csvs(d: str, suffix: str):
     return sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
 
 
+def _grid(r) -> int:
+    if "Grid_Size" in r:
+        return int(r["Grid_Size"])
+    return int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+
+
 def trace(kt_dir: str) -> str:
     calls = collections.defaultdict(list)
     for f in _csvs(kt_dir, "kernel_trace.csv"):
         for r in csv.DictReader(open(f)):
-            key = (_name(r["Kernel_Name"]), int(r["Grid_Size"]))
+            key = (_name(r["Kernel_Name"]), _grid(r))
             calls[key].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3)
     total = sum(sum(v) for v in calls.values())
     rows = sorted(calls.items(), key=lambda kv: -sum(kv[1]))
@@ -61,31 +67,34 @@ def trace(kt_dir: str) -> str:
 def _counters(dirs):
     vals = collections.defaultdict(lambda: collections.defaultdict(list))
     meta = {}
+    last = {}  # counter -> (dispatch id, kernel, value) of the last elementwise kernel
     for d in dirs:
         for f in _csvs(d, "counter_collection.csv"):
             for r in csv.DictReader(open(f)):
-                key = (_name(r["Kernel_Name"]), int(r["Grid_Size"]))
-                vals[key][r["Counter_Name"]].append(float(r["Counter_Value"]))
+                key = (_name(r["Kernel_Name"]), _grid(r))
+                c, v = r["Counter_Name"], float(r["Counter_Value"])
+                vals[key][c].append(v)
                 meta[key] = (r.get("VGPR_Count", ""), r.get("Scratch_Size", ""), r.get("LDS_Block_Size", ""))
+                did = int(r.get("Dispatch_Id", 0) or 0)
+                if "elementwise" in key[0] and (c not in last or did >= last[c][0]):
+                    last[c] = (did, key, v)
+    vals["__last_elementwise__"] = {c: [t[2]] for c, t in last.items()}
     return vals, meta
 
 
-def _phase_keys(vals):
+def _phase_keys(vals, phases=PHASES):
     keys = {}
-    for phase, pat in PHASES:
-        cand = [k for k in vals if re.search(pat, k[0])]
+    for phase, pat in phases:
+        cand = [k for k in vals if isinstance(k, tuple) and re.search(pat, k[0])]
         if cand:
             keys[phase] = max(cand, key=lambda k: k[1])
     return keys
 
 
 def _calib(vals, counter):
-    """The calibration copy: the last elementwise kernel in the run."""
-    cand = [k for k in vals if "elementwise" in k[0] and counter in vals[k]]
-    if not cand:
-        return None
-    k = max(cand, key=lambda k: k[1])
-    return sum(vals[k][counter]) / len(vals[k][counter])
+    """The calibration copy: the last elementwise kernel dispatched in the run."""
+    v = vals.get("__last_elementwise__", {}).get(counter)
+    return v[0] if v else None
 
 
 def traffic(fetch_dir, write_dir, calib_mib, out_json):
@@ -101,8 +110,10 @@ def traffic(fetch_dir, write_dir, calib_mib, out_json):
              "(factor %.4f) and WRITE %.1f KiB (factor %.4f)." % (kib, ff * kib, ff, wf * kib, wf), "",
              "| phase | kernel | FETCH KiB/launch | WRITE KiB/launch | scaled HBM MB/launch |",
              "|---|---|---:|---:|---:|"]
-    fk, wk = _phase_keys(fv), _phase_keys(wv)
-    for phase, _ in PHASES:
+    # phases whose time is one kernel's (the FFT x/y phases are two kernels each)
+    one = tuple(p for p in PHASES if p[0] in ("gather", "spread", "real_space", "fft_z_scale"))
+    fk, wk = _phase_keys(fv, one), _phase_keys(wv, one)
+    for phase, _ in one:
         if phase not in fk or phase not in wk:
             continue
         kf, kw = fk[phase], wk[phase]

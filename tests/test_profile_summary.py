@@ -19,9 +19,10 @@ def _write(path, rows):
 def test_trace_and_traffic(tmp_path):
     kt = tmp_path / "kt" / "host" / "x_kernel_trace.csv"
     rows = [dict(Kernel_Name="void (anonymous namespace)::k_gather_rt<double, 6, false>(se_tile_args)",
-                 Grid_Size=6094080, Start_Timestamp=1000, End_Timestamp=1000 + 4000000 + 1000 * i) for i in range(3)]
+                 Grid_Size_X=6094080, Grid_Size_Y=1, Grid_Size_Z=1, Start_Timestamp=1000,
+                 End_Timestamp=1000 + 4000000 + 1000 * i) for i in range(3)]
     rows += [dict(Kernel_Name="void (anonymous namespace)::k_spread_rt<double, 6, false>(se_tile_args)",
-                  Grid_Size=6094080, Start_Timestamp=0, End_Timestamp=3000000)]
+                  Grid_Size_X=6094080, Grid_Size_Y=1, Grid_Size_Z=1, Start_Timestamp=0, End_Timestamp=3000000)]
     _write(str(kt), rows)
     table = PS.trace(str(tmp_path / "kt"))
     lines = table.splitlines()
@@ -30,14 +31,14 @@ def test_trace_and_traffic(tmp_path):
 
     def pmc(d, counter, vals):
         r = []
-        for name, grid, v in vals:
-            r.append(dict(Kernel_Name=name, Grid_Size=grid, Counter_Name=counter, Counter_Value=v, VGPR_Count=8,
-                          Scratch_Size=0, LDS_Block_Size=0))
+        for i, (name, grid, v) in enumerate(vals):
+            r.append(dict(Dispatch_Id=i + 1, Kernel_Name=name, Grid_Size=grid, Counter_Name=counter, Counter_Value=v,
+                          VGPR_Count=8, Scratch_Size=0, LDS_Block_Size=0))
         _write(str(tmp_path / d / "h" / "c_counter_collection.csv"), r)
     ew = "void at::native::elementwise_kernel<128, 4>(int)"
     g6 = "void (anonymous namespace)::k_gather_rt<double, 6, false>(se_tile_args)"
-    pmc("f", "FETCH_SIZE", [(g6, 6094080, 1000.0), (g6, 6094080, 1200.0), (ew, 1 << 20, 512.0)])
-    pmc("w", "WRITE_SIZE", [(g6, 6094080, 300.0), (ew, 1 << 20, 1024.0)])
+    pmc("f", "FETCH_SIZE", [(ew, 1 << 22, 7.0), (g6, 6094080, 1000.0), (g6, 6094080, 1200.0), (ew, 1 << 20, 512.0)])
+    pmc("w", "WRITE_SIZE", [(ew, 1 << 22, 9.0), (g6, 6094080, 300.0), (ew, 1 << 20, 1024.0)])
     out = tmp_path / "t.json"
     md = PS.traffic(str(tmp_path / "f"), str(tmp_path / "w"), 1.0, str(out))
     rec = json.load(open(out))["phases"]["gather"]
