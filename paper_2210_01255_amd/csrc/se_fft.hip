@@ -715,10 +715,20 @@ __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_z_scale_multi(const se_f
 constexpr size_t kFftLds = 80 * 1024;
 constexpr size_t kFftLdsStatic = 256;  // static LDS of the line kernels (radix table), rounded up
 
+// Radix sequence of a line length.  The first Stockham stage writes each
+// butterfly's outputs RAD elements apart, so consecutive work items store
+// 16 * RAD bytes apart: for RAD = 8 (4) that is every (every other) 128-byte
+// bank row, an 8-way (4-way) LDS bank conflict, while an odd RAD spreads
+// them over all banks.  Later stages write runs of Ns >= RAD consecutive
+// elements.  So the largest odd radix, if any, goes first.
 void set_radices(int n, uint64_t* dst, int* cnt)
 {
     std::vector<int> r;
     se_smooth_factors(n, &r);
+    int odd = -1;
+    for (int i = 0; i < (int)r.size(); i++)
+        if ((r[i] & 1) && (odd < 0 || r[i] > r[odd])) odd = i;
+    if (odd > 0) std::rotate(r.begin(), r.begin() + odd, r.begin() + odd + 1);
     *cnt = (int)std::min<size_t>(r.size(), 16);
     uint64_t code = 0;
     for (int i = 0; i < *cnt; i++) code |= (uint64_t)r[i] << (4 * i);
