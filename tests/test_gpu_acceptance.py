@@ -9,7 +9,7 @@ total minus its real-space part; for D = 0 the direct sum minus the real-space
 part).  The paper reports the error within one order of magnitude of tau
 until it flattens out at the rounding floor, sometimes below tau/10 for
 D = 3.  At L = 1, Q = 1, xi = 10 the oracle's Fourier-space part has rms 1.8
-(stokeslet) and 24 (stresslet), the paper's "around 2" and "20".
+(stokeslet) and 24 (stresslet), the magnitudes the paper reports for this case.
 Checked here: no case above 10 tau (or the floor), and the geometric mean
 of err/tau within [1e-2, 10] over each sweep.
 """
