@@ -64,8 +64,8 @@ def targets_of(xi, h, P, rc, box) -> np.ndarray:
     return np.array([math.log(xi * Lc), math.log(Lc / h), float(P), math.log(xi * rc)], dtype=np.float32)
 
 
-def sample_problem(g: np.random.Generator):
-    N = int(round(math.exp(g.uniform(math.log(1e3), math.log(1e6)))))
+def sample_problem(g: np.random.Generator, n_min: float = 1e3):
+    N = int(round(math.exp(g.uniform(math.log(n_min), math.log(1e6)))))
     D = int(g.integers(0, 4))
     kernel = int(g.integers(0, 3))
     box = np.ones(3)
@@ -127,7 +127,8 @@ def _timed(plan, x, str_, nu, out, reps):
     return e0.elapsed_time(e1), e1.elapsed_time(e2) / reps
 
 
-def generate(seed: int, first: int, count: int, out_path: str, max_seconds: float = 1e9, reps: int = 3, ids=None):
+def generate(seed: int, first: int, count: int, out_path: str, max_seconds: float = 1e9, reps: int = 3, ids=None,
+             n_min: float = 1e3):
     """Runs for problems first .. first+count-1 of the seeded problem stream
     (or for the listed problem ids)."""
     import torch
@@ -140,7 +141,7 @@ def generate(seed: int, first: int, count: int, out_path: str, max_seconds: floa
             print("time budget reached before problem %d" % pid, flush=True)
             break
         g = np.random.default_rng([seed, pid])
-        N, D, kernel, box, tol = sample_problem(g)
+        N, D, kernel, box, tol = sample_problem(g, n_min)
         x, s, nu, Q = _system(g, N, D, kernel, box)
         xd = torch.tensor(x, device=dev)
         sd = torch.tensor(s, device=dev)
@@ -337,6 +338,7 @@ def main(argv=None):
     g.add_argument("--max-seconds", type=float, default=1e9)
     g.add_argument("--ids", default=None, help="comma-separated problem ids, or @file holding them")
     g.add_argument("--out", required=True)
+    g.add_argument("--n-min", type=float, default=1e3, help="smallest N of the log-uniform draw (largest 1e6)")
     t = sub.add_parser("train")
     t.add_argument("--runs", nargs="+", required=True)
     t.add_argument("--out", required=True)
@@ -354,7 +356,7 @@ def main(argv=None):
         if a.ids:
             txt = open(a.ids[1:]).read() if a.ids.startswith("@") else a.ids
             ids = [int(v) for v in txt.replace("\n", ",").split(",") if v.strip()]
-        generate(a.seed, a.first, a.count, a.out, a.max_seconds, ids=ids)
+        generate(a.seed, a.first, a.count, a.out, a.max_seconds, ids=ids, n_min=a.n_min)
         return 0
     if a.cmd == "evaluate":
         if a.weights:
