@@ -204,27 +204,45 @@ se_status check_hip(se_plan* p, hipError_t e, const char* what)
 
 }  // namespace
 
-// Twiddle tables e^{-2 pi i k/N} (complex FP64, interleaved) for the R2C axis
-// (length N0/2, and the split factors for k = 0..N0/2) and the y and z axes.
+// Twiddle tables (complex FP64, interleaved) for the R2C axis (the stages of
+// length N0/2, and the split factors e^{-2 pi i k/N0} for k = 0..N0/2) and
+// the y and z axes.  A line length n has n entries: for each Stockham stage
+// (in the order of se_fft_radix_order) with Ns = the product of the earlier
+// radices, the factors e^{-2 pi i r jn/(Ns RAD)}, r = 1..RAD-1 major and
+// jn = 0..Ns-1 minor, from entry Ns - 1 (the stages fill n - 1 entries).
 void se_fft_twiddles(const int* N, std::vector<double>* tw, int* off)
 {
     tw->clear();
     const int Nh = N[0] / 2;
-    auto push_table = [&](int n, int count) {
-        for (int k = 0; k < count; k++) {
-            long double ang = -2.0L * 3.141592653589793238462643383279502884L * k / n;
-            tw->push_back((double)std::cos(ang));
-            tw->push_back((double)std::sin(ang));
+    const long double twopi = 2.0L * 3.141592653589793238462643383279502884L;
+    auto push = [&](long double ang) {
+        tw->push_back((double)std::cos(ang));
+        tw->push_back((double)std::sin(ang));
+    };
+    // exactly n entries per table (the offsets below assume it); a length
+    // that is not 7-smooth (a class axis no line transform runs along) gets
+    // unit entries
+    auto push_stages = [&](int n) {
+        const size_t end = tw->size() + 2 * (size_t)n;
+        std::vector<int> rad;
+        if (se_fft_radix_order(n, &rad)) {
+            int Ns = 1;
+            for (int R : rad) {
+                for (int r = 1; r < R; r++)
+                    for (int jn = 0; jn < Ns; jn++) push(-twopi * r * jn / ((long double)Ns * R));
+                Ns *= R;
+            }
         }
+        while (tw->size() < end) push(0.0L);
     };
     off[0] = 0;
-    push_table(Nh, Nh);
+    push_stages(Nh);
     off[1] = Nh;
-    push_table(N[0], Nh + 1);
+    for (int k = 0; k <= Nh; k++) push(-twopi * k / N[0]);
     off[2] = 2 * Nh + 1;
-    push_table(N[1], N[1]);
+    push_stages(N[1]);
     off[3] = 2 * Nh + 1 + N[1];
-    push_table(N[2], N[2]);
+    push_stages(N[2]);
 }
 
 extern "C" {

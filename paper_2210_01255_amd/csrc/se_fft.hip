@@ -213,7 +213,6 @@ __device__ __forceinline__ void stage_ip(C<R>* buf, int off, int N, int nl, int 
     constexpr int K = ip_per_thread<RAD, E>();
     const int nb = N / RAD;
     const int total = nb * nl;
-    const int tstride = N / (Ns * RAD);
     const se_udiv dnb = make_udiv(nb), dns = make_udiv(Ns);
     const int istep = nb * es;  // between the inputs of one butterfly
     const int ostep = Ns * es;  // between its outputs
@@ -232,12 +231,15 @@ __device__ __forceinline__ void stage_ip(C<R>* buf, int off, int N, int nl, int 
             const int base = off + __mul24(lq, gs) + __mul24(lr, ls);
             int jn;
             const int jq = udiv(j, dns, &jn);
-            const int ts = __mul24(jn, tstride);
+            // this stage's twiddles w^{r jn} (w = e^{-2 pi i/(Ns RAD)}), r-major
+            // from element Ns - 1 of the table: consecutive work items read
+            // consecutive elements
+            const int tb = Ns - 1 + jn;
             const int i0 = base + __mul24(j, es);
             v[k][0] = buf[i0];
 #pragma unroll
             for (int r = 1; r < RAD; r++) {
-                C<R> w = tw[r * ts];
+                C<R> w = tw[tb + (r - 1) * Ns];
                 if (DIR < 0) w.y = -w.y;
                 v[k][r] = cmul(buf[i0 + r * istep], w);
             }
@@ -715,20 +717,11 @@ __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_z_scale_multi(const se_f
 constexpr size_t kFftLds = 80 * 1024;
 constexpr size_t kFftLdsStatic = 256;  // static LDS of the line kernels (radix table), rounded up
 
-// Radix sequence of a line length.  The first Stockham stage writes each
-// butterfly's outputs RAD elements apart, so consecutive work items store
-// 16 * RAD bytes apart: for RAD = 8 (4) that is every (every other) 128-byte
-// bank row, an 8-way (4-way) LDS bank conflict, while an odd RAD spreads
-// them over all banks.  Later stages write runs of Ns >= RAD consecutive
-// elements.  So the largest odd radix, if any, goes first.
+// Radix sequence of a line length, in the stage order of se_fft_radix_order.
 void set_radices(int n, uint64_t* dst, int* cnt)
 {
     std::vector<int> r;
-    se_smooth_factors(n, &r);
-    int odd = -1;
-    for (int i = 0; i < (int)r.size(); i++)
-        if ((r[i] & 1) && (odd < 0 || r[i] > r[odd])) odd = i;
-    if (odd > 0) std::rotate(r.begin(), r.begin() + odd, r.begin() + odd + 1);
+    se_fft_radix_order(n, &r);
     *cnt = (int)std::min<size_t>(r.size(), 16);
     uint64_t code = 0;
     for (int i = 0; i < *cnt; i++) code |= (uint64_t)r[i] << (4 * i);

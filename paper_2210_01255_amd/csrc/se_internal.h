@@ -186,6 +186,7 @@ void se_analytic_targets(const se_problem* p, se_targets* out);
 // falls back to se_select_params and says so in msg.
 se_status se_select_learned(const se_problem* p, se_params* out, std::string* msg);
 bool se_smooth_factors(int n, std::vector<int>* radices);
+bool se_fft_radix_order(int n, std::vector<int>* radices);
 void se_pkb_coefficients(int P, int nu, double beta, std::vector<double>* coef);
 // Truncated-Gaussian shape 0.91 (pi/2) P, the untruncated Gaussian's Fourier
 // transform, and the transform of the plan's window (KB or UG) at k for

@@ -130,6 +130,24 @@ bool se_smooth_factors(int n, std::vector<int>* radices)
     return m == 1;
 }
 
+// Stage order of the line FFTs: the smooth factors with the largest odd
+// radix, if any, moved to the front.  The first Stockham stage writes each
+// butterfly's outputs RAD elements apart, so consecutive work items store
+// 16 * RAD bytes apart: for RAD = 8 (4) that is every (every other) 128-byte
+// bank row, an 8-way (4-way) LDS bank conflict, while an odd RAD spreads
+// them over all banks; later stages write runs of Ns >= RAD consecutive
+// elements.  The kernels' radix codes and the twiddle tables both follow it.
+bool se_fft_radix_order(int n, std::vector<int>* radices)
+{
+    if (!se_smooth_factors(n, radices)) return false;
+    std::vector<int>& r = *radices;
+    int odd = -1;
+    for (int i = 0; i < (int)r.size(); i++)
+        if ((r[i] & 1) && (odd < 0 || r[i] > r[odd])) odd = i;
+    if (odd > 0) std::rotate(r.begin(), r.begin() + odd, r.begin() + odd + 1);
+    return true;
+}
+
 namespace {
 
 bool is_smooth(int n)
