@@ -178,6 +178,28 @@ __device__ __forceinline__ int udiv(int a, se_udiv u, int* rem)
     return q;
 }
 
+// Element loop i = threadIdx.x, + SE_FFT_THREADS, ... < n between HBM and
+// LDS: each work item reads kCopyBatch elements (ld) before it writes any of
+// them (st), so that many loads per work item are in flight at once; a plain
+// strided loop waits for each element before it issues the next load.  The
+// reads are unconditional (indices past the end read element n - 1 again),
+// which keeps them in one branch-free block; ld must accept any i < n.
+constexpr int kCopyBatch = 8;
+template <typename Ld, typename St>
+__device__ __forceinline__ void copy_batched(int n, Ld ld, St st)
+{
+    for (int i0 = threadIdx.x; i0 < n; i0 += kCopyBatch * SE_FFT_THREADS) {
+        decltype(ld(0)) t[kCopyBatch];
+#pragma unroll
+        for (int u = 0; u < kCopyBatch; u++) t[u] = ld(min(i0 + u * SE_FFT_THREADS, n - 1));
+#pragma unroll
+        for (int u = 0; u < kCopyBatch; u++) {
+            const int i = i0 + u * SE_FFT_THREADS;
+            if (i < n) st(i, t[u]);
+        }
+    }
+}
+
 // Elements (lines x length) of one in-place transform call: each work item
 // then holds at most ceil(E / RAD / SE_FFT_THREADS) butterflies.  Passes whose
 // lines are longer than kIpElems use kernels built for kIpElemsLong, the
@@ -319,14 +341,18 @@ __device__ __forceinline__ void fft_x_r2c_body(const se_fft_args& a, int blk)
     // (c z, y) of the block's first row; rows l < nl follow it
     const int64_t cz0 = row0 / a.Mg[1];
     const int y0 = (int)(row0 - cz0 * a.Mg[1]);
-    for (int i = threadIdx.x; i < nl * Nh; i += blockDim.x) {
-        int k;
-        const int l = udiv(i, dNh, &k);
-        const R* row = grid + (row0 + l) * M0;
-        R re = (2 * k < M0) ? row[2 * k] : (R)0;
-        R im = (2 * k + 1 < M0) ? row[2 * k + 1] : (R)0;
-        b0[l * Nh + k] = {re, im};
-    }
+    // element i = l Nh + k of the block
+    copy_batched(
+        nl * Nh,
+        [&](int i) {
+            int k;
+            const int l = udiv(i, dNh, &k);
+            const R* row = grid + (row0 + l) * M0;
+            const R re = (2 * k < M0) ? row[2 * k] : (R)0;
+            const R im = (2 * k + 1 < M0) ? row[2 * k + 1] : (R)0;
+            return C<R>{re, im};
+        },
+        [&](int i, C<R> v) { b0[i] = v; });
     __syncthreads();
     fft_ip<R, 1, E>(b0, 0, Nh, nl, nl, 0, Nh, 1, false, tw, s_rad, a.nrad_xh);
     const C<R>* Z = b0;
@@ -369,33 +395,44 @@ __device__ __forceinline__ void fft_x_c2r_body(const se_fft_args& a, int blk)
     const se_udiv dNh = make_udiv(Nh), dMy = make_udiv(a.Mg[1]);
     const int64_t cz0 = row0 / a.Mg[1];
     const int y0 = (int)(row0 - cz0 * a.Mg[1]);
-    for (int i = threadIdx.x; i < nl * Nh; i += blockDim.x) {
-        int k, y;
-        const int l = udiv(i, dNh, &k);
-        const int64_t cz = cz0 + udiv(y0 + l, dMy, &y);
-        const C<R>* X = spec + (cz * a.N[1] + y) * a.Hp;
-        C<R> xk = X[k];
-        C<R> xn = X[Nh - k];
-        xn.y = -xn.y;  // conj(X_{N-k})
-        C<R> Ap = {xk.x + xn.x, xk.y + xn.y};
-        C<R> d = {xk.x - xn.x, xk.y - xn.y};
-        C<R> w = twp[k];
-        w.y = -w.y;  // e^{+2 pi i k/N0}
-        C<R> Bp = cmul(d, w);
-        b0[l * Nh + k] = {Ap.x - Bp.y, Ap.y + Bp.x};  // A' + i B'
-    }
+    // element i = l Nh + k of the block; ld returns X_k and conj(X_{N-k})
+    struct pair_t {
+        C<R> xk, xn;
+    };
+    copy_batched(
+        nl * Nh,
+        [&](int i) {
+            int k, y;
+            const int l = udiv(i, dNh, &k);
+            const int64_t cz = cz0 + udiv(y0 + l, dMy, &y);
+            const C<R>* X = spec + (cz * a.N[1] + y) * a.Hp;
+            return pair_t{X[k], X[Nh - k]};
+        },
+        [&](int i, pair_t p) {
+            int k;
+            (void)udiv(i, dNh, &k);
+            C<R> xk = p.xk, xn = p.xn;
+            xn.y = -xn.y;  // conj(X_{N-k})
+            C<R> Ap = {xk.x + xn.x, xk.y + xn.y};
+            C<R> d = {xk.x - xn.x, xk.y - xn.y};
+            C<R> w = twp[k];
+            w.y = -w.y;  // e^{+2 pi i k/N0}
+            C<R> Bp = cmul(d, w);
+            b0[i] = {Ap.x - Bp.y, Ap.y + Bp.x};  // A' + i B'
+        });
     __syncthreads();
     fft_ip<R, -1, E>(b0, 0, Nh, nl, nl, 0, Nh, 1, false, tw, s_rad, a.nrad_xh);
     const C<R>* Z = b0;
     const int M0 = a.Mg[0];
-    for (int i = threadIdx.x; i < nl * Nh; i += blockDim.x) {
-        int k;
-        const int l = udiv(i, dNh, &k);
-        R* row = grid + (row0 + l) * M0;
-        C<R> z = Z[l * Nh + k];
-        if (2 * k < M0) row[2 * k] = z.x;
-        if (2 * k + 1 < M0) row[2 * k + 1] = z.y;
-    }
+    copy_batched(
+        nl * Nh, [&](int i) { return Z[i]; },
+        [&](int i, C<R> z) {
+            int k;
+            const int l = udiv(i, dNh, &k);
+            R* row = grid + (row0 + l) * M0;
+            if (2 * k < M0) row[2 * k] = z.x;
+            if (2 * k + 1 < M0) row[2 * k + 1] = z.y;
+        });
 }
 
 // ------------------------------------------------------------ y: complex
@@ -421,24 +458,30 @@ __device__ __forceinline__ void fft_y_body(const se_fft_args& a, int bid)
     const int n_in = dir > 0 ? a.Mg[1] : Ny;
     const int n_out = dir > 0 ? Ny : a.Mg[1];
     const se_udiv dC = make_udiv(Cc);
-    for (int i = threadIdx.x; i < Ny * Cc; i += blockDim.x) {
-        int col;
-        const int y = udiv(i, dC, &col);
-        int kx = kx0 + col;
-        // unconditional load from a valid address (kx0 < Hx), then select
-        const bool ok = kx < a.Hx && y < n_in;
-        const C<R> t = base[ok ? (int64_t)y * a.Hp + kx : (int64_t)kx0];
-        b0[y * Cc + col] = {ok ? t.x : (R)0, ok ? t.y : (R)0};
-    }
+    // element i = y Cc + col
+    copy_batched(
+        Ny * Cc,
+        [&](int i) {
+            int col;
+            const int y = udiv(i, dC, &col);
+            const int kx = kx0 + col;
+            // unconditional load from a valid address (kx0 < Hx), then select
+            const bool ok = kx < a.Hx && y < n_in;
+            const C<R> t = base[ok ? (int64_t)y * a.Hp + kx : (int64_t)kx0];
+            return C<R>{ok ? t.x : (R)0, ok ? t.y : (R)0};
+        },
+        [&](int i, C<R> v) { b0[i] = v; });
     __syncthreads();
     fft_ip<R, DIR, E>(b0, 0, Ny, Cc, Cc, 0, 1, Cc, true, tw, s_rad, a.nrad_y);
     const C<R>* Z = b0;
-    for (int i = threadIdx.x; i < n_out * Cc; i += blockDim.x) {
-        int col;
-        const int y = udiv(i, dC, &col);
-        int kx = kx0 + col;
-        if (kx < a.Hx) base[(int64_t)y * a.Hp + kx] = Z[y * Cc + col];
-    }
+    copy_batched(
+        n_out * Cc, [&](int i) { return Z[i]; },
+        [&](int i, C<R> v) {
+            int col;
+            const int y = udiv(i, dC, &col);
+            const int kx = kx0 + col;
+            if (kx < a.Hx) base[(int64_t)y * a.Hp + kx] = v;
+        });
 }
 
 // ------------------------------------------------------------------ scaling
@@ -567,23 +610,28 @@ __global__ void __launch_bounds__(SE_FFT_THREADS) k_fft_z(se_fft_args a)
     const int n_in = dir > 0 ? Mz : Nz;
     const int n_out = dir > 0 ? Nz : Mz;
     const se_udiv dC = make_udiv(Cc);
-    for (int i = threadIdx.x; i < Nz * Cc; i += blockDim.x) {
-        int col;
-        const int z = udiv(i, dC, &col);
-        int kx = kx0 + col;
-        const bool ok = kx < a.Hx && z < n_in && z < Mz;
-        const C<R> t = spec[ok ? z * zstride + (int64_t)y * a.Hp + kx : (int64_t)y * a.Hp + kx0];
-        b0[i] = {ok ? t.x : (R)0, ok ? t.y : (R)0};
-    }
+    copy_batched(
+        Nz * Cc,
+        [&](int i) {
+            int col;
+            const int z = udiv(i, dC, &col);
+            const int kx = kx0 + col;
+            const bool ok = kx < a.Hx && z < n_in && z < Mz;
+            const C<R> t = spec[ok ? z * zstride + (int64_t)y * a.Hp + kx : (int64_t)y * a.Hp + kx0];
+            return C<R>{ok ? t.x : (R)0, ok ? t.y : (R)0};
+        },
+        [&](int i, C<R> v) { b0[i] = v; });
     __syncthreads();
     fft_ip<R, DIR, E>(b0, 0, Nz, Cc, Cc, 0, 1, Cc, true, tw, s_rad, a.nrad_z);
     const C<R>* Z = b0;
-    for (int i = threadIdx.x; i < n_out * Cc; i += blockDim.x) {
-        int col;
-        const int z = udiv(i, dC, &col);
-        int kx = kx0 + col;
-        if (kx < a.Hx && z < Mz) spec[z * zstride + (int64_t)y * a.Hp + kx] = Z[i];
-    }
+    copy_batched(
+        n_out * Cc, [&](int i) { return Z[i]; },
+        [&](int i, C<R> v) {
+            int col;
+            const int z = udiv(i, dC, &col);
+            const int kx = kx0 + col;
+            if (kx < a.Hx && z < Mz) spec[z * zstride + (int64_t)y * a.Hp + kx] = v;
+        });
 }
 
 // Transform along z, scaling and inverse transform for one bundle of `cols`
@@ -611,15 +659,22 @@ __device__ __forceinline__ void fft_z_scale_body(const se_fft_args& a, int blk)
     const int64_t zstride = (int64_t)a.N[1] * a.Hp;
     C<R>* spec = (C<R>*)a.spec;
     const se_udiv dcs = make_udiv(cs), dC = make_udiv(Cc);
-    for (int i = threadIdx.x; i < NC * cs; i += blockDim.x) {
-        int rem, col;
-        const int c = udiv(i, dcs, &rem);
-        const int z = udiv(rem, dC, &col);
-        int kx = kx0 + col;
-        const bool ok = kx < a.Hx && z < Mz;
-        const C<R> t = spec[c * cstride + (ok ? z * zstride + (int64_t)y * a.Hp + kx : (int64_t)y * a.Hp + kx0)];
-        sets[c * csp + rem] = {ok ? t.x : (R)0, ok ? t.y : (R)0};
-    }
+    copy_batched(
+        NC * cs,
+        [&](int i) {
+            int rem, col;
+            const int c = udiv(i, dcs, &rem);
+            const int z = udiv(rem, dC, &col);
+            const int kx = kx0 + col;
+            const bool ok = kx < a.Hx && z < Mz;
+            const C<R> t = spec[c * cstride + (ok ? z * zstride + (int64_t)y * a.Hp + kx : (int64_t)y * a.Hp + kx0)];
+            return C<R>{ok ? t.x : (R)0, ok ? t.y : (R)0};
+        },
+        [&](int i, C<R> v) {
+            int rem;
+            const int c = udiv(i, dcs, &rem);
+            sets[c * csp + rem] = v;
+        });
     __syncthreads();
     // as many components per transform call as fit kIpElems (lines of one
     // component are Cc adjacent columns; components are cs apart)
@@ -641,13 +696,20 @@ __device__ __forceinline__ void fft_z_scale_body(const se_fft_args& a, int blk)
     __syncthreads();
     for (int c0 = 0; c0 < 3; c0 += gc)
         fft_ip<R, -1, E>(sets, c0 * csp, Nz, min(gc, 3 - c0) * Cc, Cc, csp, 1, Cc, true, tw, s_rad, a.nrad_z);
-    for (int i = threadIdx.x; i < 3 * cs; i += blockDim.x) {
-        int rem, col;
-        const int c = udiv(i, dcs, &rem);
-        const int z = udiv(rem, dC, &col);
-        int kx = kx0 + col;
-        if (kx < a.Hx && z < Mz) spec[c * cstride + z * zstride + (int64_t)y * a.Hp + kx] = sets[c * csp + rem];
-    }
+    copy_batched(
+        3 * cs,
+        [&](int i) {
+            int rem;
+            const int c = udiv(i, dcs, &rem);
+            return sets[c * csp + rem];
+        },
+        [&](int i, C<R> v) {
+            int rem, col;
+            const int c = udiv(i, dcs, &rem);
+            const int z = udiv(rem, dC, &col);
+            const int kx = kx0 + col;
+            if (kx < a.Hx && z < Mz) spec[c * cstride + z * zstride + (int64_t)y * a.Hp + kx] = v;
+        });
 }
 
 // Kernels over one plan's pass (neighbouring blocks share an XCD and its
