@@ -341,18 +341,32 @@ __device__ __forceinline__ void fft_x_r2c_body(const se_fft_args& a, int blk)
     // (c z, y) of the block's first row; rows l < nl follow it
     const int64_t cz0 = row0 / a.Mg[1];
     const int y0 = (int)(row0 - cz0 * a.Mg[1]);
-    // element i = l Nh + k of the block
-    copy_batched(
-        nl * Nh,
-        [&](int i) {
-            int k;
-            const int l = udiv(i, dNh, &k);
-            const R* row = grid + (row0 + l) * M0;
-            const R re = (2 * k < M0) ? row[2 * k] : (R)0;
-            const R im = (2 * k + 1 < M0) ? row[2 * k + 1] : (R)0;
-            return C<R>{re, im};
-        },
-        [&](int i, C<R> v) { b0[i] = v; });
+    // element i = l Nh + k of the block; with M0 even every pair (2k, 2k+1)
+    // is one aligned complex element of the row (or past its end)
+    if ((M0 & 1) == 0) {
+        copy_batched(
+            nl * Nh,
+            [&](int i) {
+                int k;
+                const int l = udiv(i, dNh, &k);
+                const C<R>* row = (const C<R>*)(grid + (row0 + l) * M0);
+                const C<R> t = row[2 * k < M0 ? k : 0];
+                return 2 * k < M0 ? t : C<R>{(R)0, (R)0};
+            },
+            [&](int i, C<R> v) { b0[i] = v; });
+    } else {
+        copy_batched(
+            nl * Nh,
+            [&](int i) {
+                int k;
+                const int l = udiv(i, dNh, &k);
+                const R* row = grid + (row0 + l) * M0;
+                const R re = (2 * k < M0) ? row[2 * k] : (R)0;
+                const R im = (2 * k + 1 < M0) ? row[2 * k + 1] : (R)0;
+                return C<R>{re, im};
+            },
+            [&](int i, C<R> v) { b0[i] = v; });
+    }
     __syncthreads();
     fft_ip<R, 1, E>(b0, 0, Nh, nl, nl, 0, Nh, 1, false, tw, s_rad, a.nrad_xh);
     const C<R>* Z = b0;
@@ -430,8 +444,13 @@ __device__ __forceinline__ void fft_x_c2r_body(const se_fft_args& a, int blk)
             int k;
             const int l = udiv(i, dNh, &k);
             R* row = grid + (row0 + l) * M0;
-            if (2 * k < M0) row[2 * k] = z.x;
-            if (2 * k + 1 < M0) row[2 * k + 1] = z.y;
+            if ((M0 & 1) == 0) {
+                // one aligned complex store per pair (2k, 2k+1)
+                if (2 * k < M0) ((C<R>*)row)[k] = z;
+            } else {
+                if (2 * k < M0) row[2 * k] = z.x;
+                if (2 * k + 1 < M0) row[2 * k + 1] = z.y;
+            }
         });
 }
 
