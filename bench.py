@@ -218,7 +218,7 @@ def main():
     # of setting the batch up like plan creation, outside the timed region
     with torch.cuda.stream(side):
         batch.set_geometry([x], stream=side)
-        tuned = batch.tune([fb], [ub], stream=side)[0] if args.tune else (0, 0)
+        tuned = batch.tune([fb], [ub], stream=side)[0] if args.tune else (0, 0, 0)
     side.synchronize()
     with torch.cuda.stream(side):
         for _ in range(max(1, args.warmup)):
@@ -327,7 +327,7 @@ def main():
                                "sets on the shared geometry; binding and evaluation replayed as HIP graphs" % nrhs,
                    "form": "learned+batched", "n_rhs": nrhs, "learned": pdesc(par),
                    "launch_shape": {"real_tb": int(tuned[0]), "fft_cols": int(tuned[1]),
-                                    "autotuned": bool(args.tune)},
+                                    "tile_items": int(tuned[2]), "autotuned": bool(args.tune)},
                    "plain": dict(pdesc(plain_par), safety=args.safety, n_rc=args.nrc or 400.0,
                                  pollution_rule=["h/1.05,P+4", "h/1.1,P+2"][args.pollution])},
         "plain": {"value": round(plain_value, 1), "ms_per_step": round(plain_ms, 4),

@@ -247,11 +247,14 @@ se_status se_debug_cell_list(const se_plan* plan, int32_t which, const int32_t**
  *
  * A batch owns one plan per system (same rules as se_plan_create, selector
  * ANALYTIC or LEARNED).  se_batch_execute evaluates every system on one
- * stream; the first call with a given set of pointers runs the launches
- * eagerly, then records them into a HIP graph (relaxed stream capture, no
- * memset nodes; the systems forked over four internal streams, so that they
- * form parallel branches) and later calls with the same pointers replay
- * that graph as one launch.  A null stream always runs eagerly.  The graph
+ * stream.  With two or more members it runs phase by phase: one merged
+ * launch per phase covers the work items of all members (tiles of gridding
+ * and gathering, line bundles of the FFT passes, blocks of the real-space
+ * sum), and only member-specific steps are launched per member.  The first
+ * call with a given set of pointers runs the launches eagerly, then records
+ * them into a HIP graph (relaxed stream capture, no memset nodes), and later
+ * calls with the same pointers replay that graph as one launch.  A null
+ * stream always runs eagerly.  The graph
  * is dropped by se_batch_tune, new launch shapes and pointer changes; it stays
  * valid across se_batch_set_geometry, which rewrites the plans' own buffers.
  * Arrays of pointers are host arrays of n_sys device pointers, laid out as
@@ -266,10 +269,12 @@ se_status se_batch_set_geometry(se_batch* batch, const double* const* src_xyz, c
                                 const double* const* tgt_xyz, void* stream);
 se_status se_batch_execute(se_batch* batch, const double* const* strengths, double* const* u_out, void* stream);
 /* Autotuner: for every member plan, times the candidate launch shapes of the
- * real-space blocking (target bins per block) and the FFT column bundles on
- * the bound geometry with the given strengths (synchronous, HIP events) and
- * keeps the fastest.  The results are the same for every candidate up to
- * rounding. */
+ * real-space blocking (target bins per block: automatic, 1..4), then the FFT
+ * column bundles (automatic, 2, 4, 8, 16), then the gridding and gathering
+ * work item (automatic, 4, 8, 16, 64 batches of candidates) on the bound
+ * geometry with the given strengths (synchronous, HIP events), one knob after
+ * the other, and keeps the fastest of each.  The results are the same for
+ * every candidate up to rounding. */
 se_status se_batch_tune(se_batch* batch, const double* const* strengths, double* const* u_out, void* stream);
 
 /* Opt-in wrapping of periodic coordinates: with on = 1, se_set_geometry
@@ -281,9 +286,15 @@ se_status se_batch_tune(se_batch* batch, const double* const* strengths, double*
 se_status se_plan_set_wrap(se_plan* plan, int32_t on);
 
 /* Launch-shape knobs of one plan (0 = automatic): real-space target bins per
- * block axis (1..4) and the cap on FFT column bundles (1..16, power of 2). */
-se_status se_plan_set_shape(se_plan* plan, int32_t real_tb, int32_t fft_cols);
-se_status se_plan_get_shape(const se_plan* plan, int32_t* real_tb, int32_t* fft_cols);
+ * block axis (1..4), the cap on FFT column bundles (1..16, power of 2) and
+ * the work item of gridding and gathering, in batches of 64 candidate points
+ * per grid tile (1..SE_TILE_ITEMS_MAX; a tile with more candidates is split
+ * into further items that add their sums atomically).  Results are the same
+ * for every shape up to rounding.  Errors: SE_ERR_ARG for a value out of
+ * range; takes effect at the next evaluation. */
+#define SE_TILE_ITEMS_MAX 16384
+se_status se_plan_set_shape(se_plan* plan, int32_t real_tb, int32_t fft_cols, int32_t tile_items);
+se_status se_plan_get_shape(const se_plan* plan, int32_t* real_tb, int32_t* fft_cols, int32_t* tile_items);
 
 /* ---- Learned parameter selector.
  *

@@ -27,6 +27,7 @@ SE_ERR_ARG, SE_ERR_UNSUPPORTED, SE_ERR_OUT_OF_BOX, SE_ERR_NONFINITE = -1, -2, -3
 SE_ERR_COINCIDENT, SE_ERR_TOL_UNREACHABLE, SE_ERR_NOMEM, SE_ERR_HIP, SE_ERR_STATE = -5, -6, -7, -8, -9
 SE_ERR_SCRATCH = -10
 MLP_NOALLOC_MAX_N = 16384
+TILE_ITEMS_MAX = 16384  # largest gridding/gathering work item, in batches of 64 candidates
 STATUS = {0: "SE_OK", -1: "SE_ERR_ARG", -2: "SE_ERR_UNSUPPORTED", -3: "SE_ERR_OUT_OF_BOX",
           -4: "SE_ERR_NONFINITE", -5: "SE_ERR_COINCIDENT", -6: "SE_ERR_TOL_UNREACHABLE",
           -7: "SE_ERR_NOMEM", -8: "SE_ERR_HIP", -9: "SE_ERR_STATE",
@@ -133,9 +134,9 @@ def _load():
     L.se_debug_cell_list.restype = i32
     L.se_debug_cell_list.argtypes = [vp, i32, P(vp), P(vp), P(i32 * 3), P(i32 * 3)]
     L.se_plan_set_shape.restype = i32
-    L.se_plan_set_shape.argtypes = [vp, i32, i32]
+    L.se_plan_set_shape.argtypes = [vp, i32, i32, i32]
     L.se_plan_get_shape.restype = i32
-    L.se_plan_get_shape.argtypes = [vp, P(i32), P(i32)]
+    L.se_plan_get_shape.argtypes = [vp, P(i32), P(i32), P(i32)]
     L.se_batch_create.restype = i32
     L.se_batch_create.argtypes = [P(se_problem), i32, P(vp)]
     L.se_batch_destroy.restype = i32
@@ -367,17 +368,17 @@ class Plan:
         if st != SE_OK:
             raise SEError(st, "se_plan_set_wrap")
 
-    def set_shape(self, real_tb=0, fft_cols=0):
-        st = lib.se_plan_set_shape(self.handle, int(real_tb), int(fft_cols))
+    def set_shape(self, real_tb=0, fft_cols=0, tile_items=0):
+        st = lib.se_plan_set_shape(self.handle, int(real_tb), int(fft_cols), int(tile_items))
         if st != SE_OK:
             raise SEError(st, "se_plan_set_shape")
 
     def get_shape(self):
-        tb, fc = ctypes.c_int32(), ctypes.c_int32()
-        st = lib.se_plan_get_shape(self.handle, ctypes.byref(tb), ctypes.byref(fc))
+        tb, fc, ti = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        st = lib.se_plan_get_shape(self.handle, ctypes.byref(tb), ctypes.byref(fc), ctypes.byref(ti))
         if st != SE_OK:
             raise SEError(st, "se_plan_get_shape")
-        return tb.value, fc.value
+        return tb.value, fc.value, ti.value
 
     def __del__(self):
         try:
@@ -554,7 +555,7 @@ class Batch:
         return outs
 
     def tune(self, strengths, outs=None, stream=None):
-        """Autotune every member's launch shapes; returns [(real_tb, fft_cols)]."""
+        """Autotune every member's launch shapes; returns [(real_tb, fft_cols, tile_items)]."""
         outs = self._outs(strengths, outs)
         st = lib.se_batch_tune(self.handle, _ptrs(strengths), _ptrs(outs), _stream(stream))
         if st != SE_OK:

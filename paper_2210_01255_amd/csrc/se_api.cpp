@@ -717,20 +717,23 @@ se_status se_plan_set_wrap(se_plan* plan, int32_t on)
     return SE_OK;
 }
 
-se_status se_plan_set_shape(se_plan* plan, int32_t real_tb, int32_t fft_cols)
+se_status se_plan_set_shape(se_plan* plan, int32_t real_tb, int32_t fft_cols, int32_t tile_items)
 {
     if (!plan || real_tb < 0 || real_tb > 4 || fft_cols < 0 || fft_cols > 16) return SE_ERR_ARG;
     if (fft_cols & (fft_cols - 1)) return SE_ERR_ARG;
+    if (tile_items < 0 || tile_items > SE_TILE_ITEMS_MAX) return SE_ERR_ARG;
     plan->shape_real_tb = real_tb;
     plan->shape_fft_cols = fft_cols;
+    plan->shape_tile_items = tile_items;
     return SE_OK;
 }
 
-se_status se_plan_get_shape(const se_plan* plan, int32_t* real_tb, int32_t* fft_cols)
+se_status se_plan_get_shape(const se_plan* plan, int32_t* real_tb, int32_t* fft_cols, int32_t* tile_items)
 {
-    if (!plan || !real_tb || !fft_cols) return SE_ERR_ARG;
+    if (!plan || !real_tb || !fft_cols || !tile_items) return SE_ERR_ARG;
     *real_tb = plan->shape_real_tb;
     *fft_cols = plan->shape_fft_cols;
+    *tile_items = plan->shape_tile_items;
     return SE_OK;
 }
 

@@ -89,6 +89,7 @@ std::vector<uintptr_t> schedule_key(const se_batch* b)
     for (const se_plan* p : b->plans) {
         k.push_back((uintptr_t)p->shape_real_tb);
         k.push_back((uintptr_t)p->shape_fft_cols);
+        k.push_back((uintptr_t)p->shape_tile_items);
     }
     return k;
 }
@@ -465,7 +466,7 @@ se_status se_batch_execute(se_batch* b, const double* const* f, double* const* u
     if (!s) return merged ? run_schedule(b, f, u, s) : run_eager(b, f, u, s);
 
     std::vector<uintptr_t> key;
-    key.reserve(4 * b->plans.size() + 1);
+    key.reserve(5 * b->plans.size() + 1);
     key.push_back((uintptr_t)stream);
     for (size_t i = 0; i < b->plans.size(); i++) {
         const se_plan* p = b->plans[i];
@@ -473,6 +474,7 @@ se_status se_batch_execute(se_batch* b, const double* const* f, double* const* u
         key.push_back((uintptr_t)u[i]);
         key.push_back((uintptr_t)p->shape_real_tb);
         key.push_back((uintptr_t)p->shape_fft_cols);
+        key.push_back((uintptr_t)p->shape_tile_items);
     }
     if (b->exec && key == b->key) return hipGraphLaunch(b->exec, s) == hipSuccess ? SE_OK : SE_ERR_HIP;
 
@@ -509,17 +511,20 @@ se_status se_batch_tune(se_batch* b, const double* const* f, double* const* u, v
         }
         const bool timing = p->timing;
         p->timing = false;
-        // the two knobs act on different phases: tune one, then the other
+        // the knobs act on different phases: tune one after the other
         const int tbs[5] = {0, 1, 2, 3, 4};
         const int cols[5] = {0, 2, 4, 8, 16};
-        int best_tb = 0, best_cols = 0;
-        for (int pass = 0; pass < 2 && st == SE_OK; pass++) {
+        const int items[5] = {0, 4, 8, 16, 64};
+        int best_tb = 0, best_cols = 0, best_items = 0;
+        for (int pass = 0; pass < 3 && st == SE_OK; pass++) {
             float best = 1e30f;
             for (int c = 0; c < 5; c++) {
                 const int tb = pass == 0 ? tbs[c] : best_tb;
-                const int fc = pass == 0 ? 0 : cols[c];
+                const int fc = pass == 0 ? 0 : (pass == 1 ? cols[c] : best_cols);
+                const int ti = pass == 2 ? items[c] : 0;
                 p->shape_real_tb = tb;
                 p->shape_fft_cols = fc;
+                p->shape_tile_items = ti;
                 st = se_run_plan(p, f[i], u[i], nullptr, nullptr, s);  // warm-up
                 if (st != SE_OK) break;
                 float ms = 0.f;
@@ -534,12 +539,14 @@ se_status se_batch_tune(se_batch* b, const double* const* f, double* const* u, v
                 if (ms < best) {
                     best = ms;
                     if (pass == 0) best_tb = tb;
-                    else best_cols = fc;
+                    else if (pass == 1) best_cols = fc;
+                    else best_items = ti;
                 }
             }
         }
         p->shape_real_tb = best_tb;
         p->shape_fft_cols = best_cols;
+        p->shape_tile_items = best_items;
         p->timing = timing;
     }
     hipEventDestroy(e0);

@@ -91,6 +91,7 @@ struct se_plan {
     int shape_real_tb = 0;   // launch-shape knobs (0: automatic), see se_plan_set_shape
     int wrap = 0;            // reduce periodic coordinates modulo L_i when binding (se_plan_set_wrap)
     int shape_fft_cols = 0;
+    int shape_tile_items = 0;  // gridding/gathering work item: candidates in batches of 64 (0: automatic)
     bool fp32 = false;
     int device = 0;
     int64_t ns = 0, nt = 0;

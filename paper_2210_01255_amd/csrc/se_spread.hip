@@ -1037,6 +1037,7 @@ constexpr int64_t kRtManyTiles = 8192;
 
 int rt_chunk(const se_plan* p, int64_t npts)
 {
+    if (p->shape_tile_items > 0) return p->shape_tile_items * SE_RT_KB;
     const int64_t ntiles = (int64_t)p->ntile[0] * p->ntile[1] * p->ntile[2];
     if (ntiles < kRtManyTiles) return kRtChunk;
     const se_grid_geom& g = p->g;

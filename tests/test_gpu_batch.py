@@ -170,7 +170,7 @@ def test_batch_of_64_uneven_systems_with_tuning(env):
         shapes = b.tune(f, outs, stream=st)
     st.synchronize()
     print("tuned shapes", shapes, flush=True)
-    assert all(0 <= tb <= 4 and fc in (0, 2, 4, 8, 16) for tb, fc in shapes)
+    assert all(0 <= tb <= 4 and fc in (0, 2, 4, 8, 16) and ti in (0, 4, 8, 16, 64) for tb, fc, ti in shapes)
     for _ in range(3):
         for o in outs:
             o.fill_(float("nan"))
