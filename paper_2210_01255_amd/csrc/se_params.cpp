@@ -419,6 +419,11 @@ void se_analytic_targets(const se_problem* p, se_targets* out)
         for (int it = 0; it < 200; it++) {
             double arg = rs_pref(kernel, b, Q, xi, rc) / tau_of(xi);
             double nxi = arg > 1.0 ? std::sqrt(std::log(arg)) / rc : 1.0 / rc;
+            // a relative tolerance is mapped through the Fourier-part estimate
+            // U, which underflows when xi Lc is tiny (an N_rc radius far beyond
+            // the box for a handful of sources): keep the last xi at which the
+            // mapped tolerance is positive
+            if (!std::isfinite(nxi) || !(tau_of(nxi) > 0.0)) break;
             if (std::fabs(nxi - xi) < 1e-14 * xi) {
                 xi = nxi;
                 break;

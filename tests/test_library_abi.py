@@ -78,6 +78,21 @@ def test_metric_config_shape(se):
     assert abs(p["xi"] - 86.41) < 0.05 and abs(p["rc"] - 0.0457) < 1e-4
 
 
+@pytest.mark.parametrize("kernel", ["stokeslet", "rotlet", "stresslet", "harmonic"])
+def test_a_handful_of_sources_gets_finite_parameters(se, kernel):
+    """One to ten sources in a unit box, every periodicity: the relative
+    tolerance, mapped through the Fourier-part estimate U, stays positive
+    along the xi iteration (with one source in free space the harmonic U
+    underflowed there and drove xi to infinity)."""
+    for D in range(4):
+        for n in (1, 2, 10):
+            for tol in (1e-3, 1e-8):
+                p = se.select_params(kernel=kernel, periodicity=D, tol=tol, n_src=n)
+                assert math.isfinite(p["xi"]) and p["xi"] > 0, (D, n, tol, p["xi"])
+                assert math.isfinite(p["rc"]) and p["rc"] > 0, (D, n, tol, p["rc"])
+                assert p["P"] >= 4 and min(p["M"]) >= 1, (D, n, tol, p["P"], p["M"])
+
+
 def test_bad_arguments_are_rejected(se):
     with pytest.raises(se.SEError):
         se.select_params(kernel="stokeslet", periodicity=4, tol=1e-8, n_src=10)
